@@ -1,0 +1,216 @@
+/*
+ * ewbem: exponential-window frequency-domain BEM for 3-D transient
+ * elastodynamics on AMD MI355X (gfx950).
+ *
+ * The library computes the transient boundary response of an elastic solid
+ * by the method of Xiao, Ye and Wen (arXiv:1212.3032):
+ *   - Sec. 2.2 / Sec. 3.3: sample the load history, take its damped DFT;
+ *   - Sec. 3.1: solve at the complex frequencies s_k = sigma + i k (2 pi / T),
+ *     k = 0..N_f/2 (the exponential window's damping sigma);
+ *   - Sec. 2.1: collocation BEM with constant flat triangles, system
+ *     T u = U t (free term in T), A = T and b = U t for traction loading;
+ *   - Sec. 4: the sequence A_k a_k = b_k solved by GMRES with a
+ *     block-diagonal preconditioner from an extrapolated initial guess
+ *     (Sec. 4.2, solution extrapolation); here A_k is a hierarchical matrix
+ *     (cluster tree, admissibility, adaptive cross approximation, dense
+ *     near field) instead of the paper's precorrected FFT;
+ *   - Sec. 3.2 / 3.3: conjugate fill, Hann or Blackman window, inverse DFT,
+ *     de-damping by exp(sigma t).
+ *
+ * Conventions
+ *   - Degree of freedom 3 e + i is Cartesian component i of element e, in
+ *     the caller's element order (the internal cluster-tree order is hidden).
+ *   - Complex values are interleaved double pairs (ewbem_z), the layout of
+ *     numpy/torch complex128.
+ *   - Pointers documented "host" must be host memory; "device" must be
+ *     device memory on the context's GPU (e.g. a torch tensor's data_ptr()).
+ *     Inputs are copied; the caller keeps ownership of every buffer.
+ *   - All GPU work is enqueued on the stream given to ewbem_create (borrowed,
+ *     never destroyed by the library); calls return when their results are
+ *     complete.
+ *   - Every call returns EWBEM_OK (0) or a negative status and never aborts;
+ *     ewbem_last_error() describes the last failure.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef EWBEM_H
+#define EWBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes */
+#define EWBEM_OK 0
+#define EWBEM_EINVAL (-1)   /* invalid argument (shape, range, degenerate mesh, NaN) */
+#define EWBEM_ENOMEM (-2)   /* device or host allocation failed */
+#define EWBEM_EHIP (-3)     /* a HIP runtime call failed */
+#define EWBEM_ENOCONV (-4)  /* GMRES reached maxit; outputs hold the best iterate */
+#define EWBEM_ESTATE (-5)   /* call out of order (e.g. solve before mesh) or no GPU */
+
+/* ---- operator kinds, storage, windows, preconditioners, guesses */
+#define EWBEM_OP_DENSE 0    /* every block dense (no admissible blocks) */
+#define EWBEM_OP_HMAT 1     /* hierarchical matrix with ACA far field */
+#define EWBEM_STORE_C128 0  /* far factors stored and applied in complex128 */
+#define EWBEM_STORE_C64 1   /* far factors stored and applied in complex64 (FP64 accumulation) */
+#define EWBEM_WINDOW_NONE 0
+#define EWBEM_WINDOW_HANN 1     /* W_k = (1 + cos(2 pi k / N_f)) / 2  (Sec. 3.2) */
+#define EWBEM_WINDOW_BLACKMAN 2 /* 0.42 + 0.5 cos(2 pi k/N_f) + 0.08 cos(4 pi k/N_f) */
+#define EWBEM_PREC_NONE 0
+#define EWBEM_PREC_ELEMENT 1 /* inverse of each element's 3 x 3 diagonal block */
+#define EWBEM_PREC_LEAF 2    /* inverse of each leaf cluster's diagonal block */
+#define EWBEM_GUESS_ZERO 0
+#define EWBEM_GUESS_SEM 1    /* least-squares extrapolation, Sec. 4.2 */
+#define EWBEM_GUESS_QUAD 2   /* Lagrange extrapolation 3a1 - 3a2 + a3 */
+
+typedef struct ewbem_ctx ewbem_ctx; /* opaque, owned by the library */
+
+typedef struct {
+  double re, im;
+} ewbem_z;
+
+typedef struct {
+  int32_t kind;       /* EWBEM_OP_DENSE or EWBEM_OP_HMAT (default HMAT) */
+  int32_t leaf_size;  /* max elements per leaf cluster, 1..64 (default 64) */
+  double eta_adm;     /* admissibility: min(diam) <= eta * dist (default 1.0) */
+  double aca_tol;     /* relative ACA stopping tolerance (default 1e-5) */
+  int32_t far_store;  /* EWBEM_STORE_C128 or EWBEM_STORE_C64 (default C128) */
+  int32_t self_order; /* polar rule order on the singular element, 4..32 (default 20) */
+} ewbem_op_opts;
+
+typedef struct {
+  double tol;        /* relative residual |b - A x| / |b| target (default 1e-6) */
+  int32_t restart;   /* GMRES restart length m, 1..400 (default 100) */
+  int32_t maxit;     /* iteration cap per frequency (default 2000) */
+  int32_t precond;   /* EWBEM_PREC_* (default EWBEM_PREC_LEAF) */
+  int32_t guess;     /* EWBEM_GUESS_* (default EWBEM_GUESS_SEM) */
+  int32_t sem_k;     /* K previous solutions used by the guess, 1..8 (default 3) */
+} ewbem_solver_opts;
+
+typedef struct {
+  int32_t n_solves;        /* frequencies solved by the call */
+  int32_t iters_total;     /* GMRES iterations summed over them */
+  int32_t iters_max;
+  int32_t matvecs;         /* operator applications (GMRES + guess + residuals) */
+  double resid_max;        /* largest final true relative residual */
+  double guess_resid_sum;  /* sum of |b - A x0| / |b| of the initial guesses */
+  double t_assemble_ms;    /* wall time in operator/RHS/preconditioner assembly */
+  double t_guess_ms;       /* wall time in the initial guess */
+  double t_gmres_ms;       /* wall time in GMRES */
+  double t_post_ms;        /* wall time in the inverse transform */
+  double t_matvec_ms;      /* summed HIP-event time of the matvec kernels */
+  double matvec_bytes;     /* algorithmic bytes of one matvec (last operator) */
+  double stored_bytes;     /* bytes of the stored operator (near + far) */
+  int64_t n_near, n_far;   /* block counts */
+  int64_t rank_sum, rank_max; /* far-block ranks of the last operator */
+  double t_aca_ms;         /* HIP-event time of the ACA kernels */
+  double t_near_ms;        /* HIP-event time of the near-field + self kernels */
+  double t_rhs_ms;         /* HIP-event time of the right-hand-side kernels */
+} ewbem_stats;
+
+typedef struct {
+  int64_t n_elements, n_dof;
+  int64_t n_clusters, n_leaves, n_near, n_far;
+  int64_t near_entries;    /* complex entries of all dense near blocks */
+  int32_t max_leaf, min_leaf;
+} ewbem_info_t;
+
+/* Fill option structs with their defaults. */
+void ewbem_default_op_opts(ewbem_op_opts* o);
+void ewbem_default_solver_opts(ewbem_solver_opts* o);
+
+/* Create a context on GPU ``device`` enqueuing on ``hip_stream`` (a
+ * hipStream_t, borrowed; NULL = the null stream).  device = -1 creates a
+ * host-only context: mesh, tree and partition queries work, every GPU call
+ * returns EWBEM_ESTATE. */
+int ewbem_create(ewbem_ctx** out, int32_t device, void* hip_stream);
+void ewbem_destroy(ewbem_ctx* ctx);
+/* Message of the last failure on ctx (valid until the next call on it). */
+const char* ewbem_last_error(const ewbem_ctx* ctx);
+
+/* Sec. 2.1: boundary mesh of flat triangles.  xyz: host, nv x 3 doubles;
+ * tri: host, nt x 3 vertex indices, counter-clockwise seen from outside each
+ * closed surface.  exterior = 1: the solid lies outside the surfaces
+ * (cavities), so the outward normal of the solid points into them;
+ * exterior = 0: a bounded solid.  EINVAL on bad indices or zero-area
+ * triangles. */
+int ewbem_set_mesh(ewbem_ctx* ctx, int64_t nv, const double* xyz, int64_t nt,
+                   const int32_t* tri, int32_t exterior);
+
+/* Sec. 2.1: density rho, shear modulus mu, Poisson ratio nu (c_s, c_p follow). */
+int ewbem_set_material(ewbem_ctx* ctx, double rho, double mu, double nu);
+
+/* Sec. 2.2 / 3.1: period T, N_f samples (even, >= 2; dt = T / N_f),
+ * damping sigma >= 0 of the exponential window, spectral window
+ * EWBEM_WINDOW_*. */
+int ewbem_set_time(ewbem_ctx* ctx, double period, int32_t n_f, double sigma, int32_t window);
+
+/* Sec. 2.1 / 2.2: traction load t(x, t) = t0(x) P(t).  t0: host, nt x 3
+ * (caller order); history: host, n_f samples P(n dt). */
+int ewbem_set_load_traction(ewbem_ctx* ctx, const double* t0, const double* history);
+
+/* Pressure load: t0 = -p n on each element (n pointing out of the solid), so
+ * p > 0 pushes on the solid.  p: host, nt values; history: host, n_f. */
+int ewbem_set_load_pressure(ewbem_ctx* ctx, const double* p, const double* history);
+
+int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* opts);
+int ewbem_set_solver(ewbem_ctx* ctx, const ewbem_solver_opts* opts);
+
+/* Sizes of the discretisation, cluster tree and block partition (host). */
+int ewbem_info(ewbem_ctx* ctx, ewbem_info_t* info);
+
+/* Cluster tree and partition (host output).  perm (nt): perm[t] = caller
+ * element at tree position t.  near, far: 4 int32 per block (row begin,
+ * row end, col begin, col end) as tree positions; either may be NULL.
+ * Sizes from ewbem_info. */
+int ewbem_get_partition(ewbem_ctx* ctx, int32_t* perm, int32_t* near, int32_t* far);
+
+/* Sec. 3.3 (damped DFT): P_k = (1/N_f) sum_n exp(-sigma n dt) P(n dt)
+ * exp(-2 pi i n k / N_f), k = 0..N_f/2.  phat: host, N_f/2+1 values. */
+int ewbem_load_spectrum(ewbem_ctx* ctx, ewbem_z* phat);
+
+/* Sec. 2.1: point kernels at Laplace parameter s for n pairs: U_ij(x, y)
+ * and T_ij(x, y; n(y)) (i = force direction at x, j = component at y).
+ * x, y, nrm: device, n x 3; U, T: device, n x 9 row-major (either NULL). */
+int ewbem_kernel_eval(ewbem_ctx* ctx, ewbem_z s, int64_t n, const double* x, const double* y,
+                      const double* nrm, ewbem_z* U, ewbem_z* T);
+
+/* Sec. 2.1, eq. T u = U t: dense collocation matrices at s.  T (with the
+ * free term) and U: device, N x N row-major in caller order (either NULL).
+ * Meant for small meshes and parity checks. */
+int ewbem_assemble_dense(ewbem_ctx* ctx, ewbem_z s, ewbem_z* T, ewbem_z* U);
+
+/* Sec. 4 (A_k a_k = b_k): assemble the operator A_k = T(s_k), the right-hand
+ * side b_k = P_k U(s_k) t0 and the preconditioner at frequency k. */
+int ewbem_assemble(ewbem_ctx* ctx, int32_t k, ewbem_stats* stats);
+
+/* y = A_k x with the assembled operator.  x, y: device, N (caller order). */
+int ewbem_apply(ewbem_ctx* ctx, const ewbem_z* x, ewbem_z* y);
+
+/* b_k of the assembled frequency.  b: device, N (caller order). */
+int ewbem_get_rhs(ewbem_ctx* ctx, ewbem_z* b);
+
+/* Solve A_k a_k = b_k (assembling first if needed).  x0: device, N, or NULL
+ * for the configured guess (Sec. 4.2 uses the solutions of the previous
+ * frequencies solved on this context); a: device, N.  ENOCONV if maxit is
+ * reached (a holds the last iterate). */
+int ewbem_solve_frequency(ewbem_ctx* ctx, int32_t k, const ewbem_z* x0, ewbem_z* a,
+                          ewbem_stats* stats);
+
+/* The whole path: solve k = 0..N_f/2 in order, then the inverse transform.
+ * u: device, N_f x N doubles (time-major); spec: device, (N_f/2+1) x N
+ * complex, or NULL. */
+int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats* stats);
+
+/* Sec. 3.3 (inverse): u(n dt) = Re{exp(sigma n dt) sum_k W_k a_k
+ * exp(2 pi i n k / N_f)} with a_{N_f-k} = conj(a_k).  spec: device,
+ * (N_f/2+1) x N complex (caller order); u: device, N_f x N doubles. */
+int ewbem_mft_inverse(ewbem_ctx* ctx, const ewbem_z* spec, double* u);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EWBEM_H */

@@ -1,0 +1,1301 @@
+// C-ABI of the ewbem library: context, setup, per-frequency assembly,
+// hierarchical matvec, GMRES with solution extrapolation, and the modified
+// Fourier transform back to time.  See include/ewbem.h for the contract.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ewbem.h"
+#include "aca.hpp"
+#include "host.hpp"
+#include "launch.hpp"
+#include "solver.hpp"
+
+using namespace ewbem;
+
+namespace {
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void reserve(size_t cnt) {
+    if (cnt <= n) return;
+    release();
+    if (cnt) {
+      EWBEM_HIP_CHECK(hipMalloc((void**)&p, cnt * sizeof(T)));
+      n = cnt;
+    }
+  }
+  void upload(const std::vector<T>& v, hipStream_t st) {
+    reserve(v.size());
+    if (!v.empty())
+      EWBEM_HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+};
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    EWBEM_HIP_CHECK(hipEventCreate(&a));
+    EWBEM_HIP_CHECK(hipEventCreate(&b));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  float elapsed() {
+    float ms = 0.f;
+    EWBEM_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+};
+
+void fail(int st, const std::string& m) { throw ApiError(st, m); }
+
+}  // namespace
+
+struct ewbem_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // ---- inputs
+  bool have_mesh = false, have_mat = false, have_time = false, have_load = false;
+  std::vector<double> xyz;
+  std::vector<int32_t> tri;
+  int nv = 0, nt = 0;
+  bool exterior = true;
+  double rho = 1, mu = 1, nu = 0.25;
+  double period = 1;
+  int n_f = 2;
+  double sigma = 0;
+  int window = EWBEM_WINDOW_HANN;
+  bool load_is_pressure = false;
+  std::vector<double> load_caller;  // t0 (nt*3) or p (nt), caller order
+  std::vector<double> history;
+  ewbem_op_opts op{};
+  ewbem_solver_opts so{};
+
+  // ---- derived structure (host)
+  bool structure_ok = false;  // tree + geometry + partition match the inputs
+  bool device_ok = false;     // device copies of the structure are current
+  HostGeom hg;
+  Partition part;
+  std::vector<NearBlk> near_h;
+  std::vector<long long> self_off_h;
+  std::vector<int> self_ld_h;
+  long long near_entries = 0;
+  std::vector<FarBlk> far_h;
+  std::vector<int> rank_h, status_h, kcap_prev;
+
+  // ---- device state
+  DevBuf<double> d_cen, d_nrm, d_qp, d_qw, d_vtx, d_t0, d_hist;
+  DevBuf<int> d_perm;
+  DevBuf<cd> d_phat, d_selfT, d_selfU;
+  DevBuf<NearBlk> d_near;
+  DevBuf<long long> d_self_off;
+  DevBuf<int> d_self_ld;
+  DevBuf<cd> d_D;
+  DevBuf<FarBlk> d_far;
+  DevBuf<cd> d_ws, d_ws2;
+  DevBuf<cf> d_f32;
+  DevBuf<long long> d_uo, d_vo;
+  DevBuf<int> d_rank, d_status, d_ord_small, d_ord_big;
+  DevBuf<VtTask> d_vt;
+  DevBuf<Seg> d_seg;
+  DevBuf<RowTask> d_rt;
+  DevBuf<LeafRange> d_lr;
+  int n_vt = 0, n_rt = 0, n_lr = 0;
+  DevBuf<cd> d_z, d_hpart, d_mvpart;
+  DevBuf<cd> d_rhs_part;
+  // preconditioner
+  DevBuf<cd> d_M3, d_Minv;
+  DevBuf<long long> d_minv_off, d_minv_src;
+  DevBuf<int> d_minv_dim, d_minv_row0, d_minv_ld, d_pivfail;
+  int n_minv = 0;
+  // vectors (tree order)
+  DevBuf<cd> d_b, d_x, d_r, d_w, d_u, d_zt, d_V, d_small, d_tmp_in, d_tmp_out;
+  DevBuf<cd> d_Y, d_hist_sol, d_spec;
+  int hist_n = 0, hist_head = 0;  // ring buffer of the last sem_k solutions
+  std::vector<int> hist_slot;     // newest first
+
+  int assembled_k = -1;
+  KParams P{};
+  SelfRule S{};
+  int store_c64_active = 0;
+  double matvec_bytes = 0, stored_bytes = 0;
+  int64_t rank_sum = 0, rank_max = 0;
+
+  // per-call accumulators
+  ewbem_stats acc{};
+};
+
+namespace {
+
+KParams make_params(double rho, double mu, double nu, cd s) {
+  KParams P{};
+  const double lam = 2.0 * mu * nu / (1.0 - 2.0 * nu);
+  const double cs = std::sqrt(mu / rho), cp = std::sqrt((lam + 2.0 * mu) / rho);
+  const double g = cs / cp;
+  P.s = s;
+  P.inv_cs = 1.0 / cs;
+  P.gamma = g;
+  P.g2 = g * g;
+  P.ratio = (cp / cs) * (cp / cs);
+  P.inv4pi = 1.0 / (4.0 * M_PI);
+  P.inv4pimu = 1.0 / (4.0 * M_PI * mu);
+  P.cpv = g * g / (4.0 * M_PI);
+  P.series_z2 = 0.25;
+  // Taylor coefficients of r phi, r psi in z = s r / c_s (index m = n - 2):
+  //   r phi: (-1)^n (n-1)(n-1+g^n)/n!,  r psi: (-1)^n (n-1)(n-3)(1-g^n)/n!,
+  //   r^2 phi', r^2 psi': the same times (n-3).
+  double fact = 1.0;  // n!
+  for (int n = 1; n <= 1; ++n) fact *= n;
+  for (int n = 2; n < NSER + 2; ++n) {
+    fact *= n;
+    const double sgn = (n % 2 == 0) ? 1.0 : -1.0;
+    const double gn = std::pow(g, n);
+    const double cphi = sgn * (n - 1) * (n - 1 + gn) / fact;
+    const double cpsi = sgn * (n - 1) * (n - 3) * (1.0 - gn) / fact;
+    P.c_phi[n - 2] = cphi;
+    P.c_psi[n - 2] = cpsi;
+    P.c_dphi[n - 2] = (n - 3) * cphi;
+    P.c_dpsi[n - 2] = (n - 3) * cpsi;
+  }
+  P.stat_rphi = P.c_phi[0];
+  P.stat_rpsi = P.c_psi[0];
+  return P;
+}
+
+void require_gpu(ewbem_ctx* c) {
+  if (c->device < 0) fail(EWBEM_ESTATE, "host-only context: no GPU work possible");
+}
+
+void ensure_structure(ewbem_ctx* c) {
+  if (!c->have_mesh) fail(EWBEM_ESTATE, "mesh not set");
+  if (c->structure_ok) return;
+  c->part = Partition();
+  std::vector<int> perm = build_tree(c->nv, c->xyz.data(), c->nt, c->tri.data(), c->op.leaf_size,
+                                     c->part.clusters);
+  build_geometry(c->nv, c->xyz.data(), c->nt, c->tri.data(), c->exterior, perm, c->hg);
+  build_partition(c->op.kind == EWBEM_OP_DENSE ? 0.0 : c->op.eta_adm, c->part);
+  // near-block layout (each block column-major, ld = 3 m) and the position
+  // of every element's self block inside its diagonal near block
+  c->near_h.clear();
+  c->self_off_h.assign(c->nt, -1);
+  c->self_ld_h.assign(c->nt, 0);
+  long long off = 0;
+  for (const BlockPair& bp : c->part.near) {
+    const Cluster& r = c->part.clusters[bp.row];
+    const Cluster& s = c->part.clusters[bp.col];
+    NearBlk nb{r.begin, r.size(), s.begin, s.size(), off};
+    c->near_h.push_back(nb);
+    if (bp.row == bp.col)
+      for (int a = 0; a < r.size(); ++a) {
+        c->self_off_h[r.begin + a] = off + (long long)(3 * a) * (3 * r.size()) + 3 * a;
+        c->self_ld_h[r.begin + a] = 3 * r.size();
+      }
+    off += 9LL * r.size() * s.size();
+  }
+  c->near_entries = off;
+  for (int e = 0; e < c->nt; ++e)
+    if (c->self_off_h[e] < 0) fail(EWBEM_EINVAL, "internal: element without a diagonal near block");
+  c->far_h.clear();
+  for (const BlockPair& bp : c->part.far) {
+    const Cluster& r = c->part.clusters[bp.row];
+    const Cluster& s = c->part.clusters[bp.col];
+    if (r.size() > ACA_MAXM) fail(EWBEM_EINVAL, "far block with more than 16384 row elements");
+    FarBlk fb{};
+    fb.r0 = r.begin;
+    fb.m = r.size();
+    fb.c0 = s.begin;
+    fb.n = s.size();
+    c->far_h.push_back(fb);
+  }
+  c->kcap_prev.assign(c->far_h.size(), 0);
+  c->rank_h.assign(c->far_h.size(), 0);
+  c->status_h.assign(c->far_h.size(), 0);
+  c->structure_ok = true;
+  c->device_ok = false;
+  c->assembled_k = -1;
+}
+
+std::vector<double> tree_load(ewbem_ctx* c) {
+  // traction per element in tree order
+  const HostGeom& g = c->hg;
+  std::vector<double> t0(3 * (size_t)c->nt);
+  for (int t = 0; t < c->nt; ++t) {
+    const int e = g.perm[t];
+    for (int k = 0; k < 3; ++k)
+      t0[3 * t + k] = c->load_is_pressure ? -c->load_caller[e] * g.nrm[3 * t + k]
+                                          : c->load_caller[3 * (size_t)e + k];
+  }
+  return t0;
+}
+
+void ensure_device(ewbem_ctx* c) {
+  require_gpu(c);
+  ensure_structure(c);
+  if (!c->have_mat) fail(EWBEM_ESTATE, "material not set");
+  if (!c->have_time) fail(EWBEM_ESTATE, "time grid not set");
+  if (!c->have_load) fail(EWBEM_ESTATE, "load not set");
+  if (c->device_ok) return;
+  EWBEM_HIP_CHECK(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const HostGeom& g = c->hg;
+  c->d_cen.upload(g.cen, st);
+  c->d_nrm.upload(g.nrm, st);
+  c->d_qp.upload(g.qp, st);
+  c->d_qw.upload(g.qw, st);
+  c->d_vtx.upload(g.vtx, st);
+  c->d_perm.upload(g.perm, st);
+  std::vector<double> t0 = tree_load(c);
+  c->d_t0.upload(t0, st);
+  c->d_hist.upload(c->history, st);
+  c->d_phat.reserve(c->n_f / 2 + 1);
+  launch_load_spectrum(c->d_hist.p, c->n_f, c->period, c->sigma, c->d_phat.p, st);
+  c->d_near.upload(c->near_h, st);
+  c->d_self_off.upload(c->self_off_h, st);
+  c->d_self_ld.upload(c->self_ld_h, st);
+  c->d_D.reserve(std::max<long long>(c->near_entries, 1));
+  const long long N = 3LL * c->nt;
+  c->d_selfT.reserve(9 * (size_t)c->nt);
+  c->d_selfU.reserve(9 * (size_t)c->nt);
+  c->d_rhs_part.reserve((size_t)rhs_chunks(c->nt) * N);
+  for (DevBuf<cd>* v : {&c->d_b, &c->d_x, &c->d_r, &c->d_w, &c->d_u, &c->d_zt, &c->d_tmp_in, &c->d_tmp_out})
+    v->reserve(N);
+  const int m = c->so.restart;
+  c->d_V.reserve((size_t)std::max(m + 1, c->so.sem_k) * N);
+  c->d_small.reserve(4 * (size_t)(m + 2) + 16);
+  c->d_hpart.reserve((size_t)dots_chunks(N) * std::max(m + 2, c->so.sem_k + 1));
+  c->d_Y.reserve((size_t)std::max(1, c->so.sem_k) * N);
+  c->d_hist_sol.reserve((size_t)std::max(1, c->so.sem_k) * N);
+  c->d_spec.reserve((size_t)(c->n_f / 2 + 1) * N);
+  c->d_M3.reserve(9 * (size_t)c->nt);
+  // self rule
+  c->S.nt = c->S.nr = c->op.self_order;
+  gauss_legendre01(c->op.self_order, c->S.t, c->S.wt);
+  gauss_legendre01(c->op.self_order, c->S.u, c->S.wu);
+  c->P = make_params(c->rho, c->mu, c->nu, mk(0.0));
+  c->hist_n = 0;
+  c->hist_head = 0;
+  c->hist_slot.clear();
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  c->device_ok = true;
+  c->assembled_k = -1;
+}
+
+DevGeom dev_geom(ewbem_ctx* c) {
+  DevGeom g;
+  g.ne = c->nt;
+  g.cen = c->d_cen.p;
+  g.nrm = c->d_nrm.p;
+  g.qp = c->d_qp.p;
+  g.qw = c->d_qw.p;
+  g.vtx = c->d_vtx.p;
+  return g;
+}
+
+cd s_of_k(ewbem_ctx* c, int k) { return cd{c->sigma, 2.0 * M_PI * k / c->period}; }
+
+// ---- ACA with capacity retries, then matvec task lists
+void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
+  hipStream_t st = c->stream;
+  const int nf = (int)c->far_h.size();
+  if (nf == 0) return;
+  std::vector<int> kcap(nf);
+  for (int b = 0; b < nf; ++b) {
+    const FarBlk& f = c->far_h[b];
+    const int full = 3 * std::min(f.m, f.n);
+    const bool small = f.m <= ACA_SMALL && f.n <= ACA_SMALL;
+    const int kmax = small ? ACA_KMAX_SMALL : ACA_KMAX;
+    int want = c->kcap_prev[b] > 0 ? c->rank_h[b] + std::max(9, c->rank_h[b] / 4) : 30;
+    want = ((want + 2) / 3) * 3;
+    kcap[b] = std::max(3, std::min({want, full, kmax}));
+  }
+  // main layout
+  long long total = 0;
+  for (int b = 0; b < nf; ++b) total += (long long)(3 * c->far_h[b].m + 3 * c->far_h[b].n) * kcap[b];
+  c->d_ws.reserve(total);
+  long long off = 0;
+  std::vector<int> small_ids, big_ids;
+  for (int b = 0; b < nf; ++b) {
+    FarBlk& f = c->far_h[b];
+    f.kcap = kcap[b];
+    f.U = c->d_ws.p + off;
+    off += 3LL * f.m * kcap[b];
+    f.V = c->d_ws.p + off;
+    off += 3LL * f.n * kcap[b];
+    const bool small = f.m <= ACA_SMALL && f.n <= ACA_SMALL && kcap[b] <= ACA_KMAX_SMALL;
+    (small ? small_ids : big_ids).push_back(b);
+  }
+  c->d_far.upload(c->far_h, st);
+  std::vector<int> ord(small_ids);
+  ord.insert(ord.end(), big_ids.begin(), big_ids.end());
+  c->d_ord_small.upload(ord, st);
+  c->d_rank.reserve(nf);
+  c->d_status.reserve(nf);
+  EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+  launch_aca(c->d_far.p, c->d_ord_small.p, (int)small_ids.size(), c->d_ord_small.p + small_ids.size(),
+             (int)big_ids.size(), g, c->P, c->op.aca_tol, c->d_rank.p, c->d_status.p, st);
+  EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  aca_ms += ev.elapsed();
+  // retries for blocks that ran out of capacity, in a separate buffer
+  for (int round = 0; round < 8; ++round) {
+    std::vector<int> over;
+    for (int b = 0; b < nf; ++b)
+      if (c->status_h[b] != 0) over.push_back(b);
+    if (over.empty()) break;
+    long long tot2 = 0;
+    for (int b : over) {
+      FarBlk& f = c->far_h[b];
+      const int full = 3 * std::min(f.m, f.n);
+      if (f.kcap >= std::min(full, ACA_KMAX))
+        fail(EWBEM_EINVAL, "ACA rank exceeds the per-block limit of 384");
+      f.kcap = std::min({full, ACA_KMAX, 2 * f.kcap + 6});
+      tot2 += (long long)(3 * f.m + 3 * f.n) * f.kcap;
+    }
+    c->d_ws2.release();
+    c->d_ws2.reserve(tot2);
+    long long o2 = 0;
+    for (int b : over) {
+      FarBlk& f = c->far_h[b];
+      f.U = c->d_ws2.p + o2;
+      o2 += 3LL * f.m * f.kcap;
+      f.V = c->d_ws2.p + o2;
+      o2 += 3LL * f.n * f.kcap;
+    }
+    c->d_far.upload(c->far_h, st);
+    c->d_ord_big.upload(over, st);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+    launch_aca(c->d_far.p, nullptr, 0, c->d_ord_big.p, (int)over.size(), g, c->P, c->op.aca_tol,
+               c->d_rank.p, c->d_status.p, st);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+    EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+    EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    aca_ms += ev.elapsed();
+  }
+  for (int b = 0; b < nf; ++b) {
+    if (c->status_h[b] != 0) fail(EWBEM_EINVAL, "ACA did not converge within its capacity");
+    c->kcap_prev[b] = c->far_h[b].kcap;
+  }
+}
+
+void build_matvec(ewbem_ctx* c) {
+  hipStream_t st = c->stream;
+  const int nf = (int)c->far_h.size();
+  const bool c64 = c->op.far_store == EWBEM_STORE_C64 && nf > 0;
+  c->store_c64_active = c64;
+  // z offsets and (for complex64) the compact factor store
+  std::vector<long long> zoff(nf + 1, 0), uo(nf), vo(nf);
+  long long f32tot = 0;
+  c->rank_sum = 0;
+  c->rank_max = 0;
+  for (int b = 0; b < nf; ++b) {
+    const int k = c->rank_h[b];
+    zoff[b + 1] = zoff[b] + k;
+    uo[b] = f32tot;
+    f32tot += 3LL * c->far_h[b].m * k;
+    vo[b] = f32tot;
+    f32tot += 3LL * c->far_h[b].n * k;
+    c->rank_sum += k;
+    c->rank_max = std::max<int64_t>(c->rank_max, k);
+  }
+  c->d_z.reserve(std::max<long long>(1, zoff[nf]));
+  if (c64) {
+    c->d_f32.reserve(std::max<long long>(1, f32tot));
+    c->d_uo.upload(uo, st);
+    c->d_vo.upload(vo, st);
+    launch_to_c64(c->d_far.p, nf, c->d_rank.p, c->d_uo.p, c->d_vo.p, c->d_f32.p, st);
+  }
+  // phase 1 tasks
+  std::vector<VtTask> vt;
+  for (int b = 0; b < nf; ++b) {
+    const FarBlk& f = c->far_h[b];
+    const int k = c->rank_h[b], C = 3 * f.n;
+    for (int l0 = 0; l0 < k; l0 += 4) {
+      VtTask t{};
+      t.V = c64 ? (const void*)(c->d_f32.p + vo[b] + (size_t)l0 * C) : (const void*)(f.V + (size_t)l0 * C);
+      t.zidx = zoff[b] + l0;
+      t.C = C;
+      t.x0 = 3 * f.c0;
+      t.ncol = std::min(4, k - l0);
+      vt.push_back(t);
+    }
+  }
+  // phase 2 segments per leaf
+  const std::vector<int>& leaves = c->part.leaves;
+  const int nl = (int)leaves.size();
+  std::vector<int> leaf_begin(nl);
+  for (int i = 0; i < nl; ++i) leaf_begin[i] = c->part.clusters[leaves[i]].begin;
+  auto leaf_of = [&](int begin) {
+    return (int)(std::lower_bound(leaf_begin.begin(), leaf_begin.end(), begin) - leaf_begin.begin());
+  };
+  std::vector<std::vector<Seg>> segs(nl);
+  double bytes = 0;
+  const double be_far = c64 ? 8.0 : 16.0;
+  for (const NearBlk& nb : c->near_h) {
+    const int li = leaf_of(nb.r0);
+    Seg s{};
+    s.A = c->d_D.p + nb.off;
+    s.src = 3LL * nb.c0;
+    s.ld = 3 * nb.m;
+    s.ncols = 3 * nb.n;
+    s.flags = 0;
+    segs[li].push_back(s);
+    bytes += 9.0 * nb.m * nb.n * 16.0;
+  }
+  for (int b = 0; b < nf; ++b) {
+    const FarBlk& f = c->far_h[b];
+    const int k = c->rank_h[b];
+    if (k == 0) continue;
+    bytes += 3.0 * k * (f.m + f.n) * be_far + 2.0 * k * 16.0;
+    for (int li = leaf_of(f.r0); li < nl && leaf_begin[li] < f.r0 + f.m; ++li) {
+      const Cluster& L = c->part.clusters[leaves[li]];
+      Seg s{};
+      const size_t roff = 3 * (size_t)(L.begin - f.r0);
+      s.A = c64 ? (const void*)(c->d_f32.p + uo[b] + roff) : (const void*)(f.U + roff);
+      s.src = zoff[b];
+      s.ld = 3 * f.m;
+      s.ncols = k;
+      s.flags = SEG_FROM_Z | (c64 ? SEG_C64 : 0);
+      segs[li].push_back(s);
+    }
+  }
+  const long long N = 3LL * c->nt;
+  bytes += 2.0 * N * 16.0;  // read x, write y
+  c->matvec_bytes = bytes;
+  c->stored_bytes = 0;
+  for (const NearBlk& nb : c->near_h) c->stored_bytes += 9.0 * nb.m * nb.n * 16.0;
+  for (int b = 0; b < nf; ++b)
+    c->stored_bytes += 3.0 * c->rank_h[b] * (c->far_h[b].m + c->far_h[b].n) * be_far;
+  long long total_cols = 0;
+  for (auto& v : segs)
+    for (auto& s : v) total_cols += s.ncols;
+  const long long target = std::max<long long>(96, total_cols / 4096);
+  std::vector<Seg> flat;
+  std::vector<RowTask> rt;
+  std::vector<LeafRange> lr;
+  for (int li = 0; li < nl; ++li) {
+    const Cluster& L = c->part.clusters[leaves[li]];
+    LeafRange range{3 * L.begin, 3 * L.size(), (int)rt.size(), 0};
+    long long acc = 0;
+    int s0 = (int)flat.size();
+    for (const Seg& s : segs[li]) {
+      flat.push_back(s);
+      acc += s.ncols;
+      if (acc >= target) {
+        rt.push_back(RowTask{3 * L.begin, 3 * L.size(), s0, (int)flat.size()});
+        s0 = (int)flat.size();
+        acc = 0;
+      }
+    }
+    if ((int)flat.size() > s0 || range.t0 == (int)rt.size())
+      rt.push_back(RowTask{3 * L.begin, 3 * L.size(), s0, (int)flat.size()});
+    range.t1 = (int)rt.size();
+    lr.push_back(range);
+  }
+  c->d_vt.upload(vt, st);
+  c->d_seg.upload(flat, st);
+  c->d_rt.upload(rt, st);
+  c->d_lr.upload(lr, st);
+  c->n_vt = (int)vt.size();
+  c->n_rt = (int)rt.size();
+  c->n_lr = (int)lr.size();
+  c->d_mvpart.reserve((size_t)std::max(1, c->n_rt) * HMV_MAXROWS);
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// y = A x in tree order (both device, length N); times the kernels with
+// events when ``ev`` is given.
+void apply_tree(ewbem_ctx* c, const cd* x, cd* y, EventPair* ev) {
+  hipStream_t st = c->stream;
+  if (ev) EWBEM_HIP_CHECK(hipEventRecord(ev->a, st));
+  launch_far_vt(c->d_vt.p, c->n_vt, c->store_c64_active, x, c->d_z.p, st);
+  launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, x, c->d_z.p, c->d_mvpart.p, st);
+  launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, y, st);
+  if (ev) EWBEM_HIP_CHECK(hipEventRecord(ev->b, st));
+  c->acc.matvecs += 1;
+}
+
+void precond_setup(ewbem_ctx* c) {
+  hipStream_t st = c->stream;
+  if (c->so.precond == EWBEM_PREC_ELEMENT) {
+    launch_inv3(c->d_selfT.p, c->nt, c->d_M3.p, st);
+  } else if (c->so.precond == EWBEM_PREC_LEAF) {
+    // copy each leaf's diagonal near block into a compact work array, invert
+    std::vector<long long> src, dst;
+    std::vector<int> dims, row0, ld;
+    long long off = 0;
+    for (const NearBlk& nb : c->near_h) {
+      if (nb.r0 != nb.c0) continue;
+      src.push_back(nb.off);
+      dst.push_back(off);
+      dims.push_back(3 * nb.m);
+      row0.push_back(3 * nb.r0);
+      ld.push_back(3 * nb.m);
+      off += 9LL * nb.m * nb.m;
+    }
+    c->d_Minv.reserve(off);
+    c->d_minv_src.upload(src, st);
+    c->d_minv_off.upload(dst, st);
+    c->d_minv_dim.upload(dims, st);
+    c->d_minv_row0.upload(row0, st);
+    c->d_minv_ld.upload(ld, st);
+    c->d_pivfail.reserve(dims.size());
+    c->n_minv = (int)dims.size();
+    EWBEM_HIP_CHECK(hipMemsetAsync(c->d_pivfail.p, 0, dims.size() * sizeof(int), st));
+    launch_copy_blocks(c->d_minv_src.p, c->d_minv_ld.p, c->d_minv_off.p, c->d_minv_dim.p, (int)dims.size(),
+                       c->d_D.p, c->d_Minv.p, st);
+    launch_block_inv(c->d_minv_off.p, c->d_minv_dim.p, (int)dims.size(), c->d_Minv.p, c->d_pivfail.p, st);
+    std::vector<int> pf(dims.size());
+    EWBEM_HIP_CHECK(hipMemcpyAsync(pf.data(), c->d_pivfail.p, pf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    for (int v : pf)
+      if (v) fail(EWBEM_EINVAL, "singular diagonal block in the preconditioner");
+  }
+}
+
+void precond_apply(ewbem_ctx* c, const cd* v, cd* z) {
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  if (c->so.precond == EWBEM_PREC_ELEMENT) {
+    launch_apply3(c->d_M3.p, c->nt, v, z, st);
+  } else if (c->so.precond == EWBEM_PREC_LEAF) {
+    launch_block_apply(c->d_minv_off.p, c->d_minv_dim.p, c->d_minv_row0.p, c->n_minv,
+                       c->d_Minv.p, v, z, st);
+  } else {
+    EWBEM_HIP_CHECK(hipMemcpyAsync(z, v, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+  }
+}
+
+void assemble_k(ewbem_ctx* c, int k) {
+  ensure_device(c);
+  if (k < 0 || k > c->n_f / 2) fail(EWBEM_EINVAL, "frequency index out of range 0..N_f/2");
+  hipStream_t st = c->stream;
+  const auto t0 = Clock::now();
+  c->P = make_params(c->rho, c->mu, c->nu, s_of_k(c, k));
+  const DevGeom g = dev_geom(c);
+  EventPair ev;
+  EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+  launch_self(g, c->P, c->S, c->d_selfT.p, c->d_selfU.p, st);
+  launch_near(c->d_near.p, (int)c->near_h.size(), g, c->P, c->d_D.p, st);
+  launch_scatter_self(c->d_selfT.p, c->d_self_off.p, c->nt, c->d_D.p, c->d_self_ld.p, st);
+  EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  c->acc.t_near_ms += ev.elapsed();
+  double aca_ms = 0;
+  run_aca(c, g, ev, aca_ms);
+  c->acc.t_aca_ms += aca_ms;
+  build_matvec(c);
+  EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+  launch_rhs(g, c->P, c->d_t0.p, c->d_selfU.p, c->d_phat.p + k, c->d_rhs_part.p, rhs_chunks(c->nt),
+             c->d_b.p, st);
+  EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+  precond_setup(c);
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  c->acc.t_rhs_ms += ev.elapsed();
+  c->assembled_k = k;
+  c->acc.t_assemble_ms += ms_since(t0);
+  c->acc.n_near = (int64_t)c->near_h.size();
+  c->acc.n_far = (int64_t)c->far_h.size();
+  c->acc.rank_sum = c->rank_sum;
+  c->acc.rank_max = c->rank_max;
+  c->acc.matvec_bytes = c->matvec_bytes;
+  c->acc.stored_bytes = c->stored_bytes;
+}
+
+// |v|^2 etc.: host copies of small device results
+double dev_norm(ewbem_ctx* c, const cd* v) {
+  const long long N = 3LL * c->nt;
+  cd h;
+  launch_dots(v, N, 1, v, N, c->d_hpart.p, c->d_small.p, c->stream);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(&h, c->d_small.p, sizeof(cd), hipMemcpyDeviceToHost, c->stream));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return std::sqrt(std::max(0.0, h.x));
+}
+
+// Right-preconditioned restarted GMRES with classical Gram-Schmidt applied
+// twice; the least-squares problem is updated by Givens rotations on the
+// host.  x holds x0 on entry, r = b - A x0.  Returns the final true
+// relative residual; iterations are added to the stats.
+double gmres(ewbem_ctx* c, cd* x, cd* r, int& iters_out, bool& converged) {
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  const int m = c->so.restart;
+  const double tol = c->so.tol;
+  const double bnorm = dev_norm(c, c->d_b.p);
+  iters_out = 0;
+  converged = true;
+  if (bnorm == 0.0) {
+    EWBEM_HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(cd), st));
+    return 0.0;
+  }
+  double rnorm = dev_norm(c, r);
+  double relres = rnorm / bnorm;
+  EventPair ev;
+  std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gvec(m + 1);
+  std::vector<cd> hbuf(2 * (m + 2) + 2);
+  cd* V = c->d_V.p;
+  cd* hd = c->d_small.p;            // h (m+1)
+  cd* hd2 = c->d_small.p + (m + 2); // second pass
+  cd* nd = c->d_small.p + 2 * (m + 2);
+  while (relres > tol && iters_out < c->so.maxit) {
+    const double beta = rnorm;
+    launch_axpby(cd{1.0 / beta, 0.0}, r, cd{0.0, 0.0}, V, N, st);
+    std::fill(gvec.begin(), gvec.end(), 0.0);
+    gvec[0] = beta;
+    int j = 0;
+    double est = relres;
+    for (; j < m && iters_out < c->so.maxit; ++j) {
+      cd* vj = V + (size_t)j * N;
+      cd* w = V + (size_t)(j + 1) * N;
+      precond_apply(c, vj, c->d_zt.p);
+      apply_tree(c, c->d_zt.p, w, &ev);
+      launch_dots(V, N, j + 1, w, N, c->d_hpart.p, hd, st);
+      launch_gemv_sub(V, N, j + 1, hd, w, N, st);
+      launch_dots(V, N, j + 1, w, N, c->d_hpart.p, hd2, st);
+      launch_gemv_sub(V, N, j + 1, hd2, w, N, st);
+      launch_dots(w, N, 1, w, N, c->d_hpart.p, nd, st);
+      EWBEM_HIP_CHECK(hipMemcpyAsync(hbuf.data(), c->d_small.p, (2 * (m + 2) + 1) * sizeof(cd),
+                                     hipMemcpyDeviceToHost, st));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      c->acc.t_matvec_ms += ev.elapsed();
+      ++iters_out;
+      const double hn = std::sqrt(std::max(0.0, hbuf[2 * (m + 2)].x));
+      for (int i = 0; i <= j; ++i)
+        H[(size_t)j * (m + 1) + i] = std::complex<double>(hbuf[i].x + hbuf[m + 2 + i].x,
+                                                          hbuf[i].y + hbuf[m + 2 + i].y);
+      H[(size_t)j * (m + 1) + j + 1] = hn;
+      // apply previous rotations to column j
+      for (int i = 0; i < j; ++i) {
+        std::complex<double>& a = H[(size_t)j * (m + 1) + i];
+        std::complex<double>& b = H[(size_t)j * (m + 1) + i + 1];
+        const std::complex<double> t = std::conj(cs[i]) * a + std::conj(sn[i]) * b;
+        b = -sn[i] * a + cs[i] * b;
+        a = t;
+      }
+      // new rotation annihilating H[j+1, j]
+      const std::complex<double> a = H[(size_t)j * (m + 1) + j];
+      const double bb = hn;
+      const double den = std::sqrt(std::norm(a) + bb * bb);
+      if (den == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = a / den;
+        sn[j] = bb / den;
+      }
+      H[(size_t)j * (m + 1) + j] = den;
+      H[(size_t)j * (m + 1) + j + 1] = 0.0;
+      gvec[j + 1] = -sn[j] * gvec[j];
+      gvec[j] = std::conj(cs[j]) * gvec[j];
+      est = std::abs(gvec[j + 1]) / bnorm;
+      if (hn > 0.0) launch_axpby(cd{1.0 / hn, 0.0}, w, cd{0.0, 0.0}, w, N, st);
+      if (est <= tol || hn == 0.0) {
+        ++j;
+        break;
+      }
+    }
+    // y = H^{-1} g (upper triangular j x j)
+    std::vector<std::complex<double>> y(j);
+    for (int i = j - 1; i >= 0; --i) {
+      std::complex<double> sacc = gvec[i];
+      for (int l = i + 1; l < j; ++l) sacc -= H[(size_t)l * (m + 1) + i] * y[l];
+      y[i] = sacc / H[(size_t)i * (m + 1) + i];
+    }
+    std::vector<cd> yd(j);
+    for (int i = 0; i < j; ++i) yd[i] = cd{y[i].real(), y[i].imag()};
+    EWBEM_HIP_CHECK(hipMemcpyAsync(hd, yd.data(), j * sizeof(cd), hipMemcpyHostToDevice, st));
+    launch_gemv_acc(V, N, j, hd, cd{0.0, 0.0}, c->d_u.p, N, st);
+    precond_apply(c, c->d_u.p, c->d_zt.p);
+    launch_axpby(cd{1.0, 0.0}, c->d_zt.p, cd{1.0, 0.0}, x, N, st);
+    // true residual
+    apply_tree(c, x, r, &ev);
+    launch_axpby(cd{1.0, 0.0}, c->d_b.p, cd{-1.0, 0.0}, r, N, st);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    c->acc.t_matvec_ms += ev.elapsed();
+    rnorm = dev_norm(c, r);
+    relres = rnorm / bnorm;
+    if (j == 0) break;
+  }
+  converged = relres <= tol;
+  return relres;
+}
+
+// Sec. 4.2: x0 = X R^{-1} Q^H b with Y = A X = Q R (X: the last K solutions,
+// newest first); columns with |R_jj| < 1e-12 |R_00| are dropped.  Also
+// returns r0 = b - Y s without another matvec.
+void sem_guess(ewbem_ctx* c, cd* x, cd* r) {
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  const int K = std::min(c->so.sem_k, c->hist_n);
+  EWBEM_HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(cd), st));
+  EWBEM_HIP_CHECK(hipMemcpyAsync(r, c->d_b.p, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+  if (K == 0) return;
+  EventPair ev;
+  cd* Y = c->d_Y.p;
+  cd* Q = c->d_V.p;  // GMRES basis as scratch
+  for (int j = 0; j < K; ++j) {
+    apply_tree(c, c->d_hist_sol.p + (size_t)c->hist_slot[j] * N, Y + (size_t)j * N, &ev);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    c->acc.t_matvec_ms += ev.elapsed();
+  }
+  // classical Gram-Schmidt twice on the columns of Y
+  std::vector<std::complex<double>> R((size_t)K * K, 0.0);
+  std::vector<int> kept;
+  double r00 = 0;
+  std::vector<cd> hb(2 * (K + 1));
+  for (int j = 0; j < K; ++j) {
+    const int q = (int)kept.size();
+    cd* qj = Q + (size_t)q * N;
+    EWBEM_HIP_CHECK(hipMemcpyAsync(qj, Y + (size_t)j * N, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+    std::vector<std::complex<double>> rcol(q, 0.0);
+    for (int pass = 0; pass < 2 && q > 0; ++pass) {
+      launch_dots(Q, N, q, qj, N, c->d_hpart.p, c->d_small.p, st);
+      launch_gemv_sub(Q, N, q, c->d_small.p, qj, N, st);
+      EWBEM_HIP_CHECK(hipMemcpyAsync(hb.data(), c->d_small.p, q * sizeof(cd), hipMemcpyDeviceToHost, st));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      for (int i = 0; i < q; ++i) rcol[i] += std::complex<double>(hb[i].x, hb[i].y);
+    }
+    const double nrm = dev_norm(c, qj);
+    if (j == 0) r00 = nrm;
+    if (!(nrm > 1e-12 * r00) || nrm == 0.0) continue;  // dependent history column
+    launch_axpby(cd{1.0 / nrm, 0.0}, qj, cd{0.0, 0.0}, qj, N, st);
+    for (int i = 0; i < q; ++i) R[(size_t)i * K + q] = rcol[i];
+    R[(size_t)q * K + q] = nrm;
+    kept.push_back(j);
+  }
+  const int q = (int)kept.size();
+  if (q == 0) return;
+  // s = R^{-1} Q^H b
+  launch_dots(Q, N, q, c->d_b.p, N, c->d_hpart.p, c->d_small.p, st);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(hb.data(), c->d_small.p, q * sizeof(cd), hipMemcpyDeviceToHost, st));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<std::complex<double>> sv(q);
+  for (int i = q - 1; i >= 0; --i) {
+    std::complex<double> a(hb[i].x, hb[i].y);
+    for (int l = i + 1; l < q; ++l) a -= R[(size_t)i * K + l] * sv[l];
+    sv[i] = a / R[(size_t)i * K + i];
+  }
+  // coefficients over the history slots (x0) and over Y's columns (r0)
+  const int ncap = std::max(1, c->so.sem_k);
+  std::vector<cd> cx(ncap, cd{0, 0}), cy(K, cd{0, 0});
+  for (int i = 0; i < q; ++i) {
+    cx[c->hist_slot[kept[i]]] = cd{sv[i].real(), sv[i].imag()};
+    cy[kept[i]] = cd{sv[i].real(), sv[i].imag()};
+  }
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p, cx.data(), ncap * sizeof(cd), hipMemcpyHostToDevice, st));
+  launch_gemv_acc(c->d_hist_sol.p, N, ncap, c->d_small.p, cd{0.0, 0.0}, x, N, st);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p + ncap, cy.data(), K * sizeof(cd), hipMemcpyHostToDevice, st));
+  launch_gemv_sub(Y, N, K, c->d_small.p + ncap, r, N, st);
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void push_history(ewbem_ctx* c, const cd* a) {
+  const long long N = 3LL * c->nt;
+  const int cap = std::max(1, c->so.sem_k);
+  int slot;
+  if (c->hist_n < cap) {
+    slot = c->hist_n++;
+  } else {
+    slot = c->hist_slot.back();
+    c->hist_slot.pop_back();
+  }
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_hist_sol.p + (size_t)slot * N, a, N * sizeof(cd),
+                                 hipMemcpyDeviceToDevice, c->stream));
+  c->hist_slot.insert(c->hist_slot.begin(), slot);
+}
+
+// Solve frequency k into d_x (tree order); x0 (caller order, device) optional.
+int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
+  if (c->assembled_k != k) assemble_k(c, k);
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  const auto tg = Clock::now();
+  EventPair ev;
+  if (x0) {
+    launch_permute((const cd*)x0, c->d_perm.p, c->nt, 1, c->d_x.p, st);
+    apply_tree(c, c->d_x.p, c->d_r.p, &ev);
+    launch_axpby(cd{1, 0}, c->d_b.p, cd{-1, 0}, c->d_r.p, N, st);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    c->acc.t_matvec_ms += ev.elapsed();
+  } else if (c->so.guess == EWBEM_GUESS_SEM) {
+    sem_guess(c, c->d_x.p, c->d_r.p);
+  } else if (c->so.guess == EWBEM_GUESS_QUAD && c->hist_n > 0) {
+    const int K = std::min(3, c->hist_n);
+    static const double coef[4][3] = {{0, 0, 0}, {1, 0, 0}, {2, -1, 0}, {3, -3, 1}};
+    const int ncap = std::max(1, c->so.sem_k);
+    std::vector<cd> cx(ncap, cd{0, 0});
+    for (int j = 0; j < K; ++j) cx[c->hist_slot[j]] = cd{coef[K][j], 0};
+    EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p, cx.data(), ncap * sizeof(cd), hipMemcpyHostToDevice, st));
+    launch_gemv_acc(c->d_hist_sol.p, N, ncap, c->d_small.p, cd{0, 0}, c->d_x.p, N, st);
+    apply_tree(c, c->d_x.p, c->d_r.p, &ev);
+    launch_axpby(cd{1, 0}, c->d_b.p, cd{-1, 0}, c->d_r.p, N, st);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    c->acc.t_matvec_ms += ev.elapsed();
+  } else {
+    EWBEM_HIP_CHECK(hipMemsetAsync(c->d_x.p, 0, N * sizeof(cd), st));
+    EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_r.p, c->d_b.p, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+  }
+  const double bn = dev_norm(c, c->d_b.p);
+  c->acc.guess_resid_sum += bn > 0 ? dev_norm(c, c->d_r.p) / bn : 0.0;
+  c->acc.t_guess_ms += ms_since(tg);
+  const auto ts = Clock::now();
+  int its = 0;
+  bool conv = true;
+  const double rel = gmres(c, c->d_x.p, c->d_r.p, its, conv);
+  c->acc.t_gmres_ms += ms_since(ts);
+  c->acc.n_solves += 1;
+  c->acc.iters_total += its;
+  c->acc.iters_max = std::max(c->acc.iters_max, its);
+  c->acc.resid_max = std::max(c->acc.resid_max, rel);
+  push_history(c, c->d_x.p);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_spec.p + (size_t)k * N, c->d_x.p, N * sizeof(cd),
+                                 hipMemcpyDeviceToDevice, st));
+  return conv ? EWBEM_OK : EWBEM_ENOCONV;
+}
+
+int guard(ewbem_ctx* ctx, const std::function<int()>& f) {
+  if (!ctx) return EWBEM_EINVAL;
+  try {
+    ctx->err.clear();
+    return f();
+  } catch (const ApiError& e) {
+    ctx->err = e.what();
+    return e.status;
+  } catch (const HipError& e) {
+    ctx->err = e.what();
+    return e.code == hipErrorOutOfMemory ? EWBEM_ENOMEM : EWBEM_EHIP;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return EWBEM_ENOMEM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return EWBEM_EINVAL;
+  }
+}
+
+void begin_stats(ewbem_ctx* c) { c->acc = ewbem_stats{}; }
+void end_stats(ewbem_ctx* c, ewbem_stats* out) {
+  c->acc.matvec_bytes = c->matvec_bytes;
+  c->acc.stored_bytes = c->stored_bytes;
+  c->acc.rank_sum = c->rank_sum;
+  c->acc.rank_max = c->rank_max;
+  c->acc.n_near = (int64_t)c->near_h.size();
+  c->acc.n_far = (int64_t)c->far_h.size();
+  if (out) *out = c->acc;
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ewbem_default_op_opts(ewbem_op_opts* o) {
+  if (!o) return;
+  o->kind = EWBEM_OP_HMAT;
+  o->leaf_size = 64;
+  o->eta_adm = 1.0;
+  o->aca_tol = 1e-5;
+  o->far_store = EWBEM_STORE_C128;
+  o->self_order = 20;
+}
+
+void ewbem_default_solver_opts(ewbem_solver_opts* o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->restart = 100;
+  o->maxit = 2000;
+  o->precond = EWBEM_PREC_LEAF;
+  o->guess = EWBEM_GUESS_SEM;
+  o->sem_k = 3;
+}
+
+int ewbem_create(ewbem_ctx** out, int32_t device, void* hip_stream) {
+  if (!out) return EWBEM_EINVAL;
+  *out = nullptr;
+  ewbem_ctx* c = nullptr;
+  try {
+    c = new ewbem_ctx();
+  } catch (...) {
+    return EWBEM_ENOMEM;
+  }
+  ewbem_default_op_opts(&c->op);
+  ewbem_default_solver_opts(&c->so);
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (device >= 0) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+      delete c;
+      return EWBEM_ESTATE;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return EWBEM_EHIP;
+    }
+  }
+  *out = c;
+  return EWBEM_OK;
+}
+
+void ewbem_destroy(ewbem_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+  delete ctx;
+}
+
+const char* ewbem_last_error(const ewbem_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ewbem_set_mesh(ewbem_ctx* ctx, int64_t nv, const double* xyz, int64_t nt, const int32_t* tri,
+                   int32_t exterior) {
+  return guard(ctx, [&] {
+    if (nv < 3 || nt < 1 || !xyz || !tri || nt > (1LL << 28) || nv > (1LL << 30))
+      fail(EWBEM_EINVAL, "mesh: need nv >= 3, nt >= 1 and non-null arrays");
+    if (!finite_all(xyz, 3 * (size_t)nv)) fail(EWBEM_EINVAL, "mesh: non-finite coordinates");
+    for (int64_t i = 0; i < 3 * nt; ++i)
+      if (tri[i] < 0 || tri[i] >= nv) fail(EWBEM_EINVAL, "mesh: vertex index out of range");
+    for (int64_t t = 0; t < nt; ++t) {
+      const double* a = xyz + 3 * tri[3 * t];
+      const double* b = xyz + 3 * tri[3 * t + 1];
+      const double* c = xyz + 3 * tri[3 * t + 2];
+      double e1[3], e2[3];
+      for (int k = 0; k < 3; ++k) {
+        e1[k] = b[k] - a[k];
+        e2[k] = c[k] - a[k];
+      }
+      const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                   cz = e1[0] * e2[1] - e1[1] * e2[0];
+      if (!(cx * cx + cy * cy + cz * cz > 0)) fail(EWBEM_EINVAL, "mesh: zero-area triangle");
+    }
+    ctx->xyz.assign(xyz, xyz + 3 * nv);
+    ctx->tri.assign(tri, tri + 3 * nt);
+    ctx->nv = (int)nv;
+    ctx->nt = (int)nt;
+    ctx->exterior = exterior != 0;
+    ctx->have_mesh = true;
+    ctx->have_load = false;
+    ctx->structure_ok = false;
+    ctx->device_ok = false;
+    ctx->assembled_k = -1;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_set_material(ewbem_ctx* ctx, double rho, double mu, double nu) {
+  return guard(ctx, [&] {
+    if (!(rho > 0) || !(mu > 0) || !(nu > -1.0 && nu < 0.5) || !std::isfinite(rho) || !std::isfinite(mu))
+      fail(EWBEM_EINVAL, "material: need rho > 0, mu > 0, -1 < nu < 1/2");
+    ctx->rho = rho;
+    ctx->mu = mu;
+    ctx->nu = nu;
+    ctx->have_mat = true;
+    ctx->device_ok = false;
+    ctx->assembled_k = -1;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_set_time(ewbem_ctx* ctx, double period, int32_t n_f, double sigma, int32_t window) {
+  return guard(ctx, [&] {
+    if (!(period > 0) || !std::isfinite(period) || n_f < 2 || (n_f % 2) != 0 || n_f > (1 << 20) ||
+        !(sigma >= 0) || !std::isfinite(sigma) || window < 0 || window > 2)
+      fail(EWBEM_EINVAL, "time: need T > 0, even N_f >= 2, sigma >= 0, window 0..2");
+    ctx->period = period;
+    ctx->n_f = n_f;
+    ctx->sigma = sigma;
+    ctx->window = window;
+    ctx->have_time = true;
+    ctx->have_load = false;
+    ctx->device_ok = false;
+    ctx->assembled_k = -1;
+    return EWBEM_OK;
+  });
+}
+
+static int set_load(ewbem_ctx* ctx, const double* v, size_t nv_, const double* history, bool pressure) {
+  return guard(ctx, [&] {
+    if (!ctx->have_mesh || !ctx->have_time) fail(EWBEM_ESTATE, "load: set the mesh and time grid first");
+    if (!v || !history) fail(EWBEM_EINVAL, "load: null array");
+    if (!finite_all(v, nv_) || !finite_all(history, ctx->n_f)) fail(EWBEM_EINVAL, "load: non-finite values");
+    ctx->load_caller.assign(v, v + nv_);
+    ctx->history.assign(history, history + ctx->n_f);
+    ctx->load_is_pressure = pressure;
+    ctx->have_load = true;
+    ctx->device_ok = false;
+    ctx->assembled_k = -1;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_set_load_traction(ewbem_ctx* ctx, const double* t0, const double* history) {
+  if (!ctx) return EWBEM_EINVAL;
+  return set_load(ctx, t0, 3 * (size_t)ctx->nt, history, false);
+}
+
+int ewbem_set_load_pressure(ewbem_ctx* ctx, const double* p, const double* history) {
+  if (!ctx) return EWBEM_EINVAL;
+  return set_load(ctx, p, (size_t)ctx->nt, history, true);
+}
+
+int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
+  return guard(ctx, [&] {
+    if (!o) fail(EWBEM_EINVAL, "operator options: null");
+    if ((o->kind != EWBEM_OP_DENSE && o->kind != EWBEM_OP_HMAT) || o->leaf_size < 1 || o->leaf_size > 64 ||
+        !(o->eta_adm > 0) || !(o->aca_tol > 0 && o->aca_tol < 1) ||
+        (o->far_store != EWBEM_STORE_C128 && o->far_store != EWBEM_STORE_C64) || o->self_order < 4 ||
+        o->self_order > MAX_SELF_ORDER)
+      fail(EWBEM_EINVAL, "operator options out of range");
+    ctx->op = *o;
+    ctx->structure_ok = false;
+    ctx->device_ok = false;
+    ctx->assembled_k = -1;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_set_solver(ewbem_ctx* ctx, const ewbem_solver_opts* o) {
+  return guard(ctx, [&] {
+    if (!o) fail(EWBEM_EINVAL, "solver options: null");
+    if (!(o->tol > 0) || o->restart < 1 || o->restart > 400 || o->maxit < 1 || o->precond < 0 ||
+        o->precond > 2 || o->guess < 0 || o->guess > 2 || o->sem_k < 1 || o->sem_k > 8)
+      fail(EWBEM_EINVAL, "solver options out of range");
+    ctx->so = *o;
+    ctx->device_ok = false;  // buffers depend on restart and sem_k
+    ctx->assembled_k = -1;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_info(ewbem_ctx* ctx, ewbem_info_t* info) {
+  return guard(ctx, [&] {
+    if (!info) fail(EWBEM_EINVAL, "info: null");
+    ensure_structure(ctx);
+    info->n_elements = ctx->nt;
+    info->n_dof = 3LL * ctx->nt;
+    info->n_clusters = (int64_t)ctx->part.clusters.size();
+    info->n_leaves = (int64_t)ctx->part.leaves.size();
+    info->n_near = (int64_t)ctx->part.near.size();
+    info->n_far = (int64_t)ctx->part.far.size();
+    info->near_entries = ctx->near_entries;
+    int mx = 0, mn = 1 << 30;
+    for (int l : ctx->part.leaves) {
+      mx = std::max(mx, ctx->part.clusters[l].size());
+      mn = std::min(mn, ctx->part.clusters[l].size());
+    }
+    info->max_leaf = mx;
+    info->min_leaf = mn;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_get_partition(ewbem_ctx* ctx, int32_t* perm, int32_t* nearp, int32_t* farp) {
+  return guard(ctx, [&] {
+    ensure_structure(ctx);
+    if (perm)
+      for (int t = 0; t < ctx->nt; ++t) perm[t] = ctx->hg.perm[t];
+    auto put = [&](const std::vector<BlockPair>& v, int32_t* o) {
+      for (size_t i = 0; i < v.size(); ++i) {
+        const Cluster& r = ctx->part.clusters[v[i].row];
+        const Cluster& s = ctx->part.clusters[v[i].col];
+        o[4 * i] = r.begin;
+        o[4 * i + 1] = r.end;
+        o[4 * i + 2] = s.begin;
+        o[4 * i + 3] = s.end;
+      }
+    };
+    if (nearp) put(ctx->part.near, nearp);
+    if (farp) put(ctx->part.far, farp);
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_load_spectrum(ewbem_ctx* ctx, ewbem_z* phat) {
+  return guard(ctx, [&] {
+    if (!phat) fail(EWBEM_EINVAL, "null output");
+    ensure_device(ctx);
+    EWBEM_HIP_CHECK(hipMemcpyAsync(phat, ctx->d_phat.p, (ctx->n_f / 2 + 1) * sizeof(cd),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_kernel_eval(ewbem_ctx* ctx, ewbem_z s, int64_t n, const double* x, const double* y,
+                      const double* nrm, ewbem_z* U, ewbem_z* T) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    if (!ctx->have_mat) fail(EWBEM_ESTATE, "material not set");
+    if (n < 0 || (n > 0 && (!x || !y || (T && !nrm)))) fail(EWBEM_EINVAL, "kernel_eval: bad arguments");
+    EWBEM_HIP_CHECK(hipSetDevice(ctx->device));
+    KParams P = make_params(ctx->rho, ctx->mu, ctx->nu, cd{s.re, s.im});
+    launch_kernel_eval(P, n, x, y, nrm, (cd*)U, (cd*)T, ctx->stream);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_assemble_dense(ewbem_ctx* ctx, ewbem_z s, ewbem_z* T, ewbem_z* U) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    ensure_structure(ctx);
+    if (!ctx->have_mat) fail(EWBEM_ESTATE, "material not set");
+    EWBEM_HIP_CHECK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const HostGeom& g = ctx->hg;
+    ctx->d_cen.upload(g.cen, st);
+    ctx->d_nrm.upload(g.nrm, st);
+    ctx->d_qp.upload(g.qp, st);
+    ctx->d_qw.upload(g.qw, st);
+    ctx->d_vtx.upload(g.vtx, st);
+    ctx->d_perm.upload(g.perm, st);
+    ctx->d_selfT.reserve(9 * (size_t)ctx->nt);
+    ctx->d_selfU.reserve(9 * (size_t)ctx->nt);
+    SelfRule S{};
+    S.nt = S.nr = ctx->op.self_order;
+    gauss_legendre01(S.nt, S.t, S.wt);
+    gauss_legendre01(S.nr, S.u, S.wu);
+    KParams P = make_params(ctx->rho, ctx->mu, ctx->nu, cd{s.re, s.im});
+    const DevGeom dg = dev_geom(ctx);
+    launch_self(dg, P, S, ctx->d_selfT.p, ctx->d_selfU.p, st);
+    launch_dense_pairs(dg, P, ctx->d_perm.p, (cd*)T, (cd*)U, st);
+    launch_dense_self(ctx->d_selfT.p, ctx->d_selfU.p, ctx->d_perm.p, ctx->nt, (cd*)T, (cd*)U, st);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    ctx->device_ok = false;  // geometry buffers were reused
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_assemble(ewbem_ctx* ctx, int32_t k, ewbem_stats* stats) {
+  return guard(ctx, [&] {
+    begin_stats(ctx);
+    assemble_k(ctx, k);
+    end_stats(ctx, stats);
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_apply(ewbem_ctx* ctx, const ewbem_z* x, ewbem_z* y) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    if (ctx->assembled_k < 0 || !ctx->device_ok) fail(EWBEM_ESTATE, "apply: no assembled operator");
+    if (!x || !y) fail(EWBEM_EINVAL, "apply: null vector");
+    hipStream_t st = ctx->stream;
+    launch_permute((const cd*)x, ctx->d_perm.p, ctx->nt, 1, ctx->d_tmp_in.p, st);
+    apply_tree(ctx, ctx->d_tmp_in.p, ctx->d_tmp_out.p, nullptr);
+    launch_permute(ctx->d_tmp_out.p, ctx->d_perm.p, ctx->nt, 0, (cd*)y, st);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_get_rhs(ewbem_ctx* ctx, ewbem_z* b) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    if (ctx->assembled_k < 0 || !ctx->device_ok) fail(EWBEM_ESTATE, "get_rhs: no assembled operator");
+    if (!b) fail(EWBEM_EINVAL, "get_rhs: null vector");
+    launch_permute(ctx->d_b.p, ctx->d_perm.p, ctx->nt, 0, (cd*)b, ctx->stream);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_solve_frequency(ewbem_ctx* ctx, int32_t k, const ewbem_z* x0, ewbem_z* a, ewbem_stats* stats) {
+  return guard(ctx, [&] {
+    if (!a) fail(EWBEM_EINVAL, "solve_frequency: null output");
+    begin_stats(ctx);
+    ensure_device(ctx);
+    const int rc = solve_k(ctx, k, x0);
+    launch_permute(ctx->d_x.p, ctx->d_perm.p, ctx->nt, 0, (cd*)a, ctx->stream);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    end_stats(ctx, stats);
+    if (rc != EWBEM_OK) ctx->err = "GMRES did not reach the tolerance within maxit";
+    return rc;
+  });
+}
+
+int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats* stats) {
+  return guard(ctx, [&] {
+    if (!u) fail(EWBEM_EINVAL, "solve_transient: null output");
+    begin_stats(ctx);
+    ensure_device(ctx);
+    ctx->hist_n = 0;
+    ctx->hist_slot.clear();
+    int rc = EWBEM_OK;
+    for (int k = 0; k <= ctx->n_f / 2; ++k) {
+      const int r = solve_k(ctx, k, nullptr);
+      if (r != EWBEM_OK) rc = r;
+    }
+    const auto tp = Clock::now();
+    const long long N = 3LL * ctx->nt;
+    launch_mft_inverse(ctx->d_spec.p, N, ctx->n_f, ctx->period, ctx->sigma, ctx->window, ctx->d_perm.p, u,
+                       ctx->stream);
+    if (spec)
+      for (int k = 0; k <= ctx->n_f / 2; ++k)
+        launch_permute(ctx->d_spec.p + (size_t)k * N, ctx->d_perm.p, ctx->nt, 0, (cd*)spec + (size_t)k * N,
+                       ctx->stream);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    ctx->acc.t_post_ms += ms_since(tp);
+    end_stats(ctx, stats);
+    if (rc != EWBEM_OK) ctx->err = "GMRES did not reach the tolerance within maxit at some frequency";
+    return rc;
+  });
+}
+
+int ewbem_mft_inverse(ewbem_ctx* ctx, const ewbem_z* spec, double* u) {
+  return guard(ctx, [&] {
+    if (!spec || !u) fail(EWBEM_EINVAL, "mft_inverse: null array");
+    ensure_device(ctx);
+    const long long N = 3LL * ctx->nt;
+    hipStream_t st = ctx->stream;
+    // caller order -> tree order rows, then the inverse (which writes caller order)
+    for (int k = 0; k <= ctx->n_f / 2; ++k)
+      launch_permute((const cd*)spec + (size_t)k * N, ctx->d_perm.p, ctx->nt, 1, ctx->d_spec.p + (size_t)k * N,
+                     st);
+    launch_mft_inverse(ctx->d_spec.p, N, ctx->n_f, ctx->period, ctx->sigma, ctx->window, ctx->d_perm.p, u, st);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    return EWBEM_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,382 @@
+// Assembly kernels: singular self-element integrals, dense near-field
+// blocks of the traction operator, the right-hand side U t0, and the
+// parity entry points (point kernels, dense T and U).
+//
+// Sec. 2.1: collocation of the boundary integral equation at element
+// centroids with constant elements gives T u = U t; distinct elements use
+// the 7-point rule, the element holding the collocation point uses a
+// polar-coordinate rule about it, with the free term delta_ij / 2 and the
+// principal value of the static traction kernel added in closed form.
+#include "kernel_fn.hpp"
+#include "launch.hpp"
+
+namespace ewbem {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wavefront per element: lanes cover (edge, angular node) pairs and
+// loop over the radial nodes of the polar rule about the centroid.
+__global__ __launch_bounds__(256) void k_self(DevGeom g, KParams P, SelfRule S, cd* __restrict__ selfT,
+                                              cd* __restrict__ selfU) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= g.ne) return;
+  const double* x = g.cen + 3 * e;
+  const double* n = g.nrm + 3 * e;
+  const double* v = g.vtx + 9 * e;
+  cd T[9], U[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) T[i] = U[i] = mk(0.0);
+  const int nodes = 3 * S.nt;
+  for (int idx = lane; idx < nodes; idx += 64) {
+    const int edge = idx / S.nt, a = idx - edge * S.nt;
+    const double* pa = v + 3 * edge;
+    const double* pb = v + 3 * ((edge + 1) % 3);
+    double da[3], db[3];
+    for (int k = 0; k < 3; ++k) {
+      da[k] = pa[k] - x[k];
+      db[k] = pb[k] - x[k];
+    }
+    double e3[3] = {da[1] * db[2] - da[2] * db[1], da[2] * db[0] - da[0] * db[2],
+                    da[0] * db[1] - da[1] * db[0]};
+    double l3 = rsqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]);
+    double la = rsqrt(da[0] * da[0] + da[1] * da[1] + da[2] * da[2]);
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+      e3[k] *= l3;
+      e1[k] = da[k] * la;
+    }
+    e2[0] = e3[1] * e1[2] - e3[2] * e1[1];
+    e2[1] = e3[2] * e1[0] - e3[0] * e1[2];
+    e2[2] = e3[0] * e1[1] - e3[1] * e1[0];
+    const double tb = atan2(db[0] * e2[0] + db[1] * e2[1] + db[2] * e2[2],
+                            db[0] * e1[0] + db[1] * e1[1] + db[2] * e1[2]);
+    double te[3], L = 0;
+    for (int k = 0; k < 3; ++k) {
+      te[k] = pb[k] - pa[k];
+      L += te[k] * te[k];
+    }
+    L = rsqrt(L);
+    double proj = 0;
+    for (int k = 0; k < 3; ++k) {
+      te[k] *= L;
+      proj += da[k] * te[k];
+    }
+    double m[3], h = 0;
+    for (int k = 0; k < 3; ++k) {
+      m[k] = da[k] - te[k] * proj;  // foot - x
+      h += m[k] * m[k];
+    }
+    h = sqrt(h);
+    for (int k = 0; k < 3; ++k) m[k] /= h;
+    const double th = S.t[a] * tb;
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    double rh[3];
+    for (int k = 0; k < 3; ++k) rh[k] = cs * e1[k] + sn * e2[k];
+    const double R = h / (rh[0] * m[0] + rh[1] * m[1] + rh[2] * m[2]);
+    const double wth = S.wt[a] * tb;
+    for (int b = 0; b < S.nr; ++b) {
+      const double rho = S.u[b] * R;
+      const double y[3] = {x[0] + rho * rh[0], x[1] + rho * rh[1], x[2] + rho * rh[2]};
+      const double w = wth * S.wu[b] * rho * R;
+      acc_T<true>(x, y, n, w, P, T);
+      acc_U<false>(x, y, w, P, U);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    T[i].x = wave_sum(T[i].x);
+    T[i].y = wave_sum(T[i].y);
+    U[i].x = wave_sum(U[i].x);
+    U[i].y = wave_sum(U[i].y);
+  }
+  if (lane == 0) {
+    // Principal value of the static kernel gamma^2/(4 pi r^2)(rh_i n_j - rh_j n_i):
+    // PV int rh_i / r^2 dA = -sum_edges m_i int_edge dl / r (divergence
+    // theorem in the element plane, m the outward in-plane edge normal).
+    double C[3] = {0, 0, 0};
+    for (int edge = 0; edge < 3; ++edge) {
+      const double* pa = v + 3 * edge;
+      const double* pb = v + 3 * ((edge + 1) % 3);
+      double te[3], L = 0;
+      for (int k = 0; k < 3; ++k) {
+        te[k] = pb[k] - pa[k];
+        L += te[k] * te[k];
+      }
+      L = sqrt(L);
+      double proj = 0;
+      for (int k = 0; k < 3; ++k) {
+        te[k] /= L;
+        proj += (x[k] - pa[k]) * te[k];
+      }
+      double m[3], h = 0;
+      for (int k = 0; k < 3; ++k) {
+        m[k] = pa[k] + te[k] * proj - x[k];  // foot - x, outward from x
+        h += m[k] * m[k];
+      }
+      h = sqrt(h);
+      const double l1 = -proj, l2 = L - proj;  // endpoint coordinates from the foot
+      const double I = asinh(l2 / h) - asinh(l1 / h);
+      for (int k = 0; k < 3; ++k) C[k] -= (m[k] / h) * I;
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double cpv = P.cpv * (C[i] * n[j] - n[i] * C[j]);
+        T[3 * i + j].x += cpv + (i == j ? 0.5 : 0.0);
+      }
+    for (int i = 0; i < 9; ++i) {
+      selfT[9 * (size_t)e + i] = T[i];
+      selfU[9 * (size_t)e + i] = U[i];
+    }
+  }
+}
+
+void launch_self(const DevGeom& g, const KParams& P, const SelfRule& S, cd* selfT, cd* selfU,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_self, dim3((g.ne + 3) / 4), dim3(256), 0, st, g, P, S, selfT, selfU);
+}
+
+// Dense near-field T blocks: one workgroup per block, the column cluster's
+// quadrature data staged in LDS, one (row element, column element) pair per
+// thread.  The self pair is left to k_scatter_self.
+__global__ __launch_bounds__(256) void k_near(const NearBlk* __restrict__ blks, DevGeom g, KParams P,
+                                              cd* __restrict__ D) {
+  const NearBlk B = blks[blockIdx.x];
+  __shared__ double sq[64 * 21], sw[64 * 7], sn[64 * 3], sx[64 * 3];
+  for (int i = threadIdx.x; i < B.n * 21; i += blockDim.x) sq[i] = g.qp[(size_t)B.c0 * 21 + i];
+  for (int i = threadIdx.x; i < B.n * 7; i += blockDim.x) sw[i] = g.qw[(size_t)B.c0 * 7 + i];
+  for (int i = threadIdx.x; i < B.n * 3; i += blockDim.x) sn[i] = g.nrm[(size_t)B.c0 * 3 + i];
+  for (int i = threadIdx.x; i < B.m * 3; i += blockDim.x) sx[i] = g.cen[(size_t)B.r0 * 3 + i];
+  __syncthreads();
+  const int ld = 3 * B.m;
+  for (int p = threadIdx.x; p < B.m * B.n; p += blockDim.x) {
+    const int a = p % B.m, b = p / B.m;
+    if (B.r0 + a == B.c0 + b) continue;
+    cd T[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) T[i] = mk(0.0);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) acc_T<false>(sx + 3 * a, sq + 21 * b + 3 * q, sn + 3 * b, sw[7 * b + q], P, T);
+    cd* out = D + B.off + (size_t)(3 * b) * ld + 3 * a;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) out[(size_t)j * ld + i] = T[3 * i + j];
+  }
+}
+
+void launch_near(const NearBlk* blks, int nblk, const DevGeom& g, const KParams& P, cd* D,
+                 hipStream_t st) {
+  if (nblk > 0) hipLaunchKernelGGL(k_near, dim3(nblk), dim3(256), 0, st, blks, g, P, D);
+}
+
+__global__ void k_scatter_self(const cd* __restrict__ selfT, const long long* __restrict__ self_off,
+                               const int* __restrict__ self_ld, int ne, cd* __restrict__ D) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * ne) return;
+  const int e = t / 9, ij = t - 9 * e, i = ij / 3, j = ij - 3 * i;
+  D[self_off[e] + (size_t)j * self_ld[e] + i] = selfT[t];
+}
+
+void launch_scatter_self(const cd* selfT, const long long* self_off, int ne, cd* D,
+                         const int* self_ld, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_self, dim3((9 * ne + 255) / 256), dim3(256), 0, st, selfT, self_off,
+                     self_ld, ne, D);
+}
+
+// Parity path: every off-diagonal element pair of the dense T and U,
+// written row-major in the caller's element order.
+__global__ __launch_bounds__(256) void k_dense_pairs(DevGeom g, KParams P, const int* __restrict__ perm,
+                                                     cd* __restrict__ Tout, cd* __restrict__ Uout) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ne = g.ne;
+  if (p >= ne * ne) return;
+  const int a = (int)(p % ne), b = (int)(p / ne);
+  if (a == b) return;
+  cd T[9], U[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) T[i] = U[i] = mk(0.0);
+  const double* x = g.cen + 3 * a;
+  for (int q = 0; q < 7; ++q) {
+    const double* y = g.qp + 21 * (size_t)b + 3 * q;
+    const double w = g.qw[7 * (size_t)b + q];
+    acc_T<false>(x, y, g.nrm + 3 * b, w, P, T);
+    acc_U<false>(x, y, w, P, U);
+  }
+  const long long N = 3 * ne;
+  const long long ao = perm[a], bo = perm[b];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const long long idx = (3 * ao + i) * N + 3 * bo + j;
+      if (Tout) Tout[idx] = T[3 * i + j];
+      if (Uout) Uout[idx] = U[3 * i + j];
+    }
+}
+
+void launch_dense_pairs(const DevGeom& g, const KParams& P, const int* perm, cd* Tout, cd* Uout,
+                        hipStream_t st) {
+  const long long np = (long long)g.ne * g.ne;
+  hipLaunchKernelGGL(k_dense_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, g, P, perm,
+                     Tout, Uout);
+}
+
+__global__ void k_dense_self(const cd* __restrict__ selfT, const cd* __restrict__ selfU,
+                             const int* __restrict__ perm, int ne, cd* __restrict__ Tout,
+                             cd* __restrict__ Uout) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * ne) return;
+  const int e = t / 9, ij = t - 9 * e, i = ij / 3, j = ij - 3 * i;
+  const long long N = 3LL * ne, eo = perm[e];
+  const long long idx = (3 * eo + i) * N + 3 * eo + j;
+  if (Tout) Tout[idx] = selfT[t];
+  if (Uout) Uout[idx] = selfU[t];
+}
+
+void launch_dense_self(const cd* selfT, const cd* selfU, const int* perm, int ne, cd* Tout,
+                       cd* Uout, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_self, dim3((9 * ne + 255) / 256), dim3(256), 0, st, selfT, selfU, perm,
+                     ne, Tout, Uout);
+}
+
+// Right-hand side b = P_k * U(s_k) t0 by direct summation over all element
+// pairs (7-point rule) plus the self-element U blocks.  Targets are tiled
+// 256 per workgroup, sources in chunks of RHS_CHUNK elements staged in LDS;
+// each chunk writes its own partial vector, summed in a fixed order by
+// k_rhs_finish (deterministic).
+constexpr int RHS_CHUNK = 128;
+
+__global__ __launch_bounds__(256) void k_rhs_partial(DevGeom g, KParams P, const double* __restrict__ t0,
+                                                     cd* __restrict__ partial) {
+  __shared__ double sq[RHS_CHUNK * 21], sw[RHS_CHUNK * 7], stt[RHS_CHUNK * 3];
+  const int c0 = blockIdx.y * RHS_CHUNK;
+  const int nc = min(RHS_CHUNK, g.ne - c0);
+  for (int i = threadIdx.x; i < nc * 21; i += blockDim.x) sq[i] = g.qp[(size_t)c0 * 21 + i];
+  for (int i = threadIdx.x; i < nc * 7; i += blockDim.x) sw[i] = g.qw[(size_t)c0 * 7 + i];
+  for (int i = threadIdx.x; i < nc * 3; i += blockDim.x) stt[i] = t0[(size_t)c0 * 3 + i];
+  __syncthreads();
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= g.ne) return;
+  const double x[3] = {g.cen[3 * a], g.cen[3 * a + 1], g.cen[3 * a + 2]};
+  cd u[3] = {mk(0.0), mk(0.0), mk(0.0)};
+  for (int b = 0; b < nc; ++b) {
+    if (c0 + b == a) continue;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) acc_Ut(x, sq + 21 * b + 3 * q, sw[7 * b + q], stt + 3 * b, P, u);
+  }
+  cd* out = partial + (size_t)blockIdx.y * 3 * g.ne + 3 * a;
+  out[0] = u[0];
+  out[1] = u[1];
+  out[2] = u[2];
+}
+
+__global__ void k_rhs_finish(const cd* __restrict__ partial, int nchunk, int ne, const cd* __restrict__ selfU,
+                             const double* __restrict__ t0, const cd* __restrict__ phat_k,
+                             cd* __restrict__ b) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= 3 * ne) return;
+  const int e = d / 3, i = d - 3 * e;
+  cd acc = mk(0.0);
+  for (int c = 0; c < nchunk; ++c) acc += partial[(size_t)c * 3 * ne + d];
+  for (int j = 0; j < 3; ++j) acc += selfU[9 * (size_t)e + 3 * i + j] * t0[3 * e + j];
+  b[d] = acc * phat_k[0];
+}
+
+int rhs_chunks(int ne) { return (ne + RHS_CHUNK - 1) / RHS_CHUNK; }
+
+void launch_rhs(const DevGeom& g, const KParams& P, const double* t0, const cd* selfU,
+                const cd* phat_k, cd* partial, int nchunk, cd* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_partial, dim3((g.ne + 255) / 256, nchunk), dim3(256), 0, st, g, P, t0,
+                     partial);
+  hipLaunchKernelGGL(k_rhs_finish, dim3((3 * g.ne + 255) / 256), dim3(256), 0, st, partial, nchunk,
+                     g.ne, selfU, t0, phat_k, b);
+}
+
+// Parity path: the point kernels U_ij(x, y) and T_ij(x, y; n) for n pairs.
+__global__ void k_kernel_eval(KParams P, long long n, const double* __restrict__ x,
+                              const double* __restrict__ y, const double* __restrict__ nrm,
+                              cd* __restrict__ U, cd* __restrict__ T) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  cd Ub[9], Tb[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Ub[i] = Tb[i] = mk(0.0);
+  if (U) acc_U<false>(x + 3 * p, y + 3 * p, 1.0, P, Ub);
+  if (T) acc_T<false>(x + 3 * p, y + 3 * p, nrm + 3 * p, 1.0, P, Tb);
+  for (int i = 0; i < 9; ++i) {
+    if (U) U[9 * p + i] = Ub[i];
+    if (T) T[9 * p + i] = Tb[i];
+  }
+}
+
+void launch_kernel_eval(const KParams& P, long long n, const double* x, const double* y,
+                        const double* nrm, cd* U, cd* T, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_kernel_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, n, x, y,
+                       nrm, U, T);
+}
+
+// ---- Sec. 3.3: damped DFT of the sampled load and the windowed,
+// de-damped inverse back to time.
+
+__global__ void k_load_spectrum(const double* __restrict__ hist, int n_f, double dt, double sigma,
+                                cd* __restrict__ phat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > n_f / 2) return;
+  cd acc = mk(0.0);
+  for (int n = 0; n < n_f; ++n) {
+    const long long nk = ((long long)n * k) % n_f;
+    double sn, cs;
+    sincospi(2.0 * (double)nk / n_f, &sn, &cs);
+    const double a = exp(-sigma * n * dt) * hist[n];
+    acc += cd{a * cs, -a * sn};
+  }
+  phat[k] = acc * (1.0 / n_f);
+}
+
+void launch_load_spectrum(const double* hist, int n_f, double period, double sigma, cd* phat,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_load_spectrum, dim3((n_f / 2 + 1 + 63) / 64), dim3(64), 0, st, hist, n_f,
+                     period / n_f, sigma, phat);
+}
+
+__device__ __forceinline__ double window_w(int window, int k, int n_f) {
+  if (window == 1) return 0.5 * (1.0 + cospi(2.0 * k / n_f));
+  if (window == 2) return 0.42 + 0.5 * cospi(2.0 * k / n_f) + 0.08 * cospi(4.0 * k / n_f);
+  return 1.0;
+}
+
+// u[n][caller dof] = Re{ e^{sigma n dt} sum_k W_k a_k e^{2 pi i n k / N_f} }
+// with a_{N_f-k} = conj(a_k): the k and N_f-k terms pair into 2 Re(...).
+__global__ void k_mft_inverse(const cd* __restrict__ spec, long long N, int n_f, double dt,
+                              double sigma, int window, const int* __restrict__ perm,
+                              double* __restrict__ u) {
+  const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (d >= N) return;
+  const int half = n_f / 2;
+  double acc = 0.0;
+  for (int k = 0; k <= half; ++k) {
+    const cd a = spec[(size_t)k * N + d];
+    const long long nk = ((long long)n * k) % n_f;
+    double sn, cs;
+    sincospi(2.0 * (double)nk / n_f, &sn, &cs);
+    const double re = a.x * cs - a.y * sn;
+    const double c = (k == 0 || k == half) ? 1.0 : 2.0;
+    acc += c * window_w(window, k, n_f) * re;
+  }
+  const long long e = d / 3, comp = d - 3 * e;
+  u[(size_t)n * N + 3 * perm[e] + comp] = exp(sigma * n * dt) * acc;
+}
+
+void launch_mft_inverse(const cd* spec, long long N, int n_f, double period, double sigma,
+                        int window, const int* perm, double* u, hipStream_t st) {
+  hipLaunchKernelGGL(k_mft_inverse, dim3((unsigned)((N + 255) / 256), n_f), dim3(256), 0, st, spec, N,
+                     n_f, period / n_f, sigma, window, perm, u);
+}
+
+}  // namespace ewbem

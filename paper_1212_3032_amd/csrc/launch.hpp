@@ -1,0 +1,45 @@
+// Host launchers of the HIP kernels (all enqueue on the given stream).
+#pragma once
+
+#include "common.hpp"
+
+namespace ewbem {
+
+struct SelfRule {
+  int nt, nr;                         // angular and radial orders
+  double t[MAX_SELF_ORDER], wt[MAX_SELF_ORDER];
+  double u[MAX_SELF_ORDER], wu[MAX_SELF_ORDER];
+};
+
+// Dense near-field block: rows = leaf elements [r0, r0+m), columns = leaf
+// elements [c0, c0+n) in tree order, stored column-major with ld = 3m at
+// D + off (complex128).
+struct NearBlk {
+  int r0, m, c0, n;
+  long long off;
+};
+
+// ---- assembly
+void launch_self(const DevGeom& g, const KParams& P, const SelfRule& S, cd* selfT, cd* selfU,
+                 hipStream_t st);
+void launch_near(const NearBlk* blks, int nblk, const DevGeom& g, const KParams& P, cd* D,
+                 hipStream_t st);
+void launch_scatter_self(const cd* selfT, const long long* self_off, int ne, cd* D,
+                         const int* self_ld, hipStream_t st);
+void launch_dense_pairs(const DevGeom& g, const KParams& P, const int* perm, cd* Tout, cd* Uout,
+                        hipStream_t st);
+void launch_dense_self(const cd* selfT, const cd* selfU, const int* perm, int ne, cd* Tout,
+                       cd* Uout, hipStream_t st);
+void launch_rhs(const DevGeom& g, const KParams& P, const double* t0, const cd* selfU,
+                const cd* phat_k, cd* partial, int nchunk, cd* b, hipStream_t st);
+int rhs_chunks(int ne);
+void launch_kernel_eval(const KParams& P, long long n, const double* x, const double* y,
+                        const double* nrm, cd* U, cd* T, hipStream_t st);
+
+// ---- transforms (Sec. 2.2 / 3.3)
+void launch_load_spectrum(const double* hist, int n_f, double period, double sigma, cd* phat,
+                          hipStream_t st);
+void launch_mft_inverse(const cd* spec, long long N, int n_f, double period, double sigma,
+                        int window, const int* perm, double* u, hipStream_t st);
+
+}  // namespace ewbem

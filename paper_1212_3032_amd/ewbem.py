@@ -1,0 +1,317 @@
+"""ctypes binding of libewbem.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts numpy arrays
+and torch tensors to pointers, checks shapes, and turns status codes into
+exceptions.  It fails loudly when the library has not been built.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libewbem.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
+OP_DENSE, OP_HMAT = 0, 1
+STORE_C128, STORE_C64 = 0, 1
+WINDOW_NONE, WINDOW_HANN, WINDOW_BLACKMAN = 0, 1, 2
+PREC_NONE, PREC_ELEMENT, PREC_LEAF = 0, 1, 2
+GUESS_ZERO, GUESS_SEM, GUESS_QUAD = 0, 1, 2
+
+EXPORTED = [
+    "ewbem_default_op_opts", "ewbem_default_solver_opts", "ewbem_create", "ewbem_destroy",
+    "ewbem_last_error", "ewbem_set_mesh", "ewbem_set_material", "ewbem_set_time",
+    "ewbem_set_load_traction", "ewbem_set_load_pressure", "ewbem_set_operator",
+    "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
+    "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
+    "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_mft_inverse",
+]
+
+
+class Z(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class OpOpts(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("leaf_size", C.c_int32), ("eta_adm", C.c_double),
+                ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32),
+                ("precond", C.c_int32), ("guess", C.c_int32), ("sem_k", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_solves", C.c_int32), ("iters_total", C.c_int32), ("iters_max", C.c_int32),
+                ("matvecs", C.c_int32), ("resid_max", C.c_double), ("guess_resid_sum", C.c_double),
+                ("t_assemble_ms", C.c_double), ("t_guess_ms", C.c_double),
+                ("t_gmres_ms", C.c_double), ("t_post_ms", C.c_double), ("t_matvec_ms", C.c_double),
+                ("matvec_bytes", C.c_double), ("stored_bytes", C.c_double),
+                ("n_near", C.c_int64), ("n_far", C.c_int64), ("rank_sum", C.c_int64),
+                ("rank_max", C.c_int64), ("t_aca_ms", C.c_double), ("t_near_ms", C.c_double),
+                ("t_rhs_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Info(C.Structure):
+    _fields_ = [("n_elements", C.c_int64), ("n_dof", C.c_int64), ("n_clusters", C.c_int64),
+                ("n_leaves", C.c_int64), ("n_near", C.c_int64), ("n_far", C.c_int64),
+                ("near_entries", C.c_int64), ("max_leaf", C.c_int32), ("min_leaf", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libewbem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python paper_1212_3032_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "ewbem_default_op_opts": (None, [C.POINTER(OpOpts)]),
+        "ewbem_default_solver_opts": (None, [C.POINTER(SolverOpts)]),
+        "ewbem_create": (C.c_int, [C.POINTER(P), I32, P]),
+        "ewbem_destroy": (None, [P]),
+        "ewbem_last_error": (C.c_char_p, [P]),
+        "ewbem_set_mesh": (C.c_int, [P, I64, P, I64, P, I32]),
+        "ewbem_set_material": (C.c_int, [P, D, D, D]),
+        "ewbem_set_time": (C.c_int, [P, D, I32, D, I32]),
+        "ewbem_set_load_traction": (C.c_int, [P, P, P]),
+        "ewbem_set_load_pressure": (C.c_int, [P, P, P]),
+        "ewbem_set_operator": (C.c_int, [P, C.POINTER(OpOpts)]),
+        "ewbem_set_solver": (C.c_int, [P, C.POINTER(SolverOpts)]),
+        "ewbem_info": (C.c_int, [P, C.POINTER(Info)]),
+        "ewbem_get_partition": (C.c_int, [P, P, P, P]),
+        "ewbem_load_spectrum": (C.c_int, [P, P]),
+        "ewbem_kernel_eval": (C.c_int, [P, Z, I64, P, P, P, P, P]),
+        "ewbem_assemble_dense": (C.c_int, [P, Z, P, P]),
+        "ewbem_assemble": (C.c_int, [P, I32, C.POINTER(Stats)]),
+        "ewbem_apply": (C.c_int, [P, P, P]),
+        "ewbem_get_rhs": (C.c_int, [P, P]),
+        "ewbem_solve_frequency": (C.c_int, [P, I32, P, P, C.POINTER(Stats)]),
+        "ewbem_solve_transient": (C.c_int, [P, P, P, C.POINTER(Stats)]),
+        "ewbem_mft_inverse": (C.c_int, [P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class EwbemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ewbem status {status}: {msg}")
+        self.status = status
+
+
+def default_op_opts(**kw):
+    o = OpOpts()
+    lib().ewbem_default_op_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_solver_opts(**kw):
+    o = SolverOpts()
+    lib().ewbem_default_solver_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t, dtype_name, numel=None):
+    """Device pointer of a contiguous CUDA (HIP) torch tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if str(t.dtype) != dtype_name:
+        raise TypeError(f"expected {dtype_name}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One ewbem context.  ``device`` = -1 makes a host-only context."""
+
+    def __init__(self, device=0, stream=None):
+        self._L = lib()
+        h = C.c_void_p()
+        if device >= 0 and stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        st = self._L.ewbem_create(C.byref(h), int(device), C.c_void_p(stream or 0))
+        if st != OK:
+            raise EwbemError(st, "could not create context")
+        self.h = h
+        self.device = device
+        self.nt = 0
+        self.n_f = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.ewbem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise EwbemError(st, self._L.ewbem_last_error(self.h).decode())
+        return st
+
+    # ---- setup
+    def set_mesh(self, xyz, tri, exterior=True):
+        xyz, px = _host(xyz, np.float64)
+        tri, pt = _host(tri, np.int32)
+        self._check(self._L.ewbem_set_mesh(self.h, len(xyz), px, len(tri), pt, int(bool(exterior))))
+        self.nt = len(tri)
+
+    def set_material(self, rho, mu, nu):
+        self._check(self._L.ewbem_set_material(self.h, rho, mu, nu))
+
+    def set_time(self, period, n_f, sigma, window=WINDOW_HANN):
+        self._check(self._L.ewbem_set_time(self.h, period, int(n_f), sigma, int(window)))
+        self.n_f = int(n_f)
+
+    def set_load_pressure(self, p, history):
+        p, pp = _host(p, np.float64)
+        h, ph = _host(history, np.float64)
+        if p.shape != (self.nt,) or h.shape != (self.n_f,):
+            raise ValueError("pressure must have nt values and history n_f samples")
+        self._check(self._L.ewbem_set_load_pressure(self.h, pp, ph))
+
+    def set_load_traction(self, t0, history):
+        t0, pt = _host(t0, np.float64)
+        h, ph = _host(history, np.float64)
+        if t0.size != 3 * self.nt or h.shape != (self.n_f,):
+            raise ValueError("traction must have 3 nt values and history n_f samples")
+        self._check(self._L.ewbem_set_load_traction(self.h, pt, ph))
+
+    def set_operator(self, **kw):
+        o = default_op_opts(**kw)
+        self._check(self._L.ewbem_set_operator(self.h, C.byref(o)))
+
+    def set_solver(self, **kw):
+        o = default_solver_opts(**kw)
+        self._check(self._L.ewbem_set_solver(self.h, C.byref(o)))
+
+    def info(self):
+        i = Info()
+        self._check(self._L.ewbem_info(self.h, C.byref(i)))
+        return i.as_dict()
+
+    def partition(self):
+        inf = self.info()
+        perm = np.zeros(self.nt, np.int32)
+        near = np.zeros((inf["n_near"], 4), np.int32)
+        far = np.zeros((max(inf["n_far"], 0), 4), np.int32)
+        self._check(self._L.ewbem_get_partition(
+            self.h, perm.ctypes.data_as(C.c_void_p), near.ctypes.data_as(C.c_void_p),
+            far.ctypes.data_as(C.c_void_p)))
+        return perm, near, far
+
+    # ---- compute (device tensors)
+    def load_spectrum(self):
+        out = np.zeros(self.n_f // 2 + 1, np.complex128)
+        self._check(self._L.ewbem_load_spectrum(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def kernel_eval(self, s, x, y, nrm, U=None, T=None):
+        n = x.shape[0]
+        px = _dev_ptr(x, "torch.float64", 3 * n)
+        py = _dev_ptr(y, "torch.float64", 3 * n)
+        pn = _dev_ptr(nrm, "torch.float64", 3 * n)
+        pU = _dev_ptr(U, "torch.complex128", 9 * n) if U is not None else None
+        pT = _dev_ptr(T, "torch.complex128", 9 * n) if T is not None else None
+        self._check(self._L.ewbem_kernel_eval(self.h, Z(s.real, s.imag), n, px, py, pn, pU, pT))
+
+    def assemble_dense(self, s, T=None, U=None):
+        N = 3 * self.nt
+        pT = _dev_ptr(T, "torch.complex128", N * N) if T is not None else None
+        pU = _dev_ptr(U, "torch.complex128", N * N) if U is not None else None
+        self._check(self._L.ewbem_assemble_dense(self.h, Z(complex(s).real, complex(s).imag), pT, pU))
+
+    def assemble(self, k):
+        st = Stats()
+        self._check(self._L.ewbem_assemble(self.h, int(k), C.byref(st)))
+        return st.as_dict()
+
+    def apply(self, x, y):
+        N = 3 * self.nt
+        self._check(self._L.ewbem_apply(self.h, _dev_ptr(x, "torch.complex128", N),
+                                        _dev_ptr(y, "torch.complex128", N)))
+
+    def get_rhs(self, b):
+        self._check(self._L.ewbem_get_rhs(self.h, _dev_ptr(b, "torch.complex128", 3 * self.nt)))
+
+    def solve_frequency(self, k, a, x0=None, allow_noconv=False):
+        N = 3 * self.nt
+        st = Stats()
+        px0 = _dev_ptr(x0, "torch.complex128", N) if x0 is not None else None
+        rc = self._L.ewbem_solve_frequency(self.h, int(k), px0, _dev_ptr(a, "torch.complex128", N),
+                                           C.byref(st))
+        if not (allow_noconv and rc == ENOCONV):
+            self._check(rc)
+        return st.as_dict()
+
+    def solve_transient(self, u, spec=None, allow_noconv=False):
+        N = 3 * self.nt
+        st = Stats()
+        ps = _dev_ptr(spec, "torch.complex128", (self.n_f // 2 + 1) * N) if spec is not None else None
+        rc = self._L.ewbem_solve_transient(self.h, _dev_ptr(u, "torch.float64", self.n_f * N), ps,
+                                           C.byref(st))
+        if not (allow_noconv and rc == ENOCONV):
+            self._check(rc)
+        return st.as_dict()
+
+    def mft_inverse(self, spec, u):
+        N = 3 * self.nt
+        self._check(self._L.ewbem_mft_inverse(
+            self.h, _dev_ptr(spec, "torch.complex128", (self.n_f // 2 + 1) * N),
+            _dev_ptr(u, "torch.float64", self.n_f * N)))
+
+
+def setup_from_inputs(ctx, d, op=None, solver=None):
+    """Configure a context from a ``synth.config_inputs`` dictionary."""
+    ctx.set_mesh(d["xyz"], d["tri"], exterior=bool(d.get("exterior", 1)))
+    m = d["material"]
+    ctx.set_material(m["rho"], m["mu"], m["nu"])
+    ctx.set_time(d["period"], d["n_f"], d["sigma"], d["window"])
+    ctx.set_load_pressure(d["pressure"], d["history"])
+    ctx.set_operator(**(op if op is not None else d.get("op", {})))
+    ctx.set_solver(**(solver if solver is not None else d.get("solver", {})))
+    return ctx

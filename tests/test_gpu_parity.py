@@ -1,0 +1,272 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, through the
+C-ABI, on seeded inputs of the pressurised-cavity workloads.
+
+Tolerances (relative, max-abs over max-abs unless stated):
+  point kernels, dense T and U entries, operator apply in dense mode: 1e-12
+  (FP64 with the same quadrature rules; the self-element rules differ in
+  order but both converge to ~1e-14);
+  load spectrum and inverse transform: 1e-13;
+  frequency solves: relative L2 1e-8 with GMRES tol 1e-10 (the systems are
+  second-kind and well conditioned, so error ~ residual);
+  transient (the sub-2 cavity, GMRES tol 1e-8): relative L2 1e-6;
+  H-matrix apply at ACA tol eps: relative L2 <= 30 eps against the dense
+  oracle (the ACA stopping rule bounds each block's error by ~eps relative).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bem, kernels as K, mft, solve as osolve
+from synth import config_inputs, ramp_history
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1212_3032_amd import ewbem
+    ewbem.lib()
+    return ewbem
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _ctx(E, d, op=None, solver=None):
+    c = E.Context(0)
+    E.setup_from_inputs(c, d, op=op, solver=solver)
+    return c
+
+
+def test_kernel_eval(torch_dev, E, mat):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(7)
+    n = 4096
+    x = rng.standard_normal((n, 3))
+    d = rng.standard_normal((n, 3))
+    d *= (10 ** rng.uniform(-3, 0.5, (n, 1))) / np.linalg.norm(d, axis=1, keepdims=True)
+    y = x + d
+    nr = rng.standard_normal((n, 3))
+    nr /= np.linalg.norm(nr, axis=1, keepdims=True)
+    c = E.Context(0)
+    c.set_material(1.0, 1.0, 0.25)
+    for s in (0.75, 0.75 + 3.1416j, 0.75 + 50.27j, 0.01 + 0.002j, 2.0 - 1.0j):
+        _say(f"kernel_eval s={s} n={n}")
+        tx, ty, tn = (torch.tensor(a, device=dev) for a in (x, y, nr))
+        U = torch.zeros(9 * n, dtype=torch.complex128, device=dev)
+        T = torch.zeros(9 * n, dtype=torch.complex128, device=dev)
+        c.kernel_eval(s, tx, ty, tn, U, T)
+        Uo = K.U_kernel(x, y, s, mat).reshape(n, 9)
+        To = K.T_kernel(x, y, nr, s, mat).reshape(n, 9)
+        Ug = U.cpu().numpy().reshape(n, 9)
+        Tg = T.cpu().numpy().reshape(n, 9)
+        # per pair, relative to the pair's largest entry
+        eU = (np.abs(Ug - Uo).max(axis=1) / np.abs(Uo).max(axis=1)).max()
+        eT = (np.abs(Tg - To).max(axis=1) / np.abs(To).max(axis=1)).max()
+        assert eU < 1e-12, (s, eU)
+        assert eT < 1e-12, (s, eT)
+    c.close()
+
+
+@pytest.mark.parametrize("sub", [1, 2])
+def test_dense_matrices(torch_dev, E, mat, sub):
+    torch, dev = torch_dev
+    d = config_inputs(1, sub=sub)
+    g = bem.geometry(d["xyz"], d["tri"], exterior=True)
+    N = 3 * g["ne"]
+    c = _ctx(E, d, op=dict(kind=E.OP_DENSE))
+    for k in (0, 5, 16):
+        s = mft.freq_grid(d["period"], d["n_f"], d["sigma"])[k]
+        _say(f"assemble_dense sub={sub} k={k} s={s}")
+        T = torch.zeros(N * N, dtype=torch.complex128, device=dev)
+        U = torch.zeros(N * N, dtype=torch.complex128, device=dev)
+        c.assemble_dense(s, T, U)
+        To, Uo = bem.assemble_dense(g, s, mat)
+        eT = _rel(T.cpu().numpy().reshape(N, N), To)
+        eU = _rel(U.cpu().numpy().reshape(N, N), Uo)
+        _say(f"  eT={eT:.2e} eU={eU:.2e}")
+        assert eT < 1e-12 and eU < 1e-12
+    c.close()
+
+
+def test_load_spectrum_and_inverse(torch_dev, E):
+    torch, dev = torch_dev
+    d = config_inputs(1, sub=1)
+    c = _ctx(E, d, op=dict(kind=E.OP_DENSE))
+    _say("load_spectrum")
+    ph = c.load_spectrum()
+    ref = mft.load_spectrum(d["history"], d["period"], d["sigma"])
+    assert np.abs(ph - ref).max() < 1e-13 * np.abs(ref).max()
+    rng = np.random.default_rng(11)
+    N = 3 * len(d["tri"])
+    nh = d["n_f"] // 2 + 1
+    spec = rng.standard_normal((nh, N)) + 1j * rng.standard_normal((nh, N))
+    for w in (E.WINDOW_NONE, E.WINDOW_HANN, E.WINDOW_BLACKMAN):
+        _say(f"mft_inverse window={w}")
+        c.set_time(d["period"], d["n_f"], d["sigma"], w)
+        c.set_load_pressure(d["pressure"], d["history"])
+        u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+        c.mft_inverse(torch.tensor(spec, device=dev).reshape(-1), u)
+        uo = mft.inverse(spec, d["period"], d["sigma"], w)
+        assert _rel(u.cpu().numpy().reshape(d["n_f"], N), uo) < 1e-13
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def sub2_system(mat):
+    d = config_inputs(1, sub=2)
+    g = bem.geometry(d["xyz"], d["tri"], exterior=True)
+    t0 = bem.traction_from_pressure(g, d["pressure"])
+    s_k = mft.freq_grid(d["period"], d["n_f"], d["sigma"])
+    ph = mft.load_spectrum(d["history"], d["period"], d["sigma"])
+    out = {}
+    for k in (0, 3, 16):
+        T, U = bem.assemble_dense(g, s_k[k], mat)
+        out[k] = (T, ph[k] * (U @ t0))
+    return d, out
+
+
+def test_dense_operator_apply_and_rhs(torch_dev, E, sub2_system):
+    torch, dev = torch_dev
+    d, sysk = sub2_system
+    N = 3 * len(d["tri"])
+    c = _ctx(E, d, op=dict(kind=E.OP_DENSE))
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    for k, (T, b) in sysk.items():
+        _say(f"assemble+apply dense k={k}")
+        c.assemble(k)
+        y = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.apply(torch.tensor(x, device=dev), y)
+        assert _rel(y.cpu().numpy(), T @ x) < 1e-12
+        bg = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.get_rhs(bg)
+        assert _rel(bg.cpu().numpy(), b) < 1e-12
+    c.close()
+
+
+@pytest.mark.parametrize("precond", ["none", "element", "leaf"])
+def test_frequency_solve_matches_lu(torch_dev, E, sub2_system, precond):
+    torch, dev = torch_dev
+    d, sysk = sub2_system
+    N = 3 * len(d["tri"])
+    pc = dict(none=E.PREC_NONE, element=E.PREC_ELEMENT, leaf=E.PREC_LEAF)[precond]
+    c = _ctx(E, d, op=dict(kind=E.OP_DENSE),
+             solver=dict(tol=1e-10, precond=pc, guess=E.GUESS_ZERO))
+    for k, (T, b) in sysk.items():
+        _say(f"solve_frequency precond={precond} k={k}")
+        a = torch.zeros(N, dtype=torch.complex128, device=dev)
+        st = c.solve_frequency(k, a)
+        ref = np.linalg.solve(T, b)
+        e = _l2(a.cpu().numpy(), ref)
+        _say(f"  iters={st['iters_total']} resid={st['resid_max']:.2e} err={e:.2e}")
+        assert st["resid_max"] <= 1e-10
+        assert e < 1e-8
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def config1_oracle():
+    d = config_inputs(1)
+    return d, osolve.transient(d["xyz"], d["tri"], d["material"], d["period"], d["n_f"],
+                               d["sigma"], d["window"], d["pressure"], d["history"])
+
+
+@pytest.mark.parametrize("guess", ["sem", "quad", "zero"])
+def test_config1_transient(torch_dev, E, config1_oracle, guess):
+    """The dense sub-2 cavity, N_f = 32, Hann, GMRES tol 1e-8: transient and
+    spectrum against the oracle's LU result."""
+    torch, dev = torch_dev
+    d, ref = config1_oracle
+    N = 3 * len(d["tri"])
+    gs = dict(sem=E.GUESS_SEM, quad=E.GUESS_QUAD, zero=E.GUESS_ZERO)[guess]
+    c = _ctx(E, d, solver=dict(tol=1e-8, guess=gs))
+    _say(f"config1 transient guess={guess}")
+    u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+    spec = torch.zeros((d["n_f"] // 2 + 1) * N, dtype=torch.complex128, device=dev)
+    st = c.solve_transient(u, spec)
+    eu = _l2(u.cpu().numpy().reshape(d["n_f"], N), ref["u"])
+    es = _l2(spec.cpu().numpy().reshape(-1, N), ref["spec"])
+    _say(f"  iters={st['iters_total']} eu={eu:.2e} espec={es:.2e}")
+    assert eu < 1e-6 and es < 1e-6
+    c.close()
+
+
+def test_sem_reduces_iterations(torch_dev, E):
+    """Sec. 4.2: the extrapolated guess starts closer than zero and saves
+    GMRES iterations over the frequency sequence."""
+    torch, dev = torch_dev
+    d = config_inputs(1)
+    N = 3 * len(d["tri"])
+    its = {}
+    for name, gs in (("zero", E.GUESS_ZERO), ("sem", E.GUESS_SEM)):
+        c = _ctx(E, d, solver=dict(tol=1e-8, guess=gs))
+        u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+        st = c.solve_transient(u)
+        its[name] = st["iters_total"]
+        c.close()
+    _say(f"iterations {its}")
+    assert its["sem"] < its["zero"]
+
+
+@pytest.fixture(scope="module")
+def sub3_system(mat):
+    d = config_inputs(2, sub=3)
+    g = bem.geometry(d["xyz"], d["tri"], exterior=True)
+    t0 = bem.traction_from_pressure(g, d["pressure"])
+    s_k = mft.freq_grid(d["period"], d["n_f"], d["sigma"])
+    ph = mft.load_spectrum(d["history"], d["period"], d["sigma"])
+    out = {}
+    for k in (0, 40):
+        T, U = bem.assemble_dense(g, s_k[k], mat)
+        out[k] = (T, ph[k] * (U @ t0))
+    return d, out
+
+
+@pytest.mark.parametrize("store", ["c128", "c64"])
+@pytest.mark.parametrize("aca_tol", [1e-5, 1e-8])
+def test_hmatrix_apply_and_solve(torch_dev, E, sub3_system, aca_tol, store):
+    torch, dev = torch_dev
+    d, sysk = sub3_system
+    N = 3 * len(d["tri"])
+    st_kind = E.STORE_C64 if store == "c64" else E.STORE_C128
+    c = _ctx(E, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=aca_tol,
+                           far_store=st_kind),
+             solver=dict(tol=1e-10, guess=E.GUESS_ZERO))
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    for k, (T, b) in sysk.items():
+        _say(f"hmatrix sub=3 k={k} aca_tol={aca_tol} store={store}")
+        st = c.assemble(k)
+        y = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.apply(torch.tensor(x, device=dev), y)
+        e_apply = _l2(y.cpu().numpy(), T @ x)
+        a = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.solve_frequency(k, a)
+        e_sol = _l2(a.cpu().numpy(), np.linalg.solve(T, b))
+        bound = max(30 * aca_tol, 1e-6 if store == "c64" else 1e-12)
+        _say(f"  far={st['n_far']} ranks sum={st['rank_sum']} max={st['rank_max']} "
+             f"e_apply={e_apply:.2e} e_sol={e_sol:.2e}")
+        assert st["n_far"] > 0 and st["rank_sum"] > 0
+        assert e_apply < bound
+        assert e_sol < bound
+    c.close()
