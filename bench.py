@@ -1,0 +1,220 @@
+"""Benchmark: frequency solves per second of the exponential-window BEM.
+
+One step is the whole transient solve of the pressurised spherical cavity
+at 61,440 unknowns (icosphere level 5, 20,480 triangles): for each of the
+65 damped frequencies s_k (N_f = 128) the H-matrix operator (leaf 64,
+eta = 1, ACA 1e-5), the right-hand side and the block-diagonal
+preconditioner are assembled, the initial guess is extrapolated from the
+three previous solutions, GMRES runs to a 1e-6 relative residual; then the
+windowed, de-damped inverse transform gives the time response.  Inputs are
+resident on the GPU before the timed region.
+
+Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "freq-solves/s at N=61k, 1e-6 resid: learned+FP32 vs plain FP64; H-matvec GB/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sub", type=int, default=None, help="icosphere level (default 5)")
+    ap.add_argument("--store", choices=["c128", "c64"], default="c128")
+    ap.add_argument("--c64-variant", action="store_true",
+                    help="also time the complex64-factor variant")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=48)
+    return ap.parse_args()
+
+
+def _hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(bytes_per_launch):
+    """HBM bytes per matvec from the committed rocprofv3 counter summary, if
+    it was taken on the current matvec source (else None)."""
+    p = os.path.join(ROOT, "profiles", "hmatvec_traffic.json")
+    src = os.path.join(ROOT, "paper_1212_3032_amd", "csrc", "hmatvec.hip")
+    try:
+        with open(p) as f:
+            t = json.load(f)
+        if t.get("source_sha256_16") != _hash(src):
+            return None
+        return t["hbm_bytes_per_matvec"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def run_gpu(args, store):
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    from synth import config_inputs
+
+    d = config_inputs(2, sub=args.sub)
+    dev = torch.device("cuda:0")
+    ctx = E.Context(0)
+    E.setup_from_inputs(
+        ctx, d,
+        op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5,
+                far_store=E.STORE_C64 if store == "c64" else E.STORE_C128),
+        solver=dict(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF))
+    N = 3 * len(d["tri"])
+    n_f = d["n_f"]
+    u = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
+    for w in range(args.warmup):
+        st = ctx.solve_transient(u)
+        print(f"# warmup {w}: {st['n_solves']} solves, {st['iters_total']} its, "
+              f"{st['t_assemble_ms']:.0f} ms assembly, {st['t_gmres_ms']:.0f} ms gmres",
+              file=sys.stderr, flush=True)
+    tot = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        st = ctx.solve_transient(u)
+        print(f"# step {s}: {st['iters_total']} its, resid_max {st['resid_max']:.2e}",
+              file=sys.stderr, flush=True)
+        if tot is None:
+            tot = dict(st)
+        else:
+            for k, v in st.items():
+                if k in ("resid_max", "iters_max", "rank_max"):
+                    tot[k] = max(tot[k], v)
+                elif k in ("matvec_bytes", "stored_bytes", "n_near", "n_far", "rank_sum"):
+                    tot[k] = v
+                else:
+                    tot[k] += v
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.close()
+    return d, N, elapsed, tot
+
+
+def cpu_baseline(args):
+    """The oracle (dense assembly + LU) on the host cores, on a bounded sample
+    of the same workload: ``cpu_rows`` element rows of T and U at level 5
+    and a full LU at level 3, scaled to one frequency solve at 61,440
+    unknowns (assembly linear in rows, LU cubic in N)."""
+    from threadpoolctl import threadpool_info
+    from oracle import bem, kernels as K, mft
+    from synth import config_inputs
+
+    d = config_inputs(2, sub=args.sub)
+    mat = K.material(**d["material"])
+    g = bem.geometry(d["xyz"], d["tri"])
+    s = mft.freq_grid(d["period"], d["n_f"], d["sigma"])[d["n_f"] // 4]
+    rows = min(args.cpu_rows, g["ne"])
+    t = time.perf_counter()
+    bem.assemble_rows(g, s, mat, np.arange(rows))
+    t_rows = time.perf_counter() - t
+    t_asm = t_rows * g["ne"] / rows
+    d3 = config_inputs(2, sub=3)
+    g3 = bem.geometry(d3["xyz"], d3["tri"])
+    A3, U3 = bem.assemble_dense(g3, s, mat)
+    b3 = U3 @ bem.traction_from_pressure(g3, d3["pressure"])
+    t = time.perf_counter()
+    np.linalg.solve(A3, b3)
+    t_lu3 = time.perf_counter() - t
+    N = 3 * g["ne"]
+    t_lu = t_lu3 * (N / (3 * g3["ne"])) ** 3
+    threads = 1
+    for info in threadpool_info():
+        if info.get("user_api") == "blas":
+            threads = max(threads, info.get("num_threads", 1))
+    return {
+        "value": 1.0 / (t_asm + t_lu), "unit": "freq-solves/s", "cores": threads,
+        "kind": "oracle",
+        "sample": (f"dense oracle: {rows} element rows of T and U at N={N} in {t_rows:.1f} s "
+                   f"(scaled to all rows: {t_asm:.0f} s) + LAPACK LU at N={3 * g3['ne']} in "
+                   f"{t_lu3:.2f} s (scaled by N^3: {t_lu:.0f} s); extrapolated, one frequency"),
+        "host_cpus": len(os.sched_getaffinity(0)),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build uses one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    d, N, elapsed, st = run_gpu(args, args.store)
+    solves = st["n_solves"]
+    value = solves / elapsed
+    ms_step = 1000.0 * elapsed / args.steps
+    mv_time_s = st["t_matvec_ms"] / 1000.0
+    mv_gbs = st["matvec_bytes_total"] / mv_time_s / 1e9 if mv_time_s > 0 else 0.0
+    per_launch_ms = st["t_matvec_ms"] / max(1, st["matvecs_timed"])
+    bytes_per_launch = st["matvec_bytes_total"] / max(1, st["matvecs_timed"])
+    phases = {
+        "assembly_ms": st["t_assemble_ms"] / args.steps,
+        "near_self_kernels_ms": st["t_near_ms"] / args.steps,
+        "aca_kernels_ms": st["t_aca_ms"] / args.steps,
+        "rhs_kernels_ms": st["t_rhs_ms"] / args.steps,
+        "guess_ms": st["t_guess_ms"] / args.steps,
+        "gmres_ms": st["t_gmres_ms"] / args.steps,
+        "matvec_kernels_ms": st["t_matvec_ms"] / args.steps,
+        "post_ms": st["t_post_ms"] / args.steps,
+    }
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "freq-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.store == "c128" else "f64+c64-factors",
+        "data": "synthetic",
+        "config": {
+            "workload": d["name"], "n_dof": N, "n_elements": len(d["tri"]), "n_f": d["n_f"],
+            "freq_solves_per_step": solves // args.steps, "sigma": d["sigma"], "period": d["period"],
+            "leaf": 64, "eta_adm": 1.0, "aca_tol": 1e-5, "gmres_tol": 1e-6, "guess": "LS-SEM K=3",
+            "precond": "leaf block-diagonal", "far_store": args.store, "arith": "complex128",
+        },
+        "roofline": {
+            "kernel": "H-matrix matvec (k_far_vt + k_hmv + k_hmv_reduce)",
+            "bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": mv_gbs / HBM_PEAK_GBS, "traffic": traffic_from_profiles(bytes_per_launch),
+            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": per_launch_ms,
+            "launches": st["matvecs_timed"],
+        },
+        "phases_ms_per_step": phases,
+        "gmres_iters_per_solve": st["iters_total"] / max(1, solves),
+        "resid_max": st["resid_max"],
+        "stored_operator_GB": st["stored_bytes"] / 1e9,
+        "far_blocks": st["n_far"], "near_blocks": st["n_near"], "rank_max": st["rank_max"],
+    }
+    if args.c64_variant and args.store == "c128":
+        _, _, el2, st2 = run_gpu(args, "c64")
+        out["c64_factors"] = {
+            "value": st2["n_solves"] / el2,
+            "matvec_GBps": st2["matvec_bytes_total"] / (st2["t_matvec_ms"] / 1000.0) / 1e9,
+            "gmres_iters_per_solve": st2["iters_total"] / max(1, st2["n_solves"]),
+            "resid_max": st2["resid_max"],
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,9 @@ typedef struct {
   double t_aca_ms;         /* HIP-event time of the ACA kernels */
   double t_near_ms;        /* HIP-event time of the near-field + self kernels */
   double t_rhs_ms;         /* HIP-event time of the right-hand-side kernels */
+  double matvec_bytes_total; /* algorithmic bytes summed over every timed matvec */
+  int32_t matvecs_timed;   /* matvecs included in t_matvec_ms */
+  int32_t pad0;
 } ewbem_stats;
 
 typedef struct {

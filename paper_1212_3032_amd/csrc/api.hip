@@ -37,6 +37,8 @@ struct DevBuf {
   }
   void reserve(size_t cnt) {
     if (cnt <= n) return;
+    // nothing in flight may still use the old allocation
+    if (p) EWBEM_HIP_CHECK(hipDeviceSynchronize());
     release();
     if (cnt) {
       EWBEM_HIP_CHECK(hipMalloc((void**)&p, cnt * sizeof(T)));
@@ -119,7 +121,11 @@ struct ewbem_ctx {
   DevBuf<int> d_self_ld;
   DevBuf<cd> d_D;
   DevBuf<FarBlk> d_far;
-  DevBuf<cd> d_ws, d_ws2;
+  DevBuf<cd> d_ws;
+  // one buffer per capacity-retry round of the current frequency; all stay
+  // alive until the next frequency is assembled (blocks retried in an
+  // earlier round keep pointing into their round's buffer)
+  std::vector<std::unique_ptr<DevBuf<cd>>> d_retry;
   DevBuf<cf> d_f32;
   DevBuf<long long> d_uo, d_vo;
   DevBuf<int> d_rank, d_status, d_ord_small, d_ord_big;
@@ -335,7 +341,8 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     want = ((want + 2) / 3) * 3;
     kcap[b] = std::max(3, std::min({want, full, kmax}));
   }
-  // main layout
+  // main layout (the previous frequency's retry buffers are no longer used)
+  c->d_retry.clear();
   long long total = 0;
   for (int b = 0; b < nf; ++b) total += (long long)(3 * c->far_h[b].m + 3 * c->far_h[b].n) * kcap[b];
   c->d_ws.reserve(total);
@@ -380,14 +387,15 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
       f.kcap = std::min({full, ACA_KMAX, 2 * f.kcap + 6});
       tot2 += (long long)(3 * f.m + 3 * f.n) * f.kcap;
     }
-    c->d_ws2.release();
-    c->d_ws2.reserve(tot2);
+    c->d_retry.emplace_back(new DevBuf<cd>());
+    DevBuf<cd>& buf = *c->d_retry.back();
+    buf.reserve(tot2);
     long long o2 = 0;
     for (int b : over) {
       FarBlk& f = c->far_h[b];
-      f.U = c->d_ws2.p + o2;
+      f.U = buf.p + o2;
       o2 += 3LL * f.m * f.kcap;
-      f.V = c->d_ws2.p + o2;
+      f.V = buf.p + o2;
       o2 += 3LL * f.n * f.kcap;
     }
     c->d_far.upload(c->far_h, st);
@@ -407,7 +415,30 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
   }
 }
 
+// Host-side check that a device range [p, p + n) lies inside one of the
+// live factor allocations; a failure is a library bug, reported as an error
+// instead of being launched.
+bool in_alloc(const void* p, long long n_bytes, const void* base, size_t base_bytes) {
+  const char* a = (const char*)p;
+  const char* b = (const char*)base;
+  return base && a >= b && n_bytes >= 0 && a + n_bytes <= b + base_bytes;
+}
+
+void check_far_ranges(ewbem_ctx* c) {
+  for (size_t b = 0; b < c->far_h.size(); ++b) {
+    const FarBlk& f = c->far_h[b];
+    const long long nu = 3LL * f.m * f.kcap * (long long)sizeof(cd), nv = 3LL * f.n * f.kcap * (long long)sizeof(cd);
+    bool ok = in_alloc(f.U, nu, c->d_ws.p, c->d_ws.n * sizeof(cd)) &&
+              in_alloc(f.V, nv, c->d_ws.p, c->d_ws.n * sizeof(cd));
+    for (const auto& r : c->d_retry)
+      ok = ok || (in_alloc(f.U, nu, r->p, r->n * sizeof(cd)) && in_alloc(f.V, nv, r->p, r->n * sizeof(cd)));
+    if (!ok) fail(EWBEM_EINVAL, "internal: far-block factor range outside its allocation");
+    if (c->rank_h[b] < 0 || c->rank_h[b] > f.kcap) fail(EWBEM_EINVAL, "internal: rank outside capacity");
+  }
+}
+
 void build_matvec(ewbem_ctx* c) {
+  check_far_ranges(c);
   hipStream_t st = c->stream;
   const int nf = (int)c->far_h.size();
   const bool c64 = c->op.far_store == EWBEM_STORE_C64 && nf > 0;
@@ -521,6 +552,44 @@ void build_matvec(ewbem_ctx* c) {
     range.t1 = (int)rt.size();
     lr.push_back(range);
   }
+  // every range a kernel will touch must lie inside its allocation
+  {
+    const long long ztot = zoff[nf];
+    auto store_ok = [&](const void* p, long long bytes) {
+      if (c64) return in_alloc(p, bytes, c->d_f32.p, c->d_f32.n * sizeof(cf));
+      bool ok = in_alloc(p, bytes, c->d_ws.p, c->d_ws.n * sizeof(cd));
+      for (const auto& r : c->d_retry) ok = ok || in_alloc(p, bytes, r->p, r->n * sizeof(cd));
+      return ok;
+    };
+    const long long es = c64 ? (long long)sizeof(cf) : (long long)sizeof(cd);
+    for (const VtTask& t : vt) {
+      if (t.ncol < 1 || t.ncol > 4 || t.x0 < 0 || t.x0 + (long long)t.C > N || t.zidx < 0 ||
+          t.zidx + t.ncol > ztot || !store_ok(t.V, (long long)t.ncol * t.C * es))
+        fail(EWBEM_EINVAL, "internal: phase-1 task out of range");
+    }
+    for (size_t i = 0; i < rt.size(); ++i) {
+      const RowTask& T = rt[i];
+      if (T.rows < 1 || T.rows > HMV_MAXROWS || T.row0 < 0 || T.row0 + T.rows > N || T.s0 < 0 ||
+          T.s1 > (int)flat.size() || T.s0 > T.s1)
+        fail(EWBEM_EINVAL, "internal: row task out of range");
+      for (int q = T.s0; q < T.s1; ++q) {
+        const Seg& S = flat[q];
+        const long long span = ((long long)(S.ncols - 1) * S.ld + T.rows);
+        if (S.ncols < 1 || S.ld < T.rows) fail(EWBEM_EINVAL, "internal: segment shape");
+        if (S.flags & SEG_FROM_Z) {
+          if (S.src < 0 || S.src + S.ncols > ztot || !store_ok(S.A, span * es))
+            fail(EWBEM_EINVAL, "internal: far segment out of range");
+        } else {
+          if (S.src < 0 || S.src + S.ncols > N ||
+              !in_alloc(S.A, span * (long long)sizeof(cd), c->d_D.p, c->d_D.n * sizeof(cd)))
+            fail(EWBEM_EINVAL, "internal: near segment out of range");
+        }
+      }
+    }
+    for (const LeafRange& L : lr)
+      if (L.t0 < 0 || L.t1 > (int)rt.size() || L.t0 >= L.t1 || L.rows > HMV_MAXROWS || L.row0 + L.rows > N)
+        fail(EWBEM_EINVAL, "internal: leaf range out of range");
+  }
   c->d_vt.upload(vt, st);
   c->d_seg.upload(flat, st);
   c->d_rt.upload(rt, st);
@@ -542,6 +611,13 @@ void apply_tree(ewbem_ctx* c, const cd* x, cd* y, EventPair* ev) {
   launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, y, st);
   if (ev) EWBEM_HIP_CHECK(hipEventRecord(ev->b, st));
   c->acc.matvecs += 1;
+}
+
+// add one event-timed matvec (its kernels' time and algorithmic bytes)
+void account_matvec(ewbem_ctx* c, EventPair& ev) {
+  c->acc.t_matvec_ms += ev.elapsed();
+  c->acc.matvec_bytes_total += c->matvec_bytes;
+  c->acc.matvecs_timed += 1;
 }
 
 void precond_setup(ewbem_ctx* c) {
@@ -686,7 +762,7 @@ double gmres(ewbem_ctx* c, cd* x, cd* r, int& iters_out, bool& converged) {
       EWBEM_HIP_CHECK(hipMemcpyAsync(hbuf.data(), c->d_small.p, (2 * (m + 2) + 1) * sizeof(cd),
                                      hipMemcpyDeviceToHost, st));
       EWBEM_HIP_CHECK(hipStreamSynchronize(st));
-      c->acc.t_matvec_ms += ev.elapsed();
+      account_matvec(c, ev);
       ++iters_out;
       const double hn = std::sqrt(std::max(0.0, hbuf[2 * (m + 2)].x));
       for (int i = 0; i <= j; ++i)
@@ -740,7 +816,7 @@ double gmres(ewbem_ctx* c, cd* x, cd* r, int& iters_out, bool& converged) {
     apply_tree(c, x, r, &ev);
     launch_axpby(cd{1.0, 0.0}, c->d_b.p, cd{-1.0, 0.0}, r, N, st);
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
-    c->acc.t_matvec_ms += ev.elapsed();
+    account_matvec(c, ev);
     rnorm = dev_norm(c, r);
     relres = rnorm / bnorm;
     if (j == 0) break;
@@ -765,7 +841,7 @@ void sem_guess(ewbem_ctx* c, cd* x, cd* r) {
   for (int j = 0; j < K; ++j) {
     apply_tree(c, c->d_hist_sol.p + (size_t)c->hist_slot[j] * N, Y + (size_t)j * N, &ev);
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
-    c->acc.t_matvec_ms += ev.elapsed();
+    account_matvec(c, ev);
   }
   // classical Gram-Schmidt twice on the columns of Y
   std::vector<std::complex<double>> R((size_t)K * K, 0.0);
@@ -845,7 +921,7 @@ int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
     apply_tree(c, c->d_x.p, c->d_r.p, &ev);
     launch_axpby(cd{1, 0}, c->d_b.p, cd{-1, 0}, c->d_r.p, N, st);
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
-    c->acc.t_matvec_ms += ev.elapsed();
+    account_matvec(c, ev);
   } else if (c->so.guess == EWBEM_GUESS_SEM) {
     sem_guess(c, c->d_x.p, c->d_r.p);
   } else if (c->so.guess == EWBEM_GUESS_QUAD && c->hist_n > 0) {
@@ -859,7 +935,7 @@ int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
     apply_tree(c, c->d_x.p, c->d_r.p, &ev);
     launch_axpby(cd{1, 0}, c->d_b.p, cd{-1, 0}, c->d_r.p, N, st);
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
-    c->acc.t_matvec_ms += ev.elapsed();
+    account_matvec(c, ev);
   } else {
     EWBEM_HIP_CHECK(hipMemsetAsync(c->d_x.p, 0, N * sizeof(cd), st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_r.p, c->d_b.p, N * sizeof(cd), hipMemcpyDeviceToDevice, st));

@@ -52,7 +52,8 @@ class Stats(C.Structure):
                 ("matvec_bytes", C.c_double), ("stored_bytes", C.c_double),
                 ("n_near", C.c_int64), ("n_far", C.c_int64), ("rank_sum", C.c_int64),
                 ("rank_max", C.c_int64), ("t_aca_ms", C.c_double), ("t_near_ms", C.c_double),
-                ("t_rhs_ms", C.c_double)]
+                ("t_rhs_ms", C.c_double), ("matvec_bytes_total", C.c_double),
+                ("matvecs_timed", C.c_int32), ("pad0", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
