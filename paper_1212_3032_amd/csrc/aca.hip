@@ -9,8 +9,10 @@
 // to three terms; pivots below 1e-10 of the block's largest are dropped.
 // The approximation stops when the new terms satisfy
 //   sqrt(sum_t |u_t|^2 |v_t|^2) <= tol * |S|_F,
-// with |S|_F^2 updated exactly from the inner products of the factors, or
-// when the capacity is exhausted (reported so the host can retry).  The
+// with |S|_F^2 estimated as sum_l |u_l|^2 |v_l|^2 (the cross terms between
+// different terms are left out, which keeps each step linear in the block
+// size), or when the capacity is exhausted (reported so the host can
+// retry).  The
 // next row element is the unused one with the largest entries in the new
 // columns.
 #include "kernel_fn.hpp"
@@ -81,10 +83,35 @@ __device__ __forceinline__ double block_sum(double v, double* sv) {
   return v;
 }
 
+// 3 x 3 block of T between collocation point x and element e, the 7
+// quadrature points split over LPE consecutive lanes and summed by
+// butterfly shuffles (every lane of the group ends with the full block).
+template <int LPE>
+__device__ __forceinline__ void T_elem_split(const double* x, int e, bool valid, int q, const DevGeom& g,
+                                             const KParams& P, cd* T) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) T[i] = mk(0.0);
+  if (valid) {
+    const double* n = g.nrm + 3 * (size_t)e;
+    for (int pt = q; pt < 7; pt += LPE)
+      acc_T<false>(x, g.qp + 21 * (size_t)e + 3 * pt, n, g.qw[7 * (size_t)e + pt], P, T);
+  }
+#pragma unroll
+  for (int off = 1; off < LPE; off <<= 1)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      T[i].x += __shfl_xor(T[i].x, off, 64);
+      T[i].y += __shfl_xor(T[i].y, off, 64);
+    }
+}
+
 template <int WG, int KMAX>
 __global__ __launch_bounds__(WG) void k_aca(const FarBlk* __restrict__ blks, const int* __restrict__ order,
                                             DevGeom g, KParams P, double tol, int* __restrict__ rank_out,
                                             int* __restrict__ status_out) {
+  constexpr int LPE = 4;           // lanes per element in the cross evaluations
+  constexpr int EPP = WG / LPE;    // elements per pass
+  constexpr int W = WG / 64;
   const int bid = order[blockIdx.x];
   const FarBlk B = blks[bid];
   const int R = 3 * B.m, C = 3 * B.n, kcap = B.kcap;
@@ -93,11 +120,14 @@ __global__ __launch_bounds__(WG) void k_aca(const FarBlk* __restrict__ blks, con
   __shared__ cd s_urow[3][KMAX];
   __shared__ cd s_vcol[3][KMAX];
   __shared__ unsigned s_used[ACA_MAXM / 32];
-  __shared__ double s_rv[WG / 64 + 1];
-  __shared__ int s_ri[WG / 64 + 1];
-  __shared__ double s_w[WG / 64][2];
+  __shared__ double s_rv[W + 1];
+  __shared__ int s_ri[W + 1];
+  __shared__ double s_red[W][6];
+  __shared__ cd s_alpha[3][3], s_beta[3][3];
+  __shared__ int s_nacc;
 
   const int tid = threadIdx.x;
+  const int q = tid % LPE, eo = tid / LPE;
   for (int i = tid; i < ACA_MAXM / 32; i += WG) s_used[i] = 0u;
   int k = 0, astar = 0, fails = 0, status = 0;
   double normS2 = 0.0, first_max = -1.0;
@@ -115,14 +145,14 @@ __global__ __launch_bounds__(WG) void k_aca(const FarBlk* __restrict__ blks, con
     {
       const double* xa = g.cen + 3 * (size_t)(B.r0 + astar);
       const double x[3] = {xa[0], xa[1], xa[2]};
-      for (int b = tid; b < B.n; b += WG) {
+      for (int b0 = 0; b0 < B.n; b0 += EPP) {
+        const int b = b0 + eo;
         cd T[9];
-        T_elem(x, B.c0 + b, g, P, T);
-        double mx = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const int c = 3 * b + j;
-          cd r0 = T[j], r1 = T[3 + j], r2 = T[6 + j];
+        T_elem_split<LPE>(x, B.c0 + b, b < B.n, q, g, P, T);
+        if (b < B.n && q < 3) {
+          const int c = 3 * b + q;
+          cd r0 = T[q], r1 = T[3 + q], r2 = T[6 + q];
+#pragma unroll 4
           for (int l = 0; l < k; ++l) {
             const cd vv = V[(size_t)l * C + c];
             r0 -= s_urow[0][l] * vv;
@@ -132,11 +162,11 @@ __global__ __launch_bounds__(WG) void k_aca(const FarBlk* __restrict__ blks, con
           V[(size_t)(k + 0) * C + c] = r0;
           V[(size_t)(k + 1) * C + c] = r1;
           V[(size_t)(k + 2) * C + c] = r2;
-          mx = fmax(mx, fmax(norm2(r0), fmax(norm2(r1), norm2(r2))));
-        }
-        if (mx > bestv) {
-          bestv = mx;
-          besti = b;
+          const double mx = fmax(norm2(r0), fmax(norm2(r1), norm2(r2)));
+          if (mx > bestv) {
+            bestv = mx;
+            besti = b;
+          }
         }
       }
     }
@@ -164,15 +194,17 @@ __global__ __launch_bounds__(WG) void k_aca(const FarBlk* __restrict__ blks, con
       s_vcol[j][ll] = V[(size_t)ll * C + 3 * bstar + j];
     }
     __syncthreads();
-    for (int a = tid; a < B.m; a += WG) {
-      const double* xa = g.cen + 3 * (size_t)(B.r0 + a);
+    for (int a0 = 0; a0 < B.m; a0 += EPP) {
+      const int a = a0 + eo;
+      const int ac = a < B.m ? a : 0;
+      const double* xa = g.cen + 3 * (size_t)(B.r0 + ac);
       const double x[3] = {xa[0], xa[1], xa[2]};
       cd T[9];
-      T_elem(x, B.c0 + bstar, g, P, T);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int r = 3 * a + i;
-        cd c0 = T[3 * i], c1 = T[3 * i + 1], c2 = T[3 * i + 2];
+      T_elem_split<LPE>(x, B.c0 + bstar, a < B.m, q, g, P, T);
+      if (a < B.m && q < 3) {
+        const int r = 3 * a + q;
+        cd c0 = T[3 * q], c1 = T[3 * q + 1], c2 = T[3 * q + 2];
+#pragma unroll 4
         for (int l = 0; l < k; ++l) {
           const cd uu = U[(size_t)l * R + r];
           c0 -= uu * s_vcol[0][l];
@@ -185,75 +217,97 @@ __global__ __launch_bounds__(WG) void k_aca(const FarBlk* __restrict__ blks, con
       }
     }
     __syncthreads();
-    // ---- 3 x 3 pivot block from the residual rows; complete-pivoting plan
-    cd Pm[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) Pm[i][j] = V[(size_t)(k + i) * C + 3 * bstar + j];
-    cd Br[3][3], Ac[3][3], alpha[3][3], beta[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        Br[i][j] = Ac[i][j] = mk(i == j ? 1.0 : 0.0);
-        alpha[i][j] = beta[i][j] = mk(0.0);
-      }
-    int rowl = 7, coll = 7, nacc = 0;
-    double pmax0 = 0.0;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) pmax0 = fmax(pmax0, norm2(Pm[i][j]));
-    for (int stp = 0; stp < 3; ++stp) {
-      int p = -1, q = -1;
-      double best = -1.0;
-      for (int i = 0; i < 3; ++i) {
-        if (!(rowl & (1 << i))) continue;
+    // ---- 3 x 3 pivot block: complete-pivoting elimination plan (one thread)
+    if (tid == 0) {
+      cd Pm[3][3], Br[3][3], Ac[3][3];
+      for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-          if (!(coll & (1 << j))) continue;
-          const double v = norm2(Pm[i][j]);
-          if (v > best) {
-            best = v;
-            p = i;
-            q = j;
+          Pm[i][j] = V[(size_t)(k + i) * C + 3 * bstar + j];
+          Br[i][j] = Ac[i][j] = mk(i == j ? 1.0 : 0.0);
+          s_alpha[i][j] = s_beta[i][j] = mk(0.0);
+        }
+      int rowl = 7, coll = 7, nacc = 0;
+      double pmax0 = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) pmax0 = fmax(pmax0, norm2(Pm[i][j]));
+      for (int stp = 0; stp < 3; ++stp) {
+        int p = -1, qq = -1;
+        double best = -1.0;
+        for (int i = 0; i < 3; ++i) {
+          if (!(rowl & (1 << i))) continue;
+          for (int j = 0; j < 3; ++j) {
+            if (!(coll & (1 << j))) continue;
+            const double v = norm2(Pm[i][j]);
+            if (v > best) {
+              best = v;
+              p = i;
+              qq = j;
+            }
           }
         }
+        if (p < 0 || !(best > 1e-20 * pmax0) || best == 0.0) break;
+        const cd ipiv = cinv(Pm[p][qq]);
+        for (int j = 0; j < 3; ++j) {
+          s_alpha[nacc][j] = Ac[qq][j];
+          s_beta[nacc][j] = Br[p][j] * ipiv;
+        }
+        cd f[3], h[3];
+        for (int i = 0; i < 3; ++i) f[i] = Pm[i][qq] * ipiv;
+        for (int j = 0; j < 3; ++j) h[j] = Pm[p][j] * ipiv;
+        for (int i = 0; i < 3; ++i) {
+          if (!(rowl & (1 << i)) || i == p) continue;
+          for (int j = 0; j < 3; ++j) Br[i][j] -= f[i] * Br[p][j];
+        }
+        for (int j = 0; j < 3; ++j) {
+          if (!(coll & (1 << j)) || j == qq) continue;
+          for (int i = 0; i < 3; ++i) Ac[j][i] -= h[j] * Ac[qq][i];
+        }
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            if (i != p && j != qq) Pm[i][j] -= Pm[i][qq] * h[j];
+        rowl &= ~(1 << p);
+        coll &= ~(1 << qq);
+        ++nacc;
       }
-      if (p < 0 || !(best > 1e-20 * pmax0) || best == 0.0) break;
-      const cd ipiv = cinv(Pm[p][q]);
-      for (int j = 0; j < 3; ++j) {
-        alpha[nacc][j] = Ac[q][j];
-        beta[nacc][j] = Br[p][j] * ipiv;
-      }
-      cd f[3], h[3];
-      for (int i = 0; i < 3; ++i) f[i] = Pm[i][q] * ipiv;
-      for (int j = 0; j < 3; ++j) h[j] = Pm[p][j] * ipiv;
-      for (int i = 0; i < 3; ++i) {
-        if (!(rowl & (1 << i)) || i == p) continue;
-        for (int j = 0; j < 3; ++j) Br[i][j] -= f[i] * Br[p][j];
-      }
-      for (int j = 0; j < 3; ++j) {
-        if (!(coll & (1 << j)) || j == q) continue;
-        for (int i = 0; i < 3; ++i) Ac[j][i] -= h[j] * Ac[q][i];
-      }
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          if (i != p && j != q) Pm[i][j] -= Pm[i][q] * h[j];
-      rowl &= ~(1 << p);
-      coll &= ~(1 << q);
-      ++nacc;
+      s_nacc = nacc;
     }
     __syncthreads();
+    const int nacc = s_nacc;
     // ---- form the accepted terms in place: U[:, k+t] = sum_j alpha[t][j] C_j,
-    //      V[:, k+t] = sum_i beta[t][i] R_i
+    //      V[:, k+t] = sum_i beta[t][i] R_i; accumulate their squared norms
+    double nu[3] = {0.0, 0.0, 0.0}, nvv[3] = {0.0, 0.0, 0.0};
     for (int r = tid; r < R; r += WG) {
       const cd c0 = U[(size_t)k * R + r], c1 = U[(size_t)(k + 1) * R + r], c2 = U[(size_t)(k + 2) * R + r];
-      for (int t = 0; t < nacc; ++t)
-        U[(size_t)(k + t) * R + r] = alpha[t][0] * c0 + alpha[t][1] * c1 + alpha[t][2] * c2;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t < nacc) {
+          const cd v = s_alpha[t][0] * c0 + s_alpha[t][1] * c1 + s_alpha[t][2] * c2;
+          U[(size_t)(k + t) * R + r] = v;
+          nu[t] += norm2(v);
+        }
+      }
     }
     for (int c = tid; c < C; c += WG) {
       const cd r0 = V[(size_t)k * C + c], r1 = V[(size_t)(k + 1) * C + c], r2 = V[(size_t)(k + 2) * C + c];
-      for (int t = 0; t < nacc; ++t)
-        V[(size_t)(k + t) * C + c] = beta[t][0] * r0 + beta[t][1] * r1 + beta[t][2] * r2;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t < nacc) {
+          const cd v = s_beta[t][0] * r0 + s_beta[t][1] * r1 + s_beta[t][2] * r2;
+          V[(size_t)(k + t) * C + c] = v;
+          nvv[t] += norm2(v);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      nu[t] = wsum(nu[t]);
+      nvv[t] = wsum(nvv[t]);
+    }
+    if ((tid & 63) == 0) {
+      for (int t = 0; t < 3; ++t) {
+        s_red[tid >> 6][t] = nu[t];
+        s_red[tid >> 6][3 + t] = nvv[t];
+      }
     }
     __syncthreads();
     if (nacc == 0) {
@@ -268,45 +322,18 @@ __global__ __launch_bounds__(WG) void k_aca(const FarBlk* __restrict__ blks, con
       astar = next;
       continue;
     }
-    // ---- |S|_F^2 update: sum over l of (u_l^H u_t)(v_l^H v_t), waves over l
-    const int knew = k + nacc;
-    const int w = tid >> 6, lane = tid & 63;
-    double cross = 0.0, termsq = 0.0;
-    for (int l = w; l < knew; l += WG / 64) {
-      cd du[3] = {mk(0.0), mk(0.0), mk(0.0)}, dv[3] = {mk(0.0), mk(0.0), mk(0.0)};
-      for (int r = lane; r < R; r += 64) {
-        const cd ul = U[(size_t)l * R + r];
-        for (int t = 0; t < nacc; ++t) du[t] += cmulc(ul, U[(size_t)(k + t) * R + r]);
+    // ---- stopping test with |S|_F^2 estimated by sum_l |u_l|^2 |v_l|^2
+    double termsq = 0.0;
+    for (int t = 0; t < nacc; ++t) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < W; ++w) {
+        a += s_red[w][t];
+        b += s_red[w][3 + t];
       }
-      for (int c = lane; c < C; c += 64) {
-        const cd vl = V[(size_t)l * C + c];
-        for (int t = 0; t < nacc; ++t) dv[t] += cmulc(vl, V[(size_t)(k + t) * C + c]);
-      }
-      double sre = 0.0;
-      for (int t = 0; t < nacc; ++t) {
-        du[t].x = wsum(du[t].x);
-        du[t].y = wsum(du[t].y);
-        dv[t].x = wsum(dv[t].x);
-        dv[t].y = wsum(dv[t].y);
-        const cd pr = du[t] * dv[t];
-        sre += pr.x;
-        if (l == k + t) termsq += pr.x;  // |u_t|^2 |v_t|^2
-      }
-      cross += (l < k) ? 2.0 * sre : sre;
+      termsq += a * b;
     }
-    if (lane == 0) {
-      s_w[w][0] = cross;
-      s_w[w][1] = termsq;
-    }
-    __syncthreads();
-    cross = 0.0;
-    termsq = 0.0;
-    for (int q = 0; q < WG / 64; ++q) {
-      cross += s_w[q][0];
-      termsq += s_w[q][1];
-    }
-    normS2 += cross;
-    k = knew;
+    normS2 += termsq;
+    k += nacc;
     fails = 0;
     if (termsq <= tol * tol * normS2) break;
     if (k + 3 > kcap) {

@@ -337,7 +337,10 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     const int full = 3 * std::min(f.m, f.n);
     const bool small = f.m <= ACA_SMALL && f.n <= ACA_SMALL;
     const int kmax = small ? ACA_KMAX_SMALL : ACA_KMAX;
-    int want = c->kcap_prev[b] > 0 ? c->rank_h[b] + std::max(9, c->rank_h[b] / 4) : 30;
+    // capacity: 30% above the previous frequency's rank (ranks grow with
+    // frequency), else a size-based first guess; retries are the exception
+    int want = c->kcap_prev[b] > 0 ? c->rank_h[b] + std::max(12, (3 * c->rank_h[b]) / 10)
+                                   : 24 + (f.m + f.n) / 8;
     want = ((want + 2) / 3) * 3;
     kcap[b] = std::max(3, std::min({want, full, kmax}));
   }

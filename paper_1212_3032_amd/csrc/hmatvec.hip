@@ -29,30 +29,30 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
   const VtTask T = tasks[t];
   const TS* __restrict__ V = (const TS*)T.V;
   const cd* __restrict__ xs = x + T.x0;
-  cd acc[4] = {mk(0.0), mk(0.0), mk(0.0), mk(0.0)};
+  cd a0 = mk(0.0), a1 = mk(0.0), a2 = mk(0.0), a3 = mk(0.0);
   const int C = T.C;
-  if (T.ncol == 4) {
-    for (int c = lane; c < C; c += 64) {
-      const cd xv = xs[c];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] += to_cd(V[(size_t)j * C + c]) * xv;
-    }
-  } else {
-    for (int c = lane; c < C; c += 64) {
-      const cd xv = xs[c];
-      for (int j = 0; j < T.ncol; ++j) acc[j] += to_cd(V[(size_t)j * C + c]) * xv;
-    }
+  const int nc = T.ncol;
+  // columns past ncol read column 0 again (in bounds) and are discarded
+  const TS* __restrict__ V1 = V + (size_t)(nc > 1 ? 1 : 0) * C;
+  const TS* __restrict__ V2 = V + (size_t)(nc > 2 ? 2 : 0) * C;
+  const TS* __restrict__ V3 = V + (size_t)(nc > 3 ? 3 : 0) * C;
+  for (int c = lane; c < C; c += 64) {
+    const cd xv = xs[c];
+    a0 += to_cd(V[c]) * xv;
+    a1 += to_cd(V1[c]) * xv;
+    a2 += to_cd(V2[c]) * xv;
+    a3 += to_cd(V3[c]) * xv;
   }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    acc[j].x = wsum64(acc[j].x);
-    acc[j].y = wsum64(acc[j].y);
-  }
-  if (lane < T.ncol) {
-    cd v = acc[0];
-    if (lane == 1) v = acc[1];
-    if (lane == 2) v = acc[2];
-    if (lane == 3) v = acc[3];
+  a0.x = wsum64(a0.x);
+  a0.y = wsum64(a0.y);
+  a1.x = wsum64(a1.x);
+  a1.y = wsum64(a1.y);
+  a2.x = wsum64(a2.x);
+  a2.y = wsum64(a2.y);
+  a3.x = wsum64(a3.x);
+  a3.y = wsum64(a3.y);
+  if (lane < nc) {
+    const cd v = lane == 0 ? a0 : (lane == 1 ? a1 : (lane == 2 ? a2 : a3));
     z[T.zidx + lane] = v;
   }
 }
