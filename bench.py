@@ -39,7 +39,21 @@ def parse():
                     help="also time the complex64-factor variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device-to-device three times (a kernel of known "
+                         "traffic that calibrates the HBM counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def _hash(path):
@@ -153,6 +167,8 @@ def main():
         print(json.dumps({"error": "this build uses one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
     d, N, elapsed, st = run_gpu(args, args.store)
     solves = st["n_solves"]
     value = solves / elapsed

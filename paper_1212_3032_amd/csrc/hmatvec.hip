@@ -51,9 +51,14 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
   a2.y = wsum64(a2.y);
   a3.x = wsum64(a3.x);
   a3.y = wsum64(a3.y);
-  if (lane < nc) {
-    const cd v = lane == 0 ? a0 : (lane == 1 ? a1 : (lane == 2 ? a2 : a3));
-    z[T.zidx + lane] = v;
+  // every lane holds the sums; lane 0 stores them (no lane-indexed select,
+  // which the compiler would place in scratch memory)
+  if (lane == 0) {
+    cd* zz = z + T.zidx;
+    zz[0] = a0;
+    if (nc > 1) zz[1] = a1;
+    if (nc > 2) zz[2] = a2;
+    if (nc > 3) zz[3] = a3;
   }
 }
 
