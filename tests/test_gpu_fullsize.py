@@ -1,0 +1,132 @@
+"""Parity at the benchmark's full size (61,440 unknowns, the launch
+configuration bench.py times), on outputs the oracle can compute one by one:
+sampled rows of the operator's action and of the right-hand side, the true
+residual of the solution on sampled rows, and the transient against the
+cavity's closed form.  Also the failure paths the host can force.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bem, closed_form as CF, kernels as K, mft
+from synth import config_inputs
+
+pytestmark = pytest.mark.gpu
+
+ACA_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    assert torch.cuda.is_available()
+    d = config_inputs(2)
+    g = bem.geometry(d["xyz"], d["tri"], exterior=True)
+    mat = K.material(**d["material"])
+    rng = np.random.default_rng(2012)
+    elems = np.sort(rng.choice(g["ne"], size=12, replace=False))
+    return torch, E, d, g, mat, elems
+
+
+def _ctx(E, d, **solver):
+    c = E.Context(0)
+    E.setup_from_inputs(c, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0,
+                                      aca_tol=ACA_TOL),
+                        solver=dict(dict(tol=1e-6, guess=E.GUESS_ZERO), **solver))
+    return c
+
+
+@pytest.mark.parametrize("k", [16, 64])
+def test_sampled_rows_of_apply_rhs_and_residual(setup, k):
+    torch, E, d, g, mat, elems = setup
+    dev = torch.device("cuda:0")
+    N = 3 * g["ne"]
+    s = mft.freq_grid(d["period"], d["n_f"], d["sigma"])[k]
+    ph = mft.load_spectrum(d["history"], d["period"], d["sigma"])[k]
+    _say(f"fullsize k={k}: oracle rows of {len(elems)} elements")
+    rows = bem.assemble_rows(g, s, mat, elems)
+    t0 = bem.traction_from_pressure(g, d["pressure"])
+    c = _ctx(E, d)
+    _say(f"fullsize k={k}: assemble")
+    st = c.assemble(k)
+    assert st["n_far"] > 0
+    rng = np.random.default_rng(k)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    y = torch.zeros(N, dtype=torch.complex128, device=dev)
+    c.apply(torch.tensor(x, device=dev), y)
+    idx = (3 * elems[:, None] + np.arange(3)[None, :]).reshape(-1)
+    y_ref = rows["T"] @ x
+    e_apply = np.abs(y.cpu().numpy()[idx] - y_ref).max() / np.abs(y_ref).max()
+    b = torch.zeros(N, dtype=torch.complex128, device=dev)
+    c.get_rhs(b)
+    b_ref = ph * (rows["U"] @ t0)
+    bg = b.cpu().numpy()
+    e_rhs = np.abs(bg[idx] - b_ref).max() / np.abs(b_ref).max()
+    _say(f"  e_apply={e_apply:.2e} e_rhs={e_rhs:.2e}")
+    assert e_apply < 30 * ACA_TOL
+    assert e_rhs < 1e-12
+    a = torch.zeros(N, dtype=torch.complex128, device=dev)
+    st = c.solve_frequency(k, a)
+    r = b_ref - rows["T"] @ a.cpu().numpy()
+    e_res = np.abs(r).max() / np.abs(bg).max()
+    _say(f"  solve: its={st['iters_total']} resid={st['resid_max']:.2e} dense-row resid={e_res:.2e}")
+    assert st["resid_max"] <= 1e-6
+    assert e_res < 30 * ACA_TOL
+    c.close()
+
+
+def test_transient_matches_closed_form(setup):
+    """The whole benchmark path: the mean radial wall displacement against the
+    same transform applied to the exact transfer function H(s_k); the gap is
+    the level-5 discretisation error (first order, ~0.5%)."""
+    torch, E, d, g, mat, _ = setup
+    dev = torch.device("cuda:0")
+    N = 3 * g["ne"]
+    c = _ctx(E, d, guess=E.GUESS_SEM)
+    u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+    _say("fullsize transient")
+    st = c.solve_transient(u)
+    c.close()
+    rh = g["cen"] / np.linalg.norm(g["cen"], axis=1, keepdims=True)
+    ur = np.einsum("nek,ek->ne", u.cpu().numpy().reshape(d["n_f"], -1, 3), rh)
+    s = mft.freq_grid(d["period"], d["n_f"], d["sigma"])
+    spec = mft.load_spectrum(d["history"], d["period"], d["sigma"]) * CF.sphere_H(s, 1.0, mat)
+    ref = mft.inverse(spec, d["period"], d["sigma"], d["window"])
+    err = np.linalg.norm(ur.mean(axis=1) - ref) / np.linalg.norm(ref)
+    spread = np.abs(ur - ur.mean(axis=1, keepdims=True)).max() / np.abs(ref).max()
+    _say(f"  its={st['iters_total']} resid_max={st['resid_max']:.2e} "
+         f"closed-form err={err:.3e} spread={spread:.3e}")
+    assert st["resid_max"] <= 1e-6
+    assert err < 0.02
+    assert spread < 0.05
+
+
+def test_failure_paths_forced_from_host(setup):
+    torch, E, d, g, mat, _ = setup
+    dev = torch.device("cuda:0")
+    c = E.Context(0)
+    with pytest.raises(E.EwbemError) as e:
+        c.assemble(0)
+    assert e.value.status == E.ESTATE
+    small = config_inputs(1, sub=1)
+    E.setup_from_inputs(c, small, op=dict(kind=E.OP_DENSE),
+                        solver=dict(tol=1e-12, maxit=1, guess=E.GUESS_ZERO))
+    N = 3 * len(small["tri"])
+    a = torch.zeros(N, dtype=torch.complex128, device=dev)
+    with pytest.raises(E.EwbemError) as e:
+        c.solve_frequency(3, a)
+    assert e.value.status == E.ENOCONV
+    st = c.solve_frequency(3, a, allow_noconv=True)
+    assert st["iters_total"] == 1 and np.isfinite(a.cpu().numpy()).all()
+    with pytest.raises(E.EwbemError) as e:
+        c.assemble(small["n_f"])
+    assert e.value.status == E.EINVAL
+    c.close()
