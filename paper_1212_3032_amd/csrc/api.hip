@@ -136,6 +136,7 @@ struct ewbem_ctx {
   int n_vt = 0, n_rt = 0, n_lr = 0;
   DevBuf<cd> d_z, d_hpart, d_mvpart;
   DevBuf<cd> d_rhs_part;
+  int boff_k0 = 0, boff_nk = 0;   // frequencies whose off-diagonal U t0 is in d_rhs_part
   // preconditioner
   DevBuf<cd> d_M3, d_Minv;
   DevBuf<long long> d_minv_off, d_minv_src;
@@ -289,7 +290,7 @@ void ensure_device(ewbem_ctx* c) {
   const long long N = 3LL * c->nt;
   c->d_selfT.reserve(9 * (size_t)c->nt);
   c->d_selfU.reserve(9 * (size_t)c->nt);
-  c->d_rhs_part.reserve((size_t)rhs_chunks(c->nt) * N);
+  c->boff_nk = 0;
   for (DevBuf<cd>* v : {&c->d_b, &c->d_x, &c->d_r, &c->d_w, &c->d_u, &c->d_zt, &c->d_tmp_in, &c->d_tmp_out})
     v->reserve(N);
   const int m = c->so.restart;
@@ -362,6 +363,12 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     (small ? small_ids : big_ids).push_back(b);
   }
   c->d_far.upload(c->far_h, st);
+  // largest expected work first (better load balance at the end of the launch)
+  std::stable_sort(big_ids.begin(), big_ids.end(), [&](int a, int b) {
+    const FarBlk& fa = c->far_h[a];
+    const FarBlk& fb = c->far_h[b];
+    return (long long)(fa.m + fa.n) * kcap[a] > (long long)(fb.m + fb.n) * kcap[b];
+  });
   std::vector<int> ord(small_ids);
   ord.insert(ord.end(), big_ids.begin(), big_ids.end());
   c->d_ord_small.upload(ord, st);
@@ -674,6 +681,16 @@ void precond_apply(ewbem_ctx* c, const cd* v, cd* z) {
   }
 }
 
+// Off-diagonal U(s_k) t0 for frequencies k0 .. k0+nk-1 in one batched pass.
+void rhs_precompute(ewbem_ctx* c, const DevGeom& g, int k0, int nk) {
+  const size_t need = (size_t)rhs_split(c->nt) * nk * 3 * (size_t)c->nt;
+  c->d_rhs_part.reserve(need);
+  launch_rhs_multi(g, c->P, c->sigma, 2.0 * M_PI / c->period, k0, nk, c->d_t0.p, c->d_rhs_part.p,
+                   c->stream);
+  c->boff_k0 = k0;
+  c->boff_nk = nk;
+}
+
 void assemble_k(ewbem_ctx* c, int k) {
   ensure_device(c);
   if (k < 0 || k > c->n_f / 2) fail(EWBEM_EINVAL, "frequency index out of range 0..N_f/2");
@@ -694,8 +711,9 @@ void assemble_k(ewbem_ctx* c, int k) {
   c->acc.t_aca_ms += aca_ms;
   build_matvec(c);
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-  launch_rhs(g, c->P, c->d_t0.p, c->d_selfU.p, c->d_phat.p + k, c->d_rhs_part.p, rhs_chunks(c->nt),
-             c->d_b.p, st);
+  if (k < c->boff_k0 || k >= c->boff_k0 + c->boff_nk) rhs_precompute(c, g, k, 1);
+  launch_rhs_finish(c->d_rhs_part.p, c->boff_nk, k - c->boff_k0, c->nt, c->d_selfU.p, c->d_t0.p,
+                    c->d_phat.p + k, c->d_b.p, st);
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   precond_setup(c);
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -1338,6 +1356,17 @@ int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats*
     ensure_device(ctx);
     ctx->hist_n = 0;
     ctx->hist_slot.clear();
+    {
+      // every frequency's off-diagonal U t0 in one batched pass
+      EventPair ev;
+      const auto t0 = Clock::now();
+      EWBEM_HIP_CHECK(hipEventRecord(ev.a, ctx->stream));
+      rhs_precompute(ctx, dev_geom(ctx), 0, ctx->n_f / 2 + 1);
+      EWBEM_HIP_CHECK(hipEventRecord(ev.b, ctx->stream));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+      ctx->acc.t_rhs_ms += ev.elapsed();
+      ctx->acc.t_assemble_ms += ms_since(t0);
+    }
     int rc = EWBEM_OK;
     for (int k = 0; k <= ctx->n_f / 2; ++k) {
       const int r = solve_k(ctx, k, nullptr);

@@ -243,57 +243,140 @@ void launch_dense_self(const cd* selfT, const cd* selfU, const int* perm, int ne
                      ne, Tout, Uout);
 }
 
-// Right-hand side b = P_k * U(s_k) t0 by direct summation over all element
-// pairs (7-point rule) plus the self-element U blocks.  Targets are tiled
-// 256 per workgroup, sources in chunks of RHS_CHUNK elements staged in LDS;
-// each chunk writes its own partial vector, summed in a fixed order by
-// k_rhs_finish (deterministic).
-constexpr int RHS_CHUNK = 128;
+// Right-hand side b_k = P_k U(s_k) t0 by direct summation over all element
+// pairs (7-point rule) plus the self-element U blocks, for up to RHS_NK
+// frequencies per pass.  For the frequencies s_k = sigma + i k dw of one
+// pass the exponentials share their modulus exp(-sigma r / c) and their
+// phases advance by the fixed rotation exp(-i dw r / c), so each extra
+// frequency costs a complex multiply instead of an exp and a sincos.
+// Targets are tiled 256 per workgroup, the sources split into RHS_SPLIT
+// ranges (staged in LDS, RHS_TILE elements at a time); each range writes
+// its own partial vector and k_rhs_finish sums them in a fixed order.
+constexpr int RHS_NK = 8;
+constexpr int RHS_TILE = 128;
 
-__global__ __launch_bounds__(256) void k_rhs_partial(DevGeom g, KParams P, const double* __restrict__ t0,
-                                                     cd* __restrict__ partial) {
-  __shared__ double sq[RHS_CHUNK * 21], sw[RHS_CHUNK * 7], stt[RHS_CHUNK * 3];
-  const int c0 = blockIdx.y * RHS_CHUNK;
-  const int nc = min(RHS_CHUNK, g.ne - c0);
-  for (int i = threadIdx.x; i < nc * 21; i += blockDim.x) sq[i] = g.qp[(size_t)c0 * 21 + i];
-  for (int i = threadIdx.x; i < nc * 7; i += blockDim.x) sw[i] = g.qw[(size_t)c0 * 7 + i];
-  for (int i = threadIdx.x; i < nc * 3; i += blockDim.x) stt[i] = t0[(size_t)c0 * 3 + i];
-  __syncthreads();
+__global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double sigma, double dw, int k0,
+                                                   int nk, const double* __restrict__ t0,
+                                                   cd* __restrict__ partial) {
+  __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[RHS_TILE * 3];
+  const int ne = g.ne;
+  const int kst = k0 + blockIdx.y * RHS_NK;          // first frequency of this pass
+  const int nkc = min(RHS_NK, k0 + nk - kst);        // frequencies in this pass
+  const int split = blockIdx.z, nsplit = gridDim.z;
+  const int s0 = (int)((long long)ne * split / nsplit), s1 = (int)((long long)ne * (split + 1) / nsplit);
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= g.ne) return;
-  const double x[3] = {g.cen[3 * a], g.cen[3 * a + 1], g.cen[3 * a + 2]};
-  cd u[3] = {mk(0.0), mk(0.0), mk(0.0)};
-  for (int b = 0; b < nc; ++b) {
-    if (c0 + b == a) continue;
-#pragma unroll
-    for (int q = 0; q < 7; ++q) acc_Ut(x, sq + 21 * b + 3 * q, sw[7 * b + q], stt + 3 * b, P, u);
+  const bool act = a < ne;
+  double x[3] = {0, 0, 0};
+  if (act) {
+    x[0] = g.cen[3 * a];
+    x[1] = g.cen[3 * a + 1];
+    x[2] = g.cen[3 * a + 2];
   }
-  cd* out = partial + (size_t)blockIdx.y * 3 * g.ne + 3 * a;
-  out[0] = u[0];
-  out[1] = u[1];
-  out[2] = u[2];
+  cd acc[RHS_NK][3];
+#pragma unroll
+  for (int j = 0; j < RHS_NK; ++j) acc[j][0] = acc[j][1] = acc[j][2] = mk(0.0);
+  const double gam = P.gamma, ics = P.inv_cs;
+  for (int c0 = s0; c0 < s1; c0 += RHS_TILE) {
+    const int nc = min(RHS_TILE, s1 - c0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nc * 21; i += blockDim.x) sq[i] = g.qp[(size_t)c0 * 21 + i];
+    for (int i = threadIdx.x; i < nc * 7; i += blockDim.x) sw[i] = g.qw[(size_t)c0 * 7 + i];
+    for (int i = threadIdx.x; i < nc * 3; i += blockDim.x) stt[i] = t0[(size_t)c0 * 3 + i];
+    __syncthreads();
+    if (!act) continue;
+    for (int b = 0; b < nc; ++b) {
+      if (c0 + b == a) continue;
+      const double* tb = stt + 3 * b;
+      for (int qq = 0; qq < 7; ++qq) {
+        const double* y = sq + 21 * b + 3 * qq;
+        const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double ir = 1.0 / r;
+        const double h0 = d0 * ir, h1 = d1 * ir, h2 = d2 * ir;
+        const double ht = h0 * tb[0] + h1 * tb[1] + h2 * tb[2];
+        const double sc = sw[7 * b + qq] * P.inv4pimu * ir;
+        const double zx = sigma * r * ics;      // Re z_s (same for every k)
+        const double th = dw * r * ics;         // Im z_s step per k
+        double sn, cs;
+        const double ms = exp(-zx), mp = exp(-gam * zx);
+        sincos(kst * th, &sn, &cs);
+        cd ph = cd{ms * cs, -ms * sn};
+        sincos(th, &sn, &cs);
+        const cd rot = cd{cs, -sn};
+        sincos(gam * kst * th, &sn, &cs);
+        cd php = cd{mp * cs, -mp * sn};
+        sincos(gam * th, &sn, &cs);
+        const cd rotp = cd{cs, -sn};
+#pragma unroll
+        for (int j = 0; j < RHS_NK; ++j) {
+          if (j < nkc) {
+            const cd z = cd{zx, (kst + j) * th};
+            cd rphi, rpsi;
+            if (norm2(z) < P.series_z2) {
+              cd a1 = mk(P.c_phi[NSER - 1]), b1 = mk(P.c_psi[NSER - 1]);
+              for (int m = NSER - 2; m >= 0; --m) {
+                a1 = a1 * z + P.c_phi[m];
+                b1 = b1 * z + P.c_psi[m];
+              }
+              rphi = a1;
+              rpsi = b1;
+            } else {
+              const cd iz = cinv(z);
+              const cd iz2 = iz * iz;
+              const cd gi = iz * gam;
+              rphi = ph * (1.0 + iz + iz2) - php * (gi + iz2);
+              rpsi = ph * (1.0 + 3.0 * iz + 3.0 * iz2) - php * (P.g2 + 3.0 * gi + 3.0 * iz2);
+            }
+            const cd f = rphi * sc, gg = rpsi * (sc * ht);
+            acc[j][0] += f * tb[0] - gg * h0;
+            acc[j][1] += f * tb[1] - gg * h1;
+            acc[j][2] += f * tb[2] - gg * h2;
+            ph = ph * rot;
+            php = php * rotp;
+          }
+        }
+      }
+    }
+  }
+  if (!act) return;
+#pragma unroll
+  for (int j = 0; j < RHS_NK; ++j) {
+    if (j < nkc) {
+      cd* out = partial + ((size_t)split * nk + (kst - k0 + j)) * 3 * ne + 3 * (size_t)a;
+      out[0] = acc[j][0];
+      out[1] = acc[j][1];
+      out[2] = acc[j][2];
+    }
+  }
 }
 
-__global__ void k_rhs_finish(const cd* __restrict__ partial, int nchunk, int ne, const cd* __restrict__ selfU,
-                             const double* __restrict__ t0, const cd* __restrict__ phat_k,
-                             cd* __restrict__ b) {
+// b[d] = P_k (sum over source ranges of the partials of frequency index kk
+// + U_self t0)
+__global__ void k_rhs_finish(const cd* __restrict__ partial, int nsplit, int nk, int kk, int ne,
+                             const cd* __restrict__ selfU, const double* __restrict__ t0,
+                             const cd* __restrict__ phat_k, cd* __restrict__ b) {
   const int d = blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= 3 * ne) return;
   const int e = d / 3, i = d - 3 * e;
   cd acc = mk(0.0);
-  for (int c = 0; c < nchunk; ++c) acc += partial[(size_t)c * 3 * ne + d];
+  for (int sp = 0; sp < nsplit; ++sp) acc += partial[((size_t)sp * nk + kk) * 3 * ne + d];
   for (int j = 0; j < 3; ++j) acc += selfU[9 * (size_t)e + 3 * i + j] * t0[3 * e + j];
   b[d] = acc * phat_k[0];
 }
 
-int rhs_chunks(int ne) { return (ne + RHS_CHUNK - 1) / RHS_CHUNK; }
+int rhs_split(int ne) { return ne >= 4096 ? 4 : 1; }
 
-void launch_rhs(const DevGeom& g, const KParams& P, const double* t0, const cd* selfU,
-                const cd* phat_k, cd* partial, int nchunk, cd* b, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_partial, dim3((g.ne + 255) / 256, nchunk), dim3(256), 0, st, g, P, t0,
-                     partial);
-  hipLaunchKernelGGL(k_rhs_finish, dim3((3 * g.ne + 255) / 256), dim3(256), 0, st, partial, nchunk,
-                     g.ne, selfU, t0, phat_k, b);
+void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk,
+                      const double* t0, cd* partial, hipStream_t st) {
+  if (nk <= 0) return;
+  dim3 grid((g.ne + 255) / 256, (nk + RHS_NK - 1) / RHS_NK, rhs_split(g.ne));
+  hipLaunchKernelGGL(k_rhs_multi, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, t0, partial);
+}
+
+void launch_rhs_finish(const cd* partial, int nk, int kk, int ne, const cd* selfU, const double* t0,
+                       const cd* phat_k, cd* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_finish, dim3((3 * ne + 255) / 256), dim3(256), 0, st, partial, rhs_split(ne), nk,
+                     kk, ne, selfU, t0, phat_k, b);
 }
 
 // Parity path: the point kernels U_ij(x, y) and T_ij(x, y; n) for n pairs.
