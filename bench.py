@@ -39,6 +39,12 @@ def parse():
                     help="also time the complex64-factor variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--workload", choices=["cavity", "rod-table1"], default="cavity",
+                    help="cavity: the frequency-solve benchmark (default); rod-table1: the "
+                         "three damping / extrapolation cases of the paper's Table 1 on its "
+                         "prismatic rod")
+    ap.add_argument("--rod-div", type=int, default=20,
+                    help="rod mesh: cells per unit length (20 -> 11,200 triangles)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known "
                          "traffic that calibrates the HBM counters)")
@@ -120,6 +126,63 @@ def run_gpu(args, store):
     return d, N, elapsed, tot
 
 
+def rod_table1(args):
+    """Sec. 5.1, Table 1: total GMRES iterations over the first N_w/2 + 1 = 129
+    frequencies of the prismatic rod (3 x 1 x 1, nu = 0, fixed end, step
+    traction at the free end), tol 1e-5, block-diagonal preconditioner, for
+    kappa = 2 without extrapolation, kappa = 4 without, and kappa = 4 with
+    the extrapolation (K = 4).  Lengths in metres scaled so that mu = rho = 1;
+    the paper's T = 0.0155 s is 26.8 L / c, kept in those units."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    from synth import box_mesh, ramp_history
+
+    L = 3.0
+    n = args.rod_div
+    xyz, tri, face = box_mesh((L, 1, 1), (3 * n, n, n), origin=(0, -0.5, -0.5))
+    bc = (face == 0).astype(np.int32)
+    given = np.zeros((len(tri), 3))
+    given[face == 1, 0] = -1.0
+    c_bar = np.sqrt(2.0)                       # E = 2 mu (nu = 0), rho = 1
+    period = 26.79 * L / c_bar
+    n_f = 256
+    hist = ramp_history(n_f, period, 0.0)
+    N = 3 * len(tri)
+    cases = [("kappa=2, no SEM", 2.0, E.GUESS_ZERO, 29237, 16.0),
+             ("kappa=4, no SEM", 4.0, E.GUESS_ZERO, 21758, 14.4),
+             ("kappa=4, SEM K=4", 4.0, E.GUESS_SEM, 17562, 12.1)]
+    out = []
+    dev = torch.device("cuda:0")
+    for name, kappa, guess, paper_its, paper_h in cases:
+        ctx = E.Context(0)
+        ctx.set_mesh(xyz, tri, exterior=False)
+        ctx.set_material(1.0, 1.0, 0.0)
+        ctx.set_time(period, n_f, kappa * np.log(10.0) / period, E.WINDOW_HANN)
+        ctx.set_load_mixed(bc, given, hist)
+        ctx.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5)
+        ctx.set_solver(tol=1e-5, guess=guess, sem_k=4, precond=E.PREC_LEAF, maxit=2000)
+        u = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.solve_transient(u, allow_noconv=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.close()
+        print(f"# {name}: {st['iters_total']} its in {el:.1f} s", file=sys.stderr, flush=True)
+        out.append({"case": name, "kappa": kappa, "sem": guess == E.GUESS_SEM,
+                    "total_iterations": st["iters_total"], "solves": st["n_solves"],
+                    "seconds": el, "resid_max": st["resid_max"],
+                    "paper_total_iterations": paper_its, "paper_hours": paper_h})
+    base = out[0]["total_iterations"]
+    for o in out:
+        o["iterations_vs_case1"] = o["total_iterations"] / base
+    print(json.dumps({"metric": "total GMRES iterations, Table 1 cases (prismatic rod)",
+                      "n_elements": len(tri), "n_dof": N, "n_f": n_f, "gmres_tol": 1e-5,
+                      "precond": "leaf block-diagonal", "operator": "H-matrix, ACA 1e-5",
+                      "paper_context": "pFFT BEM, 12,800 triangles, one Xeon 3.0 GHz (Sec. 5.1)",
+                      "cases": out}), flush=True)
+
+
 def cpu_baseline(args):
     """The oracle (dense assembly + LU) on the host cores, on a bounded sample
     of the same workload: ``cpu_rows`` element rows of T and U at level 5
@@ -167,6 +230,9 @@ def main():
         print(json.dumps({"error": "this build uses one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "rod-table1":
+        rod_table1(args)
+        return
     if args.copy_probe:
         copy_probe()
     d, N, elapsed, st = run_gpu(args, args.store)

@@ -158,6 +158,15 @@ int ewbem_set_load_traction(ewbem_ctx* ctx, const double* t0, const double* hist
  * p > 0 pushes on the solid.  p: host, nt values; history: host, n_f. */
 int ewbem_set_load_pressure(ewbem_ctx* ctx, const double* p, const double* history);
 
+/* Sec. 2.1, eq. Aa_b (mixed boundary conditions): bc (host, nt): 0 = the
+ * element's traction is given, 1 = its displacement is given (fixed: the
+ * given displacement must be zero, else EINVAL).  values (host, nt x 3):
+ * the given traction (bc 0) or zero (bc 1); history (host, n_f samples).
+ * The unknowns, and the outputs of the solve calls, are then the element's
+ * displacement for bc 0 and its traction for bc 1. */
+int ewbem_set_load_mixed(ewbem_ctx* ctx, const int32_t* bc, const double* values,
+                         const double* history);
+
 int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* opts);
 int ewbem_set_solver(ewbem_ctx* ctx, const ewbem_solver_opts* opts);
 

@@ -155,3 +155,19 @@ def traction_from_pressure(geom, p):
     """t = -p n: a cavity pressure p pushes on the solid against n, which
     points out of Omega (Sec. 2.1 defines n as the outward normal)."""
     return (-np.asarray(p, dtype=np.float64)[:, None] * geom["n"]).reshape(-1)
+
+
+def mixed_system(T, U, bc, given):
+    """Sec. 2.1, eq. Aa_b: the boundary conditions move the known boundary
+    values to the right-hand side of T u = U t.  For an element with a given
+    traction (bc = 0) the unknown is its displacement and its columns of T
+    stay in A; for a given displacement (bc = 1) the unknown is its traction
+    and its columns of -U go into A.  ``given`` (N_e x 3) holds the given
+    traction or displacement of each element.  Returns (A, b) with
+    b = sum_trac U t_given - sum_disp T u_given."""
+    bc = np.asarray(bc)
+    dof = np.repeat(bc, 3).astype(bool)          # True: displacement given
+    g = np.asarray(given).reshape(-1)
+    A = np.where(dof[None, :], -U, T)
+    b = U[:, ~dof] @ g[~dof] - T[:, dof] @ g[dof]
+    return A, b

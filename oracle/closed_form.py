@@ -10,6 +10,18 @@ from the compressional potential exp(-s r / c_p) / r with the wall condition
 sigma_rr = -p.  H(0) = a / (4 mu) is Lame's static result.  The transient
 responses follow by residues at the two poles of H.
 
+Prismatic rod with Poisson ratio 0 (Sec. 5.1): length L along x, fixed at
+x = 0, traction p(t) along x on the end x = L, the other faces free.  With
+nu = 0 there is no lateral contraction and the 3-D field is the 1-D bar
+u_tt = c^2 u_xx with c^2 = E / rho = 2 mu / rho, so in the Laplace domain
+
+    u(L, s)      = p(s) (c / (E s)) tanh(s L / c)
+    sigma(0, s)  = p(s) / cosh(s L / c)
+
+and for a unit step the end displacement is a triangle wave rising to
+2 L / E at t = 2 L / c and the stress at the fixed end a square wave
+between 0 and 2, both of period 4 L / c.
+
 Kelvin's static kernels (the s -> 0 limit of U and T) are written out
 independently of the oracle's dynamic kernels.
 """
@@ -82,3 +94,39 @@ def kelvin_T(x, y, n, mat):
              - (1.0 - 2.0 * nu) * (rh[..., :, None] * n[..., None, :]
                                     - n[..., :, None] * rh[..., None, :]))
     return c[..., None, None] * inner
+
+
+def rod_wave_speed(mat):
+    """c = sqrt(E / rho) of the 1-D bar (equals c_p when nu = 0)."""
+    E = 2.0 * mat["mu"] * (1.0 + mat["nu"])
+    return np.sqrt(E / mat["rho"]), E
+
+
+def rod_end_displacement_H(s, L, mat):
+    c, E = rod_wave_speed(mat)
+    s = np.asarray(s, dtype=np.complex128)
+    return (c / (E * s)) * np.tanh(s * L / c)
+
+
+def rod_fixed_stress_H(s, L, mat):
+    c, _ = rod_wave_speed(mat)
+    s = np.asarray(s, dtype=np.complex128)
+    return 1.0 / np.cosh(s * L / c)
+
+
+def rod_step_end_displacement(t, L, mat):
+    """u(L, t) for a unit step traction: triangle wave of period 4L/c."""
+    c, E = rod_wave_speed(mat)
+    t = np.asarray(t, dtype=np.float64)
+    tau = np.mod(t, 4.0 * L / c)
+    tri = np.where(tau <= 2.0 * L / c, tau, 4.0 * L / c - tau)
+    return np.where(t >= 0, c * tri / E, 0.0)
+
+
+def rod_step_fixed_stress(t, L, mat):
+    """sigma_xx(0, t) for a unit step traction: 0 before L/c, then 2 and 0
+    alternating every 2L/c."""
+    c, _ = rod_wave_speed(mat)
+    t = np.asarray(t, dtype=np.float64)
+    tau = np.mod(t - L / c, 4.0 * L / c)
+    return np.where((t >= L / c) & (tau < 2.0 * L / c), 2.0, 0.0)

@@ -24,19 +24,28 @@ def frequency_system(geom, s, mat, t0, self_order=24):
 
 
 def transient(xyz, tri, mat_params, period, n_f, sigma, window_kind,
-              pressure, history, exterior=True, self_order=24, timings=None):
-    """Displacements u(n dt) for n = 0..N_f-1 at every degree of freedom.
+              pressure, history, exterior=True, self_order=24, timings=None,
+              bc=None, given=None):
+    """Boundary unknowns a(n dt) for n = 0..N_f-1 at every degree of freedom:
+    displacements, and for elements with a given displacement (``bc`` = 1)
+    tractions.  The load is the pressure field times the history, or, when
+    ``bc`` is given, the per-element given values (``given``, N_e x 3)
+    times the history.
 
     Returns dict(s, phat, spec (N_f/2+1, N), u (N_f, N))."""
     mat = material(**mat_params)
     geom = bem.geometry(xyz, tri, exterior=exterior)
-    t0 = bem.traction_from_pressure(geom, pressure)
+    t0 = None if bc is not None else bem.traction_from_pressure(geom, pressure)
     s_k = mft.freq_grid(period, n_f, sigma)
     phat = mft.load_spectrum(history, period, sigma)
     spec = np.zeros((len(s_k), 3 * geom["ne"]), np.complex128)
     for k, s in enumerate(s_k):
         t_a = time.perf_counter()
-        A, bu = frequency_system(geom, s, mat, t0, self_order=self_order)
+        if bc is None:
+            A, bu = frequency_system(geom, s, mat, t0, self_order=self_order)
+        else:
+            T, U = bem.assemble_dense(geom, s, mat, self_order=self_order)
+            A, bu = bem.mixed_system(T, U, bc, given)
         t_b = time.perf_counter()
         spec[k] = np.linalg.solve(A, phat[k] * bu)
         t_c = time.perf_counter()

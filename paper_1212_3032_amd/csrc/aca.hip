@@ -1,5 +1,6 @@
 // Adaptive cross approximation of the admissible (far-field) blocks of the
-// traction operator, A_b ~ U V^T, one workgroup per block.
+// system matrix (columns of T, or of -U for elements with a given
+// displacement), A_b ~ U V^T, one workgroup per block.
 //
 // Each step takes the three rows of one row element (a 3 x 3n residual
 // cross row computed from the kernel minus the current approximation), picks
@@ -92,9 +93,15 @@ __device__ __forceinline__ void T_elem_split(const double* x, int e, bool valid,
 #pragma unroll
   for (int i = 0; i < 9; ++i) T[i] = mk(0.0);
   if (valid) {
-    const double* n = g.nrm + 3 * (size_t)e;
-    for (int pt = q; pt < 7; pt += LPE)
-      acc_T<false>(x, g.qp + 21 * (size_t)e + 3 * pt, n, g.qw[7 * (size_t)e + pt], P, T);
+    if (g.bc && g.bc[e]) {
+      // column of an element with a given displacement: -U (Sec. 2.1, eq. Aa_b)
+      for (int pt = q; pt < 7; pt += LPE)
+        acc_U<false>(x, g.qp + 21 * (size_t)e + 3 * pt, -g.qw[7 * (size_t)e + pt], P, T);
+    } else {
+      const double* n = g.nrm + 3 * (size_t)e;
+      for (int pt = q; pt < 7; pt += LPE)
+        acc_T<false>(x, g.qp + 21 * (size_t)e + 3 * pt, n, g.qw[7 * (size_t)e + pt], P, T);
+    }
   }
 #pragma unroll
   for (int off = 1; off < LPE; off <<= 1)

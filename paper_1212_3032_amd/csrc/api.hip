@@ -95,6 +95,7 @@ struct ewbem_ctx {
   double sigma = 0;
   int window = EWBEM_WINDOW_HANN;
   bool load_is_pressure = false;
+  std::vector<int> bc_caller;       // empty: every element has a given traction
   std::vector<double> load_caller;  // t0 (nt*3) or p (nt), caller order
   std::vector<double> history;
   ewbem_op_opts op{};
@@ -114,8 +115,8 @@ struct ewbem_ctx {
 
   // ---- device state
   DevBuf<double> d_cen, d_nrm, d_qp, d_qw, d_vtx, d_t0, d_hist;
-  DevBuf<int> d_perm;
-  DevBuf<cd> d_phat, d_selfT, d_selfU;
+  DevBuf<int> d_perm, d_bc;
+  DevBuf<cd> d_phat, d_selfT, d_selfU, d_selfA;
   DevBuf<NearBlk> d_near;
   DevBuf<long long> d_self_off;
   DevBuf<int> d_self_ld;
@@ -280,6 +281,11 @@ void ensure_device(ewbem_ctx* c) {
   c->d_perm.upload(g.perm, st);
   std::vector<double> t0 = tree_load(c);
   c->d_t0.upload(t0, st);
+  if (!c->bc_caller.empty()) {
+    std::vector<int> bct(c->nt);
+    for (int t = 0; t < c->nt; ++t) bct[t] = c->bc_caller[g.perm[t]];
+    c->d_bc.upload(bct, st);
+  }
   c->d_hist.upload(c->history, st);
   c->d_phat.reserve(c->n_f / 2 + 1);
   launch_load_spectrum(c->d_hist.p, c->n_f, c->period, c->sigma, c->d_phat.p, st);
@@ -290,6 +296,7 @@ void ensure_device(ewbem_ctx* c) {
   const long long N = 3LL * c->nt;
   c->d_selfT.reserve(9 * (size_t)c->nt);
   c->d_selfU.reserve(9 * (size_t)c->nt);
+  c->d_selfA.reserve(9 * (size_t)c->nt);
   c->boff_nk = 0;
   for (DevBuf<cd>* v : {&c->d_b, &c->d_x, &c->d_r, &c->d_w, &c->d_u, &c->d_zt, &c->d_tmp_in, &c->d_tmp_out})
     v->reserve(N);
@@ -322,6 +329,7 @@ DevGeom dev_geom(ewbem_ctx* c) {
   g.qp = c->d_qp.p;
   g.qw = c->d_qw.p;
   g.vtx = c->d_vtx.p;
+  g.bc = c->bc_caller.empty() ? nullptr : c->d_bc.p;
   return g;
 }
 
@@ -633,7 +641,7 @@ void account_matvec(ewbem_ctx* c, EventPair& ev) {
 void precond_setup(ewbem_ctx* c) {
   hipStream_t st = c->stream;
   if (c->so.precond == EWBEM_PREC_ELEMENT) {
-    launch_inv3(c->d_selfT.p, c->nt, c->d_M3.p, st);
+    launch_inv3(c->d_selfA.p, c->nt, c->d_M3.p, st);
   } else if (c->so.precond == EWBEM_PREC_LEAF) {
     // copy each leaf's diagonal near block into a compact work array, invert
     std::vector<long long> src, dst;
@@ -700,9 +708,9 @@ void assemble_k(ewbem_ctx* c, int k) {
   const DevGeom g = dev_geom(c);
   EventPair ev;
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-  launch_self(g, c->P, c->S, c->d_selfT.p, c->d_selfU.p, st);
+  launch_self(g, c->P, c->S, c->d_selfT.p, c->d_selfU.p, c->d_selfA.p, st);
   launch_near(c->d_near.p, (int)c->near_h.size(), g, c->P, c->d_D.p, st);
-  launch_scatter_self(c->d_selfT.p, c->d_self_off.p, c->nt, c->d_D.p, c->d_self_ld.p, st);
+  launch_scatter_self(c->d_selfA.p, c->d_self_off.p, c->nt, c->d_D.p, c->d_self_ld.p, st);
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
   c->acc.t_near_ms += ev.elapsed();
@@ -1145,11 +1153,22 @@ int ewbem_set_time(ewbem_ctx* ctx, double period, int32_t n_f, double sigma, int
   });
 }
 
-static int set_load(ewbem_ctx* ctx, const double* v, size_t nv_, const double* history, bool pressure) {
+static int set_load(ewbem_ctx* ctx, const double* v, size_t nv_, const double* history, bool pressure,
+                    const int32_t* bc = nullptr) {
   return guard(ctx, [&] {
     if (!ctx->have_mesh || !ctx->have_time) fail(EWBEM_ESTATE, "load: set the mesh and time grid first");
     if (!v || !history) fail(EWBEM_EINVAL, "load: null array");
     if (!finite_all(v, nv_) || !finite_all(history, ctx->n_f)) fail(EWBEM_EINVAL, "load: non-finite values");
+    if (bc) {
+      for (int e = 0; e < ctx->nt; ++e) {
+        if (bc[e] != 0 && bc[e] != 1) fail(EWBEM_EINVAL, "load: boundary-condition kind must be 0 or 1");
+        if (bc[e] == 1 && (v[3 * e] != 0.0 || v[3 * e + 1] != 0.0 || v[3 * e + 2] != 0.0))
+          fail(EWBEM_EINVAL, "load: prescribed displacements must be zero");
+      }
+      ctx->bc_caller.assign(bc, bc + ctx->nt);
+    } else {
+      ctx->bc_caller.clear();
+    }
     ctx->load_caller.assign(v, v + nv_);
     ctx->history.assign(history, history + ctx->n_f);
     ctx->load_is_pressure = pressure;
@@ -1168,6 +1187,15 @@ int ewbem_set_load_traction(ewbem_ctx* ctx, const double* t0, const double* hist
 int ewbem_set_load_pressure(ewbem_ctx* ctx, const double* p, const double* history) {
   if (!ctx) return EWBEM_EINVAL;
   return set_load(ctx, p, (size_t)ctx->nt, history, true);
+}
+
+int ewbem_set_load_mixed(ewbem_ctx* ctx, const int32_t* bc, const double* values, const double* history) {
+  if (!ctx) return EWBEM_EINVAL;
+  if (!bc) return guard(ctx, [&] {
+    fail(EWBEM_EINVAL, "load: null boundary-condition array");
+    return EWBEM_OK;
+  });
+  return set_load(ctx, values, 3 * (size_t)ctx->nt, history, false, bc);
 }
 
 int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
@@ -1289,8 +1317,9 @@ int ewbem_assemble_dense(ewbem_ctx* ctx, ewbem_z s, ewbem_z* T, ewbem_z* U) {
     gauss_legendre01(S.nt, S.t, S.wt);
     gauss_legendre01(S.nr, S.u, S.wu);
     KParams P = make_params(ctx->rho, ctx->mu, ctx->nu, cd{s.re, s.im});
-    const DevGeom dg = dev_geom(ctx);
-    launch_self(dg, P, S, ctx->d_selfT.p, ctx->d_selfU.p, st);
+    DevGeom dg = dev_geom(ctx);
+    dg.bc = nullptr;  // the raw T and U
+    launch_self(dg, P, S, ctx->d_selfT.p, ctx->d_selfU.p, nullptr, st);
     launch_dense_pairs(dg, P, ctx->d_perm.p, (cd*)T, (cd*)U, st);
     launch_dense_self(ctx->d_selfT.p, ctx->d_selfU.p, ctx->d_perm.p, ctx->nt, (cd*)T, (cd*)U, st);
     EWBEM_HIP_CHECK(hipGetLastError());

@@ -21,7 +21,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One wavefront per element: lanes cover (edge, angular node) pairs and
 // loop over the radial nodes of the polar rule about the centroid.
 __global__ __launch_bounds__(256) void k_self(DevGeom g, KParams P, SelfRule S, cd* __restrict__ selfT,
-                                              cd* __restrict__ selfU) {
+                                              cd* __restrict__ selfU, cd* __restrict__ selfA) {
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e >= g.ne) return;
@@ -129,25 +129,31 @@ __global__ __launch_bounds__(256) void k_self(DevGeom g, KParams P, SelfRule S, 
         double cpv = P.cpv * (C[i] * n[j] - n[i] * C[j]);
         T[3 * i + j].x += cpv + (i == j ? 0.5 : 0.0);
       }
+    const bool disp = g.bc && g.bc[e];
     for (int i = 0; i < 9; ++i) {
       selfT[9 * (size_t)e + i] = T[i];
       selfU[9 * (size_t)e + i] = U[i];
+      if (selfA) selfA[9 * (size_t)e + i] = disp ? -U[i] : T[i];
     }
   }
 }
 
 void launch_self(const DevGeom& g, const KParams& P, const SelfRule& S, cd* selfT, cd* selfU,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(k_self, dim3((g.ne + 3) / 4), dim3(256), 0, st, g, P, S, selfT, selfU);
+                 cd* selfA, hipStream_t st) {
+  hipLaunchKernelGGL(k_self, dim3((g.ne + 3) / 4), dim3(256), 0, st, g, P, S, selfT, selfU, selfA);
 }
 
-// Dense near-field T blocks: one workgroup per block, the column cluster's
-// quadrature data staged in LDS, one (row element, column element) pair per
-// thread.  The self pair is left to k_scatter_self.
+// Dense near-field blocks of the system matrix A (Sec. 2.1, eq. Aa_b): the
+// columns of an element with a given traction are those of T, of an element
+// with a given displacement those of -U.  One workgroup per block, the
+// column cluster's quadrature data staged in LDS, one (row element, column
+// element) pair per thread.  The self pair is left to k_scatter_self.
 __global__ __launch_bounds__(256) void k_near(const NearBlk* __restrict__ blks, DevGeom g, KParams P,
                                               cd* __restrict__ D) {
   const NearBlk B = blks[blockIdx.x];
   __shared__ double sq[64 * 21], sw[64 * 7], sn[64 * 3], sx[64 * 3];
+  __shared__ int sbc[64];
+  for (int i = threadIdx.x; i < B.n; i += blockDim.x) sbc[i] = g.bc ? g.bc[B.c0 + i] : 0;
   for (int i = threadIdx.x; i < B.n * 21; i += blockDim.x) sq[i] = g.qp[(size_t)B.c0 * 21 + i];
   for (int i = threadIdx.x; i < B.n * 7; i += blockDim.x) sw[i] = g.qw[(size_t)B.c0 * 7 + i];
   for (int i = threadIdx.x; i < B.n * 3; i += blockDim.x) sn[i] = g.nrm[(size_t)B.c0 * 3 + i];
@@ -160,8 +166,13 @@ __global__ __launch_bounds__(256) void k_near(const NearBlk* __restrict__ blks, 
     cd T[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) T[i] = mk(0.0);
+    if (sbc[b]) {
 #pragma unroll
-    for (int q = 0; q < 7; ++q) acc_T<false>(sx + 3 * a, sq + 21 * b + 3 * q, sn + 3 * b, sw[7 * b + q], P, T);
+      for (int q = 0; q < 7; ++q) acc_U<false>(sx + 3 * a, sq + 21 * b + 3 * q, -sw[7 * b + q], P, T);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) acc_T<false>(sx + 3 * a, sq + 21 * b + 3 * q, sn + 3 * b, sw[7 * b + q], P, T);
+    }
     cd* out = D + B.off + (size_t)(3 * b) * ld + 3 * a;
 #pragma unroll
     for (int j = 0; j < 3; ++j)

@@ -72,6 +72,9 @@ struct DevGeom {
   const double* qp;    // [ne][7][3] quadrature points of the 7-point rule
   const double* qw;    // [ne][7] quadrature weights times area
   const double* vtx;   // [ne][3][3] vertices
+  // per element: 0 = traction given (unknown displacement, columns of T),
+  // 1 = displacement given (unknown traction, columns of -U); null = all 0
+  const int* bc;
 };
 
 }  // namespace ewbem

@@ -20,8 +20,11 @@ struct NearBlk {
 };
 
 // ---- assembly
+// selfT, selfU: the self blocks of T (free term and principal value
+// included) and U; selfA (optional): those of the system matrix A (T, or -U
+// for an element with a given displacement).
 void launch_self(const DevGeom& g, const KParams& P, const SelfRule& S, cd* selfT, cd* selfU,
-                 hipStream_t st);
+                 cd* selfA, hipStream_t st);
 void launch_near(const NearBlk* blks, int nblk, const DevGeom& g, const KParams& P, cd* D,
                  hipStream_t st);
 void launch_scatter_self(const cd* selfT, const long long* self_off, int ne, cd* D,

@@ -23,7 +23,8 @@ GUESS_ZERO, GUESS_SEM, GUESS_QUAD = 0, 1, 2
 EXPORTED = [
     "ewbem_default_op_opts", "ewbem_default_solver_opts", "ewbem_create", "ewbem_destroy",
     "ewbem_last_error", "ewbem_set_mesh", "ewbem_set_material", "ewbem_set_time",
-    "ewbem_set_load_traction", "ewbem_set_load_pressure", "ewbem_set_operator",
+    "ewbem_set_load_traction", "ewbem_set_load_pressure", "ewbem_set_load_mixed",
+    "ewbem_set_operator",
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
     "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_mft_inverse",
@@ -92,6 +93,7 @@ def lib():
         "ewbem_set_time": (C.c_int, [P, D, I32, D, I32]),
         "ewbem_set_load_traction": (C.c_int, [P, P, P]),
         "ewbem_set_load_pressure": (C.c_int, [P, P, P]),
+        "ewbem_set_load_mixed": (C.c_int, [P, P, P, P]),
         "ewbem_set_operator": (C.c_int, [P, C.POINTER(OpOpts)]),
         "ewbem_set_solver": (C.c_int, [P, C.POINTER(SolverOpts)]),
         "ewbem_info": (C.c_int, [P, C.POINTER(Info)]),
@@ -221,6 +223,16 @@ class Context:
         if t0.size != 3 * self.nt or h.shape != (self.n_f,):
             raise ValueError("traction must have 3 nt values and history n_f samples")
         self._check(self._L.ewbem_set_load_traction(self.h, pt, ph))
+
+    def set_load_mixed(self, bc, values, history):
+        """bc: 0 = given traction, 1 = given (zero) displacement per element;
+        values: nt x 3 given tractions (zero rows for bc 1)."""
+        bc, pb = _host(bc, np.int32)
+        v, pv = _host(values, np.float64)
+        h, ph = _host(history, np.float64)
+        if bc.shape != (self.nt,) or v.size != 3 * self.nt or h.shape != (self.n_f,):
+            raise ValueError("bc must have nt entries, values 3 nt, history n_f")
+        self._check(self._L.ewbem_set_load_mixed(self.h, pb, pv, ph))
 
     def set_operator(self, **kw):
         o = default_op_opts(**kw)

@@ -6,12 +6,12 @@ the boundary-element arithmetic (no normals, no kernels, no quadrature, no
 transforms); each side of a parity test derives those on its own.
 """
 
-from .mesh import icosphere, ellipsoid, merge_meshes, random_cavity_centres
+from .mesh import icosphere, ellipsoid, merge_meshes, random_cavity_centres, box_mesh
 from .loads import ramp_history, uniform_pressure, sh_pressure, ricker_history
 from .configs import config_inputs, CONFIG_SEED_BASE
 
 __all__ = [
-    "icosphere", "ellipsoid", "merge_meshes", "random_cavity_centres",
+    "icosphere", "ellipsoid", "merge_meshes", "random_cavity_centres", "box_mesh",
     "ramp_history", "uniform_pressure", "sh_pressure", "ricker_history",
     "config_inputs", "CONFIG_SEED_BASE",
 ]

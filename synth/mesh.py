@@ -107,3 +107,47 @@ def random_cavity_centres(rng, count, box, min_dist, max_tries=100000):
         if all(np.linalg.norm(c - o) >= min_dist for o in out):
             out.append(c)
     return np.array(out)
+
+
+def box_mesh(lengths, divisions, origin=(0.0, 0.0, 0.0)):
+    """Surface of the box origin + [0,Lx] x [0,Ly] x [0,Lz], each face cut
+    into a structured grid of squares split into two triangles.
+
+    ``divisions`` = (nx, ny, nz) cells along each axis.  Returns
+    ``(xyz, tri, face)`` with ``face`` in 0..5 = (x=0, x=Lx, y=0, y=Ly, z=0,
+    z=Lz); triangles are counter-clockwise seen from outside the box."""
+    L = np.asarray(lengths, dtype=np.float64)
+    n = [int(v) for v in divisions]
+    o = np.asarray(origin, dtype=np.float64)
+    verts = {}
+    xyz = []
+
+    def vid(p):
+        key = tuple(np.round(p, 12))
+        if key not in verts:
+            verts[key] = len(xyz)
+            xyz.append(p)
+        return verts[key]
+
+    tris, faces = [], []
+    for axis in range(3):
+        u, v = [a for a in range(3) if a != axis]
+        for side in (0, 1):
+            for i in range(n[u]):
+                for j in range(n[v]):
+                    corners = []
+                    for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        p = np.zeros(3)
+                        p[axis] = side * L[axis]
+                        p[u] = (i + di) * L[u] / n[u]
+                        p[v] = (j + dj) * L[v] / n[v]
+                        corners.append(vid(o + p))
+                    a, b, c, d = corners
+                    for t in ((a, b, c), (a, c, d)):
+                        tris.append(t)
+                        faces.append(2 * axis + side)
+    xyz = np.array(xyz)
+    tri = np.array(tris, dtype=np.int64)
+    # orient outward: the right-hand normal must point away from the centre
+    tri = _orient_outward(xyz, tri, o + L / 2.0)
+    return xyz, tri.astype(np.int32), np.array(faces, dtype=np.int32)

@@ -1,0 +1,153 @@
+"""GPU parity for mixed boundary conditions (Sec. 2.1, eq. Aa_b) on the
+prismatic rod of Sec. 5.1 (3 x 1 x 1, Poisson ratio 0, fixed at x = 0, a
+traction along x on x = 3, the other faces free), against the oracle's
+column-swapped dense system, and the rod's 1-D closed form.
+
+Tolerances as in test_gpu_parity: apply and right-hand side 1e-12, solves
+1e-8 (GMRES tol 1e-10), transient 1e-6 (GMRES tol 1e-8), H-matrix solve
+30 x ACA tol.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bem, closed_form as CF, kernels as K, mft, solve as osolve
+from synth import box_mesh, ramp_history
+
+pytestmark = pytest.mark.gpu
+
+L = 3.0
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rod_inputs(div, n_f=32, period=16.0, kappa=4.0):
+    xyz, tri, face = box_mesh((L, 1, 1), div, origin=(0, -0.5, -0.5))
+    bc = (face == 0).astype(np.int32)
+    given = np.zeros((len(tri), 3))
+    given[face == 1, 0] = 1.0
+    return dict(xyz=xyz, tri=tri, face=face, bc=bc, given=given,
+                material=dict(rho=1.0, mu=1.0, nu=0.0), period=period, n_f=n_f,
+                sigma=mft.sigma_from_kappa(kappa, period), window=1,
+                history=ramp_history(n_f, period, 0.0))
+
+
+def _ctx(E, d, op, solver):
+    c = E.Context(0)
+    c.set_mesh(d["xyz"], d["tri"], exterior=False)
+    m = d["material"]
+    c.set_material(m["rho"], m["mu"], m["nu"])
+    c.set_time(d["period"], d["n_f"], d["sigma"], d["window"])
+    c.set_load_mixed(d["bc"], d["given"], d["history"])
+    c.set_operator(**op)
+    c.set_solver(**solver)
+    return c
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0"), E
+
+
+def test_mixed_dense_apply_rhs_solve(env):
+    torch, dev, E = env
+    d = rod_inputs((6, 2, 2))
+    mat = K.material(**d["material"])
+    g = bem.geometry(d["xyz"], d["tri"], exterior=False)
+    N = 3 * g["ne"]
+    c = _ctx(E, d, dict(kind=E.OP_DENSE), dict(tol=1e-10, guess=E.GUESS_ZERO))
+    s_k = mft.freq_grid(d["period"], d["n_f"], d["sigma"])
+    ph = mft.load_spectrum(d["history"], d["period"], d["sigma"])
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    for k in (0, 7, 16):
+        _say(f"rod dense k={k}")
+        T, U = bem.assemble_dense(g, s_k[k], mat)
+        A, b = bem.mixed_system(T, U, d["bc"], d["given"])
+        b = ph[k] * b
+        c.assemble(k)
+        y = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.apply(torch.tensor(x, device=dev), y)
+        assert np.abs(y.cpu().numpy() - A @ x).max() < 1e-12 * np.abs(A @ x).max()
+        bg = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.get_rhs(bg)
+        assert np.abs(bg.cpu().numpy() - b).max() < 1e-12 * np.abs(b).max()
+        a = torch.zeros(N, dtype=torch.complex128, device=dev)
+        st = c.solve_frequency(k, a)
+        ref = np.linalg.solve(A, b)
+        e = np.linalg.norm(a.cpu().numpy() - ref) / np.linalg.norm(ref)
+        _say(f"  its={st['iters_total']} err={e:.2e}")
+        assert e < 1e-8
+    c.close()
+
+
+def test_mixed_transient_matches_oracle(env):
+    torch, dev, E = env
+    d = rod_inputs((6, 2, 2), n_f=16)
+    ref = osolve.transient(d["xyz"], d["tri"], d["material"], d["period"], d["n_f"], d["sigma"],
+                           d["window"], None, d["history"], exterior=False, bc=d["bc"],
+                           given=d["given"])
+    N = 3 * len(d["tri"])
+    c = _ctx(E, d, dict(kind=E.OP_DENSE), dict(tol=1e-8, guess=E.GUESS_SEM, sem_k=4))
+    u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+    _say("rod transient")
+    c.solve_transient(u)
+    e = np.linalg.norm(u.cpu().numpy().reshape(d["n_f"], N) - ref["u"]) / np.linalg.norm(ref["u"])
+    _say(f"  err={e:.2e}")
+    assert e < 1e-6
+    c.close()
+
+
+def test_mixed_hmatrix_against_lu_and_closed_form(env):
+    torch, dev, E = env
+    d = rod_inputs((12, 4, 4))
+    mat = K.material(**d["material"])
+    g = bem.geometry(d["xyz"], d["tri"], exterior=False)
+    N = 3 * g["ne"]
+    c = _ctx(E, d, dict(kind=E.OP_HMAT, leaf_size=32, eta_adm=1.0, aca_tol=1e-6),
+             dict(tol=1e-10, guess=E.GUESS_ZERO))
+    s_k = mft.freq_grid(d["period"], d["n_f"], d["sigma"])
+    ph = mft.load_spectrum(d["history"], d["period"], d["sigma"])
+    for k in (2, 9):
+        _say(f"rod hmatrix k={k}")
+        st = c.assemble(k)
+        T, U = bem.assemble_dense(g, s_k[k], mat)
+        A, b = bem.mixed_system(T, U, d["bc"], d["given"])
+        a = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.solve_frequency(k, a)
+        ag = a.cpu().numpy()
+        ref = np.linalg.solve(A, ph[k] * b)
+        e = np.linalg.norm(ag - ref) / np.linalg.norm(ref)
+        am = ag.reshape(-1, 3) / ph[k]
+        uL = am[d["face"] == 1, 0].mean()
+        sig0 = -am[d["face"] == 0, 0].mean()
+        Hu = CF.rod_end_displacement_H(s_k[k], L, mat)
+        Hs = CF.rod_fixed_stress_H(s_k[k], L, mat)
+        _say(f"  far={st['n_far']} err vs LU={e:.2e} "
+             f"end displacement {abs(uL - Hu) / abs(Hu):.3e} fixed stress {abs(sig0 - Hs) / abs(Hs):.3e}")
+        assert st["n_far"] > 0
+        assert e < 3e-5
+        assert abs(uL - Hu) < 0.03 * abs(Hu) and abs(sig0 - Hs) < 0.08 * abs(Hs)
+    c.close()
+
+
+def test_mixed_rejects_nonzero_prescribed_displacement(env):
+    torch, dev, E = env
+    d = rod_inputs((6, 2, 2))
+    bad = d["given"].copy()
+    bad[d["face"] == 0, 1] = 1e-3
+    c = E.Context(0)
+    c.set_mesh(d["xyz"], d["tri"], exterior=False)
+    c.set_time(d["period"], d["n_f"], d["sigma"])
+    with pytest.raises(E.EwbemError) as e:
+        c.set_load_mixed(d["bc"], bad, d["history"])
+    assert e.value.status == E.EINVAL
+    c.close()
