@@ -77,7 +77,7 @@ typedef struct {
   double eta_adm;     /* admissibility: min(diam) <= eta * dist (default 1.0) */
   double aca_tol;     /* relative ACA stopping tolerance (default 1e-5) */
   int32_t far_store;  /* EWBEM_STORE_C128 or EWBEM_STORE_C64 (default C128) */
-  int32_t self_order; /* polar rule order on the singular element, 4..32 (default 20) */
+  int32_t self_order; /* polar rule order on the singular element, 4..32 (default 24) */
 } ewbem_op_opts;
 
 typedef struct {

@@ -1035,7 +1035,7 @@ void ewbem_default_op_opts(ewbem_op_opts* o) {
   o->eta_adm = 1.0;
   o->aca_tol = 1e-5;
   o->far_store = EWBEM_STORE_C128;
-  o->self_order = 20;
+  o->self_order = 24;
 }
 
 void ewbem_default_solver_opts(ewbem_solver_opts* o) {

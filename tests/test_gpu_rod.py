@@ -3,9 +3,11 @@ prismatic rod of Sec. 5.1 (3 x 1 x 1, Poisson ratio 0, fixed at x = 0, a
 traction along x on x = 3, the other faces free), against the oracle's
 column-swapped dense system, and the rod's 1-D closed form.
 
-Tolerances as in test_gpu_parity: apply and right-hand side 1e-12, solves
-1e-8 (GMRES tol 1e-10), transient 1e-6 (GMRES tol 1e-8), H-matrix solve
-30 x ACA tol.
+Tolerances: apply and right-hand side 1e-12 of the rounding scale
+max(|A| |x|) (the rod's high-frequency sums cancel strongly, so the error is
+measured against the size of the terms summed, as in the usual rounding
+bound for a matrix-vector product), solves 1e-8 (GMRES tol 1e-10),
+transient 1e-6 (GMRES tol 1e-8), H-matrix solve 30 x ACA tol.
 """
 
 import sys
@@ -73,13 +75,14 @@ def test_mixed_dense_apply_rhs_solve(env):
         T, U = bem.assemble_dense(g, s_k[k], mat)
         A, b = bem.mixed_system(T, U, d["bc"], d["given"])
         b = ph[k] * b
+        b_scale = abs(ph[k]) * (np.abs(U) @ np.abs(d["given"].reshape(-1))).max()
         c.assemble(k)
         y = torch.zeros(N, dtype=torch.complex128, device=dev)
         c.apply(torch.tensor(x, device=dev), y)
-        assert np.abs(y.cpu().numpy() - A @ x).max() < 1e-12 * np.abs(A @ x).max()
+        assert np.abs(y.cpu().numpy() - A @ x).max() < 1e-12 * (np.abs(A) @ np.abs(x)).max()
         bg = torch.zeros(N, dtype=torch.complex128, device=dev)
         c.get_rhs(bg)
-        assert np.abs(bg.cpu().numpy() - b).max() < 1e-12 * np.abs(b).max()
+        assert np.abs(bg.cpu().numpy() - b).max() < 1e-12 * b_scale
         a = torch.zeros(N, dtype=torch.complex128, device=dev)
         st = c.solve_frequency(k, a)
         ref = np.linalg.solve(A, b)
