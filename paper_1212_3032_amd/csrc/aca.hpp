@@ -5,29 +5,79 @@
 
 namespace ewbem {
 
-// Largest rank a far block may reach (per class of workgroup size), and the
-// largest number of row elements of one far block.
-constexpr int ACA_KMAX = 384;
-constexpr int ACA_KMAX_SMALL = 96;
+// Largest rank a far block may reach, and the largest number of row
+// elements of one far block.
+constexpr int ACA_KMAX = 1024;
 constexpr int ACA_MAXM = 16384;
-// Blocks with at most this many row and column elements use 64-thread
-// workgroups.
-constexpr int ACA_SMALL = 64;
 
 // Low-rank block A ~ U V^T between row elements [r0, r0+m) and column
 // elements [c0, c0+n) (tree order).  U: 3m x kcap column-major (ld 3m),
-// V: 3n x kcap column-major (ld 3n), complex128 workspace.
+// V: 3n x kcap column-major (ld 3n), complex128 workspace.  bitoff: first
+// 32-bit word of the block's used-row bit set (ceil(m / 32) words).
 struct FarBlk {
   int r0, m, c0, n;
   cd* U;
   cd* V;
   int kcap;
-  int pad;
+  int bitoff;
 };
 
-void launch_aca(const FarBlk* blks, const int* order_small, int n_small, const int* order_big,
-                int n_big, const DevGeom& g, const KParams& P, double tol, int* rank, int* status,
-                hipStream_t st);
+// Per-block state of the lock-step cross approximation.
+constexpr int ACA_ACTIVE = 0, ACA_DONE = 1, ACA_OVERFLOW = 2;
+struct AcaState {
+  int k;          // accepted rank so far
+  int astar;      // current row element
+  int bstar;      // pivot column element of the current step
+  int status;     // ACA_ACTIVE / ACA_DONE / ACA_OVERFLOW
+  int fails;      // consecutive rows found already represented
+  int nacc;       // terms accepted in the current step
+  int skip;       // the current step adds no terms
+  int pad;
+  double normS2;  // estimate of |S|_F^2 of the approximation so far
+  double first_max;               // largest entry of the first residual row
+  unsigned long long best;        // packed (score, column element): pivot search
+  unsigned long long best_row;    // packed (score, row element): next-row search
+};
+// Weights of the current step's terms on the 3 cross columns / rows.
+struct AcaPlan {
+  cd alpha[3][3];
+  cd beta[3][3];
+};
+// Row elements per wavefront in the column residual kernel (63 rows, so an
+// element's three rows never straddle two wavefronts).
+constexpr int ACA_ROWS_PER_WAVE = 21;
+
+// Initialise the state and used-row bits of blocks ids[0..n).
+void launch_aca_init(const int* ids, int n, const FarBlk* blks, AcaState* st, unsigned* used,
+                     hipStream_t s);
+// Exclusive scans over the *nact_dev active blocks in act, into offs (four
+// arrays of nact + 1 entries, stride apart): element counts n and m,
+// 64-column wavefront tasks ceil(3n / 64) and row wavefront tasks
+// ceil(m / ACA_ROWS_PER_WAVE).  totals = {the four sums, nact}.
+void launch_aca_scan(const int* act, const int* nact_dev, const FarBlk* blks, int* offs, int stride,
+                     int* totals, hipStream_t s);
+struct AcaLists {
+  const int* act;
+  int nact;
+  int tot_n, tot_m, tot_wn, tot_wm;
+  const int *offs_n, *offs_m, *offs_wn, *offs_wm;
+};
+// Device work areas of the lock-step approximation: part_v holds 3 doubles
+// per 64-column task (tot_wn), part_u 3 per 21-row-element task (tot_wm).
+struct AcaWork {
+  const FarBlk* blks;
+  AcaState* st;
+  AcaPlan* plan;
+  unsigned* used;
+  double* part_u;
+  double* part_v;
+};
+// One lock-step iteration of every active block; blocks still active are
+// appended to act_out, counted by *count (zeroed by the caller).
+void launch_aca_step(const AcaLists& L, const AcaWork& W, const DevGeom& g, const KParams& P, double tol,
+                     int* act_out, int* count, hipStream_t s);
+// rank[b] = k, status[b] = 1 for blocks that ran out of capacity, else 0.
+void launch_aca_finish(const int* ids, int n, const AcaState* st, int* rank, int* status, hipStream_t s);
 void launch_to_c64(const FarBlk* blks, int nblk, const int* rank, const long long* uo,
                    const long long* vo, cf* out, hipStream_t st);
 

@@ -129,7 +129,13 @@ struct ewbem_ctx {
   std::vector<std::unique_ptr<DevBuf<cd>>> d_retry;
   DevBuf<cf> d_f32;
   DevBuf<long long> d_uo, d_vo;
-  DevBuf<int> d_rank, d_status, d_ord_small, d_ord_big;
+  DevBuf<int> d_rank, d_status;
+  // lock-step ACA: per-block state, used-row bits, active lists and scans
+  DevBuf<AcaState> d_acast;
+  DevBuf<AcaPlan> d_acaplan;
+  DevBuf<double> d_aca_part;
+  DevBuf<unsigned> d_used;
+  DevBuf<int> d_aca_ids, d_act, d_act2, d_offs, d_tot;
   DevBuf<VtTask> d_vt;
   DevBuf<Seg> d_seg;
   DevBuf<RowTask> d_rt;
@@ -336,30 +342,78 @@ DevGeom dev_geom(ewbem_ctx* c) {
 cd s_of_k(ewbem_ctx* c, int k) { return cd{c->sigma, 2.0 * M_PI * k / c->period}; }
 
 // ---- ACA with capacity retries, then matvec task lists
+
+// Lock-step cross approximation of the far blocks ids (their FarBlk
+// entries already on the device).  One host round trip per step: the scan
+// of the active list tells the grid sizes of the step's launches.
+void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids) {
+  hipStream_t st = c->stream;
+  const int n = (int)ids.size();
+  if (n == 0) return;
+  c->d_aca_ids.upload(ids, st);
+  c->d_act.reserve(n);
+  c->d_act2.reserve(n);
+  const int stride = n + 1;
+  c->d_offs.reserve(4 * (size_t)stride);
+  c->d_tot.reserve(6);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_act.p, c->d_aca_ids.p, n * sizeof(int), hipMemcpyDeviceToDevice, st));
+  launch_aca_init(c->d_aca_ids.p, n, c->d_far.p, c->d_acast.p, c->d_used.p, st);
+  int* count = c->d_tot.p + 5;
+  EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, n, 1, st));
+  int* act = c->d_act.p;
+  int* nxt = c->d_act2.p;
+  // every step either adds at least one term or counts a failed row (at
+  // most four in a row), so the number of steps is bounded
+  const int max_steps = 5 * ACA_KMAX + 16;
+  int tot[5] = {0, 0, 0, 0, 0};
+  for (int it = 0;; ++it) {
+    launch_aca_scan(act, count, c->d_far.p, c->d_offs.p, stride, c->d_tot.p, st);
+    EWBEM_HIP_CHECK(hipMemcpyAsync(tot, c->d_tot.p, 5 * sizeof(int), hipMemcpyDeviceToHost, st));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    const int nact = tot[4];
+    if (nact == 0) break;
+    if (nact < 0 || nact > n || it > max_steps) fail(EWBEM_EINVAL, "internal: ACA active list out of range");
+    EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, 0, 1, st));
+    // the first step has the most active blocks, so the largest task counts
+    if (it == 0) {
+      c->d_aca_part.reserve(3 * ((size_t)tot[2] + (size_t)tot[3]));
+      c->d_acaplan.reserve(c->far_h.size());
+    }
+    if ((size_t)3 * ((size_t)tot[2] + (size_t)tot[3]) > c->d_aca_part.n)
+      fail(EWBEM_EINVAL, "internal: ACA task count grew");
+    AcaLists L{act, nact, tot[0], tot[1], tot[2], tot[3], c->d_offs.p, c->d_offs.p + stride,
+               c->d_offs.p + 2 * stride, c->d_offs.p + 3 * stride};
+    AcaWork W{c->d_far.p, c->d_acast.p, c->d_acaplan.p, c->d_used.p, c->d_aca_part.p,
+              c->d_aca_part.p + 3 * (size_t)tot[3]};
+    launch_aca_step(L, W, g, c->P, c->op.aca_tol, nxt, count, st);
+    std::swap(act, nxt);
+  }
+  launch_aca_finish(c->d_aca_ids.p, n, c->d_acast.p, c->d_rank.p, c->d_status.p, st);
+}
+
 void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
   hipStream_t st = c->stream;
   const int nf = (int)c->far_h.size();
   if (nf == 0) return;
+  // Capacity: 30% above the previous frequency's rank (ranks grow with
+  // frequency), else a size-based first guess; retries are the exception.
+  // 3 min(m, n) + 2 columns always suffice: a block stops at full rank, and
+  // a step adds at most three terms.
   std::vector<int> kcap(nf);
   for (int b = 0; b < nf; ++b) {
     const FarBlk& f = c->far_h[b];
-    const int full = 3 * std::min(f.m, f.n);
-    const bool small = f.m <= ACA_SMALL && f.n <= ACA_SMALL;
-    const int kmax = small ? ACA_KMAX_SMALL : ACA_KMAX;
-    // capacity: 30% above the previous frequency's rank (ranks grow with
-    // frequency), else a size-based first guess; retries are the exception
+    const int full = 3 * std::min(f.m, f.n) + 2;
     int want = c->kcap_prev[b] > 0 ? c->rank_h[b] + std::max(12, (3 * c->rank_h[b]) / 10)
                                    : 24 + (f.m + f.n) / 8;
     want = ((want + 2) / 3) * 3;
-    kcap[b] = std::max(3, std::min({want, full, kmax}));
+    kcap[b] = std::max(3, std::min({want, full, ACA_KMAX}));
   }
   // main layout (the previous frequency's retry buffers are no longer used)
   c->d_retry.clear();
-  long long total = 0;
+  long long total = 0, words = 0;
   for (int b = 0; b < nf; ++b) total += (long long)(3 * c->far_h[b].m + 3 * c->far_h[b].n) * kcap[b];
   c->d_ws.reserve(total);
   long long off = 0;
-  std::vector<int> small_ids, big_ids;
   for (int b = 0; b < nf; ++b) {
     FarBlk& f = c->far_h[b];
     f.kcap = kcap[b];
@@ -367,24 +421,19 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     off += 3LL * f.m * kcap[b];
     f.V = c->d_ws.p + off;
     off += 3LL * f.n * kcap[b];
-    const bool small = f.m <= ACA_SMALL && f.n <= ACA_SMALL && kcap[b] <= ACA_KMAX_SMALL;
-    (small ? small_ids : big_ids).push_back(b);
+    if (words > INT32_MAX - 1024) fail(EWBEM_EINVAL, "too many far blocks");
+    f.bitoff = (int)words;
+    words += (f.m + 31) / 32;
   }
+  c->d_used.reserve(words);
+  c->d_acast.reserve(nf);
   c->d_far.upload(c->far_h, st);
-  // largest expected work first (better load balance at the end of the launch)
-  std::stable_sort(big_ids.begin(), big_ids.end(), [&](int a, int b) {
-    const FarBlk& fa = c->far_h[a];
-    const FarBlk& fb = c->far_h[b];
-    return (long long)(fa.m + fa.n) * kcap[a] > (long long)(fb.m + fb.n) * kcap[b];
-  });
-  std::vector<int> ord(small_ids);
-  ord.insert(ord.end(), big_ids.begin(), big_ids.end());
-  c->d_ord_small.upload(ord, st);
   c->d_rank.reserve(nf);
   c->d_status.reserve(nf);
+  std::vector<int> all(nf);
+  for (int b = 0; b < nf; ++b) all[b] = b;
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-  launch_aca(c->d_far.p, c->d_ord_small.p, (int)small_ids.size(), c->d_ord_small.p + small_ids.size(),
-             (int)big_ids.size(), g, c->P, c->op.aca_tol, c->d_rank.p, c->d_status.p, st);
+  aca_lockstep(c, g, all);
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -399,9 +448,9 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     long long tot2 = 0;
     for (int b : over) {
       FarBlk& f = c->far_h[b];
-      const int full = 3 * std::min(f.m, f.n);
+      const int full = 3 * std::min(f.m, f.n) + 2;
       if (f.kcap >= std::min(full, ACA_KMAX))
-        fail(EWBEM_EINVAL, "ACA rank exceeds the per-block limit of 384");
+        fail(EWBEM_EINVAL, "ACA rank exceeds the per-block limit of 1024");
       f.kcap = std::min({full, ACA_KMAX, 2 * f.kcap + 6});
       tot2 += (long long)(3 * f.m + 3 * f.n) * f.kcap;
     }
@@ -417,10 +466,8 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
       o2 += 3LL * f.n * f.kcap;
     }
     c->d_far.upload(c->far_h, st);
-    c->d_ord_big.upload(over, st);
     EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-    launch_aca(c->d_far.p, nullptr, 0, c->d_ord_big.p, (int)over.size(), g, c->P, c->op.aca_tol,
-               c->d_rank.p, c->d_status.p, st);
+    aca_lockstep(c, g, over);
     EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
