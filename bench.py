@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--c64-variant", action="store_true",
                     help="also time the complex64-factor variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--aca-reuse", type=int, choices=[0, 1], default=None,
+                    help="start each frequency's ACA from the previous pivots (library default if unset)")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--workload", choices=["cavity", "rod-table1"], default="cavity",
                     help="cavity: the frequency-solve benchmark (default); rod-table1: the "
@@ -93,7 +95,8 @@ def run_gpu(args, store):
     E.setup_from_inputs(
         ctx, d,
         op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5,
-                far_store=E.STORE_C64 if store == "c64" else E.STORE_C128),
+                far_store=E.STORE_C64 if store == "c64" else E.STORE_C128,
+                **({} if args.aca_reuse is None else {"aca_reuse": args.aca_reuse})),
         solver=dict(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF))
     N = 3 * len(d["tri"])
     n_f = d["n_f"]
@@ -271,6 +274,8 @@ def main():
             "freq_solves_per_step": solves // args.steps, "sigma": d["sigma"], "period": d["period"],
             "leaf": 64, "eta_adm": 1.0, "aca_tol": 1e-5, "gmres_tol": 1e-6, "guess": "LS-SEM K=3",
             "precond": "leaf block-diagonal", "far_store": args.store, "arith": "complex128",
+            "aca_starts_per_step": {"warm": st["aca_warm_blocks"] // args.steps,
+                                    "cold": st["aca_cold_blocks"] // args.steps},
         },
         "roofline": {
             "kernel": "H-matrix matvec (k_far_vt + k_hmv + k_hmv_reduce)",

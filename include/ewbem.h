@@ -78,6 +78,11 @@ typedef struct {
   double aca_tol;     /* relative ACA stopping tolerance (default 1e-5) */
   int32_t far_store;  /* EWBEM_STORE_C128 or EWBEM_STORE_C64 (default C128) */
   int32_t self_order; /* polar rule order on the singular element, 4..32 (default 24) */
+  int32_t aca_reuse;  /* 1: start each far block's ACA from the rows and columns that gave
+                         its pivots at the previously assembled frequency, then continue
+                         with ordinary steps until the stopping test holds; 0: from scratch
+                         every time (default 1) */
+  int32_t pad;
 } ewbem_op_opts;
 
 typedef struct {
@@ -111,6 +116,9 @@ typedef struct {
   double matvec_bytes_total; /* algorithmic bytes summed over every timed matvec */
   int32_t matvecs_timed;   /* matvecs included in t_matvec_ms */
   int32_t pad0;
+  int64_t aca_warm_blocks; /* far blocks whose ACA started from previous pivots */
+  int64_t aca_cold_blocks; /* far blocks whose ACA started from scratch (capacity
+                              retries, always from scratch, are not counted again) */
 } ewbem_stats;
 
 typedef struct {

@@ -104,7 +104,7 @@ __device__ __forceinline__ int first_unused(const unsigned* __restrict__ used, i
 }
 
 __global__ void k_aca_init(const int* __restrict__ ids, int n, const FarBlk* __restrict__ blks,
-                           AcaState* __restrict__ st, unsigned* __restrict__ used) {
+                           AcaState* __restrict__ st, unsigned* __restrict__ used, int* __restrict__ nlist) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int b = ids[i];
@@ -114,6 +114,8 @@ __global__ void k_aca_init(const int* __restrict__ ids, int n, const FarBlk* __r
   st[b] = s;
   const FarBlk B = blks[b];
   for (int w = 0; w < (B.m + 31) / 32; ++w) used[B.bitoff + w] = 0u;
+  nlist[2 * b] = 0;
+  nlist[2 * b + 1] = 0;
 }
 
 // Exclusive scans over the active list (one workgroup) of the element
@@ -574,7 +576,8 @@ __global__ __launch_bounds__(256) void k_aca_finalize(const int* __restrict__ ac
                                                       const int* __restrict__ offs_wv,
                                                       const FarBlk* __restrict__ blks, AcaState* __restrict__ st,
                                                       const double* __restrict__ part_u,
-                                                      const double* __restrict__ part_v, double tol) {
+                                                      const double* __restrict__ part_v, double tol,
+                                                      int* __restrict__ plist, int* __restrict__ nlist) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= nact) return;
@@ -595,6 +598,18 @@ __global__ __launch_bounds__(256) void k_aca_finalize(const int* __restrict__ ac
     s.normS2 += termsq;
     s.k += s.nacc;
     s.fails = 0;
+    // this step's pivot elements, for a warm start at the next frequency
+    if (lane == 0) {
+      const int nr = nlist[2 * blk], nc = nlist[2 * blk + 1];
+      if (nr >= 0 && nr < B.m && nc < B.m) {
+        plist[B.poff + nr] = s.astar;
+        plist[B.poff + B.m + nc] = s.bstar;
+        nlist[2 * blk] = nr + 1;
+        nlist[2 * blk + 1] = nc + 1;
+      } else {
+        nlist[2 * blk] = -1;
+      }
+    }
     if (termsq <= tol * tol * s.normS2 || s.k >= 3 * min(B.m, B.n) || s.best_row == 0ull)
       s.status = ACA_DONE;  // converged, full rank, or every row used (exact)
     else if (s.k + 3 > B.kcap)
@@ -624,8 +639,13 @@ __global__ void k_aca_finish(const int* __restrict__ ids, int n, const AcaState*
   status[b] = st[b].status == ACA_OVERFLOW ? 1 : 0;
 }
 
-void launch_aca_init(const int* ids, int n, const FarBlk* blks, AcaState* st, unsigned* used, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_aca_init, dim3((n + 255) / 256), dim3(256), 0, s, ids, n, blks, st, used);
+void launch_aca_init(const int* ids, int n, const FarBlk* blks, AcaState* st, unsigned* used, int* nlist,
+                     hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_aca_init, dim3((n + 255) / 256), dim3(256), 0, s, ids, n, blks, st, used, nlist);
+}
+
+void launch_aca_compact(const int* ids, int n, const AcaState* st, int* act_out, int* count, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_aca_compact, dim3((n + 255) / 256), dim3(256), 0, s, ids, n, st, act_out, count);
 }
 
 void launch_aca_scan(const int* act, const int* nact_dev, const FarBlk* blks, int* offs, int stride,
@@ -649,7 +669,7 @@ void launch_aca_step(const AcaLists& L, const AcaWork& W, const DevGeom& g, cons
   hipLaunchKernelGGL(k_aca_form_v, dim3(L.tot_wn), dim3(64), 0, s, L.act, nact, L.offs_wn, W.blks, W.st, W.plan,
                      W.part_v);
   hipLaunchKernelGGL(k_aca_finalize, dim3((nact + 3) / 4), dim3(256), 0, s, L.act, nact, L.offs_wm, L.offs_wn,
-                     W.blks, W.st, W.part_u, W.part_v, tol);
+                     W.blks, W.st, W.part_u, W.part_v, tol, W.plist, W.nlist);
   hipLaunchKernelGGL(k_aca_compact, dim3((nact + 255) / 256), dim3(256), 0, s, L.act, nact, W.st, act_out, count);
 }
 

@@ -20,6 +20,8 @@ struct FarBlk {
   cd* V;
   int kcap;
   int bitoff;
+  int poff;  // pivot-element lists: rows at plist[poff..poff+m), columns at plist[poff+m..poff+2m)
+  int pad;
 };
 
 // Per-block state of the lock-step cross approximation.
@@ -47,9 +49,12 @@ struct AcaPlan {
 // element's three rows never straddle two wavefronts).
 constexpr int ACA_ROWS_PER_WAVE = 21;
 
-// Initialise the state and used-row bits of blocks ids[0..n).
-void launch_aca_init(const int* ids, int n, const FarBlk* blks, AcaState* st, unsigned* used,
+// Initialise the state, used-row bits and pivot lists of blocks ids[0..n).
+void launch_aca_init(const int* ids, int n, const FarBlk* blks, AcaState* st, unsigned* used, int* nlist,
                      hipStream_t s);
+// Active list act_out (count in *count, zeroed by the caller) of the blocks
+// ids[0..n) whose state is ACA_ACTIVE.
+void launch_aca_compact(const int* ids, int n, const AcaState* st, int* act_out, int* count, hipStream_t s);
 // Exclusive scans over the *nact_dev active blocks in act, into offs (four
 // arrays of nact + 1 entries, stride apart): element counts n and m,
 // 64-column wavefront tasks ceil(3n / 64) and row wavefront tasks
@@ -71,6 +76,8 @@ struct AcaWork {
   unsigned* used;
   double* part_u;
   double* part_v;
+  int* plist;  // pivot row / column elements of each block's accepted steps
+  int* nlist;  // per block: number of listed rows, columns (-1 rows: lists unusable)
 };
 // One lock-step iteration of every active block; blocks still active are
 // appended to act_out, counted by *count (zeroed by the caller).
@@ -80,6 +87,48 @@ void launch_aca_step(const AcaLists& L, const AcaWork& W, const DevGeom& g, cons
 void launch_aca_finish(const int* ids, int n, const AcaState* st, int* rank, int* status, hipStream_t s);
 void launch_to_c64(const FarBlk* blks, int nblk, const int* rank, const long long* uo,
                    const long long* vo, cf* out, hipStream_t st);
+
+// ---- Warm start from the previous frequency's pivots.
+// A block whose previous approximation accepted pivots in row elements
+// rows[0..nr) and column elements cols[0..nc) starts from the cross
+// approximation A(:, J) A(I, J)^+ A(I, :) on the rows I and columns J of
+// those elements, evaluated at the new frequency, and continues with the
+// ordinary steps until the stopping test holds.
+constexpr int WS_MAXLIST = 256;  // longest pivot list used for a warm start
+struct WsBlk {
+  int blk;          // far block
+  int nr, nc;       // listed row / column elements
+  int rcap;         // 3 min(nr, nc): largest rank of the cross
+  long long rr;     // Rr: 3n x 3nr column-major (column = cross row), offset in cross
+  long long cc;     // Cc: 3m x 3nc column-major (column = cross column)
+  long long w;      // W = A(I, J): 3nr x 3nc column-major, factored in place
+  int pq;           // pivot order: p[rcap] (cross rows), q[rcap] (cross columns)
+  int tu, tv;       // first U-forming task (21-row-element tiles), V-forming task (64 columns)
+  int pad;
+  long long pu, pv; // norm partials: (tasks of the block) x rcap doubles each
+  long long co;     // substitution coefficients: Mc, Nc ((rcap + 8) x rcap each), Dn (rcap + 8)
+};
+struct WsArgs {
+  const WsBlk* wb;
+  int nwarm;
+  const int* er_off;  // nwarm + 1: flattened (row element of the list, column element) offsets
+  const int* ec_off;  // nwarm + 1: flattened (column element of the list, row element) offsets
+  const int* tu_off;  // nwarm + 1: U-forming task offsets
+  const int* tv_off;  // nwarm + 1: V-forming task offsets
+  int tot_er, tot_ec, tot_tu, tot_tv;
+  cd* cross;
+  int* pq;
+  int* rho;
+  double* part;
+  cd* coef;
+  const int* lu_list;  // warm blocks by size class of W (n_lu[0..3] entries)
+  int n_lu[4];
+};
+constexpr int WS_LDS_SMALL = 2304;  // entries of W held in LDS by the three LDS classes
+constexpr int WS_LDS_MID = 4480;
+constexpr int WS_LDS_LARGE = 8960;
+constexpr int WS_LU_NR_LDS = 2;     // LDS classes hold cores of at most 128 rows
+void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s);
 
 // ---- H-matrix matvec
 // Phase 1 task: z[zidx + j] = sum_c V[c, j] x[x0 + c] for j < ncol, with V

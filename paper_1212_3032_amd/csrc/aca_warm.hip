@@ -1,0 +1,600 @@
+// Warm start of the cross approximation from the previous frequency's pivots.
+//
+// At consecutive frequencies the kernel of a far block changes smoothly, so
+// the rows and columns that made a good cross at s_{k-1} make a good cross
+// at s_k.  For a block whose previous approximation accepted pivots in row
+// elements I_e and column elements J_e (rows I = 3 I_e + {0,1,2}, columns
+// J likewise):
+//   k_ws_init       state, used-row bits (every listed row is used);
+//   k_ws_eval_rows  A(I, :) into Rr, one thread per (listed row element,
+//                   column element);
+//   k_ws_eval_cols  A(:, J) into Cc, one thread per (listed column element,
+//                   row element);
+//   k_ws_lu*        one workgroup per block: W = A(I, J), Gaussian
+//                   elimination with complete pivoting, stopping at pivots
+//                   below 1e-10 of the first (the same rule as a step of the
+//                   cold approximation); the pivot order (p_t, q_t) and the
+//                   eliminated W;
+//                   It also writes the coefficients of the substitutions;
+//   k_ws_form_u     u_t = residual of column q_t: the forward substitution
+//                   Cc(:, q) = U M with M unit upper triangular,
+//                   M[l][t] = W[p_l][q_t] / W[p_l][q_l]; column norms, and
+//                   the next row element (largest entry of the last term
+//                   among unused rows);
+//   k_ws_form_v     v_t = residual of row p_t over its pivot: the forward
+//                   substitution Rr(p, :) = N V^T with N[t][l] = W[p_t][q_l]
+//                   (l <= t);
+//   k_ws_finish     the terms up to the first that meets the stopping test,
+//                   the norm estimate sum_t |u_t|^2 |v_t|^2, the lists cut to
+//                   the kept pivots' elements, and the next row, so the
+//                   ordinary steps continue from there.
+// The terms are those the cold steps would form with the same pivots in the
+// same order; the approximation equals A(:, Jp) A(Ip, Jp)^{-1} A(Ip, :) on
+// the accepted pivots.  The ordinary steps that follow keep the usual
+// stopping test, so the warm start changes the cost, not the tolerance.
+#include "kernel_fn.hpp"
+#include "launch.hpp"
+#include "aca.hpp"
+
+namespace ewbem {
+
+namespace {
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void A_elem(const double* x, int e, const DevGeom& g, const KParams& P, cd* T) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) T[i] = mk(0.0);
+  if (g.bc && g.bc[e]) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) acc_U<false>(x, g.qp + 21 * (size_t)e + 3 * q, -g.qw[7 * (size_t)e + q], P, T);
+  } else {
+    const double* n = g.nrm + 3 * (size_t)e;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) acc_T<false>(x, g.qp + 21 * (size_t)e + 3 * q, n, g.qw[7 * (size_t)e + q], P, T);
+  }
+}
+
+__device__ __forceinline__ int find_seg(const int* __restrict__ offs, int n, int t) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ unsigned long long pack_best(double score, int idx) {
+  const float f = (float)score;
+  return ((unsigned long long)__float_as_uint(f) << 32) | (unsigned)(0x7fffffff - idx);
+}
+
+// acc -= x * m as four fused multiply-adds
+__device__ __forceinline__ void cms(cd& acc, cd x, cd m) {
+  acc.x = fma(-x.x, m.x, acc.x);
+  acc.x = fma(x.y, m.y, acc.x);
+  acc.y = fma(-x.x, m.y, acc.y);
+  acc.y = fma(-x.y, m.x, acc.y);
+}
+
+// LDS written by some lanes of a wavefront, then read by others: the
+// wavefront's LDS operations complete in order; this keeps the compiler
+// from moving them across the point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace
+
+__global__ void k_ws_init(const WsBlk* __restrict__ wb, int nwarm, const FarBlk* __restrict__ blks,
+                          AcaState* __restrict__ st, unsigned* __restrict__ used, const int* __restrict__ plist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nwarm) return;
+  const WsBlk w = wb[i];
+  const FarBlk B = blks[w.blk];
+  AcaState s{};
+  s.status = ACA_ACTIVE;
+  s.first_max = -1.0;
+  st[w.blk] = s;
+  unsigned* u = used + B.bitoff;
+  for (int q = 0; q < (B.m + 31) / 32; ++q) u[q] = 0u;
+  for (int q = 0; q < w.nr; ++q) {
+    const int a = plist[B.poff + q];
+    u[a >> 5] |= 1u << (a & 31);
+  }
+}
+
+// Rr[(3s + j), 3b + jj] = A(3 a_s + j, 3b + jj): thread per (block, s, b).
+__global__ __launch_bounds__(256) void k_ws_eval_rows(const WsBlk* __restrict__ wb, int nwarm,
+                                                      const int* __restrict__ off, const FarBlk* __restrict__ blks,
+                                                      const int* __restrict__ plist, cd* __restrict__ cross, DevGeom g,
+                                                      KParams P) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= off[nwarm]) return;
+  const int i = find_seg(off, nwarm, t);
+  const WsBlk w = wb[i];
+  const FarBlk B = blks[w.blk];
+  const int loc = t - off[i];
+  const int sidx = loc / B.n, b = loc - sidx * B.n;
+  const int a = plist[B.poff + sidx];
+  const size_t N3 = 3 * (size_t)B.n;
+  const double* xa = g.cen + 3 * (size_t)(B.r0 + a);
+  const double x[3] = {xa[0], xa[1], xa[2]};
+  cd T[9];
+  A_elem(x, B.c0 + b, g, P, T);
+  cd* Rr = cross + w.rr;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) Rr[(3 * (size_t)sidx + j) * N3 + 3 * b + jj] = T[3 * j + jj];
+}
+
+// Cc[3a + ii, (3s + jj)] = A(3a + ii, 3 b_s + jj): thread per (block, s, a).
+__global__ __launch_bounds__(256) void k_ws_eval_cols(const WsBlk* __restrict__ wb, int nwarm,
+                                                      const int* __restrict__ off, const FarBlk* __restrict__ blks,
+                                                      const int* __restrict__ plist, cd* __restrict__ cross, DevGeom g,
+                                                      KParams P) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= off[nwarm]) return;
+  const int i = find_seg(off, nwarm, t);
+  const WsBlk w = wb[i];
+  const FarBlk B = blks[w.blk];
+  const int loc = t - off[i];
+  const int sidx = loc / B.m, a = loc - sidx * B.m;
+  const int b = plist[B.poff + B.m + sidx];
+  const size_t M3 = 3 * (size_t)B.m;
+  const double* xa = g.cen + 3 * (size_t)(B.r0 + a);
+  const double x[3] = {xa[0], xa[1], xa[2]};
+  cd T[9];
+  A_elem(x, B.c0 + b, g, P, T);
+  cd* Cc = cross + w.cc;
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) Cc[(3 * (size_t)sidx + jj) * M3 + 3 * a + ii] = T[3 * ii + jj];
+}
+
+constexpr int WS_CH = 8;  // terms solved together in registers
+
+// Wavefront argmax of (value, linear index), ties to the smaller index.
+__device__ __forceinline__ void wave_argmax(double& v, int& e) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oe = __shfl_xor(e, off, 64);
+    if (ov > v || (ov == v && oe < e)) {
+      v = ov;
+      e = oe;
+    }
+  }
+}
+
+// Elimination of W with complete pivoting: one workgroup of WS_LU_NW
+// wavefronts per block.  Lanes own rows (row i = lane + 64 r; the alive rows
+// and the pivot column's entries of a lane's rows are in registers); the
+// wavefronts split the list of alive columns, which is double-buffered so
+// that each pivot costs one barrier.  W is in LDS when it has at most MAXE
+// entries; MAXE = 0 works on the copy of W in global memory (large cores).
+// NR: row chunks of 64 a lane covers (R3 <= 64 NR).
+constexpr int WS_LU_NW = 8;  // wavefronts per elimination workgroup
+template <int MAXE, int NR>
+__global__ __launch_bounds__(64 * WS_LU_NW) void k_ws_lu(const WsBlk* __restrict__ wb, const int* __restrict__ list,
+                                               const FarBlk* __restrict__ blks, const int* __restrict__ plist,
+                                               cd* __restrict__ cross, int* __restrict__ pq,
+                                               int* __restrict__ rho_out, cd* __restrict__ coef) {
+  __shared__ cd Wl[MAXE > 0 ? MAXE : 1];
+  __shared__ short cl[2][3 * WS_MAXLIST];
+  __shared__ short sP[3 * WS_MAXLIST], sQ[3 * WS_MAXLIST];
+  __shared__ double sv[2][WS_LU_NW];
+  __shared__ int se[2][WS_LU_NW];
+  constexpr int NT = 64 * WS_LU_NW;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = list[blockIdx.x];
+  const WsBlk w = wb[wi];
+  const FarBlk B = blks[w.blk];
+  const int R3 = 3 * w.nr, C3 = 3 * w.nc, tot = R3 * C3;
+  const size_t M3 = 3 * (size_t)B.m;
+  const cd* Cc = cross + w.cc;
+  cd* W = MAXE > 0 ? Wl : cross + w.w;
+  const int* rows = plist + B.poff;
+  double best = -1.0;
+  int be = 0x7fffffff;
+  for (int e = tid; e < tot; e += NT) {
+    const int i = e % R3, j = e / R3;
+    const cd v = Cc[(size_t)j * M3 + 3 * rows[i / 3] + i % 3];
+    W[e] = v;
+    const double a = norm2(v);
+    if (a > best) {
+      best = a;
+      be = e;
+    }
+  }
+  for (int j = tid; j < C3; j += NT) cl[0][j] = (short)j;
+  unsigned alive = 0u;
+  for (int r = 0; r * 64 + lane < R3; ++r) alive |= 1u << r;
+  wave_argmax(best, be);
+  if (lane == 0) {
+    sv[0][wv] = best;
+    se[0][wv] = be;
+  }
+  __syncthreads();
+  auto pick = [&](int slot) {
+    best = sv[slot][0];
+    be = se[slot][0];
+#pragma unroll
+    for (int q = 1; q < WS_LU_NW; ++q)
+      if (sv[slot][q] > best || (sv[slot][q] == best && se[slot][q] < be)) {
+        best = sv[slot][q];
+        be = se[slot][q];
+      }
+  };
+  pick(0);
+  const double max0 = best;
+  int t = 0, nac = C3;
+  while (t < w.rcap && best > 1e-20 * max0 && best > 0.0) {
+    const int p = be % R3, q = be / R3;
+    const short* L = cl[t & 1];
+    short* Ln = cl[(t + 1) & 1];
+    if (tid == 0) {
+      sP[t] = (short)p;
+      sQ[t] = (short)q;
+    }
+    if ((p & 63) == lane) alive &= ~(1u << (p >> 6));
+    // next step's column list: this one without q (the last entry takes its place)
+    const short last = L[nac - 1];
+    for (int jj = tid; jj < nac - 1; jj += NT) Ln[jj] = L[jj] == q ? last : L[jj];
+    const cd ipiv = cinv(W[q * R3 + p]);
+    cd pc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) pc[r] = (alive & (1u << r)) ? W[q * R3 + r * 64 + lane] : mk(0.0);
+    best = -1.0;
+    be = 0x7fffffff;
+    // eight columns per wavefront pass (jb, jb + NW, ..., jb + 7 NW), all
+    // loads of a row chunk issued before its stores
+    for (int jb = wv; jb < nac; jb += 8 * WS_LU_NW) {
+      int jc[8];
+      cd pr[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jj = jb + WS_LU_NW * u;
+        jc[u] = jj < nac ? L[jj] : q;
+        pr[u] = jc[u] != q ? W[jc[u] * R3 + p] * ipiv : mk(0.0);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r * 64 >= R3) break;
+        if (!(alive & (1u << r))) continue;
+        const int i = r * 64 + lane;
+        cd v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = jc[u] != q ? W[jc[u] * R3 + i] : mk(0.0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (jc[u] != q) {
+            const int e = jc[u] * R3 + i;
+            cms(v[u], pc[r], pr[u]);
+            W[e] = v[u];
+            const double a = norm2(v[u]);
+            if (a > best || (a == best && e < be)) {
+              best = a;
+              be = e;
+            }
+          }
+        }
+      }
+    }
+    wave_argmax(best, be);
+    ++t;
+    --nac;
+    if (lane == 0) {
+      sv[t & 1][wv] = best;
+      se[t & 1][wv] = be;
+    }
+    __syncthreads();
+    pick(t & 1);
+  }
+  const int rho = t;
+  if (tid == 0) rho_out[wi] = rho;
+  int* Pp = pq + w.pq;
+  int* Qp = Pp + w.rcap;
+  for (int tt = tid; tt < rho; tt += NT) {
+    Pp[tt] = sP[tt];
+    Qp[tt] = sQ[tt];
+  }
+  // coefficients of the forward substitutions, by earlier term l (rows of
+  // length rc + WS_CH, so a chunk of later terms t is contiguous):
+  //   Mc[l][t] = M[l][t] = W[p_l][q_t] / W[p_l][q_l]   (l < t)
+  //   Nc[l][t] = N[t][l] = W[p_t][q_l]                (l < t)
+  //   Dn[t]    = 1 / W[p_t][q_t]
+  const int rc = w.rcap, ldc = w.rcap + WS_CH;
+  cd* Mc = coef + w.co;
+  cd* Nc = Mc + (size_t)ldc * rc;
+  cd* Dn = Nc + (size_t)ldc * rc;
+  for (int e = tid; e < rho * rho; e += NT) {
+    const int l = e / rho, tt = e - l * rho;
+    if (l < tt) {
+      Mc[(size_t)l * ldc + tt] = W[sQ[tt] * R3 + sP[l]] * cinv(W[sQ[l] * R3 + sP[l]]);
+      Nc[(size_t)l * ldc + tt] = W[sQ[l] * R3 + sP[tt]];
+    }
+  }
+  for (int tt = tid; tt < rho; tt += NT) Dn[tt] = cinv(W[sQ[tt] * R3 + sP[tt]]);
+}
+
+// U terms: one wavefront per 21 row elements of a block.  Row r of
+// Cc(:, q) = U M is solved for U(r, :) by forward substitution; the
+// coefficients are wavefront-uniform reads of Mc.
+__global__ __launch_bounds__(64) void k_ws_form_u(WsArgs A, const FarBlk* __restrict__ blks,
+                                                  AcaState* __restrict__ st, const unsigned* __restrict__ used,
+                                                  const cd* __restrict__ coef) {
+  const int task = blockIdx.x;
+  const int i = find_seg(A.tu_off, A.nwarm, task);
+  const WsBlk w = A.wb[i];
+  const FarBlk B = blks[w.blk];
+  const int rho = A.rho[i];
+  if (rho == 0) return;
+  const int tile = task - A.tu_off[i];
+  const int lane = threadIdx.x;
+  const size_t M3 = 3 * (size_t)B.m;
+  const int r = tile * (3 * ACA_ROWS_PER_WAVE) + lane;
+  const bool valid = lane < 3 * ACA_ROWS_PER_WAVE && r < (int)M3;
+  const int rc = w.rcap, ldc = w.rcap + WS_CH;
+  const int* Qp = A.pq + w.pq + rc;
+  const cd* Cc = A.cross + w.cc;
+  const cd* __restrict__ Mc = coef + w.co;
+  cd* U = B.U;
+  double* part = A.part + w.pu + (size_t)tile * rc;
+  double elast = 0.0;
+  for (int t0 = 0; t0 < rho; t0 += WS_CH) {
+    const int nj = min(WS_CH, rho - t0);
+    cd acc[WS_CH];
+#pragma unroll
+    for (int j = 0; j < WS_CH; ++j) acc[j] = (valid && j < nj) ? Cc[(size_t)Qp[t0 + j] * M3 + r] : mk(0.0);
+    // terms t0 + j >= rho are padding: their accumulators are never stored
+    int l = 0;
+    for (; l + 2 <= t0; l += 2) {
+      const cd x0 = valid ? U[(size_t)l * M3 + r] : mk(0.0);
+      const cd x1 = valid ? U[(size_t)(l + 1) * M3 + r] : mk(0.0);
+#pragma unroll
+      for (int j = 0; j < WS_CH; ++j) {
+        cms(acc[j], x0, Mc[(size_t)l * ldc + t0 + j]);
+        cms(acc[j], x1, Mc[(size_t)(l + 1) * ldc + t0 + j]);
+      }
+    }
+    if (l < t0) {
+      const cd x = valid ? U[(size_t)l * M3 + r] : mk(0.0);
+#pragma unroll
+      for (int j = 0; j < WS_CH; ++j) cms(acc[j], x, Mc[(size_t)l * ldc + t0 + j]);
+    }
+#pragma unroll
+    for (int j = 0; j < WS_CH; ++j) {
+      if (j < nj) {
+        const cd x = acc[j];
+        if (valid) U[(size_t)(t0 + j) * M3 + r] = x;
+#pragma unroll
+        for (int jp = j + 1; jp < WS_CH; ++jp)
+          if (jp < nj) acc[jp] -= x * Mc[(size_t)(t0 + j) * ldc + t0 + jp];
+        const double q2 = valid ? norm2(x) : 0.0;
+        if (t0 + j == rho - 1) elast = q2;
+        const double sq = wsum(q2);
+        if (lane == 0) part[t0 + j] = sq;
+      }
+    }
+  }
+  // next row element: largest last-term entry among unused rows
+  const double e1 = __shfl_down(elast, 1, 64), e2 = __shfl_down(elast, 2, 64);
+  unsigned long long cand = 0ull;
+  if (valid && lane % 3 == 0) {
+    const int a = r / 3;
+    if (!(used[B.bitoff + (a >> 5)] & (1u << (a & 31)))) cand = pack_best(sqrt(elast + e1 + e2), a);
+  }
+  cand = wave_max_u64(cand);
+  if (lane == 0 && cand) atomicMax(&st[w.blk].best_row, cand);
+}
+
+// V terms: one wavefront per 64 columns of a block.  Column c of
+// Rr(p, :) = N V^T is solved for V(c, :) by forward substitution.
+__global__ __launch_bounds__(64) void k_ws_form_v(WsArgs A, const FarBlk* __restrict__ blks,
+                                                  const cd* __restrict__ coef) {
+  const int task = blockIdx.x;
+  const int i = find_seg(A.tv_off, A.nwarm, task);
+  const WsBlk w = A.wb[i];
+  const FarBlk B = blks[w.blk];
+  const int rho = A.rho[i];
+  if (rho == 0) return;
+  const int tile = task - A.tv_off[i];
+  const int lane = threadIdx.x;
+  const size_t N3 = 3 * (size_t)B.n;
+  const int c = tile * 64 + lane;
+  const bool valid = c < (int)N3;
+  const int rc = w.rcap, ldc = w.rcap + WS_CH;
+  const int* Pp = A.pq + w.pq;
+  const cd* Rr = A.cross + w.rr;
+  const cd* __restrict__ Nc = coef + w.co + (size_t)ldc * rc;
+  const cd* __restrict__ Dn = Nc + (size_t)ldc * rc;
+  cd* V = B.V;
+  double* part = A.part + w.pv + (size_t)tile * rc;
+  for (int t0 = 0; t0 < rho; t0 += WS_CH) {
+    const int nj = min(WS_CH, rho - t0);
+    cd acc[WS_CH];
+#pragma unroll
+    for (int j = 0; j < WS_CH; ++j) acc[j] = (valid && j < nj) ? Rr[(size_t)Pp[t0 + j] * N3 + c] : mk(0.0);
+    int l = 0;
+    for (; l + 2 <= t0; l += 2) {
+      const cd y0 = valid ? V[(size_t)l * N3 + c] : mk(0.0);
+      const cd y1 = valid ? V[(size_t)(l + 1) * N3 + c] : mk(0.0);
+#pragma unroll
+      for (int j = 0; j < WS_CH; ++j) {
+        cms(acc[j], y0, Nc[(size_t)l * ldc + t0 + j]);
+        cms(acc[j], y1, Nc[(size_t)(l + 1) * ldc + t0 + j]);
+      }
+    }
+    if (l < t0) {
+      const cd y = valid ? V[(size_t)l * N3 + c] : mk(0.0);
+#pragma unroll
+      for (int j = 0; j < WS_CH; ++j) cms(acc[j], y, Nc[(size_t)l * ldc + t0 + j]);
+    }
+#pragma unroll
+    for (int j = 0; j < WS_CH; ++j) {
+      if (j < nj) {
+        const cd y = acc[j] * Dn[t0 + j];
+        if (valid) V[(size_t)(t0 + j) * N3 + c] = y;
+#pragma unroll
+        for (int jp = j + 1; jp < WS_CH; ++jp)
+          if (jp < nj) acc[jp] -= y * Nc[(size_t)(t0 + j) * ldc + t0 + jp];
+        const double sq = wsum(valid ? norm2(y) : 0.0);
+        if (lane == 0) part[t0 + j] = sq;
+      }
+    }
+  }
+}
+
+// One wavefront per warm block.  The terms are taken in pivot order until
+// the stopping test of a cold step holds for one of them,
+// |u_t|^2 |v_t|^2 <= tol^2 sum_{l<=t} |u_l|^2 |v_l|^2 (that term is kept, as
+// a cold step keeps its last terms); the pivot lists shrink to the elements
+// of the kept pivots.  At least one ordinary step follows, on a row outside
+// the cross, so growth of the rank at the new frequency is still detected.
+__global__ __launch_bounds__(256) void k_ws_finish(WsArgs A, const FarBlk* __restrict__ blks,
+                                                   AcaState* __restrict__ st, const unsigned* __restrict__ used,
+                                                   int* __restrict__ plist, int* __restrict__ nlist, double tol) {
+  __shared__ unsigned char keep[4][2 * WS_MAXLIST];
+  const int wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + wv;
+  const int lane = threadIdx.x & 63;
+  if (i >= A.nwarm) return;
+  const WsBlk w = A.wb[i];
+  const FarBlk B = blks[w.blk];
+  const int rho = A.rho[i];
+  const int ntu = A.tu_off[i + 1] - A.tu_off[i], ntv = A.tv_off[i + 1] - A.tv_off[i];
+  const int* Pp = A.pq + w.pq;
+  const int* Qp = Pp + w.rcap;
+  // running norm estimate over the terms, 64 at a time
+  double normS2 = 0.0;
+  int kept = rho;
+  for (int t0 = 0; t0 < rho && kept == rho; t0 += 64) {
+    const int t = t0 + lane;
+    double term = 0.0;
+    if (t < rho) {
+      double nu = 0.0, nv = 0.0;
+      for (int q = 0; q < ntu; ++q) nu += A.part[w.pu + (size_t)q * w.rcap + t];
+      for (int q = 0; q < ntv; ++q) nv += A.part[w.pv + (size_t)q * w.rcap + t];
+      term = nu * nv;
+    }
+    // inclusive prefix sum of the terms over the lanes
+    double inc = term;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    const bool stop = t < rho && term <= tol * tol * (normS2 + inc);
+    const unsigned long long bal = __ballot(stop);
+    if (bal) {
+      const int first = __ffsll((long long)bal) - 1;
+      kept = t0 + first + 1;
+      normS2 += __shfl(inc, first, 64);
+    } else {
+      normS2 += __shfl(inc, 63, 64);
+    }
+  }
+  // pivot lists of the next frequency: elements of the kept pivots
+  unsigned char* kr = keep[wv];
+  unsigned char* kc = keep[wv] + WS_MAXLIST;
+  for (int q = lane; q < WS_MAXLIST; q += 64) kr[q] = kc[q] = 0;
+  wave_sync();
+  for (int t = lane; t < kept; t += 64) {
+    kr[Pp[t] / 3] = 1;
+    kc[Qp[t] / 3] = 1;
+  }
+  wave_sync();
+  if (lane != 0) return;
+  int* rl = plist + B.poff;
+  int* cl = plist + B.poff + B.m;
+  int nr = 0, nc = 0;
+  for (int q = 0; q < w.nr; ++q)
+    if (kr[q]) rl[nr++] = rl[q];
+  for (int q = 0; q < w.nc; ++q)
+    if (kc[q]) cl[nc++] = cl[q];
+  nlist[2 * w.blk] = nr;
+  nlist[2 * w.blk + 1] = nc;
+  AcaState s = st[w.blk];
+  s.k = kept;
+  s.normS2 = normS2;
+  if (kept >= 3 * min(B.m, B.n)) {
+    s.status = ACA_DONE;  // full rank
+  } else if (kept + 3 > B.kcap) {
+    s.status = ACA_OVERFLOW;
+  } else if (kept == 0 || s.best_row == 0ull) {
+    // no candidate from the last term: the first row outside the cross
+    int a = -1;
+    const unsigned* u = used + B.bitoff;
+    for (int q = 0; q < (B.m + 31) / 32 && a < 0; ++q) {
+      const unsigned f = ~u[q];
+      if (f) a = 32 * q + __ffs(f) - 1;
+    }
+    if (a < 0 || a >= B.m)
+      s.status = ACA_DONE;  // every row is in the cross
+    else
+      s.astar = a;
+  } else {
+    s.astar = 0x7fffffff - (int)(s.best_row & 0xffffffffu);
+  }
+  s.best_row = 0ull;
+  st[w.blk] = s;
+}
+
+void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s) {
+  if (A.nwarm <= 0) return;
+  hipLaunchKernelGGL(k_ws_init, dim3((A.nwarm + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, W.blks, W.st, W.used,
+                     W.plist);
+  if (A.tot_er > 0)
+    hipLaunchKernelGGL(k_ws_eval_rows, dim3((A.tot_er + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, A.er_off, W.blks,
+                       W.plist, A.cross, g, P);
+  if (A.tot_ec > 0)
+    hipLaunchKernelGGL(k_ws_eval_cols, dim3((A.tot_ec + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, A.ec_off, W.blks,
+                       W.plist, A.cross, g, P);
+  // the elimination in four size classes: W of up to 2304, 4480 and 8960
+  // entries in LDS (three, two and one workgroups per CU), larger in global
+  // memory
+  const int nt = 64 * WS_LU_NW;
+  const int* lst = A.lu_list;
+  if (A.n_lu[0] > 0)
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS>), dim3(A.n_lu[0]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross,
+                       A.pq, A.rho, A.coef);
+  lst += A.n_lu[0];
+  if (A.n_lu[1] > 0)
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_MID, WS_LU_NR_LDS>), dim3(A.n_lu[1]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross,
+                       A.pq, A.rho, A.coef);
+  lst += A.n_lu[1];
+  if (A.n_lu[2] > 0)
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_LARGE, WS_LU_NR_LDS>), dim3(A.n_lu[2]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross,
+                       A.pq, A.rho, A.coef);
+  lst += A.n_lu[2];
+  if (A.n_lu[3] > 0)
+    hipLaunchKernelGGL((k_ws_lu<0, (3 * WS_MAXLIST + 63) / 64>), dim3(A.n_lu[3]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho,
+                       A.coef);
+  hipLaunchKernelGGL(k_ws_form_u, dim3(A.tot_tu), dim3(64), 0, s, A, W.blks, W.st, W.used, A.coef);
+  hipLaunchKernelGGL(k_ws_form_v, dim3(A.tot_tv), dim3(64), 0, s, A, W.blks, A.coef);
+  hipLaunchKernelGGL(k_ws_finish, dim3((A.nwarm + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, W.plist,
+                     W.nlist, tol);
+}
+
+}  // namespace ewbem

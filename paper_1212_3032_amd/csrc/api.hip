@@ -45,8 +45,14 @@ struct DevBuf {
       n = cnt;
     }
   }
+  // for buffers that grow with the frequency (ranks, task lists): a quarter
+  // of headroom, so they are not reallocated at every frequency
+  void reserve_grow(size_t cnt) {
+    if (cnt <= n) return;
+    reserve(std::max(cnt, n + n / 4));
+  }
   void upload(const std::vector<T>& v, hipStream_t st) {
-    reserve(v.size());
+    reserve_grow(v.size());
     if (!v.empty())
       EWBEM_HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   }
@@ -134,6 +140,15 @@ struct ewbem_ctx {
   DevBuf<AcaState> d_acast;
   DevBuf<AcaPlan> d_acaplan;
   DevBuf<double> d_aca_part;
+  DevBuf<int> d_aca_cold;
+  // warm starts: pivot lists (kept across frequencies) and their work areas
+  bool plist_ok = false;
+  DevBuf<int> d_plist, d_nlist;
+  std::vector<int> nlist_h;
+  DevBuf<WsBlk> d_wsb;
+  DevBuf<int> d_wsoff, d_wspq, d_wsrho, d_wslu;
+  DevBuf<cd> d_cross, d_wscoef;
+  DevBuf<double> d_wspart;
   DevBuf<unsigned> d_used;
   DevBuf<int> d_aca_ids, d_act, d_act2, d_offs, d_tot;
   DevBuf<VtTask> d_vt;
@@ -249,6 +264,7 @@ void ensure_structure(ewbem_ctx* c) {
     c->far_h.push_back(fb);
   }
   c->kcap_prev.assign(c->far_h.size(), 0);
+  c->plist_ok = false;
   c->rank_h.assign(c->far_h.size(), 0);
   c->status_h.assign(c->far_h.size(), 0);
   c->structure_ok = true;
@@ -344,28 +360,120 @@ cd s_of_k(ewbem_ctx* c, int k) { return cd{c->sigma, 2.0 * M_PI * k / c->period}
 // ---- ACA with capacity retries, then matvec task lists
 
 // Lock-step cross approximation of the far blocks ids (their FarBlk
-// entries already on the device).  One host round trip per step: the scan
-// of the active list tells the grid sizes of the step's launches.
-void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids) {
+// entries already on the device).  Blocks with pivot lists from the previous
+// frequency (and warm set) start from the cross on those pivots, the others
+// from scratch; then all run the ordinary steps, one host round trip per
+// step (the scan of the active list gives the grid sizes).
+void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, bool warm, bool count_starts) {
   hipStream_t st = c->stream;
   const int n = (int)ids.size();
   if (n == 0) return;
+  std::vector<int> cold;
+  std::vector<WsBlk> wb;
+  std::vector<int> woff;  // er, ec, tu, tv offsets, 4 x (nwarm + 1)
+  long long cross = 0, er = 0, ec = 0, tu = 0, tv = 0, pqn = 0, part = 0, coefn = 0;
+  for (int b : ids) {
+    const FarBlk& f = c->far_h[b];
+    const int nr = c->nlist_h[2 * b], nc = c->nlist_h[2 * b + 1];
+    if (!warm || nr <= 0 || nc <= 0 || nr > WS_MAXLIST || nc > WS_MAXLIST) {
+      cold.push_back(b);
+      continue;
+    }
+    WsBlk w{};
+    w.blk = b;
+    w.nr = nr;
+    w.nc = nc;
+    w.rcap = std::min(3 * std::min(nr, nc), f.kcap);
+    w.rr = cross;
+    cross += 9LL * nr * f.n;
+    w.cc = cross;
+    cross += 9LL * nc * f.m;
+    w.w = cross;
+    cross += 9LL * nr * nc;
+    w.pq = (int)pqn;
+    pqn += 2LL * w.rcap;
+    const int ntu = (f.m + ACA_ROWS_PER_WAVE - 1) / ACA_ROWS_PER_WAVE, ntv = (3 * f.n + 63) / 64;
+    w.tu = (int)tu;
+    w.tv = (int)tv;
+    w.pu = part;
+    part += (long long)ntu * w.rcap;
+    w.pv = part;
+    part += (long long)ntv * w.rcap;
+    w.co = coefn;
+    coefn += 2LL * (w.rcap + 8) * w.rcap + w.rcap + 8;  // Mc, Nc, Dn with one chunk of padding
+    wb.push_back(w);
+    er += (long long)nr * f.n;
+    ec += (long long)nc * f.m;
+    tu += ntu;
+    tv += ntv;
+  }
+  const int nw = (int)wb.size();
+  if (er > INT32_MAX / 2 || ec > INT32_MAX / 2 || tu > INT32_MAX / 2 || tv > INT32_MAX / 2 || pqn > INT32_MAX / 2)
+    fail(EWBEM_EINVAL, "warm start larger than its index range");
+  AcaWork W0{c->d_far.p, c->d_acast.p, c->d_acaplan.p, c->d_used.p, nullptr, nullptr, c->d_plist.p, c->d_nlist.p};
   c->d_aca_ids.upload(ids, st);
   c->d_act.reserve(n);
   c->d_act2.reserve(n);
+  c->d_tot.reserve(6);
+  int* count = c->d_tot.p + 5;
+  if (!cold.empty()) {
+    c->d_aca_cold.upload(cold, st);
+    launch_aca_init(c->d_aca_cold.p, (int)cold.size(), c->d_far.p, c->d_acast.p, c->d_used.p, c->d_nlist.p, st);
+  }
+  if (nw > 0) {
+    woff.assign(4 * (size_t)(nw + 1), 0);
+    for (int i = 0; i < nw; ++i) {
+      const FarBlk& f = c->far_h[wb[i].blk];
+      woff[i + 1] = woff[i] + wb[i].nr * f.n;
+      woff[(nw + 1) + i + 1] = woff[(nw + 1) + i] + wb[i].nc * f.m;
+      woff[2 * (nw + 1) + i + 1] = woff[2 * (nw + 1) + i] + (f.m + ACA_ROWS_PER_WAVE - 1) / ACA_ROWS_PER_WAVE;
+      woff[3 * (nw + 1) + i + 1] = woff[3 * (nw + 1) + i] + (3 * f.n + 63) / 64;
+    }
+    c->d_wsb.upload(wb, st);
+    c->d_wsoff.upload(woff, st);
+    c->d_cross.reserve_grow(std::max<long long>(cross, 1));
+    c->d_wspq.reserve_grow(std::max<long long>(pqn, 1));
+    c->d_wsrho.reserve(nw);
+    c->d_wspart.reserve_grow(std::max<long long>(part, 1));
+    c->d_wscoef.reserve_grow(std::max<long long>(coefn, 1));
+    // size classes of the core elimination
+    std::vector<int> lu_list;
+    int n_lu[4] = {0, 0, 0, 0};
+    for (int cls = 0; cls < 4; ++cls)
+      for (int i = 0; i < nw; ++i) {
+        const long long e = 9LL * wb[i].nr * wb[i].nc;
+        const int ci = 3 * wb[i].nr > 64 * WS_LU_NR_LDS ? 3
+                       : e <= WS_LDS_SMALL             ? 0
+                       : e <= WS_LDS_MID               ? 1
+                       : e <= WS_LDS_LARGE             ? 2
+                                                       : 3;
+        if (ci == cls) {
+          lu_list.push_back(i);
+          ++n_lu[cls];
+        }
+      }
+    c->d_wslu.upload(lu_list, st);
+    WsArgs A{c->d_wsb.p, nw, c->d_wsoff.p, c->d_wsoff.p + (nw + 1), c->d_wsoff.p + 2 * (nw + 1),
+             c->d_wsoff.p + 3 * (nw + 1), (int)er, (int)ec, (int)tu, (int)tv, c->d_cross.p, c->d_wspq.p,
+             c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p, {n_lu[0], n_lu[1], n_lu[2], n_lu[3]}};
+    launch_ws(A, W0, g, c->P, c->op.aca_tol, st);
+  }
+  if (count_starts) {
+    c->acc.aca_warm_blocks += nw;
+    c->acc.aca_cold_blocks += (long long)cold.size();
+  }
+  // the active list: every block still ACA_ACTIVE after its start
+  EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, 0, 1, st));
+  launch_aca_compact(c->d_aca_ids.p, n, c->d_acast.p, c->d_act.p, count, st);
   const int stride = n + 1;
   c->d_offs.reserve(4 * (size_t)stride);
-  c->d_tot.reserve(6);
-  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_act.p, c->d_aca_ids.p, n * sizeof(int), hipMemcpyDeviceToDevice, st));
-  launch_aca_init(c->d_aca_ids.p, n, c->d_far.p, c->d_acast.p, c->d_used.p, st);
-  int* count = c->d_tot.p + 5;
-  EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, n, 1, st));
   int* act = c->d_act.p;
   int* nxt = c->d_act2.p;
   // every step either adds at least one term or counts a failed row (at
   // most four in a row), so the number of steps is bounded
   const int max_steps = 5 * ACA_KMAX + 16;
   int tot[5] = {0, 0, 0, 0, 0};
+  bool sized = false;
   for (int it = 0;; ++it) {
     launch_aca_scan(act, count, c->d_far.p, c->d_offs.p, stride, c->d_tot.p, st);
     EWBEM_HIP_CHECK(hipMemcpyAsync(tot, c->d_tot.p, 5 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -375,16 +483,17 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids) {
     if (nact < 0 || nact > n || it > max_steps) fail(EWBEM_EINVAL, "internal: ACA active list out of range");
     EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, 0, 1, st));
     // the first step has the most active blocks, so the largest task counts
-    if (it == 0) {
-      c->d_aca_part.reserve(3 * ((size_t)tot[2] + (size_t)tot[3]));
-      c->d_acaplan.reserve(c->far_h.size());
+    if (!sized) {
+      c->d_aca_part.reserve_grow(3 * ((size_t)tot[2] + (size_t)tot[3]));
+      sized = true;
     }
     if ((size_t)3 * ((size_t)tot[2] + (size_t)tot[3]) > c->d_aca_part.n)
       fail(EWBEM_EINVAL, "internal: ACA task count grew");
     AcaLists L{act, nact, tot[0], tot[1], tot[2], tot[3], c->d_offs.p, c->d_offs.p + stride,
                c->d_offs.p + 2 * stride, c->d_offs.p + 3 * stride};
-    AcaWork W{c->d_far.p, c->d_acast.p, c->d_acaplan.p, c->d_used.p, c->d_aca_part.p,
-              c->d_aca_part.p + 3 * (size_t)tot[3]};
+    AcaWork W = W0;
+    W.part_u = c->d_aca_part.p;
+    W.part_v = c->d_aca_part.p + 3 * (size_t)tot[3];
     launch_aca_step(L, W, g, c->P, c->op.aca_tol, nxt, count, st);
     std::swap(act, nxt);
   }
@@ -399,12 +508,30 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
   // frequency), else a size-based first guess; retries are the exception.
   // 3 min(m, n) + 2 columns always suffice: a block stops at full rank, and
   // a step adds at most three terms.
+  // pivot lists for warm starts: allocated with the partition, empty until a
+  // first approximation has run
+  if (!c->plist_ok) {
+    long long poff = 0;
+    for (int b = 0; b < nf; ++b) {
+      c->far_h[b].poff = (int)poff;
+      poff += 2LL * c->far_h[b].m;
+    }
+    if (poff > INT32_MAX) fail(EWBEM_EINVAL, "too many far-block rows");
+    c->d_plist.reserve(std::max<long long>(poff, 1));
+    c->d_nlist.reserve(2 * (size_t)nf);
+    EWBEM_HIP_CHECK(hipMemsetAsync(c->d_nlist.p, 0, 2 * (size_t)nf * sizeof(int), st));
+    c->nlist_h.assign(2 * (size_t)nf, 0);
+    c->plist_ok = true;
+  }
+  const bool warm = c->op.aca_reuse != 0;
   std::vector<int> kcap(nf);
   for (int b = 0; b < nf; ++b) {
     const FarBlk& f = c->far_h[b];
     const int full = 3 * std::min(f.m, f.n) + 2;
     int want = c->kcap_prev[b] > 0 ? c->rank_h[b] + std::max(12, (3 * c->rank_h[b]) / 10)
                                    : 24 + (f.m + f.n) / 8;
+    const int nr = c->nlist_h[2 * b], nc = c->nlist_h[2 * b + 1];
+    if (warm && nr > 0 && nc > 0) want = std::max(want, 3 * std::min(nr, nc) + 6);
     want = ((want + 2) / 3) * 3;
     kcap[b] = std::max(3, std::min({want, full, ACA_KMAX}));
   }
@@ -412,7 +539,7 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
   c->d_retry.clear();
   long long total = 0, words = 0;
   for (int b = 0; b < nf; ++b) total += (long long)(3 * c->far_h[b].m + 3 * c->far_h[b].n) * kcap[b];
-  c->d_ws.reserve(total);
+  c->d_ws.reserve_grow(total);
   long long off = 0;
   for (int b = 0; b < nf; ++b) {
     FarBlk& f = c->far_h[b];
@@ -427,13 +554,14 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
   }
   c->d_used.reserve(words);
   c->d_acast.reserve(nf);
+  c->d_acaplan.reserve(nf);
   c->d_far.upload(c->far_h, st);
   c->d_rank.reserve(nf);
   c->d_status.reserve(nf);
   std::vector<int> all(nf);
   for (int b = 0; b < nf; ++b) all[b] = b;
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-  aca_lockstep(c, g, all);
+  aca_lockstep(c, g, all, warm, true);
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -467,7 +595,7 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     }
     c->d_far.upload(c->far_h, st);
     EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-    aca_lockstep(c, g, over);
+    aca_lockstep(c, g, over, false, false);
     EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -478,6 +606,9 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     if (c->status_h[b] != 0) fail(EWBEM_EINVAL, "ACA did not converge within its capacity");
     c->kcap_prev[b] = c->far_h[b].kcap;
   }
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->nlist_h.data(), c->d_nlist.p, 2 * (size_t)nf * sizeof(int),
+                                 hipMemcpyDeviceToHost, st));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
 }
 
 // Host-side check that a device range [p, p + n) lies inside one of the
@@ -525,7 +656,7 @@ void build_matvec(ewbem_ctx* c) {
   }
   c->d_z.reserve(std::max<long long>(1, zoff[nf]));
   if (c64) {
-    c->d_f32.reserve(std::max<long long>(1, f32tot));
+    c->d_f32.reserve_grow(std::max<long long>(1, f32tot));
     c->d_uo.upload(uo, st);
     c->d_vo.upload(vo, st);
     launch_to_c64(c->d_far.p, nf, c->d_rank.p, c->d_uo.p, c->d_vo.p, c->d_f32.p, st);
@@ -1083,6 +1214,8 @@ void ewbem_default_op_opts(ewbem_op_opts* o) {
   o->aca_tol = 1e-5;
   o->far_store = EWBEM_STORE_C128;
   o->self_order = 24;
+  o->aca_reuse = 1;
+  o->pad = 0;
 }
 
 void ewbem_default_solver_opts(ewbem_solver_opts* o) {
@@ -1251,7 +1384,7 @@ int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
     if ((o->kind != EWBEM_OP_DENSE && o->kind != EWBEM_OP_HMAT) || o->leaf_size < 1 || o->leaf_size > 64 ||
         !(o->eta_adm > 0) || !(o->aca_tol > 0 && o->aca_tol < 1) ||
         (o->far_store != EWBEM_STORE_C128 && o->far_store != EWBEM_STORE_C64) || o->self_order < 4 ||
-        o->self_order > MAX_SELF_ORDER)
+        o->self_order > MAX_SELF_ORDER || (o->aca_reuse != 0 && o->aca_reuse != 1))
       fail(EWBEM_EINVAL, "operator options out of range");
     ctx->op = *o;
     ctx->structure_ok = false;

@@ -37,7 +37,8 @@ class Z(C.Structure):
 
 class OpOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("leaf_size", C.c_int32), ("eta_adm", C.c_double),
-                ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32)]
+                ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32),
+                ("aca_reuse", C.c_int32), ("pad", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
@@ -54,7 +55,8 @@ class Stats(C.Structure):
                 ("n_near", C.c_int64), ("n_far", C.c_int64), ("rank_sum", C.c_int64),
                 ("rank_max", C.c_int64), ("t_aca_ms", C.c_double), ("t_near_ms", C.c_double),
                 ("t_rhs_ms", C.c_double), ("matvec_bytes_total", C.c_double),
-                ("matvecs_timed", C.c_int32), ("pad0", C.c_int32)]
+                ("matvecs_timed", C.c_int32), ("pad0", C.c_int32),
+                ("aca_warm_blocks", C.c_int64), ("aca_cold_blocks", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -272,6 +272,42 @@ def test_hmatrix_apply_and_solve(torch_dev, E, sub3_system, aca_tol, store):
     c.close()
 
 
+def test_hmatrix_warm_start(torch_dev, E, sub3_system):
+    """ACA started from the previous frequency's pivots, over eleven
+    consecutive frequencies (k = 30..40), against ACA from scratch at k = 40:
+    both operators and solutions within the ACA bound of the dense ones, and
+    the warm-started ranks do not drift above the cold ones."""
+    torch, dev = torch_dev
+    d, sysk = sub3_system
+    T, b = sysk[40]
+    N = 3 * len(d["tri"])
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    tol = 1e-6
+    out = {}
+    for reuse, ks in ((0, [40]), (1, list(range(30, 41)))):
+        c = _ctx(E, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=tol, aca_reuse=reuse),
+                 solver=dict(tol=1e-10, guess=E.GUESS_ZERO))
+        for k in ks:
+            st = c.assemble(k)
+        y = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.apply(torch.tensor(x, device=dev), y)
+        e_apply = _l2(y.cpu().numpy(), T @ x)
+        a = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.solve_frequency(40, a)
+        e_sol = _l2(a.cpu().numpy(), np.linalg.solve(T, b))
+        _say(f"reuse={reuse} warm={st['aca_warm_blocks']} cold={st['aca_cold_blocks']} "
+             f"ranks sum={st['rank_sum']} max={st['rank_max']} e_apply={e_apply:.2e} e_sol={e_sol:.2e}")
+        if reuse:
+            assert st["aca_warm_blocks"] == st["n_far"] and st["aca_cold_blocks"] == 0
+        else:
+            assert st["aca_warm_blocks"] == 0 and st["aca_cold_blocks"] == st["n_far"]
+        assert e_apply < 30 * tol and e_sol < 30 * tol
+        out[reuse] = st["rank_sum"]
+        c.close()
+    assert out[1] <= 1.25 * out[0]
+
+
 def test_config1_transient_blackman(torch_dev, E, mat):
     """Sec. 3.2: the Blackman window through the same path, against the
     oracle's transient with the same window."""

@@ -26,6 +26,8 @@ def test_library_exports_every_declared_symbol():
 def test_defaults():
     o = ewbem.default_op_opts()
     assert (o.kind, o.leaf_size, o.eta_adm, o.aca_tol) == (ewbem.OP_HMAT, 64, 1.0, 1e-5)
+    # the fields after the doubles sit where the C struct has them
+    assert (o.far_store, o.self_order, o.aca_reuse, o.pad) == (ewbem.STORE_C128, 24, 1, 0)
     s = ewbem.default_solver_opts()
     assert (s.tol, s.restart, s.guess, s.sem_k) == (1e-6, 100, ewbem.GUESS_SEM, 3)
 
@@ -94,6 +96,8 @@ def test_input_validation():
         c.set_time(8.0, 31, 0.75)
     with pytest.raises(ewbem.EwbemError):
         c.set_operator(leaf_size=65)
+    with pytest.raises(ewbem.EwbemError):
+        c.set_operator(aca_reuse=2)
     c.set_mesh(xyz, tri)
     c.set_time(8.0, 16, 0.75)
     with pytest.raises(ewbem.EwbemError):
