@@ -166,11 +166,14 @@ struct LeafRange {
 
 constexpr int HMV_MAXROWS = 192;
 
-void launch_far_vt(const VtTask* tasks, int ntask, int store_c64, const cd* x, cd* z,
-                   hipStream_t st);
-void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, const cd* z,
-                cd* partial, hipStream_t st);
-void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, cd* y,
-                       hipStream_t st);
+// nrhs = 1..4 right-hand sides: columns of x (stride ldx), z (ldz), the
+// partial sums (ldp) and y (ldy).
+void launch_far_vt(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, int nrhs, cd* z,
+                   long long ldz, hipStream_t st);
+void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, long long ldx, int nrhs,
+                const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st);
+void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, long long ldp, int nrhs, cd* y,
+                       long long ldy, hipStream_t st);
+constexpr int HMV_MAXRHS = 4;
 
 }  // namespace ewbem

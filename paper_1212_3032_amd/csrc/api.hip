@@ -157,6 +157,7 @@ struct ewbem_ctx {
   DevBuf<LeafRange> d_lr;
   int n_vt = 0, n_rt = 0, n_lr = 0;
   DevBuf<cd> d_z, d_hpart, d_mvpart;
+  long long z_len = 0, mvpart_len = 0;  // one right-hand side's share of d_z, d_mvpart
   DevBuf<cd> d_rhs_part;
   int boff_k0 = 0, boff_nk = 0;   // frequencies whose off-diagonal U t0 is in d_rhs_part
   // preconditioner
@@ -654,7 +655,8 @@ void build_matvec(ewbem_ctx* c) {
     c->rank_sum += k;
     c->rank_max = std::max<int64_t>(c->rank_max, k);
   }
-  c->d_z.reserve(std::max<long long>(1, zoff[nf]));
+  c->z_len = std::max<long long>(1, zoff[nf]);
+  c->d_z.reserve_grow((size_t)HMV_MAXRHS * c->z_len);
   if (c64) {
     c->d_f32.reserve_grow(std::max<long long>(1, f32tot));
     c->d_uo.upload(uo, st);
@@ -793,7 +795,8 @@ void build_matvec(ewbem_ctx* c) {
   c->n_vt = (int)vt.size();
   c->n_rt = (int)rt.size();
   c->n_lr = (int)lr.size();
-  c->d_mvpart.reserve((size_t)std::max(1, c->n_rt) * HMV_MAXROWS);
+  c->mvpart_len = (long long)std::max(1, c->n_rt) * HMV_MAXROWS;
+  c->d_mvpart.reserve_grow((size_t)HMV_MAXRHS * c->mvpart_len);
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
 }
 
@@ -802,11 +805,23 @@ void build_matvec(ewbem_ctx* c) {
 void apply_tree(ewbem_ctx* c, const cd* x, cd* y, EventPair* ev) {
   hipStream_t st = c->stream;
   if (ev) EWBEM_HIP_CHECK(hipEventRecord(ev->a, st));
-  launch_far_vt(c->d_vt.p, c->n_vt, c->store_c64_active, x, c->d_z.p, st);
-  launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, x, c->d_z.p, c->d_mvpart.p, st);
-  launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, y, st);
+  launch_far_vt(c->d_vt.p, c->n_vt, c->store_c64_active, x, 0, 1, c->d_z.p, 0, st);
+  launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, x, 0, 1, c->d_z.p, 0, c->d_mvpart.p, 0, st);
+  launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, 0, 1, y, 0, st);
   if (ev) EWBEM_HIP_CHECK(hipEventRecord(ev->b, st));
   c->acc.matvecs += 1;
+}
+
+// Y(:, j) = A X(:, j) for j < nrhs <= 4, columns N apart (tree order): the
+// operator is read once for all of them.
+void apply_tree_multi(ewbem_ctx* c, const cd* X, cd* Y, int nrhs) {
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  if (nrhs < 1 || nrhs > HMV_MAXRHS) fail(EWBEM_EINVAL, "internal: matvec right-hand sides out of range");
+  launch_far_vt(c->d_vt.p, c->n_vt, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st);
+  launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, X, N, nrhs, c->d_z.p, c->z_len, c->d_mvpart.p, c->mvpart_len, st);
+  launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, c->mvpart_len, nrhs, Y, N, st);
+  c->acc.matvecs += nrhs;
 }
 
 // add one event-timed matvec (its kernels' time and algorithmic bytes)
@@ -1042,14 +1057,16 @@ void sem_guess(ewbem_ctx* c, cd* x, cd* r) {
   EWBEM_HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(cd), st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(r, c->d_b.p, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
   if (K == 0) return;
-  EventPair ev;
   cd* Y = c->d_Y.p;
   cd* Q = c->d_V.p;  // GMRES basis as scratch
-  for (int j = 0; j < K; ++j) {
-    apply_tree(c, c->d_hist_sol.p + (size_t)c->hist_slot[j] * N, Y + (size_t)j * N, &ev);
-    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
-    account_matvec(c, ev);
-  }
+  // Y(:, j) = A (history slot j): the history vectors are copied into the
+  // order of Y, then the operator is applied to up to four at once
+  for (int j = 0; j < K; ++j)
+    EWBEM_HIP_CHECK(hipMemcpyAsync(Q + (size_t)j * N, c->d_hist_sol.p + (size_t)c->hist_slot[j] * N,
+                                   N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+  for (int j0 = 0; j0 < K; j0 += HMV_MAXRHS)
+    apply_tree_multi(c, Q + (size_t)j0 * N, Y + (size_t)j0 * N, std::min(HMV_MAXRHS, K - j0));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
   // classical Gram-Schmidt twice on the columns of Y
   std::vector<std::complex<double>> R((size_t)K * K, 0.0);
   std::vector<int> kept;

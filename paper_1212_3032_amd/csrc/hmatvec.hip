@@ -9,7 +9,9 @@
 // into tasks of similar column counts; one workgroup streams one task
 // (column-major, coalesced along rows) and writes a partial result.
 // k_hmv_reduce sums the partials of each leaf in a fixed order, so the
-// result is deterministic (no atomics).
+// result is deterministic (no atomics).  All three take one to four
+// right-hand sides (the extrapolated guess applies the operator to several
+// earlier solutions at once).
 #include "aca.hpp"
 
 namespace ewbem {
@@ -20,16 +22,24 @@ __device__ __forceinline__ double wsum64(double v) {
   return v;
 }
 
-template <typename TS>
+// NR right-hand sides at once (columns of x, z, partial and y, strides ldx,
+// ldz, ldp, ldy): every factor and near-block entry is loaded once and
+// multiplied against the NR vectors.
+template <typename TS, int NR>
 __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks, int ntask,
-                                                const cd* __restrict__ x, cd* __restrict__ z) {
+                                                const cd* __restrict__ x, long long ldx, cd* __restrict__ z,
+                                                long long ldz) {
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= ntask) return;
   const VtTask T = tasks[t];
   const TS* __restrict__ V = (const TS*)T.V;
   const cd* __restrict__ xs = x + T.x0;
-  cd a0 = mk(0.0), a1 = mk(0.0), a2 = mk(0.0), a3 = mk(0.0);
+  cd a[4][NR];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) a[k][q] = mk(0.0);
   const int C = T.C;
   const int nc = T.ncol;
   // columns past ncol read column 0 again (in bounds) and are discarded
@@ -37,107 +47,149 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
   const TS* __restrict__ V2 = V + (size_t)(nc > 2 ? 2 : 0) * C;
   const TS* __restrict__ V3 = V + (size_t)(nc > 3 ? 3 : 0) * C;
   for (int c = lane; c < C; c += 64) {
-    const cd xv = xs[c];
-    a0 += to_cd(V[c]) * xv;
-    a1 += to_cd(V1[c]) * xv;
-    a2 += to_cd(V2[c]) * xv;
-    a3 += to_cd(V3[c]) * xv;
+    const cd v0 = to_cd(V[c]), v1 = to_cd(V1[c]), v2 = to_cd(V2[c]), v3 = to_cd(V3[c]);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const cd xv = xs[c + q * ldx];
+      a[0][q] += v0 * xv;
+      a[1][q] += v1 * xv;
+      a[2][q] += v2 * xv;
+      a[3][q] += v3 * xv;
+    }
   }
-  a0.x = wsum64(a0.x);
-  a0.y = wsum64(a0.y);
-  a1.x = wsum64(a1.x);
-  a1.y = wsum64(a1.y);
-  a2.x = wsum64(a2.x);
-  a2.y = wsum64(a2.y);
-  a3.x = wsum64(a3.x);
-  a3.y = wsum64(a3.y);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      a[k][q].x = wsum64(a[k][q].x);
+      a[k][q].y = wsum64(a[k][q].y);
+    }
   // every lane holds the sums; lane 0 stores them (no lane-indexed select,
   // which the compiler would place in scratch memory)
   if (lane == 0) {
-    cd* zz = z + T.zidx;
-    zz[0] = a0;
-    if (nc > 1) zz[1] = a1;
-    if (nc > 2) zz[2] = a2;
-    if (nc > 3) zz[3] = a3;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      cd* zz = z + T.zidx + q * ldz;
+      zz[0] = a[0][q];
+      if (nc > 1) zz[1] = a[1][q];
+      if (nc > 2) zz[2] = a[2][q];
+      if (nc > 3) zz[3] = a[3][q];
+    }
   }
 }
 
-void launch_far_vt(const VtTask* tasks, int ntask, int store_c64, const cd* x, cd* z,
-                   hipStream_t st) {
-  if (ntask <= 0) return;
+template <int NR>
+void far_vt_nr(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, cd* z, long long ldz,
+               hipStream_t st) {
   dim3 grid((ntask + 3) / 4);
   if (store_c64)
-    hipLaunchKernelGGL(k_far_vt<cf>, grid, dim3(256), 0, st, tasks, ntask, x, z);
+    hipLaunchKernelGGL((k_far_vt<cf, NR>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
   else
-    hipLaunchKernelGGL(k_far_vt<cd>, grid, dim3(256), 0, st, tasks, ntask, x, z);
+    hipLaunchKernelGGL((k_far_vt<cd, NR>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
 }
 
-template <typename TS>
-__device__ __forceinline__ cd panel_dot(const TS* __restrict__ A, const cd* __restrict__ src, int ld,
-                                        int ncols, int r, int g, int G) {
-  cd acc = mk(0.0);
+void launch_far_vt(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, int nrhs, cd* z,
+                   long long ldz, hipStream_t st) {
+  if (ntask <= 0) return;
+  switch (nrhs) {
+    case 1: far_vt_nr<1>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 2: far_vt_nr<2>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 3: far_vt_nr<3>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 4: far_vt_nr<4>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    default: throw ApiError(-1, "matvec: 1 to 4 right-hand sides");
+  }
+}
+
+template <typename TS, int NR>
+__device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __restrict__ src, long long lds,
+                                          int ld, int ncols, int r, int g, int G, cd (&acc)[NR]) {
   int c = g;
   for (; c + 3 * G < ncols; c += 4 * G) {
     const cd a0 = to_cd(A[(size_t)c * ld + r]);
     const cd a1 = to_cd(A[(size_t)(c + G) * ld + r]);
     const cd a2 = to_cd(A[(size_t)(c + 2 * G) * ld + r]);
     const cd a3 = to_cd(A[(size_t)(c + 3 * G) * ld + r]);
-    acc += a0 * src[c];
-    acc += a1 * src[c + G];
-    acc += a2 * src[c + 2 * G];
-    acc += a3 * src[c + 3 * G];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const cd* sq = src + q * lds;
+      acc[q] += a0 * sq[c];
+      acc[q] += a1 * sq[c + G];
+      acc[q] += a2 * sq[c + 2 * G];
+      acc[q] += a3 * sq[c + 3 * G];
+    }
   }
-  for (; c < ncols; c += G) acc += to_cd(A[(size_t)c * ld + r]) * src[c];
-  return acc;
+  for (; c < ncols; c += G) {
+    const cd a0 = to_cd(A[(size_t)c * ld + r]);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] += a0 * src[c + q * lds];
+  }
 }
 
+template <int NR>
 __global__ __launch_bounds__(256) void k_hmv(const RowTask* __restrict__ tasks, const Seg* __restrict__ segs,
-                                             const cd* __restrict__ x, const cd* __restrict__ z,
-                                             cd* __restrict__ partial) {
+                                             const cd* __restrict__ x, long long ldx, const cd* __restrict__ z,
+                                             long long ldz, cd* __restrict__ partial, long long ldp) {
   const RowTask T = tasks[blockIdx.x];
   const int rows_pad = (T.rows + 63) & ~63;
   const int G = 256 / rows_pad;
   const int r = threadIdx.x % rows_pad, g = threadIdx.x / rows_pad;
-  __shared__ cd red[256];
-  cd acc = mk(0.0);
+  __shared__ cd red[NR][256];
+  cd acc[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] = mk(0.0);
   if (g < G && r < T.rows) {
     for (int s = T.s0; s < T.s1; ++s) {
       const Seg S = segs[s];
-      const cd* src = ((S.flags & SEG_FROM_Z) ? z : x) + S.src;
+      const bool fz = (S.flags & SEG_FROM_Z) != 0;
+      const cd* src = (fz ? z : x) + S.src;
+      const long long lds = fz ? ldz : ldx;
       if (S.flags & SEG_C64)
-        acc += panel_dot((const cf*)S.A, src, S.ld, S.ncols, r, g, G);
+        panel_dot<cf, NR>((const cf*)S.A, src, lds, S.ld, S.ncols, r, g, G, acc);
       else
-        acc += panel_dot((const cd*)S.A, src, S.ld, S.ncols, r, g, G);
+        panel_dot<cd, NR>((const cd*)S.A, src, lds, S.ld, S.ncols, r, g, G, acc);
     }
   }
-  red[threadIdx.x] = acc;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) red[q][threadIdx.x] = acc[q];
   __syncthreads();
   if (threadIdx.x < T.rows) {
-    cd s = red[threadIdx.x];
-    for (int q = 1; q < G; ++q) s += red[q * rows_pad + threadIdx.x];
-    partial[(size_t)blockIdx.x * HMV_MAXROWS + threadIdx.x] = s;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      cd s = red[q][threadIdx.x];
+      for (int k = 1; k < G; ++k) s += red[q][k * rows_pad + threadIdx.x];
+      partial[q * ldp + (size_t)blockIdx.x * HMV_MAXROWS + threadIdx.x] = s;
+    }
   }
 }
 
-void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, const cd* z,
-                cd* partial, hipStream_t st) {
-  if (ntask > 0) hipLaunchKernelGGL(k_hmv, dim3(ntask), dim3(256), 0, st, tasks, segs, x, z, partial);
+void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, long long ldx, int nrhs,
+                const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st) {
+  if (ntask <= 0) return;
+  switch (nrhs) {
+    case 1: hipLaunchKernelGGL(k_hmv<1>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    case 2: hipLaunchKernelGGL(k_hmv<2>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    case 3: hipLaunchKernelGGL(k_hmv<3>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    case 4: hipLaunchKernelGGL(k_hmv<4>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    default: throw ApiError(-1, "matvec: 1 to 4 right-hand sides");
+  }
 }
 
-__global__ void k_hmv_reduce(const LeafRange* __restrict__ leaves, const cd* __restrict__ partial,
-                             cd* __restrict__ y) {
+__global__ void k_hmv_reduce(const LeafRange* __restrict__ leaves, const cd* __restrict__ partial, long long ldp,
+                             cd* __restrict__ y, long long ldy) {
   const LeafRange L = leaves[blockIdx.x];
   const int r = threadIdx.x;
   if (r >= L.rows) return;
+  const int q = blockIdx.y;
+  const cd* pq = partial + q * ldp;
   cd s = mk(0.0);
-  for (int t = L.t0; t < L.t1; ++t) s += partial[(size_t)t * HMV_MAXROWS + r];
-  y[L.row0 + r] = s;
+  for (int t = L.t0; t < L.t1; ++t) s += pq[(size_t)t * HMV_MAXROWS + r];
+  y[q * ldy + L.row0 + r] = s;
 }
 
-void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, cd* y,
-                       hipStream_t st) {
+void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, long long ldp, int nrhs, cd* y,
+                       long long ldy, hipStream_t st) {
   if (nleaf > 0)
-    hipLaunchKernelGGL(k_hmv_reduce, dim3(nleaf), dim3(HMV_MAXROWS), 0, st, leaves, partial, y);
+    hipLaunchKernelGGL(k_hmv_reduce, dim3(nleaf, nrhs), dim3(HMV_MAXROWS), 0, st, leaves, partial, ldp, y, ldy);
 }
 
 }  // namespace ewbem
