@@ -274,8 +274,8 @@ def main():
             "freq_solves_per_step": solves // args.steps, "sigma": d["sigma"], "period": d["period"],
             "leaf": 64, "eta_adm": 1.0, "aca_tol": 1e-5, "gmres_tol": 1e-6, "guess": "LS-SEM K=3",
             "precond": "leaf block-diagonal", "far_store": args.store, "arith": "complex128",
-            "aca_starts_per_step": {"warm": st["aca_warm_blocks"] // args.steps,
-                                    "cold": st["aca_cold_blocks"] // args.steps},
+            "aca_block_starts_per_frequency": {"warm": st["aca_warm_blocks"] / max(1, solves),
+                                               "cold": st["aca_cold_blocks"] / max(1, solves)},
         },
         "roofline": {
             "kernel": "H-matrix matvec (k_far_vt + k_hmv + k_hmv_reduce)",
