@@ -24,6 +24,21 @@ between 0 and 2, both of period 4 L / c.
 
 Kelvin's static kernels (the s -> 0 limit of U and T) are written out
 independently of the oracle's dynamic kernels.
+
+Spherical cavity under a wall pressure p(s) Y(x) with Y a spherical
+harmonic of degree l (the pressure pushes the solid away from the cavity, so
+sigma_rr = -p Y and the wall shear vanishes).  In the Laplace domain the
+displacement outside the cavity is u = grad Phi + curl curl (x Psi) with
+Phi = A k_l(s r / c_p) Y and Psi = B k_l(s r / c_s) Y, where k_l is the
+decaying modified spherical Bessel function, so that
+    u = u_r(r) Y e_r + u_t(r) grad_1 Y,
+    u_r = f' + l(l+1) g / r,   u_t = (f + g) / r + g',
+with f = A k_l(k_p r), g = B k_l(k_s r) and grad_1 Y = r grad Y the surface
+gradient on the unit sphere.  The two wall conditions,
+    lambda k_p^2 f + 2 mu u_r' = -p,
+    2 f'/r - 2 f / r^2 + g'' + (l(l+1) - 2) g / r^2 = 0,
+fix A and B (for l = 0 only the first applies and the field is the uniform
+case above).
 """
 
 from math import pi
@@ -130,3 +145,132 @@ def rod_step_fixed_stress(t, L, mat):
     t = np.asarray(t, dtype=np.float64)
     tau = np.mod(t - L / c, 4.0 * L / c)
     return np.where((t >= L / c) & (tau < 2.0 * L / c), 2.0, 0.0)
+
+
+# ---- spherical-harmonic wall pressure on a spherical cavity
+
+def _kl_coeffs(l):
+    """k_l(x) = exp(-x) sum_n c[n] x^{-n} (n = 1..l+1), the reverse Bessel
+    polynomial form of the decaying modified spherical Bessel function."""
+    from math import factorial
+    c = np.zeros(l + 3)
+    for j in range(l + 1):
+        c[j + 1] = factorial(l + j) / (factorial(j) * factorial(l - j) * 2.0 ** j)
+    return c
+
+
+def _kl_derivative(c):
+    """Coefficients of d/dx of exp(-x) sum c[n] x^{-n}."""
+    d = np.zeros(len(c) + 1)
+    for n, cn in enumerate(c):
+        d[n] -= cn              # from exp(-x)'
+        d[n + 1] -= n * cn      # from (x^{-n})'
+    return d
+
+
+def mod_sph_bessel_k(l, x):
+    """k_l(x), k_l'(x), k_l''(x) for complex x (normalised so that
+    k_0(x) = exp(-x) / x)."""
+    x = np.asarray(x, dtype=np.complex128)
+    c0 = _kl_coeffs(l)
+    c1 = _kl_derivative(c0)
+    c2 = _kl_derivative(c1)
+    out = []
+    for c in (c0, c1, c2):
+        v = np.zeros_like(x)
+        for n, cn in enumerate(c):
+            if cn != 0.0:
+                v = v + cn * x ** (-n)
+        out.append(np.exp(-x) * v)
+    return tuple(out)
+
+
+def sphere_sh_modes(s, l, a, mat):
+    """Amplitudes (A, B) of the two potentials for a unit wall pressure
+    coefficient, and the wall displacement factors (Hr, Ht): at r = a,
+    u = Hr Y e_r + Ht grad_1 Y."""
+    s = complex(s)
+    kp, ks = s / mat["cp"], s / mat["cs"]
+    lam, mu = mat["lam"], mat["mu"]
+    L = l * (l + 1)
+    fp = mod_sph_bessel_k(l, kp * a)   # values at r = a of k_l(kp r) and its x-derivatives
+    gs = mod_sph_bessel_k(l, ks * a)
+    # f, f', f'' per unit A; g, g', g'' per unit B (derivatives in r)
+    f = (fp[0], kp * fp[1], kp * kp * fp[2])
+    g = (gs[0], ks * gs[1], ks * ks * gs[2])
+    # sigma_rr: lambda kp^2 f + 2 mu (f'' + L (g'/a - g/a^2))
+    m11 = lam * kp * kp * f[0] + 2 * mu * f[2]
+    m12 = 2 * mu * L * (g[1] / a - g[0] / a ** 2)
+    if l == 0:
+        A, B = -1.0 / m11, 0.0
+    else:
+        # shear: 2 f'/a - 2 f / a^2 + g'' + (L - 2) g / a^2 = 0
+        m21 = 2 * f[1] / a - 2 * f[0] / a ** 2
+        m22 = g[2] + (L - 2) * g[0] / a ** 2
+        A, B = np.linalg.solve(np.array([[m11, m12], [m21, m22]]), np.array([-1.0, 0.0]))
+    Hr = A * f[1] + L * B * g[0] / a
+    Ht = (A * f[0] + B * g[0]) / a + B * g[1]
+    return A, B, Hr, Ht
+
+
+def sphere_sh_radial(r, s, l, a, mat):
+    """u_r(r), u_t(r) outside the cavity for a unit wall pressure coefficient."""
+    A, B, _, _ = sphere_sh_modes(s, l, a, mat)
+    s = complex(s)
+    kp, ks = s / mat["cp"], s / mat["cs"]
+    r = np.asarray(r, dtype=np.float64)
+    fp = mod_sph_bessel_k(l, kp * r)
+    gs = mod_sph_bessel_k(l, ks * r)
+    f, f1 = A * fp[0], A * kp * fp[1]
+    g, g1 = B * gs[0], B * ks * gs[1]
+    L = l * (l + 1)
+    return f1 + L * g / r, (f + g) / r + g1
+
+
+def surface_gradient(Y, xhat, h=1e-5):
+    """grad_1 Y at unit vectors xhat by central differences in the tangent
+    plane (Y takes an (n, 3) array of unit vectors)."""
+    xhat = np.asarray(xhat, dtype=np.float64)
+    ref = np.where(np.abs(xhat[:, :1]) < 0.9, [[1.0, 0.0, 0.0]], [[0.0, 1.0, 0.0]])
+    e1 = np.cross(xhat, ref)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(xhat, e1)
+    out = np.zeros_like(xhat)
+    for e in (e1, e2):
+        fp = Y((xhat + h * e) / np.linalg.norm(xhat + h * e, axis=1, keepdims=True))
+        fm = Y((xhat - h * e) / np.linalg.norm(xhat - h * e, axis=1, keepdims=True))
+        out += ((fp - fm) / (2 * h))[:, None] * e
+    return out
+
+
+def sphere_sh_displacement(x, s, l, a, mat, Y, gradY=None):
+    """Displacement at points x (|x| >= a, cavity centred at the origin) for
+    the wall pressure coefficient 1 times Y (degree l).  Y maps unit vectors
+    to values; gradY (optional) to surface gradients."""
+    x = np.asarray(x, dtype=np.float64)
+    r = np.linalg.norm(x, axis=1)
+    xh = x / r[:, None]
+    ur, ut = sphere_sh_radial(r, s, l, a, mat)
+    yv = Y(xh)
+    gy = surface_gradient(Y, xh) if gradY is None else gradY(xh)
+    return (ur * yv)[:, None] * xh + ut[:, None] * gy
+
+
+def legendre_Y(l):
+    """Axisymmetric harmonic P_l(cos theta) and its exact surface gradient."""
+    from numpy.polynomial import legendre as Lg
+    c = np.zeros(l + 1)
+    c[l] = 1.0
+    dc = Lg.legder(c)
+
+    def Y(xh):
+        return Lg.legval(xh[:, 2], c)
+
+    def gradY(xh):
+        # grad_1 P_l(z) = P_l'(z) (e_z - z xhat)
+        z = xh[:, 2]
+        ez = np.zeros_like(xh)
+        ez[:, 2] = 1.0
+        return Lg.legval(z, dc)[:, None] * (ez - z[:, None] * xh)
+
+    return Y, gradY
