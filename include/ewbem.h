@@ -175,6 +175,23 @@ int ewbem_set_load_pressure(ewbem_ctx* ctx, const double* p, const double* histo
 int ewbem_set_load_mixed(ewbem_ctx* ctx, const int32_t* bc, const double* values,
                          const double* history);
 
+/* Scattering of a plane S-wave by the cavity (the boundary integral equation
+ * of Sec. 2.1 with the scattered field's traction as the given data; every
+ * element traction-free).  The incident field is
+ *   u_inc(x, t) = pol f(t - dir . x / c_s),  f(t) = (1 - 2a) exp(-a),
+ *   a = (pi ricker_fc (t - t0))^2,
+ * with f sampled at n dt (ewbem_set_time first).  In the Laplace domain its
+ * traction on a surface of normal n (out of the solid) is
+ *   t_inc(s) = -(mu s / c_s) F(s) exp(-s dir . x / c_s) (pol (dir . n) + dir (pol . n)),
+ * and the load is the scattered-field traction -t_inc at each element's
+ * centroid.  The unknowns and every output are the scattered displacement;
+ * the total motion is u_sc + u_inc.  dir and pol (host, 3 each) are
+ * normalised; EINVAL if either is zero, if they are not orthogonal
+ * (|dir . pol| > 1e-9 after normalising), or for ricker_fc <= 0.  Replaces
+ * any earlier load. */
+int ewbem_set_load_incident_s(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
+                              double t0);
+
 int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* opts);
 int ewbem_set_solver(ewbem_ctx* ctx, const ewbem_solver_opts* opts);
 

@@ -157,6 +157,15 @@ def traction_from_pressure(geom, p):
     return (-np.asarray(p, dtype=np.float64)[:, None] * geom["n"]).reshape(-1)
 
 
+def incident_s_load(geom, s, mat, direction, polarisation):
+    """Scattered-field load of a plane S-wave on a traction-free boundary, for
+    a unit wavelet spectrum: t_sc = -sigma_inc n at each element's centroid
+    (n out of the solid), flattened to 3 N_e."""
+    from .closed_form import plane_s_wave_stress
+    S = plane_s_wave_stress(geom["cen"], s, mat, direction, polarisation)
+    return (-np.einsum("eij,ej->ei", S, geom["n"])).reshape(-1)
+
+
 def mixed_system(T, U, bc, given):
     """Sec. 2.1, eq. Aa_b: the boundary conditions move the known boundary
     values to the right-hand side of T u = U t.  For an element with a given

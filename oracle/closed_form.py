@@ -274,3 +274,25 @@ def legendre_Y(l):
         return Lg.legval(z, dc)[:, None] * (ez - z[:, None] * xh)
 
     return Y, gradY
+
+
+# ---- plane S-wave (the incident field of the scattering load)
+
+def plane_s_wave(x, s, mat, direction, polarisation):
+    """Laplace transform of u(x, t) = pol f(t - dir . x / c_s) for a unit
+    spectrum F(s) = 1: pol exp(-s dir . x / c_s), shape (n, 3)."""
+    d = np.asarray(direction, float)
+    q = np.asarray(polarisation, float)
+    x = np.atleast_2d(np.asarray(x, float))
+    return np.exp(-complex(s) * (x @ d) / mat["cs"])[:, None] * q[None, :]
+
+
+def plane_s_wave_stress(x, s, mat, direction, polarisation):
+    """Its stress, sigma = 2 mu eps with eps = -(s / 2 c_s) (pol d^T + d pol^T)
+    times the phase (the wave is divergence free), shape (n, 3, 3)."""
+    d = np.asarray(direction, float)
+    q = np.asarray(polarisation, float)
+    x = np.atleast_2d(np.asarray(x, float))
+    ph = np.exp(-complex(s) * (x @ d) / mat["cs"])
+    S = -(mat["mu"] * complex(s) / mat["cs"]) * (np.outer(q, d) + np.outer(d, q))
+    return ph[:, None, None] * S[None]

@@ -53,3 +53,24 @@ def transient(xyz, tri, mat_params, period, n_f, sigma, window_kind,
             timings.append((t_b - t_a, t_c - t_b))
     u = mft.inverse(spec, period, sigma, window_kind)
     return dict(s=s_k, phat=phat, spec=spec, u=u, geom=geom, mat=mat, t0=t0)
+
+
+def transient_incident_s(xyz, tri, mat_params, period, n_f, sigma, window_kind, direction, polarisation,
+                         history, exterior=True, self_order=24):
+    """Scattered displacement on a traction-free boundary under the plane
+    S-wave u_inc = pol f(t - dir . x / c_s), f sampled in ``history``:
+    b_k = U(s_k) t_sc(s_k) F_k with t_sc the negated traction of the incident
+    wave (Sec. 2.1 equation with the scattered field as the unknown).
+
+    Returns dict(s, phat, spec (N_f/2+1, N), u (N_f, N))."""
+    mat = material(**mat_params)
+    geom = bem.geometry(xyz, tri, exterior=exterior)
+    s_k = mft.freq_grid(period, n_f, sigma)
+    phat = mft.load_spectrum(history, period, sigma)
+    spec = np.zeros((len(s_k), 3 * geom["ne"]), np.complex128)
+    for k, s in enumerate(s_k):
+        T, U = bem.assemble_dense(geom, s, mat, self_order=self_order)
+        t_sc = bem.incident_s_load(geom, s, mat, direction, polarisation)
+        spec[k] = np.linalg.solve(T, phat[k] * (U @ t_sc))
+    u = mft.inverse(spec, period, sigma, window_kind)
+    return dict(s=s_k, phat=phat, spec=spec, u=u, geom=geom, mat=mat)

@@ -101,6 +101,9 @@ struct ewbem_ctx {
   double sigma = 0;
   int window = EWBEM_WINDOW_HANN;
   bool load_is_pressure = false;
+  // plane S-wave incident load: u_inc = pol f(t - dir . x / c_s), f Ricker
+  bool load_incident = false;
+  double inc_dir[3] = {1, 0, 0}, inc_pol[3] = {0, 0, 1}, inc_fc = 0, inc_t0 = 0;
   std::vector<int> bc_caller;       // empty: every element has a given traction
   std::vector<double> load_caller;  // t0 (nt*3) or p (nt), caller order
   std::vector<double> history;
@@ -120,7 +123,7 @@ struct ewbem_ctx {
   std::vector<int> rank_h, status_h, kcap_prev;
 
   // ---- device state
-  DevBuf<double> d_cen, d_nrm, d_qp, d_qw, d_vtx, d_t0, d_hist;
+  DevBuf<double> d_cen, d_nrm, d_qp, d_qw, d_vtx, d_t0, d_hist, d_tau;
   DevBuf<int> d_perm, d_bc;
   DevBuf<cd> d_phat, d_selfT, d_selfU, d_selfA;
   DevBuf<NearBlk> d_near;
@@ -274,9 +277,24 @@ void ensure_structure(ewbem_ctx* c) {
 }
 
 std::vector<double> tree_load(ewbem_ctx* c) {
-  // traction per element in tree order
+  // traction per element in tree order; for the incident S-wave, the
+  // frequency-independent factor g of the scattered-field load
+  //   t_sc(s) = s F(s) exp(-s dir.x / c_s) g,  g = (mu / c_s)(pol (dir.n) + dir (pol.n))
+  // (the negated traction of the plane wave on a surface of normal n)
   const HostGeom& g = c->hg;
   std::vector<double> t0(3 * (size_t)c->nt);
+  if (c->load_incident) {
+    const double cs = std::sqrt(c->mu / c->rho), f = c->mu / cs;
+    const double* d = c->inc_dir;
+    const double* q = c->inc_pol;
+    for (int t = 0; t < c->nt; ++t) {
+      const double* n = &g.nrm[3 * (size_t)t];
+      const double dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+      const double qn = q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+      for (int k = 0; k < 3; ++k) t0[3 * (size_t)t + k] = f * (q[k] * dn + d[k] * qn);
+    }
+    return t0;
+  }
   for (int t = 0; t < c->nt; ++t) {
     const int e = g.perm[t];
     for (int k = 0; k < 3; ++k)
@@ -304,6 +322,15 @@ void ensure_device(ewbem_ctx* c) {
   c->d_perm.upload(g.perm, st);
   std::vector<double> t0 = tree_load(c);
   c->d_t0.upload(t0, st);
+  if (c->load_incident) {
+    // arrival delay of the plane wave at each collocation point
+    const double cs = std::sqrt(c->mu / c->rho);
+    std::vector<double> tau(c->nt);
+    for (int t = 0; t < c->nt; ++t)
+      tau[t] = (c->inc_dir[0] * g.cen[3 * (size_t)t] + c->inc_dir[1] * g.cen[3 * (size_t)t + 1] +
+                c->inc_dir[2] * g.cen[3 * (size_t)t + 2]) / cs;
+    c->d_tau.upload(tau, st);
+  }
   if (!c->bc_caller.empty()) {
     std::vector<int> bct(c->nt);
     for (int t = 0; t < c->nt; ++t) bct[t] = c->bc_caller[g.perm[t]];
@@ -886,8 +913,8 @@ void precond_apply(ewbem_ctx* c, const cd* v, cd* z) {
 void rhs_precompute(ewbem_ctx* c, const DevGeom& g, int k0, int nk) {
   const size_t need = (size_t)rhs_split(c->nt) * nk * 3 * (size_t)c->nt;
   c->d_rhs_part.reserve(need);
-  launch_rhs_multi(g, c->P, c->sigma, 2.0 * M_PI / c->period, k0, nk, c->d_t0.p, c->d_rhs_part.p,
-                   c->stream);
+  launch_rhs_multi(g, c->P, c->sigma, 2.0 * M_PI / c->period, k0, nk, c->d_t0.p,
+                   c->load_incident ? c->d_tau.p : nullptr, c->d_rhs_part.p, c->stream);
   c->boff_k0 = k0;
   c->boff_nk = nk;
 }
@@ -914,7 +941,7 @@ void assemble_k(ewbem_ctx* c, int k) {
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
   if (k < c->boff_k0 || k >= c->boff_k0 + c->boff_nk) rhs_precompute(c, g, k, 1);
   launch_rhs_finish(c->d_rhs_part.p, c->boff_nk, k - c->boff_k0, c->nt, c->d_selfU.p, c->d_t0.p,
-                    c->d_phat.p + k, c->d_b.p, st);
+                    c->load_incident ? c->d_tau.p : nullptr, s_of_k(c, k), c->d_phat.p + k, c->d_b.p, st);
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   precond_setup(c);
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -1369,6 +1396,7 @@ static int set_load(ewbem_ctx* ctx, const double* v, size_t nv_, const double* h
     ctx->load_caller.assign(v, v + nv_);
     ctx->history.assign(history, history + ctx->n_f);
     ctx->load_is_pressure = pressure;
+    ctx->load_incident = false;
     ctx->have_load = true;
     ctx->device_ok = false;
     ctx->assembled_k = -1;
@@ -1393,6 +1421,47 @@ int ewbem_set_load_mixed(ewbem_ctx* ctx, const int32_t* bc, const double* values
     return EWBEM_OK;
   });
   return set_load(ctx, values, 3 * (size_t)ctx->nt, history, false, bc);
+}
+
+int ewbem_set_load_incident_s(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
+                              double t0) {
+  return guard(ctx, [&] {
+    if (!ctx->have_mesh || !ctx->have_time) fail(EWBEM_ESTATE, "load: set the mesh and time grid first");
+    if (!dir || !pol) fail(EWBEM_EINVAL, "incident wave: null direction or polarisation");
+    if (!finite_all(dir, 3) || !finite_all(pol, 3) || !std::isfinite(ricker_fc) || !std::isfinite(t0) ||
+        !(ricker_fc > 0))
+      fail(EWBEM_EINVAL, "incident wave: non-finite input or non-positive frequency");
+    const double nd = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    const double np = std::sqrt(pol[0] * pol[0] + pol[1] * pol[1] + pol[2] * pol[2]);
+    if (!(nd > 0) || !(np > 0)) fail(EWBEM_EINVAL, "incident wave: zero direction or polarisation");
+    double dd[3], pp[3], dp = 0;
+    for (int k = 0; k < 3; ++k) {
+      dd[k] = dir[k] / nd;
+      pp[k] = pol[k] / np;
+      dp += dd[k] * pp[k];
+    }
+    if (std::fabs(dp) > 1e-9) fail(EWBEM_EINVAL, "incident S-wave: polarisation must be normal to the direction");
+    const double dt = ctx->period / ctx->n_f;
+    ctx->history.resize(ctx->n_f);
+    for (int n = 0; n < ctx->n_f; ++n) {
+      const double a = std::pow(M_PI * ricker_fc * (n * dt - t0), 2);
+      ctx->history[n] = (1.0 - 2.0 * a) * std::exp(-a);
+    }
+    for (int k = 0; k < 3; ++k) {
+      ctx->inc_dir[k] = dd[k];
+      ctx->inc_pol[k] = pp[k];
+    }
+    ctx->inc_fc = ricker_fc;
+    ctx->inc_t0 = t0;
+    ctx->bc_caller.clear();
+    ctx->load_caller.clear();
+    ctx->load_is_pressure = false;
+    ctx->load_incident = true;
+    ctx->have_load = true;
+    ctx->device_ok = false;
+    ctx->assembled_k = -1;
+    return EWBEM_OK;
+  });
 }
 
 int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {

@@ -263,13 +263,16 @@ void launch_dense_self(const cd* selfT, const cd* selfU, const int* perm, int ne
 // Targets are tiled 256 per workgroup, the sources split into RHS_SPLIT
 // ranges (staged in LDS, RHS_TILE elements at a time); each range writes
 // its own partial vector and k_rhs_finish sums them in a fixed order.
+// INC: the load of a plane wave, exp(-s_k tau_e) t0_e per source element,
+// whose phase advances with the frequency in the same way.
 constexpr int RHS_NK = 8;
 constexpr int RHS_TILE = 128;
 
+template <bool INC>
 __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double sigma, double dw, int k0,
                                                    int nk, const double* __restrict__ t0,
-                                                   cd* __restrict__ partial) {
-  __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[RHS_TILE * 3];
+                                                   const double* __restrict__ tau, cd* __restrict__ partial) {
+  __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[RHS_TILE * 3], stau[INC ? RHS_TILE : 1];
   const int ne = g.ne;
   const int kst = k0 + blockIdx.y * RHS_NK;          // first frequency of this pass
   const int nkc = min(RHS_NK, k0 + nk - kst);        // frequencies in this pass
@@ -293,11 +296,24 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
     for (int i = threadIdx.x; i < nc * 21; i += blockDim.x) sq[i] = g.qp[(size_t)c0 * 21 + i];
     for (int i = threadIdx.x; i < nc * 7; i += blockDim.x) sw[i] = g.qw[(size_t)c0 * 7 + i];
     for (int i = threadIdx.x; i < nc * 3; i += blockDim.x) stt[i] = t0[(size_t)c0 * 3 + i];
+    if (INC)
+      for (int i = threadIdx.x; i < nc; i += blockDim.x) stau[i] = tau[c0 + i];
     __syncthreads();
     if (!act) continue;
     for (int b = 0; b < nc; ++b) {
       if (c0 + b == a) continue;
       const double* tb = stt + 3 * b;
+      // incident wave: the source's load at s_kst and its step to s_{k+1}
+      cd sph = mk(1.0), srot = mk(1.0);
+      if (INC) {
+        double sn, cs;
+        const double ta = stau[b];
+        sincos(kst * dw * ta, &sn, &cs);
+        const double m = exp(-sigma * ta);
+        sph = cd{m * cs, -m * sn};
+        sincos(dw * ta, &sn, &cs);
+        srot = cd{cs, -sn};
+      }
       for (int qq = 0; qq < 7; ++qq) {
         const double* y = sq + 21 * b + 3 * qq;
         const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
@@ -318,6 +334,7 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
         cd php = cd{mp * cs, -mp * sn};
         sincos(gam * th, &sn, &cs);
         const cd rotp = cd{cs, -sn};
+        cd sp = sph;
 #pragma unroll
         for (int j = 0; j < RHS_NK; ++j) {
           if (j < nkc) {
@@ -338,7 +355,12 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
               rphi = ph * (1.0 + iz + iz2) - php * (gi + iz2);
               rpsi = ph * (1.0 + 3.0 * iz + 3.0 * iz2) - php * (P.g2 + 3.0 * gi + 3.0 * iz2);
             }
-            const cd f = rphi * sc, gg = rpsi * (sc * ht);
+            cd f = rphi * sc, gg = rpsi * (sc * ht);
+            if (INC) {
+              f = f * sp;
+              gg = gg * sp;
+              sp = sp * srot;
+            }
             acc[j][0] += f * tb[0] - gg * h0;
             acc[j][1] += f * tb[1] - gg * h1;
             acc[j][2] += f * tb[2] - gg * h2;
@@ -365,29 +387,44 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
 // + U_self t0)
 __global__ void k_rhs_finish(const cd* __restrict__ partial, int nsplit, int nk, int kk, int ne,
                              const cd* __restrict__ selfU, const double* __restrict__ t0,
-                             const cd* __restrict__ phat_k, cd* __restrict__ b) {
+                             const double* __restrict__ tau, cd s_k, const cd* __restrict__ phat_k,
+                             cd* __restrict__ b) {
   const int d = blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= 3 * ne) return;
   const int e = d / 3, i = d - 3 * e;
   cd acc = mk(0.0);
   for (int sp = 0; sp < nsplit; ++sp) acc += partial[((size_t)sp * nk + kk) * 3 * ne + d];
-  for (int j = 0; j < 3; ++j) acc += selfU[9 * (size_t)e + 3 * i + j] * t0[3 * e + j];
-  b[d] = acc * phat_k[0];
+  cd self = mk(0.0);
+  for (int j = 0; j < 3; ++j) self += selfU[9 * (size_t)e + 3 * i + j] * t0[3 * e + j];
+  if (tau) {
+    // exp(-s_k tau_e) on the element's own load, and the factor s_k of the
+    // incident wave's traction
+    double sn, cs;
+    sincos(s_k.y * tau[e], &sn, &cs);
+    const double m = exp(-s_k.x * tau[e]);
+    acc += self * cd{m * cs, -m * sn};
+    b[d] = acc * phat_k[0] * s_k;
+  } else {
+    b[d] = (acc + self) * phat_k[0];
+  }
 }
 
 int rhs_split(int ne) { return ne >= 4096 ? 4 : 1; }
 
 void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk,
-                      const double* t0, cd* partial, hipStream_t st) {
+                      const double* t0, const double* tau, cd* partial, hipStream_t st) {
   if (nk <= 0) return;
   dim3 grid((g.ne + 255) / 256, (nk + RHS_NK - 1) / RHS_NK, rhs_split(g.ne));
-  hipLaunchKernelGGL(k_rhs_multi, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, t0, partial);
+  if (tau)
+    hipLaunchKernelGGL(k_rhs_multi<true>, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, t0, tau, partial);
+  else
+    hipLaunchKernelGGL(k_rhs_multi<false>, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, t0, tau, partial);
 }
 
 void launch_rhs_finish(const cd* partial, int nk, int kk, int ne, const cd* selfU, const double* t0,
-                       const cd* phat_k, cd* b, hipStream_t st) {
+                       const double* tau, cd s_k, const cd* phat_k, cd* b, hipStream_t st) {
   hipLaunchKernelGGL(k_rhs_finish, dim3((3 * ne + 255) / 256), dim3(256), 0, st, partial, rhs_split(ne), nk,
-                     kk, ne, selfU, t0, phat_k, b);
+                     kk, ne, selfU, t0, tau, s_k, phat_k, b);
 }
 
 // Parity path: the point kernels U_ij(x, y) and T_ij(x, y; n) for n pairs.

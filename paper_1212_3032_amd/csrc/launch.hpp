@@ -35,11 +35,14 @@ void launch_dense_self(const cd* selfT, const cd* selfU, const int* perm, int ne
                        cd* Uout, hipStream_t st);
 // Off-diagonal part of U(s_k) t0 for k = k0 .. k0+nk-1 (s_k = sigma + i k dw)
 // into partial[rhs_split(ne)][nk][3 ne]; then b_k = P_k (sum + U_self t0).
+// With tau (per element, tree order) the load of element e at s_k is
+// exp(-s_k tau_e) t0_e (a plane wave arriving at tau_e), and
+// b_k = P_k s_k (sum + U_self exp(-s_k tau) t0).
 int rhs_split(int ne);
 void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk,
-                      const double* t0, cd* partial, hipStream_t st);
+                      const double* t0, const double* tau, cd* partial, hipStream_t st);
 void launch_rhs_finish(const cd* partial, int nk, int kk, int ne, const cd* selfU, const double* t0,
-                       const cd* phat_k, cd* b, hipStream_t st);
+                       const double* tau, cd s_k, const cd* phat_k, cd* b, hipStream_t st);
 void launch_kernel_eval(const KParams& P, long long n, const double* x, const double* y,
                         const double* nrm, cd* U, cd* T, hipStream_t st);
 

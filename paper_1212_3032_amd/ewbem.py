@@ -24,6 +24,7 @@ EXPORTED = [
     "ewbem_default_op_opts", "ewbem_default_solver_opts", "ewbem_create", "ewbem_destroy",
     "ewbem_last_error", "ewbem_set_mesh", "ewbem_set_material", "ewbem_set_time",
     "ewbem_set_load_traction", "ewbem_set_load_pressure", "ewbem_set_load_mixed",
+    "ewbem_set_load_incident_s",
     "ewbem_set_operator",
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
@@ -96,6 +97,7 @@ def lib():
         "ewbem_set_load_traction": (C.c_int, [P, P, P]),
         "ewbem_set_load_pressure": (C.c_int, [P, P, P]),
         "ewbem_set_load_mixed": (C.c_int, [P, P, P, P]),
+        "ewbem_set_load_incident_s": (C.c_int, [P, P, P, D, D]),
         "ewbem_set_operator": (C.c_int, [P, C.POINTER(OpOpts)]),
         "ewbem_set_solver": (C.c_int, [P, C.POINTER(SolverOpts)]),
         "ewbem_info": (C.c_int, [P, C.POINTER(Info)]),
@@ -235,6 +237,16 @@ class Context:
         if bc.shape != (self.nt,) or v.size != 3 * self.nt or h.shape != (self.n_f,):
             raise ValueError("bc must have nt entries, values 3 nt, history n_f")
         self._check(self._L.ewbem_set_load_mixed(self.h, pb, pv, ph))
+
+    def set_load_incident_s(self, direction, polarisation, ricker_fc, t0):
+        """Plane S-wave u_inc = pol f(t - dir.x / c_s), f a Ricker wavelet of
+        centre frequency ricker_fc peaking at t0; outputs are the scattered
+        displacement."""
+        d, pd = _host(direction, np.float64)
+        q, pq = _host(polarisation, np.float64)
+        if d.shape != (3,) or q.shape != (3,):
+            raise ValueError("direction and polarisation must have 3 entries")
+        self._check(self._L.ewbem_set_load_incident_s(self.h, pd, pq, float(ricker_fc), float(t0)))
 
     def set_operator(self, **kw):
         o = default_op_opts(**kw)
