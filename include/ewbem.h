@@ -241,6 +241,18 @@ int ewbem_solve_frequency(ewbem_ctx* ctx, int32_t k, const ewbem_z* x0, ewbem_z*
  * complex, or NULL. */
 int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats* stats);
 
+/* Several problems at once (one context each, all distinct): up to
+ * per_launch of them run concurrently from host threads, each with its
+ * whole frequency loop on its own context's stream (contexts created on the
+ * same stream serialise).  u_out[i] (device, n_f x 3 nt of context i) as in
+ * ewbem_solve_transient.  stats (optional) sums the contexts' counters and
+ * times and takes the maxima of resid_max, iters_max and rank_max.  Returns
+ * the first hard error of any context, else ENOCONV if any frequency of any
+ * context missed the tolerance (its outputs are still written), else OK;
+ * EINVAL for null or repeated contexts or per_launch < 1. */
+int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewbem_stats* stats,
+                                int32_t per_launch);
+
 /* Sec. 3.3 (inverse): u(n dt) = Re{exp(sigma n dt) sum_k W_k a_k
  * exp(2 pi i n k / N_f)} with a_{N_f-k} = conj(a_k).  spec: device,
  * (N_f/2+1) x N complex (caller order); u: device, N_f x N doubles. */

@@ -7,6 +7,8 @@
 #include <complex>
 #include <cstring>
 #include <functional>
+#include <thread>
+#include <atomic>
 #include <memory>
 #include <new>
 #include <string>
@@ -1682,6 +1684,72 @@ int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats*
     if (rc != EWBEM_OK) ctx->err = "GMRES did not reach the tolerance within maxit at some frequency";
     return rc;
   });
+}
+
+int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewbem_stats* stats,
+                                int32_t per_launch) {
+  if (n < 0 || per_launch < 1 || (n > 0 && (!ctxs || !u_out))) return EWBEM_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !u_out[i]) return EWBEM_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return EWBEM_EINVAL;  // one context, one problem
+  }
+  std::vector<int> rc(n, EWBEM_OK);
+  std::vector<ewbem_stats> st(n);
+  std::atomic<int> next{0};
+  auto worker = [&] {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) break;
+      if (ctxs[i]->device >= 0 && hipSetDevice(ctxs[i]->device) != hipSuccess) {
+        rc[i] = EWBEM_EHIP;
+        continue;
+      }
+      rc[i] = ewbem_solve_transient(ctxs[i], u_out[i], nullptr, &st[i]);
+    }
+  };
+  const int nth = std::min(n, (int)per_launch);
+  std::vector<std::thread> th;
+  for (int t = 1; t < nth; ++t) th.emplace_back(worker);
+  if (nth > 0) worker();
+  for (auto& t : th) t.join();
+  if (stats) {
+    ewbem_stats a{};
+    for (int i = 0; i < n; ++i) {
+      const ewbem_stats& b = st[i];
+      a.n_solves += b.n_solves;
+      a.iters_total += b.iters_total;
+      a.iters_max = std::max(a.iters_max, b.iters_max);
+      a.matvecs += b.matvecs;
+      a.resid_max = std::max(a.resid_max, b.resid_max);
+      a.guess_resid_sum += b.guess_resid_sum;
+      a.t_assemble_ms += b.t_assemble_ms;
+      a.t_guess_ms += b.t_guess_ms;
+      a.t_gmres_ms += b.t_gmres_ms;
+      a.t_post_ms += b.t_post_ms;
+      a.t_matvec_ms += b.t_matvec_ms;
+      a.matvec_bytes += b.matvec_bytes;
+      a.stored_bytes += b.stored_bytes;
+      a.n_near += b.n_near;
+      a.n_far += b.n_far;
+      a.rank_sum += b.rank_sum;
+      a.rank_max = std::max(a.rank_max, b.rank_max);
+      a.t_aca_ms += b.t_aca_ms;
+      a.t_near_ms += b.t_near_ms;
+      a.t_rhs_ms += b.t_rhs_ms;
+      a.matvec_bytes_total += b.matvec_bytes_total;
+      a.matvecs_timed += b.matvecs_timed;
+      a.aca_warm_blocks += b.aca_warm_blocks;
+      a.aca_cold_blocks += b.aca_cold_blocks;
+    }
+    *stats = a;
+  }
+  int out = EWBEM_OK;
+  for (int i = 0; i < n; ++i)
+    if (rc[i] != EWBEM_OK && rc[i] != EWBEM_ENOCONV) return rc[i];
+  for (int i = 0; i < n; ++i)
+    if (rc[i] == EWBEM_ENOCONV) out = EWBEM_ENOCONV;
+  return out;
 }
 
 int ewbem_mft_inverse(ewbem_ctx* ctx, const ewbem_z* spec, double* u) {

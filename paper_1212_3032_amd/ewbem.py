@@ -28,7 +28,8 @@ EXPORTED = [
     "ewbem_set_operator",
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
-    "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_mft_inverse",
+    "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_batch_solve_transient",
+    "ewbem_mft_inverse",
 ]
 
 
@@ -110,6 +111,7 @@ def lib():
         "ewbem_get_rhs": (C.c_int, [P, P]),
         "ewbem_solve_frequency": (C.c_int, [P, I32, P, P, C.POINTER(Stats)]),
         "ewbem_solve_transient": (C.c_int, [P, P, P, C.POINTER(Stats)]),
+        "ewbem_batch_solve_transient": (C.c_int, [P, I32, P, C.POINTER(Stats), I32]),
         "ewbem_mft_inverse": (C.c_int, [P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -330,6 +332,24 @@ class Context:
         self._check(self._L.ewbem_mft_inverse(
             self.h, _dev_ptr(spec, "torch.complex128", (self.n_f // 2 + 1) * N),
             _dev_ptr(u, "torch.float64", self.n_f * N)))
+
+
+def batch_solve_transient(ctxs, outs, per_launch=16, allow_noconv=False):
+    """Solve the transients of several contexts (distinct, ideally each on its
+    own stream) concurrently; outs[i] is context i's n_f x 3 nt float64
+    device tensor.  Returns the aggregated stats."""
+    if len(ctxs) != len(outs):
+        raise ValueError("one output per context")
+    n = len(ctxs)
+    hs = (C.c_void_p * max(n, 1))(*[c.h.value for c in ctxs])
+    us = (C.c_void_p * max(n, 1))(*[_dev_ptr(u, "torch.float64", c.n_f * 3 * c.nt).value
+                                    for c, u in zip(ctxs, outs)])
+    st = Stats()
+    rc = lib().ewbem_batch_solve_transient(hs, n, us, C.byref(st), int(per_launch))
+    if rc != OK and not (allow_noconv and rc == ENOCONV):
+        raise EwbemError(rc, "batch transient solve failed: " + "; ".join(
+            (lib().ewbem_last_error(c.h) or b"").decode() for c in ctxs))
+    return st.as_dict()
 
 
 def setup_from_inputs(ctx, d, op=None, solver=None):
