@@ -64,6 +64,8 @@ extern "C" {
 #define EWBEM_GUESS_ZERO 0
 #define EWBEM_GUESS_SEM 1    /* least-squares extrapolation, Sec. 4.2 */
 #define EWBEM_GUESS_QUAD 2   /* Lagrange extrapolation 3a1 - 3a2 + a3 */
+#define EWBEM_GUESS_LEARNED 3 /* least-squares extrapolation with one more column, the
+                                 trained network's prediction (ewbem_guess_train) */
 
 typedef struct ewbem_ctx ewbem_ctx; /* opaque, owned by the library */
 
@@ -119,7 +121,29 @@ typedef struct {
   int64_t aca_warm_blocks; /* far blocks whose ACA started from previous pivots */
   int64_t aca_cold_blocks; /* far blocks whose ACA started from scratch (capacity
                               retries, always from scratch, are not counted again) */
+  int64_t guess_learned;   /* frequencies whose guess included the network's prediction */
+  double pod_energy;       /* ewbem_guess_train: fraction of the training solutions'
+                              squared norm inside the reduced basis */
+  double train_loss_first; /* ewbem_guess_train: mean squared error of the network on */
+  double train_loss_last;  /*   its samples before the first and after the last step */
 } ewbem_stats;
+
+/* Training of the learned initial guess (ewbem_guess_train). */
+typedef struct {
+  int32_t n_modes;     /* reduced coordinates r: basis size (default 64) */
+  int32_t hidden;      /* width of each hidden layer (default 256) */
+  int32_t n_hidden;    /* hidden layers, 0..8 (default 3) */
+  int32_t epochs;      /* full-batch Adam steps (default 2000) */
+  double lr;           /* Adam step size, cosine-decayed to lr / 10 (default 1e-3) */
+  int32_t power_iters; /* subspace iterations of the randomized range finder (default 2) */
+  int32_t load_kind;   /* 0: each case is nt x 3 tractions; 1: nt pressures (default 0) */
+  uint64_t seed;       /* initial weights, the range finder's sketch and the
+                          augmentation weights (default 1) */
+  int32_t augment;     /* virtual cases per case: random complex combinations of the
+                          cases' coordinate sequences (exact, the solution being
+                          linear in the load), 0..64 (default 4) */
+  int32_t pad;
+} ewbem_train_opts;
 
 typedef struct {
   int64_t n_elements, n_dof;
@@ -131,6 +155,7 @@ typedef struct {
 /* Fill option structs with their defaults. */
 void ewbem_default_op_opts(ewbem_op_opts* o);
 void ewbem_default_solver_opts(ewbem_solver_opts* o);
+void ewbem_default_train_opts(ewbem_train_opts* o);
 
 /* Create a context on GPU ``device`` enqueuing on ``hip_stream`` (a
  * hipStream_t, borrowed; NULL = the null stream).  device = -1 creates a
@@ -252,6 +277,75 @@ int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats*
  * EINVAL for null or repeated contexts or per_launch < 1. */
 int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewbem_stats* stats,
                                 int32_t per_launch);
+
+/* ---- Learned initial guess (an addition to the method; Sec. 4.2 supplies
+ * the extrapolation it extends).
+ *
+ * ewbem_guess_train solves the whole frequency sequence for n_cases loads
+ * (same mesh, material, time grid, operator and solver settings, and the
+ * load history of the context's current traction or pressure load), then
+ *   - takes the r dominant left singular directions of all those solutions
+ *     (randomized range finder with power_iters subspace iterations on
+ *     r + 16 columns, then the exact eigen-decomposition of the sketch):
+ *     the basis Phi, N x r with orthonormal columns;
+ *   - forms, for every case and k = 3..N_f/2, the reduced coordinates
+ *     c_j = Phi^H a_j of the solutions at k-1, k-2, k-3 and at k; the
+ *     network's input is [Re, Im of c_{k-1}, c_{k-2}, c_{k-3}] / nu with
+ *     nu = |c_{k-1}|, followed by f and f^2 (f = k / (N_f/2)); its target is
+ *     [Re, Im of c_k - (3 c_{k-1} - 3 c_{k-2} + c_{k-3})] / nu; the samples
+ *     also come from augment x n_cases virtual cases, each a combination of
+ *     the cases' coordinate sequences with complex N(0, 1/n_cases) weights;
+ *   - fits a network of n_hidden GELU layers of width hidden (bf16 weights
+ *     and activations in the products, fp32 accumulation) by full-batch Adam
+ *     on the mean squared error.
+ * With EWBEM_GUESS_LEARNED, frequency k >= 3 then adds the vector
+ *   Phi (3 c_{k-1} - 3 c_{k-2} + c_{k-3} + nu y)  (y: network output)
+ * as one more column to the least-squares extrapolation, so the guess is
+ * never worse in residual than the extrapolation alone over the same
+ * history; k < 3 uses the extrapolation alone.  The context's own load is
+ * restored afterwards.  loads: host, n_cases x nt x 3 tractions
+ * (load_kind 0) or n_cases x nt pressures (1), caller order.  stats sum the
+ * training solves and report pod_energy and the fit's losses.  ESTATE
+ * without mesh, time grid and a traction or pressure load; EINVAL if
+ * N_f < 6, n_modes exceeds the snapshots n_cases (N_f/2 + 1) or N, or there
+ * are more than 65535 snapshots.  ENOCONV if a training solve missed the
+ * tolerance (the model is still fitted).  A new mesh drops the model. */
+int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, const ewbem_train_opts* opts,
+                      ewbem_stats* stats);
+
+/* Serialise the model (basis in caller order, network) into buf (host).
+ * buf = NULL: *len receives the size.  EINVAL if *len is too small (then
+ * *len is the size needed); ESTATE without a model.  Layout: 8 bytes
+ * "EWBGUESS"; int32 version 1, N, r, L; int32 widths dims[0..L]; fp64 pod
+ * energy, first and last training loss; fp32 parameters (per layer W_l row-
+ * major dims[l+1] x dims[l], then b_l); complex128 basis N x r column-major.
+ * All little-endian, no padding. */
+int ewbem_guess_save(const ewbem_ctx* ctx, void* buf, size_t* len);
+
+/* Load a model written by ewbem_guess_save (host buffer of len bytes) for
+ * a mesh with the same number of unknowns.  EINVAL on a malformed or
+ * mismatched buffer; ESTATE without a mesh.  Host-only contexts accept it. */
+int ewbem_guess_load(ewbem_ctx* ctx, const void* buf, size_t len);
+
+/* The model's basis size (n_modes, may be NULL) and basis (phi: device,
+ * N x r complex column-major in caller order, or NULL). */
+int ewbem_guess_basis(ewbem_ctx* ctx, int32_t* n_modes, ewbem_z* phi);
+
+/* The network's kernels on caller data (all arrays device fp32, row-major):
+ * n_layers layers of widths dims[0..n_layers] (host), GELU after all but the
+ * last, params laid out as in the saved model.  ewbem_mlp_eval: y (batch x
+ * dims[L]) = net(x) (x: batch x dims[0]); with target (batch x dims[L]):
+ * loss = mean of (y - target)^2 over all batch dims[L] entries and, if grad
+ * is given, grad = d loss / d params.  batch = 0 writes nothing (grad zero,
+ * loss 0).  ewbem_mlp_train: epochs full-batch Adam steps (beta 0.9, 0.999,
+ * eps 1e-8, constant step lr) on that loss, params updated in place;
+ * loss_first / loss_last (optional) before the first and after the last
+ * step. */
+int ewbem_mlp_eval(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, const float* params, int64_t batch,
+                   const float* x, const float* target, float* y, float* grad, double* loss);
+int ewbem_mlp_train(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, float* params, int64_t batch,
+                    const float* x, const float* target, int32_t epochs, double lr, double* loss_first,
+                    double* loss_last);
 
 /* Sec. 3.3 (inverse): u(n dt) = Re{exp(sigma n dt) sum_k W_k a_k
  * exp(2 pi i n k / N_f)} with a_{N_f-k} = conj(a_k).  spec: device,

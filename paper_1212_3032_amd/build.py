@@ -18,7 +18,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libewbem.so")
 
-SOURCES = ["host.cpp", "assemble.hip", "aca.hip", "aca_warm.hip", "hmatvec.hip", "solver.hip", "api.hip"]
+SOURCES = ["host.cpp", "assemble.hip", "aca.hip", "aca_warm.hip", "hmatvec.hip", "solver.hip", "learn.hip", "learn_host.cpp", "api.hip"]
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -11,6 +11,7 @@
 #include <atomic>
 #include <memory>
 #include <new>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,7 @@
 #include "aca.hpp"
 #include "host.hpp"
 #include "launch.hpp"
+#include "learn.hpp"
 #include "solver.hpp"
 
 using namespace ewbem;
@@ -84,6 +86,18 @@ struct EventPair {
 
 void fail(int st, const std::string& m) { throw ApiError(st, m); }
 
+}  // namespace
+
+namespace {
+// A trained network with its reduced basis (what ewbem_guess_save stores).
+struct LearnedModel {
+  bool ok = false;
+  int r = 0;                               // reduced coordinates
+  MlpShape shape;                          // dims: 6 r + 2, hidden..., 2 r
+  std::vector<float> params;               // flat fp32 parameters
+  std::vector<std::complex<double>> phi;   // basis, N x r column-major, caller dof order
+  double energy = 0, loss0 = 0, loss1 = 0;  // training snapshots' energy in the basis; fit losses
+};
 }  // namespace
 
 struct ewbem_ctx {
@@ -174,7 +188,18 @@ struct ewbem_ctx {
   DevBuf<cd> d_b, d_x, d_r, d_w, d_u, d_zt, d_V, d_small, d_tmp_in, d_tmp_out;
   DevBuf<cd> d_Y, d_hist_sol, d_spec;
   int hist_n = 0, hist_head = 0;  // ring buffer of the last sem_k solutions
-  std::vector<int> hist_slot;     // newest first
+  std::vector<int> hist_slot;  // newest first
+  std::vector<int> hist_kidx;  // frequency index of each of those slots
+
+  // learned initial guess: the model (host, caller dof order) and its device
+  // copies; reduced coordinates of the last three solutions in a ring
+  LearnedModel lm;
+  bool lm_dev = false;  // device copies of lm current
+  DevBuf<cd> d_phi, d_lcoef, d_lpred, d_lx;
+  DevBuf<float> d_lp, d_lfeat, d_lact, d_lpre, d_ly, d_lkf;
+  DevBuf<int> d_lidx;
+  DevBuf<double> d_lnu;
+  std::vector<int> lc_slot, lc_kidx;  // newest first
 
   int assembled_k = -1;
   KParams P{};
@@ -306,13 +331,52 @@ std::vector<double> tree_load(ewbem_ctx* c) {
   return t0;
 }
 
+// Device copies of the learned model: the basis in tree order, the
+// parameters, and the inference buffers (one sample).
+void learned_upload(ewbem_ctx* c) {
+  const LearnedModel& m = c->lm;
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  const int r = m.r;
+  std::vector<cd> ph((size_t)N * r);
+  for (int j = 0; j < r; ++j)
+    for (int t = 0; t < c->nt; ++t) {
+      const size_t e = (size_t)c->hg.perm[t];
+      for (int i = 0; i < 3; ++i) {
+        const std::complex<double> v = m.phi[(size_t)j * N + 3 * e + i];
+        ph[(size_t)j * N + 3 * (size_t)t + i] = cd{v.real(), v.imag()};
+      }
+    }
+  c->d_phi.upload(ph, st);
+  c->d_lp.upload(m.params, st);
+  const int L = m.shape.n_layers();
+  c->d_lcoef.reserve(3 * (size_t)r);
+  c->d_lpred.reserve(r);
+  c->d_lx.reserve(N);
+  c->d_lfeat.reserve(m.shape.dims[0]);
+  c->d_lact.reserve(std::max<size_t>(1, m.shape.hidden_sum()));
+  c->d_lpre.reserve(std::max<size_t>(1, m.shape.hidden_sum()));
+  c->d_ly.reserve(m.shape.dims[L]);
+  c->d_lkf.reserve(1);
+  c->d_lidx.reserve(4);
+  c->d_lnu.reserve(1);
+  c->d_hpart.reserve((size_t)dots_chunks(N) * r);
+  c->lc_slot.clear();
+  c->lc_kidx.clear();
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  c->lm_dev = true;
+}
+
 void ensure_device(ewbem_ctx* c) {
   require_gpu(c);
   ensure_structure(c);
   if (!c->have_mat) fail(EWBEM_ESTATE, "material not set");
   if (!c->have_time) fail(EWBEM_ESTATE, "time grid not set");
   if (!c->have_load) fail(EWBEM_ESTATE, "load not set");
-  if (c->device_ok) return;
+  if (c->device_ok) {
+    if (c->lm.ok && !c->lm_dev) learned_upload(c);
+    return;
+  }
   EWBEM_HIP_CHECK(hipSetDevice(c->device));
   hipStream_t st = c->stream;
   const HostGeom& g = c->hg;
@@ -353,10 +417,10 @@ void ensure_device(ewbem_ctx* c) {
   for (DevBuf<cd>* v : {&c->d_b, &c->d_x, &c->d_r, &c->d_w, &c->d_u, &c->d_zt, &c->d_tmp_in, &c->d_tmp_out})
     v->reserve(N);
   const int m = c->so.restart;
-  c->d_V.reserve((size_t)std::max(m + 1, c->so.sem_k) * N);
+  c->d_V.reserve((size_t)std::max(m + 1, c->so.sem_k + 1) * N);
   c->d_small.reserve(4 * (size_t)(m + 2) + 16);
   c->d_hpart.reserve((size_t)dots_chunks(N) * std::max(m + 2, c->so.sem_k + 1));
-  c->d_Y.reserve((size_t)std::max(1, c->so.sem_k) * N);
+  c->d_Y.reserve((size_t)(c->so.sem_k + 1) * N);
   c->d_hist_sol.reserve((size_t)std::max(1, c->so.sem_k) * N);
   c->d_spec.reserve((size_t)(c->n_f / 2 + 1) * N);
   c->d_M3.reserve(9 * (size_t)c->nt);
@@ -368,7 +432,10 @@ void ensure_device(ewbem_ctx* c) {
   c->hist_n = 0;
   c->hist_head = 0;
   c->hist_slot.clear();
+  c->hist_kidx.clear();
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  c->lm_dev = false;
+  if (c->lm.ok) learned_upload(c);
   c->device_ok = true;
   c->assembled_k = -1;
 }
@@ -1079,29 +1146,35 @@ double gmres(ewbem_ctx* c, cd* x, cd* r, int& iters_out, bool& converged) {
 // Sec. 4.2: x0 = X R^{-1} Q^H b with Y = A X = Q R (X: the last K solutions,
 // newest first); columns with |R_jj| < 1e-12 |R_00| are dropped.  Also
 // returns r0 = b - Y s without another matvec.
-void sem_guess(ewbem_ctx* c, cd* x, cd* r) {
+// Least-squares extrapolation (Sec. 4.2, eqs. a0, lsem, a0-solution): x0 = X s
+// with s minimising |b - A X s|, X the last K solutions and, when extra is
+// given, one more column (the learned guess).  r receives b - A x0.
+void sem_guess(ewbem_ctx* c, cd* x, cd* r, const cd* extra = nullptr) {
   hipStream_t st = c->stream;
   const long long N = 3LL * c->nt;
   const int K = std::min(c->so.sem_k, c->hist_n);
+  const int Kt = K + (extra ? 1 : 0);
   EWBEM_HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(cd), st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(r, c->d_b.p, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
-  if (K == 0) return;
+  if (Kt == 0) return;
   cd* Y = c->d_Y.p;
   cd* Q = c->d_V.p;  // GMRES basis as scratch
-  // Y(:, j) = A (history slot j): the history vectors are copied into the
-  // order of Y, then the operator is applied to up to four at once
+  // Y(:, j) = A X(:, j): the columns are copied into the order of Y, then the
+  // operator is applied to up to four at once
   for (int j = 0; j < K; ++j)
     EWBEM_HIP_CHECK(hipMemcpyAsync(Q + (size_t)j * N, c->d_hist_sol.p + (size_t)c->hist_slot[j] * N,
                                    N * sizeof(cd), hipMemcpyDeviceToDevice, st));
-  for (int j0 = 0; j0 < K; j0 += HMV_MAXRHS)
-    apply_tree_multi(c, Q + (size_t)j0 * N, Y + (size_t)j0 * N, std::min(HMV_MAXRHS, K - j0));
+  if (extra)
+    EWBEM_HIP_CHECK(hipMemcpyAsync(Q + (size_t)K * N, extra, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+  for (int j0 = 0; j0 < Kt; j0 += HMV_MAXRHS)
+    apply_tree_multi(c, Q + (size_t)j0 * N, Y + (size_t)j0 * N, std::min(HMV_MAXRHS, Kt - j0));
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
   // classical Gram-Schmidt twice on the columns of Y
-  std::vector<std::complex<double>> R((size_t)K * K, 0.0);
+  std::vector<std::complex<double>> R((size_t)Kt * Kt, 0.0);
   std::vector<int> kept;
   double r00 = 0;
-  std::vector<cd> hb(2 * (K + 1));
-  for (int j = 0; j < K; ++j) {
+  std::vector<cd> hb(2 * (Kt + 1));
+  for (int j = 0; j < Kt; ++j) {
     const int q = (int)kept.size();
     cd* qj = Q + (size_t)q * N;
     EWBEM_HIP_CHECK(hipMemcpyAsync(qj, Y + (size_t)j * N, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
@@ -1115,10 +1188,10 @@ void sem_guess(ewbem_ctx* c, cd* x, cd* r) {
     }
     const double nrm = dev_norm(c, qj);
     if (j == 0) r00 = nrm;
-    if (!(nrm > 1e-12 * r00) || nrm == 0.0) continue;  // dependent history column
+    if (!(nrm > 1e-12 * r00) || nrm == 0.0) continue;  // dependent column
     launch_axpby(cd{1.0 / nrm, 0.0}, qj, cd{0.0, 0.0}, qj, N, st);
-    for (int i = 0; i < q; ++i) R[(size_t)i * K + q] = rcol[i];
-    R[(size_t)q * K + q] = nrm;
+    for (int i = 0; i < q; ++i) R[(size_t)i * Kt + q] = rcol[i];
+    R[(size_t)q * Kt + q] = nrm;
     kept.push_back(j);
   }
   const int q = (int)kept.size();
@@ -1130,24 +1203,31 @@ void sem_guess(ewbem_ctx* c, cd* x, cd* r) {
   std::vector<std::complex<double>> sv(q);
   for (int i = q - 1; i >= 0; --i) {
     std::complex<double> a(hb[i].x, hb[i].y);
-    for (int l = i + 1; l < q; ++l) a -= R[(size_t)i * K + l] * sv[l];
-    sv[i] = a / R[(size_t)i * K + i];
+    for (int l = i + 1; l < q; ++l) a -= R[(size_t)i * Kt + l] * sv[l];
+    sv[i] = a / R[(size_t)i * Kt + i];
   }
-  // coefficients over the history slots (x0) and over Y's columns (r0)
+  // coefficients over the history slots and the extra column (x0), and over
+  // Y's columns (r0)
   const int ncap = std::max(1, c->so.sem_k);
-  std::vector<cd> cx(ncap, cd{0, 0}), cy(K, cd{0, 0});
+  std::vector<cd> cx(ncap, cd{0, 0}), cy(Kt, cd{0, 0});
+  cd cext{0, 0};
   for (int i = 0; i < q; ++i) {
-    cx[c->hist_slot[kept[i]]] = cd{sv[i].real(), sv[i].imag()};
-    cy[kept[i]] = cd{sv[i].real(), sv[i].imag()};
+    const cd v{sv[i].real(), sv[i].imag()};
+    if (kept[i] < K)
+      cx[c->hist_slot[kept[i]]] = v;
+    else
+      cext = v;
+    cy[kept[i]] = v;
   }
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p, cx.data(), ncap * sizeof(cd), hipMemcpyHostToDevice, st));
   launch_gemv_acc(c->d_hist_sol.p, N, ncap, c->d_small.p, cd{0.0, 0.0}, x, N, st);
-  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p + ncap, cy.data(), K * sizeof(cd), hipMemcpyHostToDevice, st));
-  launch_gemv_sub(Y, N, K, c->d_small.p + ncap, r, N, st);
+  if (extra) launch_axpby(cext, extra, cd{1.0, 0.0}, x, N, st);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p + ncap, cy.data(), Kt * sizeof(cd), hipMemcpyHostToDevice, st));
+  launch_gemv_sub(Y, N, Kt, c->d_small.p + ncap, r, N, st);
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
 }
 
-void push_history(ewbem_ctx* c, const cd* a) {
+void push_history(ewbem_ctx* c, const cd* a, int k) {
   const long long N = 3LL * c->nt;
   const int cap = std::max(1, c->so.sem_k);
   int slot;
@@ -1156,10 +1236,54 @@ void push_history(ewbem_ctx* c, const cd* a) {
   } else {
     slot = c->hist_slot.back();
     c->hist_slot.pop_back();
+    c->hist_kidx.pop_back();
   }
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_hist_sol.p + (size_t)slot * N, a, N * sizeof(cd),
                                  hipMemcpyDeviceToDevice, c->stream));
   c->hist_slot.insert(c->hist_slot.begin(), slot);
+  c->hist_kidx.insert(c->hist_kidx.begin(), k);
+}
+
+// ---- learned initial guess
+
+// Reduced coordinates Phi^H a of the solution at frequency k into the ring
+// of the last three.
+void push_coords(ewbem_ctx* c, const cd* a, int k) {
+  const long long N = 3LL * c->nt;
+  const int r = c->lm.r;
+  int slot;
+  if ((int)c->lc_slot.size() < 3) {
+    slot = (int)c->lc_slot.size();
+  } else {
+    slot = c->lc_slot.back();
+    c->lc_slot.pop_back();
+    c->lc_kidx.pop_back();
+  }
+  launch_dots(c->d_phi.p, N, r, a, N, c->d_hpart.p, c->d_lcoef.p + (size_t)slot * r, c->stream);
+  c->lc_slot.insert(c->lc_slot.begin(), slot);
+  c->lc_kidx.insert(c->lc_kidx.begin(), k);
+}
+
+// The network's guess at frequency k (tree order, in d_lx), or null when the
+// coordinates of k-1, k-2 and k-3 are not all in the ring.
+const cd* learned_guess(ewbem_ctx* c, int k) {
+  if (k < 3 || c->lc_kidx.size() < 3 || c->lc_kidx[0] != k - 1 || c->lc_kidx[1] != k - 2 ||
+      c->lc_kidx[2] != k - 3)
+    return nullptr;
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  const int r = c->lm.r;
+  const int idx[4] = {c->lc_slot[0], c->lc_slot[1], c->lc_slot[2], -1};
+  const float kf = (float)k / (float)(c->n_f / 2);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_lidx.p, idx, sizeof(idx), hipMemcpyHostToDevice, st));
+  EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_lkf.p, &kf, sizeof(float), hipMemcpyHostToDevice, st));
+  launch_learn_samples(c->d_lcoef.p, r, c->d_lidx.p, c->d_lkf.p, 1, c->d_lfeat.p, nullptr, c->d_lnu.p, st);
+  mlp_forward(c->lm.shape, c->d_lp.p, 1, c->d_lfeat.p, c->d_lact.p, c->d_lpre.p, c->d_ly.p, st);
+  launch_learn_compose(c->d_lcoef.p, r, c->d_lidx.p, c->d_lnu.p, c->d_ly.p, c->d_lpred.p, st);
+  launch_gemv_acc(c->d_phi.p, N, r, c->d_lpred.p, cd{0.0, 0.0}, c->d_lx.p, N, st);
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // idx and kf live on this frame
+  c->acc.guess_learned += 1;
+  return c->d_lx.p;
 }
 
 // Solve frequency k into d_x (tree order); x0 (caller order, device) optional.
@@ -1175,8 +1299,13 @@ int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
     launch_axpby(cd{1, 0}, c->d_b.p, cd{-1, 0}, c->d_r.p, N, st);
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
     account_matvec(c, ev);
-  } else if (c->so.guess == EWBEM_GUESS_SEM) {
-    sem_guess(c, c->d_x.p, c->d_r.p);
+  } else if (c->so.guess == EWBEM_GUESS_SEM || c->so.guess == EWBEM_GUESS_LEARNED) {
+    const cd* extra = nullptr;
+    if (c->so.guess == EWBEM_GUESS_LEARNED) {
+      if (!c->lm.ok) fail(EWBEM_ESTATE, "learned guess: no trained or loaded model");
+      extra = learned_guess(c, k);
+    }
+    sem_guess(c, c->d_x.p, c->d_r.p, extra);
   } else if (c->so.guess == EWBEM_GUESS_QUAD && c->hist_n > 0) {
     const int K = std::min(3, c->hist_n);
     static const double coef[4][3] = {{0, 0, 0}, {1, 0, 0}, {2, -1, 0}, {3, -3, 1}};
@@ -1205,10 +1334,37 @@ int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
   c->acc.iters_total += its;
   c->acc.iters_max = std::max(c->acc.iters_max, its);
   c->acc.resid_max = std::max(c->acc.resid_max, rel);
-  push_history(c, c->d_x.p);
+  push_history(c, c->d_x.p, k);
+  if (c->so.guess == EWBEM_GUESS_LEARNED && c->lm.ok) push_coords(c, c->d_x.p, k);
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_spec.p + (size_t)k * N, c->d_x.p, N * sizeof(cd),
                                  hipMemcpyDeviceToDevice, st));
   return conv ? EWBEM_OK : EWBEM_ENOCONV;
+}
+
+// Every frequency of the current load in order, the solutions into d_spec.
+int frequency_loop(ewbem_ctx* c) {
+  c->hist_n = 0;
+  c->hist_slot.clear();
+  c->hist_kidx.clear();
+  c->lc_slot.clear();
+  c->lc_kidx.clear();
+  {
+    // every frequency's off-diagonal U t0 in one batched pass
+    EventPair ev;
+    const auto t0 = Clock::now();
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, c->stream));
+    rhs_precompute(c, dev_geom(c), 0, c->n_f / 2 + 1);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, c->stream));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->acc.t_rhs_ms += ev.elapsed();
+    c->acc.t_assemble_ms += ms_since(t0);
+  }
+  int rc = EWBEM_OK;
+  for (int k = 0; k <= c->n_f / 2; ++k) {
+    const int r = solve_k(c, k, nullptr);
+    if (r != EWBEM_OK) rc = r;
+  }
+  return rc;
 }
 
 int guard(ewbem_ctx* ctx, const std::function<int()>& f) {
@@ -1246,6 +1402,192 @@ bool finite_all(const double* v, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
   return true;
+}
+
+// ---- training of the learned guess
+
+using zc = std::complex<double>;
+
+std::vector<zc> to_host(ewbem_ctx* c, const cd* d, size_t n) {
+  std::vector<cd> h(n);
+  if (n) EWBEM_HIP_CHECK(hipMemcpyAsync(h.data(), d, n * sizeof(cd), hipMemcpyDeviceToHost, c->stream));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  std::vector<zc> z(n);
+  for (size_t i = 0; i < n; ++i) z[i] = zc(h[i].x, h[i].y);
+  return z;
+}
+
+void to_device(ewbem_ctx* c, const std::vector<zc>& z, cd* d) {
+  std::vector<cd> h(z.size());
+  for (size_t i = 0; i < z.size(); ++i) h[i] = cd{z[i].real(), z[i].imag()};
+  if (!h.empty())
+    EWBEM_HIP_CHECK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(cd), hipMemcpyHostToDevice, c->stream));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+// Gram matrix G = Y^H Y (l x l, row-major, host) of the columns of Y (n x l, ld n).
+std::vector<zc> gram(ewbem_ctx* c, const cd* Y, long long n, int l, cd* part, cd* g) {
+  for (int j = 0; j < l; ++j) launch_dots(Y, n, l, Y + (size_t)j * n, n, part, g + (size_t)j * l, c->stream);
+  const std::vector<zc> gc = to_host(c, g, (size_t)l * l);  // column j = Y^H y_j
+  std::vector<zc> G((size_t)l * l);
+  for (int i = 0; i < l; ++i)
+    for (int j = 0; j < l; ++j) G[(size_t)i * l + j] = gc[(size_t)j * l + i];
+  return G;
+}
+
+// Orthonormalise the columns of Y (n x l) in place by Cholesky-QR,
+// Y <- Y R^{-1} with Y^H Y = R^H R, three times; a Gram matrix too
+// ill-conditioned to factor gets a small diagonal shift first (shifted
+// Cholesky-QR: the later passes restore orthogonality).  tmp: n x l.
+void cholqr3(ewbem_ctx* c, cd* Y, long long n, int l, cd* tmp, cd* part, cd* g) {
+  for (int pass = 0; pass < 3; ++pass) {
+    std::vector<zc> G = gram(c, Y, n, l, part, g);
+    double tr = 0.0;
+    for (int i = 0; i < l; ++i) tr += G[(size_t)i * l + i].real();
+    std::vector<zc> Lf = G;
+    // a (numerically) rank-deficient sketch gets a tiny diagonal shift
+    for (double shift = 0.0; !cholesky(Lf, l);) {
+      shift = shift == 0.0 ? 1e-14 * tr : shift * 100.0;
+      if (!(shift < tr)) fail(EWBEM_EINVAL, "guess training: the snapshots span too few directions");
+      Lf = G;
+      for (int i = 0; i < l; ++i) Lf[(size_t)i * l + i] += shift;
+    }
+    const std::vector<zc> Ri = inverse_lh(Lf, l);
+    std::vector<zc> cols((size_t)l * l);  // column j of R^{-1}, contiguous
+    for (int i = 0; i < l; ++i)
+      for (int j = 0; j < l; ++j) cols[(size_t)j * l + i] = Ri[(size_t)i * l + j];
+    to_device(c, cols, g);
+    for (int j = 0; j < l; ++j)
+      launch_gemv_acc(Y, n, l, g + (size_t)j * l, cd{0.0, 0.0}, tmp + (size_t)j * n, n, c->stream);
+    EWBEM_HIP_CHECK(hipMemcpyAsync(Y, tmp, (size_t)n * l * sizeof(cd), hipMemcpyDeviceToDevice, c->stream));
+  }
+}
+
+// Proper orthogonal decomposition of the snapshots S (N x M, ld N) by a
+// randomized range finder with q subspace iterations and l columns, then
+// the eigen-decomposition of the sketch: Phi (N x r) spans the r dominant
+// left singular directions.  Returns the fraction of |S|_F^2 they hold.
+double pod_basis(ewbem_ctx* c, const cd* S, long long N, int M, int r, int l, int q, uint64_t seed, cd* Phi) {
+  hipStream_t st = c->stream;
+  DevBuf<cd> om, Q, tq, Z, tz, g, part;
+  om.reserve((size_t)M * l);
+  Q.reserve((size_t)N * l);
+  tq.reserve((size_t)N * l);
+  Z.reserve((size_t)M * l);
+  tz.reserve((size_t)M * l);
+  g.reserve((size_t)l * l + 1);
+  part.reserve((size_t)std::max({dots_chunks(N) * (long long)M, dots_chunks(N) * (long long)l,
+                                 dots_chunks(M) * (long long)l, 512LL}));
+  {
+    std::mt19937_64 rng(seed ^ 0x9e3779b97f4a7c15ULL);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<zc> o((size_t)M * l);
+    for (auto& v : o) v = zc(nd(rng), nd(rng));
+    to_device(c, o, om.p);
+  }
+  auto range = [&](const cd* X, cd* Yo) {  // Yo = S X (X: M x l)
+    for (int j = 0; j < l; ++j) launch_gemv_acc(S, N, M, X + (size_t)j * M, cd{0.0, 0.0}, Yo + (size_t)j * N, N, st);
+  };
+  auto corange = [&](const cd* Y, cd* Xo) {  // Xo = S^H Y (Y: N x l)
+    for (int j = 0; j < l; ++j) launch_dots(S, N, M, Y + (size_t)j * N, N, part.p, Xo + (size_t)j * M, st);
+  };
+  range(om.p, Q.p);
+  cholqr3(c, Q.p, N, l, tq.p, part.p, g.p);
+  for (int it = 0; it < q; ++it) {
+    corange(Q.p, Z.p);
+    cholqr3(c, Z.p, M, l, tz.p, part.p, g.p);
+    range(Z.p, Q.p);
+    cholqr3(c, Q.p, N, l, tq.p, part.p, g.p);
+  }
+  // B = Q^H S; B B^H = Z^H Z with Z = S^H Q
+  corange(Q.p, Z.p);
+  const std::vector<zc> G = gram(c, Z.p, M, l, part.p, g.p);
+  std::vector<double> w;
+  std::vector<zc> V;
+  herm_eig(G, l, w, V);
+  std::vector<zc> cols((size_t)l * r);
+  for (int j = 0; j < r; ++j)
+    for (int i = 0; i < l; ++i) cols[(size_t)j * l + i] = V[(size_t)i * l + j];
+  to_device(c, cols, g.p);
+  for (int j = 0; j < r; ++j)
+    launch_gemv_acc(Q.p, N, l, g.p + (size_t)j * l, cd{0.0, 0.0}, Phi + (size_t)j * N, N, st);
+  launch_dots(S, N * (long long)M, 1, S, N * (long long)M, part.p, g.p, st);
+  const double tot = to_host(c, g.p, 1)[0].real();
+  double top = 0.0;
+  for (int j = 0; j < r; ++j) top += std::max(0.0, w[j]);
+  return tot > 0.0 ? top / tot : 1.0;
+}
+
+double loss_sum(ewbem_ctx* c, const double* part, int nb) {
+  std::vector<double> h(nb);
+  EWBEM_HIP_CHECK(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (double v : h) s += v;
+  return s;
+}
+
+// Full-batch Adam on M samples (X: M x dims[0], T: M x dims[L]) minimising
+// the mean squared error; P (device) in place.  cosine: the step size decays
+// from lr to lr / 10 over the epochs, else stays lr.  loss0 / loss1: the
+// mean squared error before the first and after the last step.
+void train_mlp(ewbem_ctx* c, const MlpShape& s, float* P, long long M, const float* X, const float* T, int epochs,
+               double lr, bool cosine, double& loss0, double& loss1) {
+  hipStream_t st = c->stream;
+  const size_t np = s.n_params();
+  const int dL = s.dims[s.n_layers()];
+  const long long nout = M * dL;
+  DevBuf<float> G, m1, m2, act, pre, Y, dY, work;
+  DevBuf<double> part;
+  G.reserve(np);
+  m1.reserve(np);
+  m2.reserve(np);
+  act.reserve(std::max<size_t>(1, s.hidden_sum() * M));
+  pre.reserve(std::max<size_t>(1, s.hidden_sum() * M));
+  Y.reserve(nout);
+  dY.reserve(nout);
+  work.reserve(2 * (size_t)s.max_width() * M);
+  const int nb = loss_blocks(nout);
+  part.reserve(nb);
+  EWBEM_HIP_CHECK(hipMemsetAsync(m1.p, 0, np * sizeof(float), st));
+  EWBEM_HIP_CHECK(hipMemsetAsync(m2.p, 0, np * sizeof(float), st));
+  const float scale = (float)(2.0 / (double)nout);
+  const double b1 = 0.9, b2 = 0.999;
+  for (int ep = 0; ep < epochs; ++ep) {
+    mlp_forward(s, P, M, X, act.p, pre.p, Y.p, st);
+    launch_mlp_loss(Y.p, T, nout, scale, dY.p, part.p, st);
+    if (ep == 0) loss0 = loss_sum(c, part.p, nb) / (double)nout;
+    mlp_backward(s, P, M, X, act.p, pre.p, dY.p, work.p, G.p, st);
+    const double f = cosine && epochs > 1 ? 0.1 + 0.45 * (1.0 + std::cos(M_PI * ep / (epochs - 1))) : 1.0;
+    AdamStep a{(float)(lr * f), (float)b1, (float)b2, 1e-8f, (float)(1.0 - std::pow(b1, ep + 1)),
+               (float)(1.0 - std::pow(b2, ep + 1))};
+    launch_adam(P, G.p, m1.p, m2.p, (long long)np, a, st);
+  }
+  mlp_forward(s, P, M, X, act.p, pre.p, Y.p, st);
+  launch_mlp_loss(Y.p, T, nout, scale, nullptr, part.p, st);
+  loss1 = loss_sum(c, part.p, nb) / (double)nout;
+  if (epochs == 0) loss0 = loss1;
+  EWBEM_HIP_CHECK(hipGetLastError());
+}
+
+MlpShape mlp_shape(int n_layers, const int32_t* dims) {
+  if (n_layers < 1 || n_layers > 16 || !dims) fail(EWBEM_EINVAL, "network: need 1..16 layers and their widths");
+  MlpShape s;
+  for (int l = 0; l <= n_layers; ++l) {
+    if (dims[l] < 1 || dims[l] > 8192) fail(EWBEM_EINVAL, "network: widths must be 1..8192");
+    s.dims.push_back(dims[l]);
+  }
+  return s;
+}
+
+// Serialised model: magic, then int32 version, n_dof, r, n_layers, dims,
+// then fp64 energy, loss0, loss1, then the fp32 parameters, then the basis
+// (n_dof x r complex128, column-major, caller dof order).
+constexpr char kModelMagic[8] = {'E', 'W', 'B', 'G', 'U', 'E', 'S', 'S'};
+constexpr int32_t kModelVersion = 1;
+
+size_t model_bytes(const LearnedModel& m, long long N) {
+  return 8 + 4 * (4 + m.shape.dims.size()) + 3 * 8 + 4 * m.params.size() + 16 * (size_t)N * m.r;
 }
 
 }  // namespace
@@ -1341,6 +1683,8 @@ int ewbem_set_mesh(ewbem_ctx* ctx, int64_t nv, const double* xyz, int64_t nt, co
     ctx->exterior = exterior != 0;
     ctx->have_mesh = true;
     ctx->have_load = false;
+    ctx->lm = LearnedModel{};  // its basis belongs to the old mesh
+    ctx->lm_dev = false;
     ctx->structure_ok = false;
     ctx->device_ok = false;
     ctx->assembled_k = -1;
@@ -1486,7 +1830,7 @@ int ewbem_set_solver(ewbem_ctx* ctx, const ewbem_solver_opts* o) {
   return guard(ctx, [&] {
     if (!o) fail(EWBEM_EINVAL, "solver options: null");
     if (!(o->tol > 0) || o->restart < 1 || o->restart > 400 || o->maxit < 1 || o->precond < 0 ||
-        o->precond > 2 || o->guess < 0 || o->guess > 2 || o->sem_k < 1 || o->sem_k > 8)
+        o->precond > 2 || o->guess < 0 || o->guess > 3 || o->sem_k < 1 || o->sem_k > 8)
       fail(EWBEM_EINVAL, "solver options out of range");
     ctx->so = *o;
     ctx->device_ok = false;  // buffers depend on restart and sem_k
@@ -1651,24 +1995,7 @@ int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats*
     if (!u) fail(EWBEM_EINVAL, "solve_transient: null output");
     begin_stats(ctx);
     ensure_device(ctx);
-    ctx->hist_n = 0;
-    ctx->hist_slot.clear();
-    {
-      // every frequency's off-diagonal U t0 in one batched pass
-      EventPair ev;
-      const auto t0 = Clock::now();
-      EWBEM_HIP_CHECK(hipEventRecord(ev.a, ctx->stream));
-      rhs_precompute(ctx, dev_geom(ctx), 0, ctx->n_f / 2 + 1);
-      EWBEM_HIP_CHECK(hipEventRecord(ev.b, ctx->stream));
-      EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-      ctx->acc.t_rhs_ms += ev.elapsed();
-      ctx->acc.t_assemble_ms += ms_since(t0);
-    }
-    int rc = EWBEM_OK;
-    for (int k = 0; k <= ctx->n_f / 2; ++k) {
-      const int r = solve_k(ctx, k, nullptr);
-      if (r != EWBEM_OK) rc = r;
-    }
+    const int rc = frequency_loop(ctx);
     const auto tp = Clock::now();
     const long long N = 3LL * ctx->nt;
     launch_mft_inverse(ctx->d_spec.p, N, ctx->n_f, ctx->period, ctx->sigma, ctx->window, ctx->d_perm.p, u,
@@ -1741,6 +2068,7 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
       a.matvecs_timed += b.matvecs_timed;
       a.aca_warm_blocks += b.aca_warm_blocks;
       a.aca_cold_blocks += b.aca_cold_blocks;
+      a.guess_learned += b.guess_learned;
     }
     *stats = a;
   }
@@ -1750,6 +2078,333 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
   for (int i = 0; i < n; ++i)
     if (rc[i] == EWBEM_ENOCONV) out = EWBEM_ENOCONV;
   return out;
+}
+
+void ewbem_default_train_opts(ewbem_train_opts* o) {
+  if (!o) return;
+  *o = ewbem_train_opts{};
+  o->n_modes = 64;
+  o->hidden = 256;
+  o->n_hidden = 3;
+  o->epochs = 2000;
+  o->lr = 1e-3;
+  o->power_iters = 2;
+  o->load_kind = 0;
+  o->seed = 1;
+  o->augment = 4;
+}
+
+int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, const ewbem_train_opts* o,
+                      ewbem_stats* stats) {
+  return guard(ctx, [&] {
+    if (!o || !loads || n_cases < 1) fail(EWBEM_EINVAL, "guess_train: need options, loads and n_cases >= 1");
+    if (o->n_modes < 1 || o->n_modes > 1024 || o->hidden < 1 || o->hidden > 4096 || o->n_hidden < 0 ||
+        o->n_hidden > 8 || o->epochs < 0 || o->epochs > 1000000 || !(o->lr > 0) || !std::isfinite(o->lr) ||
+        o->power_iters < 0 || o->power_iters > 10 || (o->load_kind != 0 && o->load_kind != 1) ||
+        o->augment < 0 || o->augment > 64)
+      fail(EWBEM_EINVAL, "guess_train: options out of range");
+    if (!ctx->have_mesh || !ctx->have_time || !ctx->have_load)
+      fail(EWBEM_ESTATE, "guess_train: set the mesh, time grid and a load (its history is used) first");
+    if (ctx->load_incident || !ctx->bc_caller.empty())
+      fail(EWBEM_ESTATE, "guess_train: needs a traction or pressure load (its history is used)");
+    const int nk = ctx->n_f / 2 + 1;
+    if (nk < 4) fail(EWBEM_EINVAL, "guess_train: needs N_f >= 6 (three previous frequencies per sample)");
+    const long long N = 3LL * ctx->nt;
+    const long long Mll = (long long)n_cases * nk;
+    if (Mll > 65535) fail(EWBEM_EINVAL, "guess_train: n_cases (N_f/2 + 1) must not exceed 65535 snapshots");
+    const int M = (int)Mll;
+    const int r = o->n_modes;
+    if (r > M || r > N) fail(EWBEM_EINVAL, "guess_train: n_modes exceeds the number of snapshots or unknowns");
+    const size_t per = o->load_kind == 1 ? (size_t)ctx->nt : 3 * (size_t)ctx->nt;
+    if (!finite_all(loads, per * n_cases)) fail(EWBEM_EINVAL, "guess_train: non-finite load values");
+    begin_stats(ctx);
+    // data: every case's solutions at all frequencies, with the configured
+    // solver (extrapolation instead of the model being replaced)
+    const std::vector<double> saved_load = ctx->load_caller;
+    const bool saved_pressure = ctx->load_is_pressure;
+    const int saved_guess = ctx->so.guess;
+    ctx->lm = LearnedModel{};
+    ctx->lm_dev = false;
+    if (ctx->so.guess == EWBEM_GUESS_LEARNED) ctx->so.guess = EWBEM_GUESS_SEM;
+    DevBuf<cd> S;
+    int rc = EWBEM_OK;
+    try {
+      ensure_device(ctx);
+      S.reserve((size_t)N * M);
+      for (int cs = 0; cs < n_cases; ++cs) {
+        ctx->load_caller.assign(loads + per * cs, loads + per * (cs + 1));
+        ctx->load_is_pressure = o->load_kind == 1;
+        ctx->device_ok = false;
+        ensure_device(ctx);
+        const int r1 = frequency_loop(ctx);
+        if (r1 != EWBEM_OK) rc = r1;
+        EWBEM_HIP_CHECK(hipMemcpyAsync(S.p + (size_t)cs * nk * N, ctx->d_spec.p, (size_t)nk * N * sizeof(cd),
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+      }
+    } catch (...) {
+      ctx->load_caller = saved_load;
+      ctx->load_is_pressure = saved_pressure;
+      ctx->so.guess = saved_guess;
+      ctx->device_ok = false;
+      throw;
+    }
+    ctx->load_caller = saved_load;
+    ctx->load_is_pressure = saved_pressure;
+    ctx->so.guess = saved_guess;
+    hipStream_t st = ctx->stream;
+    // reduced basis and every snapshot's coordinates
+    DevBuf<cd> phi, coef, part;
+    phi.reserve((size_t)N * r);
+    const int l = std::min(M, r + 16);
+    const double energy = pod_basis(ctx, S.p, N, M, r, l, o->power_iters, o->seed, phi.p);
+    coef.reserve((size_t)M * r);
+    part.reserve((size_t)dots_chunks(N) * r);
+    for (int m = 0; m < M; ++m) launch_dots(phi.p, N, r, S.p + (size_t)m * N, N, part.p, coef.p + (size_t)m * r, st);
+    S.release();
+    // the solutions depend linearly on the load, so any combination of the
+    // cases' coordinate sequences is the sequence of the combined load:
+    // augment virtual cases with complex Gaussian weights
+    const int n_virt = o->augment * n_cases;
+    const int n_all = n_cases + n_virt;
+    if (n_virt > 0) {
+      DevBuf<cd> tab, wv;
+      tab.reserve((size_t)n_all * nk * r);
+      EWBEM_HIP_CHECK(hipMemcpyAsync(tab.p, coef.p, (size_t)M * r * sizeof(cd), hipMemcpyDeviceToDevice, st));
+      std::mt19937_64 rng(o->seed * 0x2545f4914f6cdd1dULL + 7);
+      std::normal_distribution<double> nd(0.0, std::sqrt(0.5 / n_cases));
+      std::vector<zc> w((size_t)n_virt * n_cases);
+      for (auto& v : w) v = zc(nd(rng), nd(rng));
+      wv.reserve(w.size());
+      to_device(ctx, w, wv.p);
+      const long long blk = (long long)nk * r;  // one case's coordinate sequence
+      for (int v = 0; v < n_virt; ++v)
+        launch_gemv_acc(tab.p, blk, n_cases, wv.p + (size_t)v * n_cases, cd{0.0, 0.0},
+                        tab.p + (size_t)(n_cases + v) * blk, blk, st);
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      std::swap(coef.p, tab.p);
+      std::swap(coef.n, tab.n);
+    }
+    // samples: k = 3 .. N_f/2 of every case
+    std::vector<int> idx;
+    std::vector<float> kf;
+    for (int cs = 0; cs < n_all; ++cs)
+      for (int k = 3; k < nk; ++k) {
+        const int b = cs * nk;
+        idx.insert(idx.end(), {b + k - 1, b + k - 2, b + k - 3, b + k});
+        kf.push_back((float)k / (float)(nk - 1));
+      }
+    const int ns = (int)kf.size();
+    MlpShape shape;
+    shape.dims.push_back(6 * r + 2);
+    for (int h = 0; h < o->n_hidden; ++h) shape.dims.push_back(o->hidden);
+    shape.dims.push_back(2 * r);
+    DevBuf<int> d_idx;
+    DevBuf<float> d_kf, X, T, P;
+    d_idx.upload(idx, st);
+    d_kf.upload(kf, st);
+    X.reserve((size_t)ns * shape.dims[0]);
+    T.reserve((size_t)ns * 2 * r);
+    launch_learn_samples(coef.p, r, d_idx.p, d_kf.p, ns, X.p, T.p, nullptr, st);
+    // initial weights N(0, 1 / fan-in); the last layer starts at zero, so the
+    // untrained network returns the quadratic extrapolation
+    std::vector<float> p0(shape.n_params(), 0.f);
+    {
+      std::mt19937_64 rng(o->seed);
+      for (int ly = 0; ly + 1 < shape.n_layers(); ++ly) {
+        std::normal_distribution<double> nd(0.0, 1.0 / std::sqrt((double)shape.dims[ly]));
+        const size_t w0 = shape.woff(ly), nw = (size_t)shape.dims[ly + 1] * shape.dims[ly];
+        for (size_t i = 0; i < nw; ++i) p0[w0 + i] = (float)nd(rng);
+      }
+    }
+    P.upload(p0, st);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    LearnedModel m;
+    train_mlp(ctx, shape, P.p, ns, X.p, T.p, o->epochs, o->lr, true, m.loss0, m.loss1);
+    m.params.resize(p0.size());
+    EWBEM_HIP_CHECK(hipMemcpyAsync(m.params.data(), P.p, p0.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    const std::vector<zc> pt = to_host(ctx, phi.p, (size_t)N * r);  // tree order
+    m.phi.assign((size_t)N * r, 0.0);
+    for (int j = 0; j < r; ++j)
+      for (int t = 0; t < ctx->nt; ++t) {
+        const size_t e = (size_t)ctx->hg.perm[t];
+        for (int i = 0; i < 3; ++i) m.phi[(size_t)j * N + 3 * e + i] = pt[(size_t)j * N + 3 * (size_t)t + i];
+      }
+    m.ok = true;
+    m.r = r;
+    m.shape = shape;
+    m.energy = energy;
+    ctx->lm = std::move(m);
+    ctx->lm_dev = false;
+    ctx->device_ok = false;  // the caller's own load goes back to the device
+    end_stats(ctx, stats);
+    if (stats) {
+      stats->pod_energy = ctx->lm.energy;
+      stats->train_loss_first = ctx->lm.loss0;
+      stats->train_loss_last = ctx->lm.loss1;
+    }
+    if (rc != EWBEM_OK) ctx->err = "GMRES did not reach the tolerance at some training frequency";
+    return rc;
+  });
+}
+
+int ewbem_guess_save(const ewbem_ctx* cctx, void* buf, size_t* len) {
+  ewbem_ctx* ctx = const_cast<ewbem_ctx*>(cctx);  // only the error message changes
+  return guard(ctx, [&] {
+    if (!len) fail(EWBEM_EINVAL, "guess_save: null length");
+    if (!ctx->lm.ok) fail(EWBEM_ESTATE, "guess_save: no trained or loaded model");
+    const LearnedModel& m = ctx->lm;
+    const long long N = (long long)m.phi.size() / m.r;
+    const size_t need = model_bytes(m, N);
+    if (!buf) {
+      *len = need;
+      return EWBEM_OK;
+    }
+    if (*len < need) {
+      *len = need;
+      fail(EWBEM_EINVAL, "guess_save: buffer too small");
+    }
+    char* p = (char*)buf;
+    auto put = [&](const void* v, size_t n) {
+      std::memcpy(p, v, n);
+      p += n;
+    };
+    put(kModelMagic, 8);
+    const int32_t hdr[4] = {kModelVersion, (int32_t)N, m.r, m.shape.n_layers()};
+    put(hdr, sizeof(hdr));
+    for (int d : m.shape.dims) {
+      const int32_t v = d;
+      put(&v, 4);
+    }
+    const double f[3] = {m.energy, m.loss0, m.loss1};
+    put(f, sizeof(f));
+    put(m.params.data(), 4 * m.params.size());
+    put(m.phi.data(), 16 * m.phi.size());
+    *len = need;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_guess_load(ewbem_ctx* ctx, const void* buf, size_t len) {
+  return guard(ctx, [&] {
+    if (!buf) fail(EWBEM_EINVAL, "guess_load: null buffer");
+    if (!ctx->have_mesh) fail(EWBEM_ESTATE, "guess_load: set the mesh first");
+    const char* p = (const char*)buf;
+    const char* end = p + len;
+    auto get = [&](void* v, size_t n) {
+      if ((size_t)(end - p) < n) fail(EWBEM_EINVAL, "guess_load: truncated model");
+      std::memcpy(v, p, n);
+      p += n;
+    };
+    char magic[8];
+    get(magic, 8);
+    if (std::memcmp(magic, kModelMagic, 8) != 0) fail(EWBEM_EINVAL, "guess_load: not a model");
+    int32_t hdr[4];
+    get(hdr, sizeof(hdr));
+    if (hdr[0] != kModelVersion) fail(EWBEM_EINVAL, "guess_load: unknown model version");
+    const long long N = 3LL * ctx->nt;
+    if (hdr[1] != N) fail(EWBEM_EINVAL, "guess_load: the model belongs to a mesh with another number of unknowns");
+    const int r = hdr[2];
+    if (r < 1 || r > 1024 || r > N) fail(EWBEM_EINVAL, "guess_load: bad basis size");
+    std::vector<int32_t> dims(hdr[3] + 1 > 0 && hdr[3] <= 16 ? hdr[3] + 1 : 0);
+    if (dims.empty()) fail(EWBEM_EINVAL, "guess_load: bad layer count");
+    get(dims.data(), 4 * dims.size());
+    LearnedModel m;
+    m.shape = mlp_shape(hdr[3], dims.data());
+    if (m.shape.dims[0] != 6 * r + 2 || m.shape.dims.back() != 2 * r)
+      fail(EWBEM_EINVAL, "guess_load: network widths do not match the basis");
+    double f[3];
+    get(f, sizeof(f));
+    m.params.resize(m.shape.n_params());
+    get(m.params.data(), 4 * m.params.size());
+    m.phi.resize((size_t)N * r);
+    get(m.phi.data(), 16 * m.phi.size());
+    if (p != end) fail(EWBEM_EINVAL, "guess_load: trailing bytes");
+    for (float v : m.params)
+      if (!std::isfinite(v)) fail(EWBEM_EINVAL, "guess_load: non-finite parameters");
+    if (!finite_all((const double*)m.phi.data(), 2 * m.phi.size())) fail(EWBEM_EINVAL, "guess_load: non-finite basis");
+    m.ok = true;
+    m.r = r;
+    m.energy = f[0];
+    m.loss0 = f[1];
+    m.loss1 = f[2];
+    ctx->lm = std::move(m);
+    ctx->lm_dev = false;
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_guess_basis(ewbem_ctx* ctx, int32_t* n_modes, ewbem_z* phi) {
+  return guard(ctx, [&] {
+    if (!ctx->lm.ok) fail(EWBEM_ESTATE, "guess_basis: no trained or loaded model");
+    if (n_modes) *n_modes = ctx->lm.r;
+    if (phi) {
+      require_gpu(ctx);
+      std::vector<cd> h(ctx->lm.phi.size());
+      for (size_t i = 0; i < h.size(); ++i) h[i] = cd{ctx->lm.phi[i].real(), ctx->lm.phi[i].imag()};
+      EWBEM_HIP_CHECK(hipMemcpyAsync(phi, h.data(), h.size() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    }
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_mlp_eval(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, const float* params, int64_t batch,
+                   const float* x, const float* target, float* y, float* grad, double* loss) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    const MlpShape s = mlp_shape(n_layers, dims);
+    if (batch < 0 || batch > (1LL << 24)) fail(EWBEM_EINVAL, "mlp_eval: batch out of range");
+    if (!params || (batch > 0 && (!x || !y))) fail(EWBEM_EINVAL, "mlp_eval: null array");
+    if (batch > 0 && grad && !target) fail(EWBEM_EINVAL, "mlp_eval: the gradient needs a target");
+    if (loss) *loss = 0.0;
+    hipStream_t st = ctx->stream;
+    const size_t np = s.n_params();
+    if (batch == 0) {
+      if (grad) EWBEM_HIP_CHECK(hipMemsetAsync(grad, 0, np * sizeof(float), st));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      return EWBEM_OK;
+    }
+    const int dL = s.dims[n_layers];
+    const long long nout = batch * dL;
+    DevBuf<float> act, pre, dY, work;
+    DevBuf<double> part;
+    act.reserve(std::max<size_t>(1, s.hidden_sum() * batch));
+    pre.reserve(std::max<size_t>(1, s.hidden_sum() * batch));
+    mlp_forward(s, params, batch, x, act.p, pre.p, y, st);
+    if (target) {
+      const int nb = loss_blocks(nout);
+      part.reserve(nb);
+      dY.reserve(nout);
+      launch_mlp_loss(y, target, nout, (float)(2.0 / (double)nout), dY.p, part.p, st);
+      const double l = loss_sum(ctx, part.p, nb) / (double)nout;
+      if (loss) *loss = l;
+      if (grad) {
+        work.reserve(2 * (size_t)s.max_width() * batch);
+        mlp_backward(s, params, batch, x, act.p, pre.p, dY.p, work.p, grad, st);
+      }
+    }
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_mlp_train(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, float* params, int64_t batch,
+                    const float* x, const float* target, int32_t epochs, double lr, double* loss_first,
+                    double* loss_last) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    const MlpShape s = mlp_shape(n_layers, dims);
+    if (batch < 1 || batch > (1LL << 24) || epochs < 0 || epochs > 1000000 || !(lr > 0) || !std::isfinite(lr))
+      fail(EWBEM_EINVAL, "mlp_train: need batch >= 1, epochs >= 0, lr > 0");
+    if (!params || !x || !target) fail(EWBEM_EINVAL, "mlp_train: null array");
+    double l0 = 0.0, l1 = 0.0;
+    train_mlp(ctx, s, params, batch, x, target, epochs, lr, false, l0, l1);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    if (loss_first) *loss_first = l0;
+    if (loss_last) *loss_last = l1;
+    return EWBEM_OK;
+  });
 }
 
 int ewbem_mft_inverse(ewbem_ctx* ctx, const ewbem_z* spec, double* u) {

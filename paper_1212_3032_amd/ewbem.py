@@ -18,7 +18,7 @@ OP_DENSE, OP_HMAT = 0, 1
 STORE_C128, STORE_C64 = 0, 1
 WINDOW_NONE, WINDOW_HANN, WINDOW_BLACKMAN = 0, 1, 2
 PREC_NONE, PREC_ELEMENT, PREC_LEAF = 0, 1, 2
-GUESS_ZERO, GUESS_SEM, GUESS_QUAD = 0, 1, 2
+GUESS_ZERO, GUESS_SEM, GUESS_QUAD, GUESS_LEARNED = 0, 1, 2, 3
 
 EXPORTED = [
     "ewbem_default_op_opts", "ewbem_default_solver_opts", "ewbem_create", "ewbem_destroy",
@@ -29,7 +29,8 @@ EXPORTED = [
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
     "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_batch_solve_transient",
-    "ewbem_mft_inverse",
+    "ewbem_mft_inverse", "ewbem_default_train_opts", "ewbem_guess_train", "ewbem_guess_save",
+    "ewbem_guess_load", "ewbem_guess_basis", "ewbem_mlp_eval", "ewbem_mlp_train",
 ]
 
 
@@ -58,10 +59,19 @@ class Stats(C.Structure):
                 ("rank_max", C.c_int64), ("t_aca_ms", C.c_double), ("t_near_ms", C.c_double),
                 ("t_rhs_ms", C.c_double), ("matvec_bytes_total", C.c_double),
                 ("matvecs_timed", C.c_int32), ("pad0", C.c_int32),
-                ("aca_warm_blocks", C.c_int64), ("aca_cold_blocks", C.c_int64)]
+                ("aca_warm_blocks", C.c_int64), ("aca_cold_blocks", C.c_int64),
+                ("guess_learned", C.c_int64), ("pod_energy", C.c_double),
+                ("train_loss_first", C.c_double), ("train_loss_last", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("n_modes", C.c_int32), ("hidden", C.c_int32), ("n_hidden", C.c_int32),
+                ("epochs", C.c_int32), ("lr", C.c_double), ("power_iters", C.c_int32),
+                ("load_kind", C.c_int32), ("seed", C.c_uint64), ("augment", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -113,6 +123,13 @@ def lib():
         "ewbem_solve_transient": (C.c_int, [P, P, P, C.POINTER(Stats)]),
         "ewbem_batch_solve_transient": (C.c_int, [P, I32, P, C.POINTER(Stats), I32]),
         "ewbem_mft_inverse": (C.c_int, [P, P, P]),
+        "ewbem_default_train_opts": (None, [C.POINTER(TrainOpts)]),
+        "ewbem_guess_train": (C.c_int, [P, I32, P, C.POINTER(TrainOpts), C.POINTER(Stats)]),
+        "ewbem_guess_save": (C.c_int, [P, P, C.POINTER(C.c_size_t)]),
+        "ewbem_guess_load": (C.c_int, [P, P, C.c_size_t]),
+        "ewbem_guess_basis": (C.c_int, [P, C.POINTER(I32), P]),
+        "ewbem_mlp_eval": (C.c_int, [P, I32, P, P, I64, P, P, P, P, C.POINTER(D)]),
+        "ewbem_mlp_train": (C.c_int, [P, I32, P, P, I64, P, P, I32, D, C.POINTER(D), C.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -139,6 +156,14 @@ def default_op_opts(**kw):
 def default_solver_opts(**kw):
     o = SolverOpts()
     lib().ewbem_default_solver_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_train_opts(**kw):
+    o = TrainOpts()
+    lib().ewbem_default_train_opts(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -326,6 +351,74 @@ class Context:
         if not (allow_noconv and rc == ENOCONV):
             self._check(rc)
         return st.as_dict()
+
+    def guess_train(self, loads, pressures=False, allow_noconv=False, **kw):
+        """Train the learned guess on several loads (n_cases x nt x 3
+        tractions, or n_cases x nt pressures); keyword options as in
+        TrainOpts.  Returns the stats (training solves, pod_energy, losses)."""
+        o = default_train_opts(load_kind=1 if pressures else 0, **kw)
+        per = self.nt if pressures else 3 * self.nt
+        a, pa = _host(loads, np.float64)
+        if a.size % per != 0 or a.size == 0:
+            raise ValueError(f"loads must hold n_cases x {per} values")
+        st = Stats()
+        rc = self._L.ewbem_guess_train(self.h, a.size // per, pa, C.byref(o), C.byref(st))
+        if not (allow_noconv and rc == ENOCONV):
+            self._check(rc)
+        return st.as_dict()
+
+    def guess_save(self):
+        n = C.c_size_t(0)
+        self._check(self._L.ewbem_guess_save(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self._L.ewbem_guess_save(self.h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def guess_load(self, data):
+        data = bytes(data)
+        buf = C.create_string_buffer(data, len(data))
+        self._check(self._L.ewbem_guess_load(self.h, buf, len(data)))
+
+    def guess_basis(self, phi=None):
+        """Basis size r; with phi (device complex128 tensor of N x r entries,
+        column-major, i.e. shape (r, N)) also the basis."""
+        r = C.c_int32(0)
+        self._check(self._L.ewbem_guess_basis(self.h, C.byref(r), None))
+        if phi is not None:
+            self._check(self._L.ewbem_guess_basis(
+                self.h, C.byref(r), _dev_ptr(phi, "torch.complex128", 3 * self.nt * r.value)))
+        return r.value
+
+    def mlp_eval(self, dims, params, x, y, target=None, grad=None):
+        """The network's kernels on device float32 tensors; returns the loss
+        (0 without a target)."""
+        d, pd = _host(dims, np.int32)
+        L = d.size - 1
+        batch = x.numel() // int(d[0]) if int(d[0]) > 0 else 0
+        np_ = sum(int(d[l + 1]) * int(d[l]) + int(d[l + 1]) for l in range(L))
+        loss = C.c_double(0.0)
+        self._check(self._L.ewbem_mlp_eval(
+            self.h, L, pd, _dev_ptr(params, "torch.float32", np_), batch,
+            _dev_ptr(x, "torch.float32", batch * int(d[0])) if batch else None,
+            _dev_ptr(target, "torch.float32", batch * int(d[-1])) if target is not None else None,
+            _dev_ptr(y, "torch.float32", batch * int(d[-1])) if batch else None,
+            _dev_ptr(grad, "torch.float32", np_) if grad is not None else None, C.byref(loss)))
+        return loss.value
+
+    def mlp_train(self, dims, params, x, target, epochs, lr):
+        """Full-batch Adam steps on device float32 tensors (params in place);
+        returns (first loss, last loss)."""
+        d, pd = _host(dims, np.int32)
+        L = d.size - 1
+        batch = x.numel() // int(d[0])
+        np_ = sum(int(d[l + 1]) * int(d[l]) + int(d[l + 1]) for l in range(L))
+        l0, l1 = C.c_double(0.0), C.c_double(0.0)
+        self._check(self._L.ewbem_mlp_train(
+            self.h, L, pd, _dev_ptr(params, "torch.float32", np_), batch,
+            _dev_ptr(x, "torch.float32", batch * int(d[0])),
+            _dev_ptr(target, "torch.float32", batch * int(d[-1])), int(epochs), float(lr),
+            C.byref(l0), C.byref(l1)))
+        return l0.value, l1.value
 
     def mft_inverse(self, spec, u):
         N = 3 * self.nt

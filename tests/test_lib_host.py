@@ -119,3 +119,52 @@ def test_gpu_calls_refused_on_host_context():
     with pytest.raises(ewbem.EwbemError) as e:
         c.assemble(0)
     assert e.value.status == ewbem.ESTATE
+
+
+def _model_blob(n_dof, r, dims, rng, magic=b"EWBGUESS", version=1):
+    import struct
+    n_p = sum(dims[l + 1] * dims[l] + dims[l + 1] for l in range(len(dims) - 1))
+    head = magic + struct.pack("<4i", version, n_dof, r, len(dims) - 1) + struct.pack(f"<{len(dims)}i", *dims)
+    head += struct.pack("<3d", 0.99, 1e-2, 1e-4)
+    p = rng.standard_normal(n_p).astype("<f4").tobytes()
+    phi = (rng.standard_normal(n_dof * r) + 1j * rng.standard_normal(n_dof * r)).astype("<c16").tobytes()
+    return head + p + phi
+
+
+def test_learned_model_format_on_host_context():
+    c, xyz, tri = _ctx(2)
+    N = 3 * len(tri)
+    rng = np.random.default_rng(1)
+    o = ewbem.default_train_opts()
+    assert (o.n_modes, o.hidden, o.n_hidden, o.epochs, o.lr, o.power_iters, o.load_kind, o.seed,
+            o.augment, o.pad) == (64, 256, 3, 2000, 1e-3, 2, 0, 1, 4, 0)
+    with pytest.raises(ewbem.EwbemError) as e:
+        c.guess_save()  # no model yet
+    assert e.value.status == ewbem.ESTATE
+    r = 5
+    dims = [6 * r + 2, 16, 16, 2 * r]
+    blob = _model_blob(N, r, dims, rng)
+    c.guess_load(blob)
+    assert c.guess_save() == blob  # a byte-exact round trip
+    assert c.guess_basis() == r
+    bad = [blob[:-1], blob + b"\0", b"X" + blob[1:], _model_blob(N + 3, r, dims, rng),
+           _model_blob(N, r, [6 * r + 1, 16, 2 * r], rng), _model_blob(N, r, dims, rng, version=2),
+           _model_blob(N, r, [6 * r + 2], rng)]
+    for b in bad:
+        with pytest.raises(ewbem.EwbemError) as e:
+            c.guess_load(b)
+        assert e.value.status == ewbem.EINVAL
+    nan = bytearray(blob)
+    nan[len(blob) - 8:] = np.array([np.nan]).tobytes()
+    with pytest.raises(ewbem.EwbemError):
+        c.guess_load(bytes(nan))
+    assert c.guess_save() == blob  # failed loads keep the model
+    # the learned guess is a valid solver choice; 4 is not
+    c.set_solver(guess=ewbem.GUESS_LEARNED)
+    with pytest.raises(ewbem.EwbemError):
+        c.set_solver(guess=4)
+    # a new mesh drops the model
+    c.set_mesh(xyz, tri)
+    with pytest.raises(ewbem.EwbemError):
+        c.guess_save()
+    c.close()
