@@ -41,10 +41,17 @@ def parse():
     ap.add_argument("--aca-reuse", type=int, choices=[0, 1], default=None,
                     help="start each frequency's ACA from the previous pivots (library default if unset)")
     ap.add_argument("--cpu-rows", type=int, default=48)
-    ap.add_argument("--workload", choices=["cavity", "rod-table1"], default="cavity",
+    ap.add_argument("--workload", choices=["cavity", "rod-table1", "learned", "batch12"], default="cavity",
                     help="cavity: the frequency-solve benchmark (default); rod-table1: the "
                          "three damping / extrapolation cases of the paper's Table 1 on its "
-                         "prismatic rod")
+                         "prismatic rod; learned: the cavity under spherical-harmonic "
+                         "pressures, learned guess with complex64 factors against plain FP64; "
+                         "batch12: twelve cavities of uneven size (levels 3-5) solved "
+                         "concurrently against one at a time")
+    ap.add_argument("--wave", type=int, default=6,
+                    help="batch12 workload: problems alive and solved concurrently at once")
+    ap.add_argument("--train-cases", type=int, default=8,
+                    help="learned workload: loads the guess is trained on")
     ap.add_argument("--rod-div", type=int, default=20,
                     help="rod mesh: cells per unit length (20 -> 11,200 triangles)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -186,6 +193,163 @@ def rod_table1(args):
                       "cases": out}), flush=True)
 
 
+def learned_workload(args):
+    """The level-5 cavity under spherical-harmonic pressure loads (sums of 4
+    real harmonics up to degree 6, N(0, 1) coefficients): the guess is
+    trained on the first --train-cases loads (untimed), then --steps
+    held-out loads are solved twice, timed: plain FP64 (complex128 factors,
+    least-squares extrapolation) and learned + FP32 (complex64 factors,
+    FP64 Arnoldi and residuals, the trained guess as an extra column)."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    from synth import config_inputs
+
+    d = config_inputs(4, sub=args.sub)
+    dev = torch.device("cuda:0")
+    N, n_f = 3 * len(d["tri"]), d["n_f"]
+    loads = d["loads"]
+    n_tr = min(args.train_cases, len(d["train"]))
+    held = d["held_out"][:args.steps]
+    op = dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5)
+
+    def make(store, guess):
+        c = E.Context(0)
+        c.set_mesh(d["xyz"], d["tri"], exterior=True)
+        m = d["material"]
+        c.set_material(m["rho"], m["mu"], m["nu"])
+        c.set_time(d["period"], n_f, d["sigma"], d["window"])
+        c.set_load_pressure(loads[0], d["history"])
+        c.set_operator(far_store=store, **op)
+        c.set_solver(tol=1e-6, guess=guess, sem_k=3, precond=E.PREC_LEAF)
+        return c
+
+    u = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
+    cl = make(E.STORE_C64, E.GUESS_LEARNED)
+    t = time.perf_counter()
+    tr = cl.guess_train(loads[[d["train"][i] for i in range(n_tr)]], pressures=True)
+    t_train = time.perf_counter() - t
+    print(f"# trained on {n_tr} loads in {t_train:.1f} s: pod energy {tr['pod_energy']:.8f}, "
+          f"loss {tr['train_loss_first']:.3e} -> {tr['train_loss_last']:.3e}", file=sys.stderr, flush=True)
+    cp = make(E.STORE_C128, E.GUESS_SEM)
+    cp.set_load_pressure(loads[held[0]], d["history"])
+    cp.solve_transient(u)  # warmup: the learned context was warmed by its training solves
+    res = {}
+    for name, c in (("plain_fp64", cp), ("learned_fp32", cl)):
+        tot = dict(its=0, solves=0, resid=0.0, guess=0.0, learned=0, t=0.0, t_gmres=0.0)
+        for i in held:
+            c.set_load_pressure(loads[i], d["history"])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = c.solve_transient(u)
+            torch.cuda.synchronize()
+            tot["t"] += time.perf_counter() - t
+            tot["its"] += st["iters_total"]
+            tot["solves"] += st["n_solves"]
+            tot["resid"] = max(tot["resid"], st["resid_max"])
+            tot["guess"] += st["guess_resid_sum"]
+            tot["learned"] += st["guess_learned"]
+            tot["t_gmres"] += st["t_gmres_ms"]
+            print(f"# {name} load {i}: {st['iters_total']} its, guess residual sum "
+                  f"{st['guess_resid_sum']:.3e}", file=sys.stderr, flush=True)
+        res[name] = {"value": tot["solves"] / tot["t"], "gmres_iters_per_solve": tot["its"] / tot["solves"],
+                     "resid_max": tot["resid"], "guess_resid_mean": tot["guess"] / tot["solves"],
+                     "learned_guesses": tot["learned"], "gmres_ms_per_solve": tot["t_gmres"] / tot["solves"],
+                     "ms_per_step": 1000.0 * tot["t"] / len(held)}
+    cl.close()
+    cp.close()
+    lf, pf = res["learned_fp32"], res["plain_fp64"]
+    print(json.dumps({
+        "metric": METRIC, "value": lf["value"], "unit": "freq-solves/s", "n_gpus": 1,
+        "steps": len(held), "warmup": 1, "ms_per_step": lf["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+c64-factors+bf16-net", "data": "synthetic",
+        "config": {"workload": d["name"] + " (held-out loads)", "n_dof": N, "n_f": n_f,
+                   "train_loads": n_tr, "held_out_loads": [int(i) for i in held], "gmres_tol": 1e-6,
+                   "aca_tol": 1e-5, "n_modes": 64, "network": "3 x 256 GELU, bf16 products"},
+        "plain_fp64": pf, "learned_fp32": lf, "speedup_vs_plain": lf["value"] / pf["value"],
+        "training": {"seconds": t_train, "solves": tr["n_solves"], "pod_energy": tr["pod_energy"],
+                     "loss_first": tr["train_loss_first"], "loss_last": tr["train_loss_last"]},
+    }), flush=True)
+
+
+def batch12_workload(args):
+    """Twelve independent cavities (spheres and ellipsoids with semi-axes in
+    [0.5, 2], icosphere levels 3-5, seeded pressure amplitudes; N_f = 128,
+    complex64 factors, FP64 Arnoldi and residuals, ACA 1e-5, GMRES 1e-6).
+    Timed twice from fresh contexts (tree, first cold ACA and all included):
+    one problem at a time, and through the concurrent batch entry in waves
+    of --wave problems (one context and stream each; a wave's contexts are
+    closed before the next, which bounds the memory held at once)."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    from synth import config_inputs
+
+    probs = config_inputs(3, sub=args.sub)["problems"]
+    dev = torch.device("cuda:0")
+
+    def make(d, st=None):
+        c = E.Context(0, stream=None if st is None else st.cuda_stream)
+        E.setup_from_inputs(c, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5,
+                                          far_store=E.STORE_C64),
+                            solver=dict(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF))
+        return c
+
+    def out(d):
+        return torch.zeros(d["n_f"] * 3 * len(d["tri"]), dtype=torch.float64, device=dev)
+
+    small = min(probs, key=lambda d: len(d["tri"]))
+    c = make(small)
+    c.solve_transient(out(small))  # warmup: library and runtime start-up
+    c.close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    seq_solves = seq_its = 0
+    for d in probs:
+        c = make(d)
+        st = c.solve_transient(out(d))
+        c.close()
+        seq_solves += st["n_solves"]
+        seq_its += st["iters_total"]
+        print(f"# one at a time: {d['name']} {st['iters_total']} its", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    # waves with the sizes dealt round-robin, largest first
+    order = sorted(range(len(probs)), key=lambda i: -len(probs[i]["tri"]))
+    n_waves = (len(probs) + args.wave - 1) // args.wave
+    waves = [[order[j] for j in range(w, len(order), n_waves)] for w in range(n_waves)]
+    t = time.perf_counter()
+    bat_solves = bat_its = 0
+    resid = 0.0
+    for w in waves:
+        streams = [torch.cuda.Stream() for _ in w]
+        ctxs = [make(probs[i], st) for i, st in zip(w, streams)]
+        st = E.batch_solve_transient(ctxs, [out(probs[i]) for i in w], per_launch=16)
+        torch.cuda.synchronize()
+        free, total = torch.cuda.mem_get_info()
+        for c in ctxs:
+            c.close()
+        bat_solves += st["n_solves"]
+        bat_its += st["iters_total"]
+        resid = max(resid, st["resid_max"])
+        print(f"# wave {[probs[i]['name'] for i in w]}: {st['iters_total']} its; device memory in use "
+              f"before closing {(total - free) / 1e9:.0f} GB", file=sys.stderr, flush=True)
+    t_bat = time.perf_counter() - t
+    n_dofs = [3 * len(d["tri"]) for d in probs]
+    print(json.dumps({
+        "metric": "freq-solves/s, twelve uneven cavities (complex64 factors, 1e-6 residual)",
+        "value": bat_solves / t_bat, "unit": "freq-solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000.0 * t_bat, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+c64-factors", "data": "synthetic",
+        "config": {"workload": "12-cavities-batched", "n_dof": n_dofs, "n_dof_total": int(sum(n_dofs)),
+                   "n_f": probs[0]["n_f"], "aca_tol": 1e-5, "gmres_tol": 1e-6,
+                   "waves": [[probs[i]["name"] for i in w] for w in waves]},
+        "one_at_a_time": {"value": seq_solves / t_seq, "ms": 1000.0 * t_seq,
+                          "gmres_iters_per_solve": seq_its / seq_solves},
+        "concurrent": {"value": bat_solves / t_bat, "ms": 1000.0 * t_bat,
+                       "gmres_iters_per_solve": bat_its / bat_solves, "resid_max": resid},
+        "speedup_concurrent": (bat_solves / t_bat) / (seq_solves / t_seq),
+    }), flush=True)
+
+
 def cpu_baseline(args):
     """The oracle (dense assembly + LU) on the host cores, on a bounded sample
     of the same workload: ``cpu_rows`` element rows of T and U at level 5
@@ -235,6 +399,12 @@ def main():
         sys.exit(2)
     if args.workload == "rod-table1":
         rod_table1(args)
+        return
+    if args.workload == "learned":
+        learned_workload(args)
+        return
+    if args.workload == "batch12":
+        batch12_workload(args)
         return
     if args.copy_probe:
         copy_probe()
