@@ -132,6 +132,10 @@ def run_gpu(args, store):
                     tot[k] += v
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    info = ctx.info()
+    tot["matvec_shapes"] = {"cols_per_wave": info["mv_cols"], "task_div": info["mv_task_div"],
+                            "tuned": info["mv_tuned"], "tuned_ms": info["mv_tune_best_ms"],
+                            "default_ms": info["mv_tune_default_ms"]}
     ctx.close()
     return d, N, elapsed, tot
 
@@ -306,10 +310,12 @@ def batch12_workload(args):
     for d in probs:
         c = make(d)
         st = c.solve_transient(out(d))
+        free, total = torch.cuda.mem_get_info()
         c.close()
         seq_solves += st["n_solves"]
         seq_its += st["iters_total"]
-        print(f"# one at a time: {d['name']} {st['iters_total']} its", file=sys.stderr, flush=True)
+        print(f"# one at a time: {d['name']} {st['iters_total']} its, {(total - free) / 1e9:.0f} GB in use",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t
     # waves with the sizes dealt round-robin, largest first
@@ -455,6 +461,7 @@ def main():
             "launches": st["matvecs_timed"],
         },
         "phases_ms_per_step": phases,
+        "matvec_shapes": st["matvec_shapes"],
         "gmres_iters_per_solve": st["iters_total"] / max(1, solves),
         "resid_max": st["resid_max"],
         "stored_operator_GB": st["stored_bytes"] / 1e9,

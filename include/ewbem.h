@@ -84,7 +84,11 @@ typedef struct {
                          its pivots at the previously assembled frequency, then continue
                          with ordinary steps until the stopping test holds; 0: from scratch
                          every time (default 1) */
-  int32_t pad;
+  int32_t autotune;   /* 1: on the first assembled operator (and again after the partition
+                         changes), time every pair of matvec task shapes -- 2, 4 or 8 factor
+                         columns per phase-1 wavefront, and phase-2 tasks of 1/2048, 1/4096
+                         or 1/8192 of all panel columns -- and keep the fastest; 0: 4 and
+                         1/4096 (default 1).  The shapes change the summation order only. */
 } ewbem_op_opts;
 
 typedef struct {
@@ -150,6 +154,12 @@ typedef struct {
   int64_t n_clusters, n_leaves, n_near, n_far;
   int64_t near_entries;    /* complex entries of all dense near blocks */
   int32_t max_leaf, min_leaf;
+  int32_t mv_cols;         /* matvec shapes in use: factor columns per phase-1 wavefront */
+  int32_t mv_task_div;     /*   phase-2 task size = all panel columns / mv_task_div (>= 96) */
+  int32_t mv_tuned;        /*   1 once chosen by timing (ewbem_op_opts.autotune) */
+  int32_t pad;
+  double mv_tune_best_ms;    /* tuning: one matvec with the chosen shapes, and with the */
+  double mv_tune_default_ms; /*   default ones (4, 4096), on the operator it ran on; 0 before */
 } ewbem_info_t;
 
 /* Fill option structs with their defaults. */

@@ -138,7 +138,7 @@ struct VtTask {
   long long zidx;
   int C;           // column length 3n
   int x0;          // 3 * c0
-  int ncol;        // <= 4
+  int ncol;        // <= the columns per wavefront of the launch (2, 4 or 8)
   int pad;
 };
 
@@ -168,8 +168,8 @@ constexpr int HMV_MAXROWS = 192;
 
 // nrhs = 1..4 right-hand sides: columns of x (stride ldx), z (ldz), the
 // partial sums (ldp) and y (ldy).
-void launch_far_vt(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, int nrhs, cd* z,
-                   long long ldz, hipStream_t st);
+void launch_far_vt(const VtTask* tasks, int ntask, int cols_per_wave, int store_c64, const cd* x, long long ldx,
+                   int nrhs, cd* z, long long ldz, hipStream_t st);
 void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, long long ldx, int nrhs,
                 const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st);
 void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, long long ldp, int nrhs, cd* y,

@@ -175,6 +175,12 @@ struct ewbem_ctx {
   DevBuf<RowTask> d_rt;
   DevBuf<LeafRange> d_lr;
   int n_vt = 0, n_rt = 0, n_lr = 0;
+  // matvec task shapes: factor columns per phase-1 wavefront and the phase-2
+  // task size (total panel columns / mv_div per task); chosen by timing on
+  // the first assembled operator when op.autotune is set
+  int mv_cols = 4, mv_div = 4096, vt_cols = 4;
+  bool mv_tuned = false;
+  double mv_best_ms = 0, mv_default_ms = 0;  // tuning: fastest and default shapes' matvec time
   DevBuf<cd> d_z, d_hpart, d_mvpart;
   long long z_len = 0, mvpart_len = 0;  // one right-hand side's share of d_z, d_mvpart
   DevBuf<cd> d_rhs_part;
@@ -296,6 +302,9 @@ void ensure_structure(ewbem_ctx* c) {
   }
   c->kcap_prev.assign(c->far_h.size(), 0);
   c->plist_ok = false;
+  c->mv_tuned = false;
+  c->mv_cols = 4;
+  c->mv_div = 4096;
   c->rank_h.assign(c->far_h.size(), 0);
   c->status_h.assign(c->far_h.size(), 0);
   c->structure_ok = true;
@@ -760,17 +769,18 @@ void build_matvec(ewbem_ctx* c) {
     launch_to_c64(c->d_far.p, nf, c->d_rank.p, c->d_uo.p, c->d_vo.p, c->d_f32.p, st);
   }
   // phase 1 tasks
+  const int vc = c->mv_cols;
   std::vector<VtTask> vt;
   for (int b = 0; b < nf; ++b) {
     const FarBlk& f = c->far_h[b];
     const int k = c->rank_h[b], C = 3 * f.n;
-    for (int l0 = 0; l0 < k; l0 += 4) {
+    for (int l0 = 0; l0 < k; l0 += vc) {
       VtTask t{};
       t.V = c64 ? (const void*)(c->d_f32.p + vo[b] + (size_t)l0 * C) : (const void*)(f.V + (size_t)l0 * C);
       t.zidx = zoff[b] + l0;
       t.C = C;
       t.x0 = 3 * f.c0;
-      t.ncol = std::min(4, k - l0);
+      t.ncol = std::min(vc, k - l0);
       vt.push_back(t);
     }
   }
@@ -823,7 +833,7 @@ void build_matvec(ewbem_ctx* c) {
   long long total_cols = 0;
   for (auto& v : segs)
     for (auto& s : v) total_cols += s.ncols;
-  const long long target = std::max<long long>(96, total_cols / 4096);
+  const long long target = std::max<long long>(96, total_cols / c->mv_div);
   std::vector<Seg> flat;
   std::vector<RowTask> rt;
   std::vector<LeafRange> lr;
@@ -857,7 +867,7 @@ void build_matvec(ewbem_ctx* c) {
     };
     const long long es = c64 ? (long long)sizeof(cf) : (long long)sizeof(cd);
     for (const VtTask& t : vt) {
-      if (t.ncol < 1 || t.ncol > 4 || t.x0 < 0 || t.x0 + (long long)t.C > N || t.zidx < 0 ||
+      if (t.ncol < 1 || t.ncol > vc || t.x0 < 0 || t.x0 + (long long)t.C > N || t.zidx < 0 ||
           t.zidx + t.ncol > ztot || !store_ok(t.V, (long long)t.ncol * t.C * es))
         fail(EWBEM_EINVAL, "internal: phase-1 task out of range");
     }
@@ -885,6 +895,7 @@ void build_matvec(ewbem_ctx* c) {
         fail(EWBEM_EINVAL, "internal: leaf range out of range");
   }
   c->d_vt.upload(vt, st);
+  c->vt_cols = vc;
   c->d_seg.upload(flat, st);
   c->d_rt.upload(rt, st);
   c->d_lr.upload(lr, st);
@@ -901,7 +912,7 @@ void build_matvec(ewbem_ctx* c) {
 void apply_tree(ewbem_ctx* c, const cd* x, cd* y, EventPair* ev) {
   hipStream_t st = c->stream;
   if (ev) EWBEM_HIP_CHECK(hipEventRecord(ev->a, st));
-  launch_far_vt(c->d_vt.p, c->n_vt, c->store_c64_active, x, 0, 1, c->d_z.p, 0, st);
+  launch_far_vt(c->d_vt.p, c->n_vt, c->vt_cols, c->store_c64_active, x, 0, 1, c->d_z.p, 0, st);
   launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, x, 0, 1, c->d_z.p, 0, c->d_mvpart.p, 0, st);
   launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, 0, 1, y, 0, st);
   if (ev) EWBEM_HIP_CHECK(hipEventRecord(ev->b, st));
@@ -914,7 +925,7 @@ void apply_tree_multi(ewbem_ctx* c, const cd* X, cd* Y, int nrhs) {
   hipStream_t st = c->stream;
   const long long N = 3LL * c->nt;
   if (nrhs < 1 || nrhs > HMV_MAXRHS) fail(EWBEM_EINVAL, "internal: matvec right-hand sides out of range");
-  launch_far_vt(c->d_vt.p, c->n_vt, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st);
+  launch_far_vt(c->d_vt.p, c->n_vt, c->vt_cols, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st);
   launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, X, N, nrhs, c->d_z.p, c->z_len, c->d_mvpart.p, c->mvpart_len, st);
   launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, c->mvpart_len, nrhs, Y, N, st);
   c->acc.matvecs += nrhs;
@@ -988,6 +999,62 @@ void rhs_precompute(ewbem_ctx* c, const DevGeom& g, int k0, int nk) {
   c->boff_nk = nk;
 }
 
+double dev_norm(ewbem_ctx* c, const cd* v);
+
+// Matvec task shapes by measurement: every pair of candidate phase-1 column
+// counts and phase-2 task sizes is built and timed (one warm apply, then
+// three timed) on the operator just assembled; the fastest is kept for the
+// rest of the context's life (until the partition changes).
+void tune_matvec(ewbem_ctx* c) {
+  static const int kCols[] = {2, 4, 8};
+  static const int kDivs[] = {2048, 4096, 8192};
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  {
+    std::vector<cd> xh(N);
+    for (long long i = 0; i < N; ++i) xh[i] = cd{std::cos(0.37 * i), std::sin(0.11 * i)};
+    EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_tmp_in.p, xh.data(), N * sizeof(cd), hipMemcpyHostToDevice, st));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  }
+  EventPair ev;
+  double best = 1e300, yref = 0.0;
+  int bc = c->mv_cols, bd = c->mv_div;
+  bool first = true;
+  for (int nc : kCols)
+    for (int dv : kDivs) {
+      c->mv_cols = nc;
+      c->mv_div = dv;
+      build_matvec(c);
+      apply_tree(c, c->d_tmp_in.p, c->d_tmp_out.p, nullptr);
+      EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+      for (int i = 0; i < 3; ++i) apply_tree(c, c->d_tmp_in.p, c->d_tmp_out.p, nullptr);
+      EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      const double ms = ev.elapsed() / 3.0;
+      // every shape computes the same product up to summation order
+      if (first) {
+        EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_w.p, c->d_tmp_out.p, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+        yref = dev_norm(c, c->d_w.p);
+        first = false;
+      } else {
+        EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_zt.p, c->d_tmp_out.p, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+        launch_axpby(cd{-1.0, 0.0}, c->d_w.p, cd{1.0, 0.0}, c->d_zt.p, N, st);
+        if (dev_norm(c, c->d_zt.p) > 1e-12 * yref) fail(EWBEM_EINVAL, "internal: matvec task shapes disagree");
+      }
+      if (nc == 4 && dv == 4096) c->mv_default_ms = ms;
+      if (ms < best) {
+        best = ms;
+        bc = nc;
+        bd = dv;
+      }
+    }
+  c->mv_cols = bc;
+  c->mv_div = bd;
+  c->mv_tuned = true;
+  c->mv_best_ms = best;
+  build_matvec(c);
+}
+
 void assemble_k(ewbem_ctx* c, int k) {
   ensure_device(c);
   if (k < 0 || k > c->n_f / 2) fail(EWBEM_EINVAL, "frequency index out of range 0..N_f/2");
@@ -1007,6 +1074,7 @@ void assemble_k(ewbem_ctx* c, int k) {
   run_aca(c, g, ev, aca_ms);
   c->acc.t_aca_ms += aca_ms;
   build_matvec(c);
+  if (c->op.autotune && !c->mv_tuned && !c->far_h.empty()) tune_matvec(c);
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
   if (k < c->boff_k0 || k >= c->boff_k0 + c->boff_nk) rhs_precompute(c, g, k, 1);
   launch_rhs_finish(c->d_rhs_part.p, c->boff_nk, k - c->boff_k0, c->nt, c->d_selfU.p, c->d_t0.p,
@@ -1603,7 +1671,7 @@ void ewbem_default_op_opts(ewbem_op_opts* o) {
   o->far_store = EWBEM_STORE_C128;
   o->self_order = 24;
   o->aca_reuse = 1;
-  o->pad = 0;
+  o->autotune = 1;
 }
 
 void ewbem_default_solver_opts(ewbem_solver_opts* o) {
@@ -1816,7 +1884,8 @@ int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
     if ((o->kind != EWBEM_OP_DENSE && o->kind != EWBEM_OP_HMAT) || o->leaf_size < 1 || o->leaf_size > 64 ||
         !(o->eta_adm > 0) || !(o->aca_tol > 0 && o->aca_tol < 1) ||
         (o->far_store != EWBEM_STORE_C128 && o->far_store != EWBEM_STORE_C64) || o->self_order < 4 ||
-        o->self_order > MAX_SELF_ORDER || (o->aca_reuse != 0 && o->aca_reuse != 1))
+        o->self_order > MAX_SELF_ORDER || (o->aca_reuse != 0 && o->aca_reuse != 1) ||
+        (o->autotune != 0 && o->autotune != 1))
       fail(EWBEM_EINVAL, "operator options out of range");
     ctx->op = *o;
     ctx->structure_ok = false;
@@ -1857,6 +1926,12 @@ int ewbem_info(ewbem_ctx* ctx, ewbem_info_t* info) {
     }
     info->max_leaf = mx;
     info->min_leaf = mn;
+    info->mv_cols = ctx->mv_cols;
+    info->mv_task_div = ctx->mv_div;
+    info->mv_tuned = ctx->mv_tuned ? 1 : 0;
+    info->pad = 0;
+    info->mv_tune_best_ms = ctx->mv_tuned ? ctx->mv_best_ms : 0.0;
+    info->mv_tune_default_ms = ctx->mv_tuned ? ctx->mv_default_ms : 0.0;
     return EWBEM_OK;
   });
 }

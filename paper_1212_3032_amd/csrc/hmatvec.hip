@@ -1,8 +1,8 @@
 // Hierarchical-matrix matvec y = A x, A = sum_near D + sum_far U V^T.
 //
 // Phase 1 (k_far_vt): z_b = V_b^T x_sigma for every far block, one
-// wavefront per group of up to four factor columns; each column is read
-// once, coalesced, and reduced across the wavefront.
+// wavefront per group of up to 2, 4 or 8 factor columns (tuned); each column
+// is read once, coalesced, and reduced across the wavefront.
 // Phase 2 (k_hmv): row ownership by leaf cluster.  Every leaf's rows see a
 // panel made of its dense near blocks (times x) and the matching row slices
 // of the U factors of the far blocks above it (times z).  The panel is cut
@@ -24,8 +24,9 @@ __device__ __forceinline__ double wsum64(double v) {
 
 // NR right-hand sides at once (columns of x, z, partial and y, strides ldx,
 // ldz, ldp, ldy): every factor and near-block entry is loaded once and
-// multiplied against the NR vectors.
-template <typename TS, int NR>
+// multiplied against the NR vectors.  Phase 1 takes NC factor columns per
+// wavefront (a tuning choice).
+template <typename TS, int NR, int NC>
 __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks, int ntask,
                                                 const cd* __restrict__ x, long long ldx, cd* __restrict__ z,
                                                 long long ldz) {
@@ -35,30 +36,30 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
   const VtTask T = tasks[t];
   const TS* __restrict__ V = (const TS*)T.V;
   const cd* __restrict__ xs = x + T.x0;
-  cd a[4][NR];
+  cd a[NC][NR];
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < NC; ++k)
 #pragma unroll
     for (int q = 0; q < NR; ++q) a[k][q] = mk(0.0);
   const int C = T.C;
   const int nc = T.ncol;
   // columns past ncol read column 0 again (in bounds) and are discarded
-  const TS* __restrict__ V1 = V + (size_t)(nc > 1 ? 1 : 0) * C;
-  const TS* __restrict__ V2 = V + (size_t)(nc > 2 ? 2 : 0) * C;
-  const TS* __restrict__ V3 = V + (size_t)(nc > 3 ? 3 : 0) * C;
+  const TS* __restrict__ Vc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) Vc[k] = V + (size_t)(nc > k ? k : 0) * C;
   for (int c = lane; c < C; c += 64) {
-    const cd v0 = to_cd(V[c]), v1 = to_cd(V1[c]), v2 = to_cd(V2[c]), v3 = to_cd(V3[c]);
+    cd v[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[k] = to_cd(Vc[k][c]);
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const cd xv = xs[c + q * ldx];
-      a[0][q] += v0 * xv;
-      a[1][q] += v1 * xv;
-      a[2][q] += v2 * xv;
-      a[3][q] += v3 * xv;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) a[k][q] += v[k] * xv;
     }
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < NC; ++k)
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       a[k][q].x = wsum64(a[k][q].x);
@@ -70,33 +71,43 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       cd* zz = z + T.zidx + q * ldz;
-      zz[0] = a[0][q];
-      if (nc > 1) zz[1] = a[1][q];
-      if (nc > 2) zz[2] = a[2][q];
-      if (nc > 3) zz[3] = a[3][q];
+#pragma unroll
+      for (int k = 0; k < NC; ++k)
+        if (nc > k) zz[k] = a[k][q];
     }
   }
 }
 
-template <int NR>
+template <int NR, int NC>
 void far_vt_nr(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, cd* z, long long ldz,
                hipStream_t st) {
   dim3 grid((ntask + 3) / 4);
   if (store_c64)
-    hipLaunchKernelGGL((k_far_vt<cf, NR>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
+    hipLaunchKernelGGL((k_far_vt<cf, NR, NC>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
   else
-    hipLaunchKernelGGL((k_far_vt<cd, NR>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
+    hipLaunchKernelGGL((k_far_vt<cd, NR, NC>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
 }
 
-void launch_far_vt(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, int nrhs, cd* z,
-                   long long ldz, hipStream_t st) {
-  if (ntask <= 0) return;
+template <int NC>
+void far_vt_nc(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, int nrhs, cd* z,
+               long long ldz, hipStream_t st) {
   switch (nrhs) {
-    case 1: far_vt_nr<1>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
-    case 2: far_vt_nr<2>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
-    case 3: far_vt_nr<3>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
-    case 4: far_vt_nr<4>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 1: far_vt_nr<1, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 2: far_vt_nr<2, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 3: far_vt_nr<3, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 4: far_vt_nr<4, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
     default: throw ApiError(-1, "matvec: 1 to 4 right-hand sides");
+  }
+}
+
+void launch_far_vt(const VtTask* tasks, int ntask, int cols_per_wave, int store_c64, const cd* x, long long ldx,
+                   int nrhs, cd* z, long long ldz, hipStream_t st) {
+  if (ntask <= 0) return;
+  switch (cols_per_wave) {
+    case 2: far_vt_nc<2>(tasks, ntask, store_c64, x, ldx, nrhs, z, ldz, st); break;
+    case 4: far_vt_nc<4>(tasks, ntask, store_c64, x, ldx, nrhs, z, ldz, st); break;
+    case 8: far_vt_nc<8>(tasks, ntask, store_c64, x, ldx, nrhs, z, ldz, st); break;
+    default: throw ApiError(-1, "matvec: 2, 4 or 8 factor columns per wavefront");
   }
 }
 

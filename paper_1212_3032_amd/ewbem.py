@@ -41,7 +41,7 @@ class Z(C.Structure):
 class OpOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("leaf_size", C.c_int32), ("eta_adm", C.c_double),
                 ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32),
-                ("aca_reuse", C.c_int32), ("pad", C.c_int32)]
+                ("aca_reuse", C.c_int32), ("autotune", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
@@ -77,7 +77,9 @@ class TrainOpts(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n_elements", C.c_int64), ("n_dof", C.c_int64), ("n_clusters", C.c_int64),
                 ("n_leaves", C.c_int64), ("n_near", C.c_int64), ("n_far", C.c_int64),
-                ("near_entries", C.c_int64), ("max_leaf", C.c_int32), ("min_leaf", C.c_int32)]
+                ("near_entries", C.c_int64), ("max_leaf", C.c_int32), ("min_leaf", C.c_int32),
+                ("mv_cols", C.c_int32), ("mv_task_div", C.c_int32), ("mv_tuned", C.c_int32),
+                ("pad", C.c_int32), ("mv_tune_best_ms", C.c_double), ("mv_tune_default_ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -1,0 +1,55 @@
+"""The matvec's task shapes chosen by timing (ewbem_op_opts.autotune) change
+only the summation order: the tuned and the default operator give the same
+products (1e-13 relative; the library itself also checks every candidate
+against the first, 1e-12) and the same solutions."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from synth import icosphere, ramp_history, uniform_pressure
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(E, xyz, tri, autotune):
+    c = E.Context(0)
+    c.set_mesh(xyz, tri, exterior=True)
+    c.set_material(1.0, 1.0, 0.25)
+    c.set_time(8.0, 32, 0.75, 1)
+    c.set_load_pressure(uniform_pressure(len(tri)), ramp_history(32, 8.0, 0.05))
+    c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-6, autotune=autotune)
+    c.set_solver(tol=1e-10, guess=E.GUESS_SEM)
+    return c
+
+
+@pytest.mark.parametrize("sub", [3, 4])
+def test_tuned_shapes_give_the_same_operator(sub):
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    dev = torch.device("cuda:0")
+    xyz, tri = icosphere(sub)
+    N = 3 * len(tri)
+    a, b = _ctx(E, xyz, tri, 1), _ctx(E, xyz, tri, 0)
+    g = torch.Generator().manual_seed(sub)
+    x = torch.randn(N, dtype=torch.complex128, generator=g).to(dev)
+    for c in (a, b):
+        c.assemble(5)
+    ya, yb = torch.zeros_like(x), torch.zeros_like(x)
+    a.apply(x, ya)
+    b.apply(x, yb)
+    ia, ib = a.info(), b.info()
+    e = float(torch.linalg.norm(ya - yb) / torch.linalg.norm(yb))
+    print(f"level {sub}: tuned shapes cols {ia['mv_cols']} div {ia['mv_task_div']}; "
+          f"default {ib['mv_cols']} / {ib['mv_task_div']}; products differ by {e:.1e}", flush=True)
+    sys.stdout.flush()
+    assert ia["mv_tuned"] == 1 and ia["mv_cols"] in (2, 4, 8) and ia["mv_task_div"] in (2048, 4096, 8192)
+    assert ib["mv_tuned"] == 0 and (ib["mv_cols"], ib["mv_task_div"]) == (4, 4096)
+    assert e < 1e-13
+    sa, sb = torch.zeros_like(x), torch.zeros_like(x)
+    a.solve_frequency(6, sa)
+    b.solve_frequency(6, sb)
+    assert float(torch.linalg.norm(sa - sb) / torch.linalg.norm(sb)) < 1e-9
+    a.close()
+    b.close()

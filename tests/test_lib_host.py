@@ -27,7 +27,7 @@ def test_defaults():
     o = ewbem.default_op_opts()
     assert (o.kind, o.leaf_size, o.eta_adm, o.aca_tol) == (ewbem.OP_HMAT, 64, 1.0, 1e-5)
     # the fields after the doubles sit where the C struct has them
-    assert (o.far_store, o.self_order, o.aca_reuse, o.pad) == (ewbem.STORE_C128, 24, 1, 0)
+    assert (o.far_store, o.self_order, o.aca_reuse, o.autotune) == (ewbem.STORE_C128, 24, 1, 1)
     s = ewbem.default_solver_opts()
     assert (s.tol, s.restart, s.guess, s.sem_k) == (1e-6, 100, ewbem.GUESS_SEM, 3)
 
