@@ -54,6 +54,9 @@ def parse():
                     help="learned workload: loads the guess is trained on")
     ap.add_argument("--rod-div", type=int, default=20,
                     help="rod mesh: cells per unit length (20 -> 11,200 triangles)")
+    ap.add_argument("--read-probe", action="store_true",
+                    help="also time a plain streaming read of 8 GiB (torch's sum over float64), the "
+                         "practical HBM read rate the matvec's fraction can be set against")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known "
                          "traffic that calibrates the HBM counters)")
@@ -69,6 +72,25 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     del a, b
+
+
+def read_probe():
+    """GB/s of torch's float64 sum over 8 GiB (best of five, after one warm run)."""
+    import torch
+    a = torch.ones((8 << 30) // 8, dtype=torch.float64, device="cuda:0")
+    a.sum()
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        a.sum()
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a
+    torch.cuda.empty_cache()
+    return (8 << 30) / (best * 1e-3) / 1e9
 
 
 def _hash(path):
@@ -467,6 +489,8 @@ def main():
         "stored_operator_GB": st["stored_bytes"] / 1e9,
         "far_blocks": st["n_far"], "near_blocks": st["n_near"], "rank_max": st["rank_max"],
     }
+    if args.read_probe:
+        out["roofline"]["stream_read_probe_GBps"] = read_probe()
     if args.c64_variant and args.store == "c128":
         _, _, el2, st2 = run_gpu(args, "c64")
         out["c64_factors"] = {
