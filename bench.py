@@ -56,9 +56,9 @@ def parse():
                     help="learned workload: loads the guess is trained on")
     ap.add_argument("--rod-div", type=int, default=20,
                     help="rod mesh: cells per unit length (20 -> 11,200 triangles)")
-    ap.add_argument("--read-probe", action="store_true",
-                    help="also time a plain streaming read of 8 GiB (torch's sum over float64), the "
-                         "practical HBM read rate the matvec's fraction can be set against")
+    ap.add_argument("--no-read-probe", action="store_true",
+                    help="skip timing a plain streaming read of 8 GiB (torch's sum over float64), the "
+                         "practical HBM read rate the matvec's fraction is set against")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known "
                          "traffic that calibrates the HBM counters)")
@@ -545,14 +545,20 @@ def main():
             "launches": st["matvecs_timed"],
         },
         "phases_ms_per_step": phases,
+        "rates_freq_solves_per_s": {
+            "end_to_end": value,
+            "assembly_only": solves / (st["t_assemble_ms"] / 1000.0),
+            "solve_only": solves / ((st["t_guess_ms"] + st["t_gmres_ms"]) / 1000.0)},
         "matvec_shapes": st["matvec_shapes"],
         "gmres_iters_per_solve": st["iters_total"] / max(1, solves),
         "resid_max": st["resid_max"],
         "stored_operator_GB": st["stored_bytes"] / 1e9,
         "far_blocks": st["n_far"], "near_blocks": st["n_near"], "rank_max": st["rank_max"],
     }
-    if args.read_probe:
-        out["roofline"]["stream_read_probe_GBps"] = read_probe()
+    if not args.no_read_probe:
+        rp = read_probe()
+        out["roofline"]["stream_read_probe_GBps"] = rp
+        out["roofline"]["frac_of_stream_read_probe"] = mv_gbs / rp
     if args.c64_variant and args.store == "c128":
         _, _, el2, st2 = run_gpu(args, "c64")
         out["c64_factors"] = {
