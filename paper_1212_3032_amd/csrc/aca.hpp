@@ -127,6 +127,7 @@ struct WsArgs {
 constexpr int WS_LDS_SMALL = 2304;  // entries of W held in LDS by the three LDS classes
 constexpr int WS_LDS_MID = 4480;
 constexpr int WS_LDS_LARGE = 8960;
+constexpr int WS_CH = 8;             // substitution terms solved together in registers (coefficient padding)
 constexpr int WS_LU_NR_LDS = 2;     // LDS classes hold cores of at most 128 rows
 void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s);
 

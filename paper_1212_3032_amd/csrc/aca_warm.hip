@@ -172,7 +172,6 @@ __global__ __launch_bounds__(256) void k_ws_eval_cols(const WsBlk* __restrict__ 
     for (int ii = 0; ii < 3; ++ii) Cc[(3 * (size_t)sidx + jj) * M3 + 3 * a + ii] = T[3 * ii + jj];
 }
 
-constexpr int WS_CH = 8;  // terms solved together in registers
 
 // Wavefront argmax of (value, linear index), ties to the smaller index.
 __device__ __forceinline__ void wave_argmax(double& v, int& e) {

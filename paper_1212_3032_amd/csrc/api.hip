@@ -506,7 +506,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     w.pv = part;
     part += (long long)ntv * w.rcap;
     w.co = coefn;
-    coefn += 2LL * (w.rcap + 8) * w.rcap + w.rcap + 8;  // Mc, Nc, Dn with one chunk of padding
+    coefn += 2LL * (w.rcap + WS_CH) * w.rcap + w.rcap + WS_CH;  // Mc, Nc, Dn with one chunk of padding
     wb.push_back(w);
     er += (long long)nr * f.n;
     ec += (long long)nc * f.m;

@@ -168,3 +168,28 @@ def test_learned_model_format_on_host_context():
     with pytest.raises(ewbem.EwbemError):
         c.guess_save()
     c.close()
+
+
+def test_product_and_oracle_share_no_code():
+    """The library and its binding never import the oracle, and the oracle
+    never imports the library; synth/ (inputs only) is the one shared module."""
+    import ast
+    def imports(path):
+        names = set()
+        for root, _, files in os.walk(path):
+            for f in files:
+                if f.endswith(".py"):
+                    tree = ast.parse(open(os.path.join(root, f)).read())
+                    for node in ast.walk(tree):
+                        if isinstance(node, ast.Import):
+                            names.update(a.name.split(".")[0] for a in node.names)
+                        elif isinstance(node, ast.ImportFrom) and node.module and node.level == 0:
+                            names.add(node.module.split(".")[0])
+        return names
+    assert "oracle" not in imports(os.path.join(ROOT, "paper_1212_3032_amd"))
+    assert "paper_1212_3032_amd" not in imports(os.path.join(ROOT, "oracle"))
+    for root, _, files in os.walk(os.path.join(ROOT, "paper_1212_3032_amd", "csrc")):
+        for f in files:
+            assert "oracle" not in open(os.path.join(root, f), errors="ignore").read().lower(), f
+    assert "paper_1212_3032_amd" not in imports(os.path.join(ROOT, "synth"))
+    assert "oracle" not in imports(os.path.join(ROOT, "synth"))
