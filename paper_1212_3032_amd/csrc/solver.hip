@@ -164,12 +164,121 @@ void launch_apply3(const cd* M, int ne, const cd* v, cd* z, hipStream_t st) {
 }
 
 // ---- leaf block-diagonal preconditioner: Gauss-Jordan inversion with
-// partial pivoting of each diagonal near block (n x n, column-major),
-// one workgroup per block, in place in a work copy in global memory.
+// partial pivoting of each diagonal near block (n x n, column-major).
+//
+// Blocks of up to BI_NP = 128 rows: the whole block lives in the registers
+// of one 1024-thread workgroup (thread = row r, columns g, g + 8, ...), and
+// rows are never swapped: at step k the pivot is the unused row p with the
+// largest |A[p][k]|, row p is scaled and column k eliminated from every
+// other row in place.  The result B then holds the inverse with rows and
+// columns permuted: inv[i][c] = B[piv[i]][q[c]], q the inverse of piv, which
+// the final store undoes.  Three barriers per pivot, no global traffic
+// between the load and the store.
+constexpr int BI_NP = 128;                 // rows per block, padded
+constexpr int BI_G = 1024 / BI_NP;         // column groups
+constexpr int BI_CPT = BI_NP / BI_G;       // columns per thread
+
+__global__ __launch_bounds__(1024) void k_block_inv_reg(const long long* __restrict__ offs,
+                                                        const int* __restrict__ dims, cd* __restrict__ W,
+                                                        int* __restrict__ piv_fail) {
+  const int b = blockIdx.x;
+  const int n = dims[b];
+  if (n > BI_NP) return;  // larger blocks: k_block_inv
+  cd* A = W + offs[b];
+  const int t = threadIdx.x;
+  const int r = t % BI_NP, g = t / BI_NP;
+  const int lane = t & 63, wv = r >> 6;  // wave index within the column group
+  // s_col alternates with the step: rows still updating from step k read
+  // it while column k + 1 is written
+  __shared__ cd s_row[BI_NP], s_col[2][BI_NP];
+  __shared__ double s_bv[2];
+  __shared__ int s_bi[2], s_piv[BI_NP], s_q[BI_NP];
+  __shared__ cd s_inv;
+  cd a[BI_CPT];
+#pragma unroll
+  for (int j = 0; j < BI_CPT; ++j) {
+    const int c = g + BI_G * j;
+    a[j] = (r < n && c < n) ? A[(size_t)c * n + r] : mk(0.0);
+  }
+  bool used = r >= n;
+  for (int k = 0; k < n; ++k) {
+    const int gk = k % BI_G, jk = k / BI_G;
+    // this thread's entry of column k (meaningful in group gk)
+    cd ck = mk(0.0);
+#pragma unroll
+    for (int j = 0; j < BI_CPT; ++j)
+      if (j == jk) ck = a[j];
+    if (g == gk) {
+      // arg max over the unused rows; used rows score -1, ties to the lower row
+      double v = used ? -1.0 : norm2(ck);
+      int vi = r;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(vi, off, 64);
+        if (ov > v || (ov == v && oi < vi)) {
+          v = ov;
+          vi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_bv[wv] = v;
+        s_bi[wv] = vi;
+      }
+      if (r < n) s_col[k & 1][r] = ck;
+    }
+    __syncthreads();
+    const int p = (s_bv[1] > s_bv[0] || (s_bv[1] == s_bv[0] && s_bi[1] < s_bi[0])) ? s_bi[1] : s_bi[0];
+    if (r == p) {
+      // the pivot's row, scaled; column k of the result holds 1 / pivot
+      if (g == gk) {
+        const bool ok = norm2(ck) > 0.0;
+        if (!ok) piv_fail[b] = 1;
+        s_inv = ok ? cinv(ck) : mk(0.0);
+        s_piv[k] = p;
+        s_q[p] = k;
+      }
+    }
+    __syncthreads();
+    const cd ip = s_inv;
+    if (r == p) {
+#pragma unroll
+      for (int j = 0; j < BI_CPT; ++j) {
+        const int c = g + BI_G * j;
+        if (c < n) {
+          a[j] = (c == k) ? ip : a[j] * ip;
+          s_row[c] = a[j];
+        }
+      }
+      used = true;
+    }
+    __syncthreads();
+    if (r != p && r < n) {
+      const cd f = s_col[k & 1][r];
+#pragma unroll
+      for (int j = 0; j < BI_CPT; ++j) {
+        const int c = g + BI_G * j;
+        if (c < n) a[j] = (c == k) ? -(f * ip) : a[j] - f * s_row[c];
+      }
+    }
+  }
+  __syncthreads();
+  if (r < n) {
+    const int i = s_q[r];
+#pragma unroll
+    for (int j = 0; j < BI_CPT; ++j) {
+      const int c = g + BI_G * j;
+      if (c < n) A[(size_t)s_piv[c] * n + i] = a[j];
+    }
+  }
+}
+
+// Larger blocks (up to HMV_MAXROWS_S rows): one 256-thread workgroup per
+// block, in place in global memory, explicit row swaps.
 __global__ __launch_bounds__(256) void k_block_inv(const long long* __restrict__ offs, const int* __restrict__ dims,
                                                    cd* __restrict__ W, int* __restrict__ piv_fail) {
   const int b = blockIdx.x;
   const int n = dims[b];
+  if (n <= BI_NP) return;  // k_block_inv_reg
   cd* A = W + offs[b];
   __shared__ int s_piv[HMV_MAXROWS_S];
   __shared__ double s_v[256];
@@ -247,7 +356,9 @@ __global__ __launch_bounds__(256) void k_block_inv(const long long* __restrict__
 
 void launch_block_inv(const long long* offs, const int* dims, int nblk, cd* W, int* piv_fail,
                       hipStream_t st) {
-  if (nblk > 0) hipLaunchKernelGGL(k_block_inv, dim3(nblk), dim3(256), 0, st, offs, dims, W, piv_fail);
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(k_block_inv_reg, dim3(nblk), dim3(1024), 0, st, offs, dims, W, piv_fail);
+  hipLaunchKernelGGL(k_block_inv, dim3(nblk), dim3(256), 0, st, offs, dims, W, piv_fail);
 }
 
 // z[row0 + r] = sum_c Minv_b[r, c] v[row0 + c], one workgroup per leaf
