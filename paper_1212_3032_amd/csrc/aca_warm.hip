@@ -337,20 +337,22 @@ __global__ __launch_bounds__(64 * WS_LU_NW) void k_ws_lu(const WsBlk* __restrict
   for (int tt = tid; tt < rho; tt += NT) Dn[tt] = cinv(W[sQ[tt] * R3 + sP[tt]]);
 }
 
-// U terms: one wavefront per 21 row elements of a block.  Row r of
-// Cc(:, q) = U M is solved for U(r, :) by forward substitution; the
-// coefficients are wavefront-uniform reads of Mc.
-__global__ __launch_bounds__(64) void k_ws_form_u(WsArgs A, const FarBlk* __restrict__ blks,
-                                                  AcaState* __restrict__ st, const unsigned* __restrict__ used,
-                                                  const cd* __restrict__ coef) {
-  const int task = blockIdx.x;
+// U terms: one wavefront per 21 row elements of a block (four independent
+// wavefronts per workgroup, so that more of them are resident per compute
+// unit).  Row r of Cc(:, q) = U M is solved for U(r, :) by forward
+// substitution; the coefficients are wavefront-uniform reads of Mc.
+__global__ __launch_bounds__(256) void k_ws_form_u(WsArgs A, const FarBlk* __restrict__ blks,
+                                                   AcaState* __restrict__ st, const unsigned* __restrict__ used,
+                                                   const cd* __restrict__ coef) {
+  const int task = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  if (task >= A.tot_tu) return;
   const int i = find_seg(A.tu_off, A.nwarm, task);
   const WsBlk w = A.wb[i];
   const FarBlk B = blks[w.blk];
   const int rho = A.rho[i];
   if (rho == 0) return;
   const int tile = task - A.tu_off[i];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const size_t M3 = 3 * (size_t)B.m;
   const int r = tile * (3 * ACA_ROWS_PER_WAVE) + lane;
   const bool valid = lane < 3 * ACA_ROWS_PER_WAVE && r < (int)M3;
@@ -408,18 +410,19 @@ __global__ __launch_bounds__(64) void k_ws_form_u(WsArgs A, const FarBlk* __rest
   if (lane == 0 && cand) atomicMax(&st[w.blk].best_row, cand);
 }
 
-// V terms: one wavefront per 64 columns of a block.  Column c of
-// Rr(p, :) = N V^T is solved for V(c, :) by forward substitution.
-__global__ __launch_bounds__(64) void k_ws_form_v(WsArgs A, const FarBlk* __restrict__ blks,
-                                                  const cd* __restrict__ coef) {
-  const int task = blockIdx.x;
+// V terms: one wavefront per 64 columns of a block (four per workgroup).
+// Column c of Rr(p, :) = N V^T is solved for V(c, :) by forward substitution.
+__global__ __launch_bounds__(256) void k_ws_form_v(WsArgs A, const FarBlk* __restrict__ blks,
+                                                   const cd* __restrict__ coef) {
+  const int task = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  if (task >= A.tot_tv) return;
   const int i = find_seg(A.tv_off, A.nwarm, task);
   const WsBlk w = A.wb[i];
   const FarBlk B = blks[w.blk];
   const int rho = A.rho[i];
   if (rho == 0) return;
   const int tile = task - A.tv_off[i];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const size_t N3 = 3 * (size_t)B.n;
   const int c = tile * 64 + lane;
   const bool valid = c < (int)N3;
@@ -590,8 +593,8 @@ void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParam
   if (A.n_lu[3] > 0)
     hipLaunchKernelGGL((k_ws_lu<0, (3 * WS_MAXLIST + 63) / 64>), dim3(A.n_lu[3]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho,
                        A.coef);
-  hipLaunchKernelGGL(k_ws_form_u, dim3(A.tot_tu), dim3(64), 0, s, A, W.blks, W.st, W.used, A.coef);
-  hipLaunchKernelGGL(k_ws_form_v, dim3(A.tot_tv), dim3(64), 0, s, A, W.blks, A.coef);
+  hipLaunchKernelGGL(k_ws_form_u, dim3((A.tot_tu + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, A.coef);
+  hipLaunchKernelGGL(k_ws_form_v, dim3((A.tot_tv + 3) / 4), dim3(256), 0, s, A, W.blks, A.coef);
   hipLaunchKernelGGL(k_ws_finish, dim3((A.nwarm + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, W.plist,
                      W.nlist, tol);
 }
