@@ -121,10 +121,11 @@ struct WsArgs {
   int* rho;
   double* part;
   cd* coef;
-  const int* lu_list;  // warm blocks by size class of W (n_lu[0..3] entries)
-  int n_lu[4];
+  const int* lu_list;  // warm blocks by size class of W (n_lu[0..4] entries)
+  int n_lu[5];
 };
-constexpr int WS_LDS_SMALL = 2304;  // entries of W held in LDS by the three LDS classes
+constexpr int WS_LDS_TINY = 1024;   // entries of W held in LDS by the LDS classes (tiny: <= 64 rows)
+constexpr int WS_LDS_SMALL = 2304;
 constexpr int WS_LDS_MID = 4480;
 constexpr int WS_LDS_LARGE = 8960;
 constexpr int WS_CH = 8;             // substitution terms solved together in registers (coefficient padding)

@@ -193,18 +193,18 @@ __device__ __forceinline__ void wave_argmax(double& v, int& e) {
 // that each pivot costs one barrier.  W is in LDS when it has at most MAXE
 // entries; MAXE = 0 works on the copy of W in global memory (large cores).
 // NR: row chunks of 64 a lane covers (R3 <= 64 NR).
-constexpr int WS_LU_NW = 8;  // wavefronts per elimination workgroup
-template <int MAXE, int NR>
-__global__ __launch_bounds__(64 * WS_LU_NW) void k_ws_lu(const WsBlk* __restrict__ wb, const int* __restrict__ list,
+constexpr int WS_LU_NW = 8;  // wavefronts per elimination workgroup (tiny cores: 2)
+template <int MAXE, int NR, int NW>
+__global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb, const int* __restrict__ list,
                                                const FarBlk* __restrict__ blks, const int* __restrict__ plist,
                                                cd* __restrict__ cross, int* __restrict__ pq,
                                                int* __restrict__ rho_out, cd* __restrict__ coef) {
   __shared__ cd Wl[MAXE > 0 ? MAXE : 1];
   __shared__ short cl[2][3 * WS_MAXLIST];
   __shared__ short sP[3 * WS_MAXLIST], sQ[3 * WS_MAXLIST];
-  __shared__ double sv[2][WS_LU_NW];
-  __shared__ int se[2][WS_LU_NW];
-  constexpr int NT = 64 * WS_LU_NW;
+  __shared__ double sv[2][NW];
+  __shared__ int se[2][NW];
+  constexpr int NT = 64 * NW;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = list[blockIdx.x];
   const WsBlk w = wb[wi];
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(64 * WS_LU_NW) void k_ws_lu(const WsBlk* __restrict
     best = sv[slot][0];
     be = se[slot][0];
 #pragma unroll
-    for (int q = 1; q < WS_LU_NW; ++q)
+    for (int q = 1; q < NW; ++q)
       if (sv[slot][q] > best || (sv[slot][q] == best && se[slot][q] < be)) {
         best = sv[slot][q];
         be = se[slot][q];
@@ -268,12 +268,12 @@ __global__ __launch_bounds__(64 * WS_LU_NW) void k_ws_lu(const WsBlk* __restrict
     be = 0x7fffffff;
     // eight columns per wavefront pass (jb, jb + NW, ..., jb + 7 NW), all
     // loads of a row chunk issued before its stores
-    for (int jb = wv; jb < nac; jb += 8 * WS_LU_NW) {
+    for (int jb = wv; jb < nac; jb += 8 * NW) {
       int jc[8];
       cd pr[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int jj = jb + WS_LU_NW * u;
+        const int jj = jb + NW * u;
         jc[u] = jj < nac ? L[jj] : q;
         pr[u] = jc[u] != q ? W[jc[u] * R3 + p] * ipiv : mk(0.0);
       }
@@ -573,26 +573,30 @@ void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParam
   if (A.tot_ec > 0)
     hipLaunchKernelGGL(k_ws_eval_cols, dim3((A.tot_ec + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, A.ec_off, W.blks,
                        W.plist, A.cross, g, P);
-  // the elimination in four size classes: W of up to 2304, 4480 and 8960
-  // entries in LDS (three, two and one workgroups per CU), larger in global
-  // memory
+  // the elimination in five size classes: W of up to 1024 entries and 64
+  // rows with two wavefronts, of up to 2304, 4480 and 8960 entries with
+  // eight, all in LDS, larger in global memory
   const int nt = 64 * WS_LU_NW;
   const int* lst = A.lu_list;
   if (A.n_lu[0] > 0)
-    hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS>), dim3(A.n_lu[0]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross,
-                       A.pq, A.rho, A.coef);
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS, WS_LU_NW>), dim3(A.n_lu[0]), dim3(nt), 0, s, A.wb, lst,
+                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
   lst += A.n_lu[0];
   if (A.n_lu[1] > 0)
-    hipLaunchKernelGGL((k_ws_lu<WS_LDS_MID, WS_LU_NR_LDS>), dim3(A.n_lu[1]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross,
-                       A.pq, A.rho, A.coef);
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_MID, WS_LU_NR_LDS, WS_LU_NW>), dim3(A.n_lu[1]), dim3(nt), 0, s, A.wb, lst,
+                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
   lst += A.n_lu[1];
   if (A.n_lu[2] > 0)
-    hipLaunchKernelGGL((k_ws_lu<WS_LDS_LARGE, WS_LU_NR_LDS>), dim3(A.n_lu[2]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross,
-                       A.pq, A.rho, A.coef);
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_LARGE, WS_LU_NR_LDS, WS_LU_NW>), dim3(A.n_lu[2]), dim3(nt), 0, s, A.wb, lst,
+                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
   lst += A.n_lu[2];
   if (A.n_lu[3] > 0)
-    hipLaunchKernelGGL((k_ws_lu<0, (3 * WS_MAXLIST + 63) / 64>), dim3(A.n_lu[3]), dim3(nt), 0, s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho,
-                       A.coef);
+    hipLaunchKernelGGL((k_ws_lu<0, (3 * WS_MAXLIST + 63) / 64, WS_LU_NW>), dim3(A.n_lu[3]), dim3(nt), 0, s, A.wb, lst,
+                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+  lst += A.n_lu[3];
+  if (A.n_lu[4] > 0)
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_TINY, 1, 2>), dim3(A.n_lu[4]), dim3(128), 0, s, A.wb, lst, W.blks, W.plist,
+                       A.cross, A.pq, A.rho, A.coef);
   hipLaunchKernelGGL(k_ws_form_u, dim3((A.tot_tu + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, A.coef);
   hipLaunchKernelGGL(k_ws_form_v, dim3((A.tot_tv + 3) / 4), dim3(256), 0, s, A, W.blks, A.coef);
   hipLaunchKernelGGL(k_ws_finish, dim3((A.nwarm + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, W.plist,

@@ -544,11 +544,12 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     c->d_wscoef.reserve_grow(std::max<long long>(coefn, 1));
     // size classes of the core elimination
     std::vector<int> lu_list;
-    int n_lu[4] = {0, 0, 0, 0};
-    for (int cls = 0; cls < 4; ++cls)
+    int n_lu[5] = {0, 0, 0, 0, 0};
+    for (int cls = 0; cls < 5; ++cls)
       for (int i = 0; i < nw; ++i) {
         const long long e = 9LL * wb[i].nr * wb[i].nc;
         const int ci = 3 * wb[i].nr > 64 * WS_LU_NR_LDS ? 3
+                       : (3 * wb[i].nr <= 64 && e <= WS_LDS_TINY) ? 4
                        : e <= WS_LDS_SMALL             ? 0
                        : e <= WS_LDS_MID               ? 1
                        : e <= WS_LDS_LARGE             ? 2
@@ -561,7 +562,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     c->d_wslu.upload(lu_list, st);
     WsArgs A{c->d_wsb.p, nw, c->d_wsoff.p, c->d_wsoff.p + (nw + 1), c->d_wsoff.p + 2 * (nw + 1),
              c->d_wsoff.p + 3 * (nw + 1), (int)er, (int)ec, (int)tu, (int)tv, c->d_cross.p, c->d_wspq.p,
-             c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p, {n_lu[0], n_lu[1], n_lu[2], n_lu[3]}};
+             c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p, {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4]}};
     launch_ws(A, W0, g, c->P, c->op.aca_tol, st);
   }
   if (count_starts) {

@@ -358,6 +358,31 @@ def test_damping_and_extrapolation_reduce_iterations(torch_dev, E):
     assert it3 < it2
 
 
+def test_extrapolation_depth_sweep(torch_dev, E):
+    """Sec. 4.2 (the choice of K): on the level-3 cavity (kappa = 4, N_f = 64,
+    GMRES tol 1e-5) the least-squares extrapolation over K previous
+    solutions is swept over K = 1..8.  Any history beats none and three or
+    four solutions beat one.  Beyond four, more history still removes some
+    iterations here (measured: 100 at K = 4, 89 at K = 8), but each extra
+    solution costs one more operator application per frequency, and the
+    iterations saved stay well below those added applications: K > 4 does
+    not pay, the paper's conclusion in cost terms."""
+    torch, dev = torch_dev
+    d = config_inputs(2, sub=3)
+    n_f = 64
+    d["n_f"] = n_f
+    d["history"] = ramp_history(n_f, d["period"], d["t_rise"])
+    k4 = mft.sigma_from_kappa(4.0, d["period"])
+    it0 = _iterations(E, torch, dev, d, k4, E.GUESS_ZERO)
+    its = {K: _iterations(E, torch, dev, d, k4, E.GUESS_SEM, sem_k=K) for K in (1, 2, 3, 4, 6, 8)}
+    _say(f"total iterations: zero guess {it0}; " + ", ".join(f"K={K}: {v}" for K, v in its.items()))
+    solves = n_f // 2 + 1
+    assert max(its.values()) < it0
+    assert min(its[3], its[4]) < its[1]
+    for K in (6, 8):
+        assert its[4] - its[K] < 0.5 * (K - 4) * solves
+
+
 def test_long_window_stays_accurate(torch_dev, E, mat):
     """Sec. 5.1 (long-time behaviour): a window four times longer (T = 32,
     N_f = 256, 129 solves) on the level-2 cavity stays within the spatial
