@@ -98,6 +98,11 @@ typedef struct {
   int32_t precond;   /* EWBEM_PREC_* (default EWBEM_PREC_LEAF) */
   int32_t guess;     /* EWBEM_GUESS_* (default EWBEM_GUESS_SEM) */
   int32_t sem_k;     /* K previous solutions used by the guess, 1..8 (default 3) */
+  int32_t pipeline;  /* 1: in ewbem_solve_transient, the next frequency's ACA runs on a second
+                        stream (library-owned, default priority, from a second host thread)
+                        while GMRES solves the current one, into a second factor slot (the
+                        far factors' memory doubles); results are unchanged.  0: one
+                        frequency after the other (default 1) */
 } ewbem_solver_opts;
 
 typedef struct {
@@ -107,7 +112,8 @@ typedef struct {
   int32_t matvecs;         /* operator applications (GMRES + guess + residuals) */
   double resid_max;        /* largest final true relative residual */
   double guess_resid_sum;  /* sum of |b - A x0| / |b| of the initial guesses */
-  double t_assemble_ms;    /* wall time in operator/RHS/preconditioner assembly */
+  double t_assemble_ms;    /* wall time in operator/RHS/preconditioner assembly (with the
+                              pipeline it includes the ACA time that overlapped GMRES) */
   double t_guess_ms;       /* wall time in the initial guess */
   double t_gmres_ms;       /* wall time in GMRES */
   double t_post_ms;        /* wall time in the inverse transform */

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <thread>
 #include <atomic>
@@ -147,11 +148,15 @@ struct ewbem_ctx {
   DevBuf<int> d_self_ld;
   DevBuf<cd> d_D;
   DevBuf<FarBlk> d_far;
-  DevBuf<cd> d_ws;
+  // far factors in two slots: the next frequency's ACA fills one while the
+  // current frequency's GMRES reads the other (fslot: the matvec's slot)
+  DevBuf<cd> d_wsf[2];
+  int fslot = 0;
+  hipStream_t astream = nullptr;  // the overlapped ACA's stream (library-owned)
   // one buffer per capacity-retry round of the current frequency; all stay
   // alive until the next frequency is assembled (blocks retried in an
   // earlier round keep pointing into their round's buffer)
-  std::vector<std::unique_ptr<DevBuf<cd>>> d_retry;
+  std::vector<std::unique_ptr<DevBuf<cd>>> d_retry[2];
   DevBuf<cf> d_f32;
   DevBuf<long long> d_uo, d_vo;
   DevBuf<int> d_rank, d_status;
@@ -387,6 +392,7 @@ void ensure_device(ewbem_ctx* c) {
     return;
   }
   EWBEM_HIP_CHECK(hipSetDevice(c->device));
+  if (!c->astream) EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking));
   hipStream_t st = c->stream;
   const HostGeom& g = c->hg;
   c->d_cen.upload(g.cen, st);
@@ -470,8 +476,8 @@ cd s_of_k(ewbem_ctx* c, int k) { return cd{c->sigma, 2.0 * M_PI * k / c->period}
 // frequency (and warm set) start from the cross on those pivots, the others
 // from scratch; then all run the ordinary steps, one host round trip per
 // step (the scan of the active list gives the grid sizes).
-void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, bool warm, bool count_starts) {
-  hipStream_t st = c->stream;
+void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, bool warm, bool count_starts,
+                  hipStream_t st) {
   const int n = (int)ids.size();
   if (n == 0) return;
   std::vector<int> cold;
@@ -607,8 +613,8 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
   launch_aca_finish(c->d_aca_ids.p, n, c->d_acast.p, c->d_rank.p, c->d_status.p, st);
 }
 
-void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
-  hipStream_t st = c->stream;
+// Far factors of every block into factor slot ``slot`` on stream st.
+void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipStream_t st, int slot) {
   const int nf = (int)c->far_h.size();
   if (nf == 0) return;
   // Capacity: 30% above the previous frequency's rank (ranks grow with
@@ -643,17 +649,18 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     kcap[b] = std::max(3, std::min({want, full, ACA_KMAX}));
   }
   // main layout (the previous frequency's retry buffers are no longer used)
-  c->d_retry.clear();
+  c->d_retry[slot].clear();
   long long total = 0, words = 0;
   for (int b = 0; b < nf; ++b) total += (long long)(3 * c->far_h[b].m + 3 * c->far_h[b].n) * kcap[b];
-  c->d_ws.reserve_grow(total);
+  DevBuf<cd>& ws = c->d_wsf[slot];
+  ws.reserve_grow(total);
   long long off = 0;
   for (int b = 0; b < nf; ++b) {
     FarBlk& f = c->far_h[b];
     f.kcap = kcap[b];
-    f.U = c->d_ws.p + off;
+    f.U = ws.p + off;
     off += 3LL * f.m * kcap[b];
-    f.V = c->d_ws.p + off;
+    f.V = ws.p + off;
     off += 3LL * f.n * kcap[b];
     if (words > INT32_MAX - 1024) fail(EWBEM_EINVAL, "too many far blocks");
     f.bitoff = (int)words;
@@ -668,7 +675,7 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
   std::vector<int> all(nf);
   for (int b = 0; b < nf; ++b) all[b] = b;
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-  aca_lockstep(c, g, all, warm, true);
+  aca_lockstep(c, g, all, warm, true, st);
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -689,8 +696,8 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
       f.kcap = std::min({full, ACA_KMAX, 2 * f.kcap + 6});
       tot2 += (long long)(3 * f.m + 3 * f.n) * f.kcap;
     }
-    c->d_retry.emplace_back(new DevBuf<cd>());
-    DevBuf<cd>& buf = *c->d_retry.back();
+    c->d_retry[slot].emplace_back(new DevBuf<cd>());
+    DevBuf<cd>& buf = *c->d_retry[slot].back();
     buf.reserve(tot2);
     long long o2 = 0;
     for (int b : over) {
@@ -702,7 +709,7 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms) {
     }
     c->d_far.upload(c->far_h, st);
     EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-    aca_lockstep(c, g, over, false, false);
+    aca_lockstep(c, g, over, false, false, st);
     EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -731,9 +738,9 @@ void check_far_ranges(ewbem_ctx* c) {
   for (size_t b = 0; b < c->far_h.size(); ++b) {
     const FarBlk& f = c->far_h[b];
     const long long nu = 3LL * f.m * f.kcap * (long long)sizeof(cd), nv = 3LL * f.n * f.kcap * (long long)sizeof(cd);
-    bool ok = in_alloc(f.U, nu, c->d_ws.p, c->d_ws.n * sizeof(cd)) &&
-              in_alloc(f.V, nv, c->d_ws.p, c->d_ws.n * sizeof(cd));
-    for (const auto& r : c->d_retry)
+    const DevBuf<cd>& ws = c->d_wsf[c->fslot];
+    bool ok = in_alloc(f.U, nu, ws.p, ws.n * sizeof(cd)) && in_alloc(f.V, nv, ws.p, ws.n * sizeof(cd));
+    for (const auto& r : c->d_retry[c->fslot])
       ok = ok || (in_alloc(f.U, nu, r->p, r->n * sizeof(cd)) && in_alloc(f.V, nv, r->p, r->n * sizeof(cd)));
     if (!ok) fail(EWBEM_EINVAL, "internal: far-block factor range outside its allocation");
     if (c->rank_h[b] < 0 || c->rank_h[b] > f.kcap) fail(EWBEM_EINVAL, "internal: rank outside capacity");
@@ -862,8 +869,8 @@ void build_matvec(ewbem_ctx* c) {
     const long long ztot = zoff[nf];
     auto store_ok = [&](const void* p, long long bytes) {
       if (c64) return in_alloc(p, bytes, c->d_f32.p, c->d_f32.n * sizeof(cf));
-      bool ok = in_alloc(p, bytes, c->d_ws.p, c->d_ws.n * sizeof(cd));
-      for (const auto& r : c->d_retry) ok = ok || in_alloc(p, bytes, r->p, r->n * sizeof(cd));
+      bool ok = in_alloc(p, bytes, c->d_wsf[c->fslot].p, c->d_wsf[c->fslot].n * sizeof(cd));
+      for (const auto& r : c->d_retry[c->fslot]) ok = ok || in_alloc(p, bytes, r->p, r->n * sizeof(cd));
       return ok;
     };
     const long long es = c64 ? (long long)sizeof(cf) : (long long)sizeof(cd);
@@ -1056,7 +1063,9 @@ void tune_matvec(ewbem_ctx* c) {
   build_matvec(c);
 }
 
-void assemble_k(ewbem_ctx* c, int k) {
+// Operator, right-hand side and preconditioner of frequency k.  aca_done:
+// the far factors of k are already in slot fslot (the overlapped ACA).
+void assemble_k(ewbem_ctx* c, int k, bool aca_done = false) {
   ensure_device(c);
   if (k < 0 || k > c->n_f / 2) fail(EWBEM_EINVAL, "frequency index out of range 0..N_f/2");
   hipStream_t st = c->stream;
@@ -1071,9 +1080,14 @@ void assemble_k(ewbem_ctx* c, int k) {
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
   c->acc.t_near_ms += ev.elapsed();
-  double aca_ms = 0;
-  run_aca(c, g, ev, aca_ms);
-  c->acc.t_aca_ms += aca_ms;
+  if (!aca_done) {
+    double aca_ms = 0;
+    // with the pipeline the slot the matvec reads is left alone
+    const int slot = c->so.pipeline ? 1 - c->fslot : c->fslot;
+    run_aca(c, g, ev, aca_ms, st, slot);
+    c->fslot = slot;
+    c->acc.t_aca_ms += aca_ms;
+  }
   build_matvec(c);
   if (c->op.autotune && !c->mv_tuned && !c->far_h.empty()) tune_matvec(c);
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
@@ -1429,8 +1443,48 @@ int frequency_loop(ewbem_ctx* c) {
     c->acc.t_assemble_ms += ms_since(t0);
   }
   int rc = EWBEM_OK;
-  for (int k = 0; k <= c->n_f / 2; ++k) {
-    const int r = solve_k(c, k, nullptr);
+  const int nk = c->n_f / 2 + 1;
+  // the pipeline: while GMRES solves frequency k on the caller's stream,
+  // the far factors of k + 1 are approximated on the library's second
+  // stream by a second host thread, into the factor slot the matvec of k
+  // does not read; the rest of k + 1's assembly follows the solve
+  const bool pipe = c->so.pipeline && !c->far_h.empty();
+  for (int k = 0; k < nk; ++k) {
+    if (!pipe || k + 1 == nk) {
+      const int r = solve_k(c, k, nullptr);
+      if (r != EWBEM_OK) rc = r;
+      continue;
+    }
+    if (c->assembled_k != k) assemble_k(c, k);
+    const int slot = 1 - c->fslot;
+    c->P = make_params(c->rho, c->mu, c->nu, s_of_k(c, k + 1));
+    const DevGeom g = dev_geom(c);
+    double aca_ms = 0.0, aca_wall = 0.0;
+    std::exception_ptr err;
+    std::thread th([&, g, slot] {
+      try {
+        EWBEM_HIP_CHECK(hipSetDevice(c->device));
+        EventPair ev;
+        const auto t0 = Clock::now();
+        run_aca(c, g, ev, aca_ms, c->astream, slot);
+        aca_wall = ms_since(t0);
+      } catch (...) {
+        err = std::current_exception();
+      }
+    });
+    int r = EWBEM_OK;
+    try {
+      r = solve_k(c, k, nullptr);
+    } catch (...) {
+      th.join();
+      throw;
+    }
+    th.join();
+    if (err) std::rethrow_exception(err);
+    c->fslot = slot;
+    c->acc.t_aca_ms += aca_ms;
+    c->acc.t_assemble_ms += aca_wall;
+    assemble_k(c, k + 1, true);
     if (r != EWBEM_OK) rc = r;
   }
   return rc;
@@ -1683,6 +1737,7 @@ void ewbem_default_solver_opts(ewbem_solver_opts* o) {
   o->precond = EWBEM_PREC_LEAF;
   o->guess = EWBEM_GUESS_SEM;
   o->sem_k = 3;
+  o->pipeline = 1;
 }
 
 int ewbem_create(ewbem_ctx** out, int32_t device, void* hip_stream) {
@@ -1718,6 +1773,11 @@ void ewbem_destroy(ewbem_ctx* ctx) {
   if (ctx->device >= 0) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->astream) {
+      (void)hipStreamSynchronize(ctx->astream);
+      (void)hipStreamDestroy(ctx->astream);
+      ctx->astream = nullptr;
+    }
   }
   delete ctx;
 }
@@ -1900,7 +1960,8 @@ int ewbem_set_solver(ewbem_ctx* ctx, const ewbem_solver_opts* o) {
   return guard(ctx, [&] {
     if (!o) fail(EWBEM_EINVAL, "solver options: null");
     if (!(o->tol > 0) || o->restart < 1 || o->restart > 400 || o->maxit < 1 || o->precond < 0 ||
-        o->precond > 2 || o->guess < 0 || o->guess > 3 || o->sem_k < 1 || o->sem_k > 8)
+        o->precond > 2 || o->guess < 0 || o->guess > 3 || o->sem_k < 1 || o->sem_k > 8 ||
+        (o->pipeline != 0 && o->pipeline != 1))
       fail(EWBEM_EINVAL, "solver options out of range");
     ctx->so = *o;
     ctx->device_ok = false;  // buffers depend on restart and sem_k

@@ -46,7 +46,8 @@ class OpOpts(C.Structure):
 
 class SolverOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("maxit", C.c_int32),
-                ("precond", C.c_int32), ("guess", C.c_int32), ("sem_k", C.c_int32)]
+                ("precond", C.c_int32), ("guess", C.c_int32), ("sem_k", C.c_int32),
+                ("pipeline", C.c_int32)]
 
 
 class Stats(C.Structure):
