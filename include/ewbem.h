@@ -102,7 +102,9 @@ typedef struct {
                         stream (library-owned, default priority, from a second host thread)
                         while GMRES solves the current one, into a second factor slot (the
                         far factors' memory doubles); results are unchanged.  0: one
-                        frequency after the other (default 1) */
+                        frequency after the other (default 0: the overlap gains a few percent
+                        on one problem, and several problems solved concurrently already
+                        overlap their phases) */
 } ewbem_solver_opts;
 
 typedef struct {

@@ -1737,7 +1737,7 @@ void ewbem_default_solver_opts(ewbem_solver_opts* o) {
   o->precond = EWBEM_PREC_LEAF;
   o->guess = EWBEM_GUESS_SEM;
   o->sem_k = 3;
-  o->pipeline = 1;
+  o->pipeline = 0;
 }
 
 int ewbem_create(ewbem_ctx** out, int32_t device, void* hip_stream) {

@@ -29,7 +29,7 @@ def test_defaults():
     # the fields after the doubles sit where the C struct has them
     assert (o.far_store, o.self_order, o.aca_reuse, o.autotune) == (ewbem.STORE_C128, 24, 1, 1)
     s = ewbem.default_solver_opts()
-    assert (s.tol, s.restart, s.guess, s.sem_k, s.pipeline) == (1e-6, 100, ewbem.GUESS_SEM, 3, 1)
+    assert (s.tol, s.restart, s.guess, s.sem_k, s.pipeline) == (1e-6, 100, ewbem.GUESS_SEM, 3, 0)
 
 
 def _ctx(sub=3, leaf=64, eta=1.0, kind=ewbem.OP_HMAT, axes=None):
