@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--aca-reuse", type=int, choices=[0, 1], default=None,
                     help="start each frequency's ACA from the previous pivots (library default if unset)")
     ap.add_argument("--cpu-rows", type=int, default=48)
-    ap.add_argument("--workload", choices=["cavity", "rod-table1", "learned", "batch12", "scene"],
+    ap.add_argument("--workload", choices=["cavity", "rod-table1", "learned", "batch12", "scene", "loads"],
                     default="cavity",
                     help="cavity: the frequency-solve benchmark (default); rod-table1: the "
                          "three damping / extrapolation cases of the paper's Table 1 on its "
@@ -51,9 +51,13 @@ def parse():
                          "pressures, learned guess with complex64 factors against plain FP64; "
                          "batch12: twelve cavities of uneven size (levels 3-5) solved "
                          "concurrently against one at a time; scene: twelve cavities in one "
-                         "mesh scattering a plane S-wave (level 3 unless --sub)")
+                         "mesh scattering a plane S-wave (level 3 unless --sub); loads: the "
+                         "cavity under --n-loads pressure loads through one frequency loop "
+                         "against one transient per load")
     ap.add_argument("--wave", type=int, default=6,
                     help="batch12 workload: problems alive and solved concurrently at once")
+    ap.add_argument("--n-loads", type=int, default=8,
+                    help="loads workload: loads solved through one frequency loop")
     ap.add_argument("--train-cases", type=int, default=8,
                     help="learned workload: loads the guess is trained on")
     ap.add_argument("--rod-div", type=int, default=20,
@@ -301,6 +305,75 @@ def learned_workload(args):
     }), flush=True)
 
 
+def loads_workload(args):
+    """The level-5 cavity under --n-loads spherical-harmonic pressure loads
+    (the held-out loads of the learned workload first), complex128 factors,
+    GMRES 1e-6: one transient per load (every frequency assembled once per
+    load) against all loads through one frequency loop (assembled once for
+    all).  Both on one context after a warm-up transient."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    from synth import config_inputs
+
+    d = config_inputs(4, sub=args.sub)
+    dev = torch.device("cuda:0")
+    N, n_f = 3 * len(d["tri"]), d["n_f"]
+    order = list(d["held_out"]) + list(d["train"])
+    pick = order[:args.n_loads]
+    loads = d["loads"][pick]
+    c = E.Context(0)
+    c.set_mesh(d["xyz"], d["tri"], exterior=True)
+    m = d["material"]
+    c.set_material(m["rho"], m["mu"], m["nu"])
+    c.set_time(d["period"], n_f, d["sigma"], d["window"])
+    c.set_load_pressure(loads[0], d["history"])
+    c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5,
+                   far_store=E.STORE_C64 if args.store == "c64" else E.STORE_C128)
+    c.set_solver(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF)
+    u1 = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
+    c.solve_transient(u1)  # warm-up: tree, tuning, first (cold) ACA
+    torch.cuda.synchronize()
+    seq = dict(t=0.0, solves=0, its=0, asm=0.0, gmres=0.0)
+    for l in range(len(loads)):
+        c.set_load_pressure(loads[l], d["history"])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = c.solve_transient(u1)
+        torch.cuda.synchronize()
+        seq["t"] += time.perf_counter() - t
+        seq["solves"] += st["n_solves"]
+        seq["its"] += st["iters_total"]
+        seq["asm"] += st["t_assemble_ms"]
+        seq["gmres"] += st["t_gmres_ms"]
+        print(f"# one at a time, load {pick[l]}: {st['iters_total']} its", file=sys.stderr, flush=True)
+    u = torch.zeros(len(loads) * n_f * N, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = c.solve_transient_loads(loads, u, pressures=True)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t
+    c.close()
+    v = st["n_solves"] / t_multi
+    pv = seq["solves"] / seq["t"]
+    # the last load's transient, alone and within the batch
+    same = (torch.linalg.norm(u[(len(loads) - 1) * n_f * N:] - u1) / torch.linalg.norm(u1)).item()
+    print(f"# {len(loads)} loads together: {st['iters_total']} its, {t_multi:.2f} s; one at a time "
+          f"{seq['its']} its, {seq['t']:.2f} s; last load's transients differ by {same:.1e}",
+          file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": METRIC, "value": v, "unit": "freq-solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000.0 * t_multi, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.store == "c128" else "f64+c64-factors", "data": "synthetic",
+        "config": {"workload": d["name"] + f" ({len(loads)} pressure loads, one frequency loop)",
+                   "n_dof": N, "n_f": n_f, "n_loads": len(loads), "gmres_tol": 1e-6, "aca_tol": 1e-5},
+        "together": {"seconds": t_multi, "solves": st["n_solves"], "gmres_iters": st["iters_total"],
+                     "assemble_ms": st["t_assemble_ms"], "gmres_ms": st["t_gmres_ms"]},
+        "one_at_a_time": {"value": pv, "seconds": seq["t"], "solves": seq["solves"], "gmres_iters": seq["its"],
+                          "assemble_ms": seq["asm"], "gmres_ms": seq["gmres"]},
+        "speedup": v / pv, "last_load_rel_diff": same,
+    }), flush=True)
+
+
 def batch12_workload(args):
     """Twelve independent cavities (spheres and ellipsoids with semi-axes in
     [0.5, 2], icosphere levels 3-5, seeded pressure amplitudes; N_f = 128,
@@ -497,6 +570,9 @@ def main():
         return
     if args.workload == "scene":
         scene_workload(args)
+        return
+    if args.workload == "loads":
+        loads_workload(args)
         return
     if args.copy_probe:
         copy_probe()

@@ -284,6 +284,22 @@ int ewbem_solve_frequency(ewbem_ctx* ctx, int32_t k, const ewbem_z* x0, ewbem_z*
  * complex, or NULL. */
 int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats* stats);
 
+/* Several loads on one mesh: t(x, t) = t0_l(x) P(t) for l < n_loads with the
+ * history P of the context's current traction or pressure load.  Every
+ * frequency's operator, self terms and preconditioner are assembled once
+ * and serve all loads (each with its own right-hand side, extrapolation
+ * history and GMRES), so each load's result is that of
+ * ewbem_solve_transient with that load on the same operators.  loads: host,
+ * n_loads x nt x 3 tractions (pressure 0) or n_loads x nt pressures
+ * (pressure 1), caller order.  u: device, n_loads x n_f x N doubles (load-
+ * major, each as in ewbem_solve_transient); spec: device, n_loads x
+ * (N_f/2+1) x N complex, or NULL.  The learned guess is not used here (the
+ * extrapolation alone).  The context's own load is unchanged.  ESTATE
+ * without mesh, time grid and a traction or pressure load; ENOCONV as for
+ * ewbem_solve_transient. */
+int ewbem_solve_transient_loads(ewbem_ctx* ctx, int32_t n_loads, const double* loads, int32_t pressure,
+                                double* u, ewbem_z* spec, ewbem_stats* stats);
+
 /* Several problems at once (one context each, all distinct): up to
  * per_launch of them run concurrently from host threads, each with its
  * whole frequency loop on its own context's stream (contexts created on the
@@ -321,7 +337,8 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
  * as one more column to the least-squares extrapolation, so the guess is
  * never worse in residual than the extrapolation alone over the same
  * history; k < 3 uses the extrapolation alone.  The context's own load is
- * restored afterwards.  loads: host, n_cases x nt x 3 tractions
+ * unchanged (the training loads run through the multi-load loop of
+ * ewbem_solve_transient_loads).  loads: host, n_cases x nt x 3 tractions
  * (load_kind 0) or n_cases x nt pressures (1), caller order.  stats sum the
  * training solves and report pod_energy and the fit's losses.  ESTATE
  * without mesh, time grid and a traction or pressure load; EINVAL if

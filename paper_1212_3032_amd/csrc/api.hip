@@ -1009,6 +1009,13 @@ void rhs_precompute(ewbem_ctx* c, const DevGeom& g, int k0, int nk) {
 
 double dev_norm(ewbem_ctx* c, const cd* v);
 
+// b_k of the current load from its off-diagonal sums (d_rhs_part) and the
+// self elements' U of the assembled frequency.
+void rhs_finish_k(ewbem_ctx* c, int k) {
+  launch_rhs_finish(c->d_rhs_part.p, c->boff_nk, k - c->boff_k0, c->nt, c->d_selfU.p, c->d_t0.p,
+                    c->load_incident ? c->d_tau.p : nullptr, s_of_k(c, k), c->d_phat.p + k, c->d_b.p, c->stream);
+}
+
 // Matvec task shapes by measurement: every pair of candidate phase-1 column
 // counts and phase-2 task sizes is built and timed (one warm apply, then
 // three timed) on the operator just assembled; the fastest is kept for the
@@ -1092,8 +1099,7 @@ void assemble_k(ewbem_ctx* c, int k, bool aca_done = false) {
   if (c->op.autotune && !c->mv_tuned && !c->far_h.empty()) tune_matvec(c);
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
   if (k < c->boff_k0 || k >= c->boff_k0 + c->boff_nk) rhs_precompute(c, g, k, 1);
-  launch_rhs_finish(c->d_rhs_part.p, c->boff_nk, k - c->boff_k0, c->nt, c->d_selfU.p, c->d_t0.p,
-                    c->load_incident ? c->d_tau.p : nullptr, s_of_k(c, k), c->d_phat.p + k, c->d_b.p, st);
+  rhs_finish_k(c, k);
   EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
   precond_setup(c);
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -1488,6 +1494,120 @@ int frequency_loop(ewbem_ctx* c) {
     if (r != EWBEM_OK) rc = r;
   }
   return rc;
+}
+
+// ---- several loads (same history) through one frequency loop
+
+// What differs between the loads of a multi-load run: the traction, its
+// off-diagonal sums for every frequency, the extrapolation history and where
+// the spectrum goes (tree order, N_f/2 + 1 rows of N).
+struct LoadRun {
+  DevBuf<double> t0;
+  DevBuf<cd> rhs_part;
+  DevBuf<cd> hist_sol;
+  std::vector<int> hist_slot, hist_kidx;
+  int hist_n = 0;
+  cd* spec = nullptr;
+};
+
+template <typename T>
+void swap_buf(DevBuf<T>& a, DevBuf<T>& b) {
+  std::swap(a.p, b.p);
+  std::swap(a.n, b.n);
+}
+
+// Exchange a load's state with the context's (twice restores it).
+void swap_load(ewbem_ctx* c, LoadRun& L) {
+  swap_buf(c->d_t0, L.t0);
+  swap_buf(c->d_rhs_part, L.rhs_part);
+  swap_buf(c->d_hist_sol, L.hist_sol);
+  std::swap(c->hist_slot, L.hist_slot);
+  std::swap(c->hist_kidx, L.hist_kidx);
+  std::swap(c->hist_n, L.hist_n);
+}
+
+// Every frequency once for all loads: the operator, preconditioner and self
+// terms are assembled once per frequency and each load's right-hand side,
+// guess and GMRES follow.  A load's solutions match those of
+// frequency_loop for that load alone on the same operators.
+int multi_load_loop(ewbem_ctx* c, std::vector<LoadRun>& loads) {
+  const long long N = 3LL * c->nt;
+  const int nk = c->n_f / 2 + 1;
+  hipStream_t st = c->stream;
+  const DevGeom g = dev_geom(c);
+  const int ncap = std::max(1, c->so.sem_k);
+  {
+    EventPair ev;
+    const auto t0 = Clock::now();
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+    for (LoadRun& L : loads) {
+      L.hist_sol.reserve((size_t)ncap * N);
+      swap_load(c, L);
+      rhs_precompute(c, g, 0, nk);
+      swap_load(c, L);
+    }
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    c->acc.t_rhs_ms += ev.elapsed();
+    c->acc.t_assemble_ms += ms_since(t0);
+  }
+  const int saved_guess = c->so.guess;
+  if (c->so.guess == EWBEM_GUESS_LEARNED) c->so.guess = EWBEM_GUESS_SEM;  // no per-load coordinate rings
+  int rc = EWBEM_OK;
+  try {
+    for (int k = 0; k < nk; ++k)
+      for (size_t l = 0; l < loads.size(); ++l) {
+        LoadRun& L = loads[l];
+        swap_load(c, L);
+        try {
+          if (c->assembled_k != k)
+            assemble_k(c, k);  // b of this load too
+          else
+            rhs_finish_k(c, k);
+          const int r = solve_k(c, k, nullptr);
+          if (r != EWBEM_OK) rc = r;
+          EWBEM_HIP_CHECK(hipMemcpyAsync(L.spec + (size_t)k * N, c->d_x.p, N * sizeof(cd),
+                                         hipMemcpyDeviceToDevice, st));
+        } catch (...) {
+          swap_load(c, L);
+          throw;
+        }
+        swap_load(c, L);
+      }
+  } catch (...) {
+    c->so.guess = saved_guess;
+    c->assembled_k = -1;
+    c->boff_nk = 0;
+    throw;
+  }
+  c->so.guess = saved_guess;
+  // the right-hand side and off-diagonal sums now in the context are the
+  // last load's: the context's own load is rebuilt on its next solve
+  c->assembled_k = -1;
+  c->boff_nk = 0;
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  return rc;
+}
+
+// One LoadRun per case: tree-order tractions from caller-order values
+// (nt x 3 tractions, or nt pressures when pressure), spectra at spec_base.
+std::vector<LoadRun> make_load_runs(ewbem_ctx* c, int n, const double* loads, bool pressure, cd* spec_base) {
+  const long long N = 3LL * c->nt;
+  const int nk = c->n_f / 2 + 1;
+  const size_t per = pressure ? (size_t)c->nt : 3 * (size_t)c->nt;
+  const std::vector<double> saved = c->load_caller;
+  const bool saved_p = c->load_is_pressure;
+  std::vector<LoadRun> runs(n);
+  for (int i = 0; i < n; ++i) {
+    c->load_caller.assign(loads + per * i, loads + per * (i + 1));
+    c->load_is_pressure = pressure;
+    runs[i].t0.upload(tree_load(c), c->stream);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));  // the host vector is a temporary
+    runs[i].spec = spec_base + (size_t)i * nk * N;
+  }
+  c->load_caller = saved;
+  c->load_is_pressure = saved_p;
+  return runs;
 }
 
 int guard(ewbem_ctx* ctx, const std::function<int()>& f) {
@@ -2217,6 +2337,44 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
   return out;
 }
 
+int ewbem_solve_transient_loads(ewbem_ctx* ctx, int32_t n_loads, const double* loads, int32_t pressure, double* u,
+                                ewbem_z* spec, ewbem_stats* stats) {
+  return guard(ctx, [&] {
+    if (n_loads < 1 || !loads || !u || (pressure != 0 && pressure != 1))
+      fail(EWBEM_EINVAL, "solve_transient_loads: need n_loads >= 1, loads, u and pressure 0 or 1");
+    if (!ctx->have_mesh || !ctx->have_time || !ctx->have_load)
+      fail(EWBEM_ESTATE, "solve_transient_loads: set the mesh, time grid and a load (its history is used) first");
+    if (ctx->load_incident || !ctx->bc_caller.empty())
+      fail(EWBEM_ESTATE, "solve_transient_loads: needs a traction or pressure load (its history is used)");
+    const size_t per = pressure ? (size_t)ctx->nt : 3 * (size_t)ctx->nt;
+    if (!finite_all(loads, per * n_loads)) fail(EWBEM_EINVAL, "solve_transient_loads: non-finite load values");
+    begin_stats(ctx);
+    ensure_device(ctx);
+    const long long N = 3LL * ctx->nt;
+    const int nk = ctx->n_f / 2 + 1;
+    DevBuf<cd> sp;
+    sp.reserve((size_t)n_loads * nk * N);
+    std::vector<LoadRun> runs = make_load_runs(ctx, n_loads, loads, pressure == 1, sp.p);
+    const int rc = multi_load_loop(ctx, runs);
+    const auto tp = Clock::now();
+    for (int l = 0; l < n_loads; ++l) {
+      const cd* sl = sp.p + (size_t)l * nk * N;
+      launch_mft_inverse(sl, N, ctx->n_f, ctx->period, ctx->sigma, ctx->window, ctx->d_perm.p,
+                         u + (size_t)l * ctx->n_f * N, ctx->stream);
+      if (spec)
+        for (int k = 0; k < nk; ++k)
+          launch_permute(sl + (size_t)k * N, ctx->d_perm.p, ctx->nt, 0, (cd*)spec + ((size_t)l * nk + k) * N,
+                         ctx->stream);
+    }
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    ctx->acc.t_post_ms += ms_since(tp);
+    end_stats(ctx, stats);
+    if (rc != EWBEM_OK) ctx->err = "GMRES did not reach the tolerance within maxit at some frequency";
+    return rc;
+  });
+}
+
 void ewbem_default_train_opts(ewbem_train_opts* o) {
   if (!o) return;
   *o = ewbem_train_opts{};
@@ -2257,8 +2415,6 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     begin_stats(ctx);
     // data: every case's solutions at all frequencies, with the configured
     // solver (extrapolation instead of the model being replaced)
-    const std::vector<double> saved_load = ctx->load_caller;
-    const bool saved_pressure = ctx->load_is_pressure;
     const int saved_guess = ctx->so.guess;
     ctx->lm = LearnedModel{};
     ctx->lm_dev = false;
@@ -2268,25 +2424,13 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     try {
       ensure_device(ctx);
       S.reserve((size_t)N * M);
-      for (int cs = 0; cs < n_cases; ++cs) {
-        ctx->load_caller.assign(loads + per * cs, loads + per * (cs + 1));
-        ctx->load_is_pressure = o->load_kind == 1;
-        ctx->device_ok = false;
-        ensure_device(ctx);
-        const int r1 = frequency_loop(ctx);
-        if (r1 != EWBEM_OK) rc = r1;
-        EWBEM_HIP_CHECK(hipMemcpyAsync(S.p + (size_t)cs * nk * N, ctx->d_spec.p, (size_t)nk * N * sizeof(cd),
-                                       hipMemcpyDeviceToDevice, ctx->stream));
-      }
+      // every frequency assembled once for all cases (snapshot m = case nk + k)
+      std::vector<LoadRun> runs = make_load_runs(ctx, n_cases, loads, o->load_kind == 1, S.p);
+      rc = multi_load_loop(ctx, runs);
     } catch (...) {
-      ctx->load_caller = saved_load;
-      ctx->load_is_pressure = saved_pressure;
       ctx->so.guess = saved_guess;
-      ctx->device_ok = false;
       throw;
     }
-    ctx->load_caller = saved_load;
-    ctx->load_is_pressure = saved_pressure;
     ctx->so.guess = saved_guess;
     hipStream_t st = ctx->stream;
     // reduced basis and every snapshot's coordinates
@@ -2372,7 +2516,6 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     m.energy = energy;
     ctx->lm = std::move(m);
     ctx->lm_dev = false;
-    ctx->device_ok = false;  // the caller's own load goes back to the device
     end_stats(ctx, stats);
     if (stats) {
       stats->pod_energy = ctx->lm.energy;

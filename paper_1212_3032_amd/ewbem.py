@@ -28,7 +28,8 @@ EXPORTED = [
     "ewbem_set_operator",
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
-    "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_batch_solve_transient",
+    "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_solve_transient_loads",
+    "ewbem_batch_solve_transient",
     "ewbem_mft_inverse", "ewbem_default_train_opts", "ewbem_guess_train", "ewbem_guess_save",
     "ewbem_guess_load", "ewbem_guess_basis", "ewbem_mlp_eval", "ewbem_mlp_train",
 ]
@@ -124,6 +125,7 @@ def lib():
         "ewbem_get_rhs": (C.c_int, [P, P]),
         "ewbem_solve_frequency": (C.c_int, [P, I32, P, P, C.POINTER(Stats)]),
         "ewbem_solve_transient": (C.c_int, [P, P, P, C.POINTER(Stats)]),
+        "ewbem_solve_transient_loads": (C.c_int, [P, I32, P, I32, P, P, C.POINTER(Stats)]),
         "ewbem_batch_solve_transient": (C.c_int, [P, I32, P, C.POINTER(Stats), I32]),
         "ewbem_mft_inverse": (C.c_int, [P, P, P]),
         "ewbem_default_train_opts": (None, [C.POINTER(TrainOpts)]),
@@ -351,6 +353,24 @@ class Context:
         ps = _dev_ptr(spec, "torch.complex128", (self.n_f // 2 + 1) * N) if spec is not None else None
         rc = self._L.ewbem_solve_transient(self.h, _dev_ptr(u, "torch.float64", self.n_f * N), ps,
                                            C.byref(st))
+        if not (allow_noconv and rc == ENOCONV):
+            self._check(rc)
+        return st.as_dict()
+
+    def solve_transient_loads(self, loads, u, spec=None, pressures=False, allow_noconv=False):
+        """Several loads with the current load's history on shared per-
+        frequency operators: loads n_loads x nt x 3 tractions (or n_loads x
+        nt pressures), u a device float64 tensor of n_loads x n_f x N."""
+        N = 3 * self.nt
+        per = self.nt if pressures else 3 * self.nt
+        a, pa = _host(loads, np.float64)
+        if a.size % per != 0 or a.size == 0:
+            raise ValueError(f"loads must hold n_loads x {per} values")
+        n = a.size // per
+        ps = _dev_ptr(spec, "torch.complex128", n * (self.n_f // 2 + 1) * N) if spec is not None else None
+        st = Stats()
+        rc = self._L.ewbem_solve_transient_loads(self.h, n, pa, 1 if pressures else 0,
+                                                 _dev_ptr(u, "torch.float64", n * self.n_f * N), ps, C.byref(st))
         if not (allow_noconv and rc == ENOCONV):
             self._check(rc)
         return st.as_dict()

@@ -119,6 +119,14 @@ def test_gpu_calls_refused_on_host_context():
     with pytest.raises(ewbem.EwbemError) as e:
         c.assemble(0)
     assert e.value.status == ewbem.ESTATE
+    # the multi-load entry checks its arguments before it needs a device
+    import ctypes
+    L = ewbem.lib()
+    p = np.ascontiguousarray(d["pressure"], dtype=np.float64)
+    pp = p.ctypes.data_as(ctypes.c_void_p)
+    assert L.ewbem_solve_transient_loads(c.h, 0, pp, 1, None, None, None) == ewbem.EINVAL
+    assert L.ewbem_solve_transient_loads(c.h, 1, pp, 1, None, None, None) == ewbem.EINVAL
+    assert L.ewbem_solve_transient_loads(c.h, 1, pp, 2, None, None, None) == ewbem.EINVAL
 
 
 def _model_blob(n_dof, r, dims, rng, magic=b"EWBGUESS", version=1):
