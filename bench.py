@@ -333,7 +333,7 @@ def loads_workload(args):
     u1 = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
     c.solve_transient(u1)  # warm-up: tree, tuning, first (cold) ACA
     torch.cuda.synchronize()
-    seq = dict(t=0.0, solves=0, its=0, asm=0.0, gmres=0.0)
+    seq = dict(t=0.0, solves=0, its=0, asm=0.0, gmres=0.0, mv_ms=0.0, mv_b=0.0, mv_n=0)
     for l in range(len(loads)):
         c.set_load_pressure(loads[l], d["history"])
         torch.cuda.synchronize()
@@ -345,6 +345,9 @@ def loads_workload(args):
         seq["its"] += st["iters_total"]
         seq["asm"] += st["t_assemble_ms"]
         seq["gmres"] += st["t_gmres_ms"]
+        seq["mv_ms"] += st["t_matvec_ms"]
+        seq["mv_b"] += st["matvec_bytes_total"]
+        seq["mv_n"] += st["matvecs_timed"]
         print(f"# one at a time, load {pick[l]}: {st['iters_total']} its", file=sys.stderr, flush=True)
     u = torch.zeros(len(loads) * n_f * N, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
@@ -367,9 +370,12 @@ def loads_workload(args):
         "config": {"workload": d["name"] + f" ({len(loads)} pressure loads, one frequency loop)",
                    "n_dof": N, "n_f": n_f, "n_loads": len(loads), "gmres_tol": 1e-6, "aca_tol": 1e-5},
         "together": {"seconds": t_multi, "solves": st["n_solves"], "gmres_iters": st["iters_total"],
-                     "assemble_ms": st["t_assemble_ms"], "gmres_ms": st["t_gmres_ms"]},
+                     "assemble_ms": st["t_assemble_ms"], "gmres_ms": st["t_gmres_ms"],
+                     "matvec_launches": st["matvecs_timed"], "matvec_ms": st["t_matvec_ms"],
+                     "matvec_GBps": st["matvec_bytes_total"] / st["t_matvec_ms"] / 1e6},
         "one_at_a_time": {"value": pv, "seconds": seq["t"], "solves": seq["solves"], "gmres_iters": seq["its"],
-                          "assemble_ms": seq["asm"], "gmres_ms": seq["gmres"]},
+                          "assemble_ms": seq["asm"], "gmres_ms": seq["gmres"], "matvec_launches": seq["mv_n"],
+                          "matvec_ms": seq["mv_ms"], "matvec_GBps": seq["mv_b"] / seq["mv_ms"] / 1e6},
         "speedup": v / pv, "last_load_rel_diff": same,
     }), flush=True)
 

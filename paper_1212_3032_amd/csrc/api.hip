@@ -217,6 +217,7 @@ struct ewbem_ctx {
   SelfRule S{};
   int store_c64_active = 0;
   double matvec_bytes = 0, stored_bytes = 0;
+  double matvec_rhs_bytes = 0;  // the part of matvec_bytes each right-hand side adds
   int64_t rank_sum = 0, rank_max = 0;
 
   // per-call accumulators
@@ -801,7 +802,7 @@ void build_matvec(ewbem_ctx* c) {
     return (int)(std::lower_bound(leaf_begin.begin(), leaf_begin.end(), begin) - leaf_begin.begin());
   };
   std::vector<std::vector<Seg>> segs(nl);
-  double bytes = 0;
+  double bytes = 0, rhs_bytes = 0;
   const double be_far = c64 ? 8.0 : 16.0;
   for (const NearBlk& nb : c->near_h) {
     const int li = leaf_of(nb.r0);
@@ -819,6 +820,7 @@ void build_matvec(ewbem_ctx* c) {
     const int k = c->rank_h[b];
     if (k == 0) continue;
     bytes += 3.0 * k * (f.m + f.n) * be_far + 2.0 * k * 16.0;
+    rhs_bytes += 2.0 * k * 16.0;
     for (int li = leaf_of(f.r0); li < nl && leaf_begin[li] < f.r0 + f.m; ++li) {
       const Cluster& L = c->part.clusters[leaves[li]];
       Seg s{};
@@ -833,7 +835,9 @@ void build_matvec(ewbem_ctx* c) {
   }
   const long long N = 3LL * c->nt;
   bytes += 2.0 * N * 16.0;  // read x, write y
+  rhs_bytes += 2.0 * N * 16.0;
   c->matvec_bytes = bytes;
+  c->matvec_rhs_bytes = rhs_bytes;
   c->stored_bytes = 0;
   for (const NearBlk& nb : c->near_h) c->stored_bytes += 9.0 * nb.m * nb.n * 16.0;
   for (int b = 0; b < nf; ++b)
@@ -1232,6 +1236,189 @@ double gmres(ewbem_ctx* c, cd* x, cd* r, int& iters_out, bool& converged) {
   return relres;
 }
 
+// The same GMRES for up to four systems A x_l = b_l on one operator, in
+// lock-step: each step's preconditioned vectors of the systems still
+// iterating go through one multi-right-hand-side matvec (the operator read
+// once for all), and one host synchronisation serves all their Arnoldi
+// coefficients.  Per system the arithmetic is that of gmres() in the same
+// order, so each result equals a lone solve's.  Vm: nb x (m+1) x N Krylov
+// bases; Z, W: 4 x N staging; small: nb x (2 (m+2) + 2) coefficients.
+struct GmresLane {
+  cd* b = nullptr;
+  cd* x = nullptr;
+  cd* r = nullptr;
+  cd* V = nullptr;
+  cd* hd = nullptr;  // h (m+2), second pass (m+2), |w|^2
+  double bnorm = 0, rnorm = 0, relres = 0;
+  int j = 0, its = 0;
+  bool done = false, arnoldi = false;
+  std::vector<std::complex<double>> H, cs, sn, g;
+};
+
+void gmres_multi(ewbem_ctx* c, std::vector<GmresLane>& L, cd* Z, cd* W) {
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  const int m = c->so.restart;
+  const double tol = c->so.tol;
+  const int nb = (int)L.size();
+  if (nb < 1 || nb > HMV_MAXRHS) fail(EWBEM_EINVAL, "internal: 1 to 4 systems per lock-step GMRES");
+  const int hs = 2 * (m + 2) + 2;
+  std::vector<cd> hb((size_t)nb * hs);
+  EventPair ev;
+  // |b|, |r0| of every system, one synchronisation
+  auto norms = [&](bool of_b, const std::vector<int>& who) {
+    for (int l : who) launch_dots(of_b ? L[l].b : L[l].r, N, 1, of_b ? L[l].b : L[l].r, N, c->d_hpart.p, L[l].hd, st);
+    for (int l : who)
+      EWBEM_HIP_CHECK(hipMemcpyAsync(&hb[(size_t)l * hs], L[l].hd, sizeof(cd), hipMemcpyDeviceToHost, st));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    for (int l : who) (of_b ? L[l].bnorm : L[l].rnorm) = std::sqrt(std::max(0.0, hb[(size_t)l * hs].x));
+  };
+  std::vector<int> all(nb);
+  for (int l = 0; l < nb; ++l) {
+    all[l] = l;
+    L[l].H.assign((size_t)(m + 1) * m, 0.0);
+    L[l].cs.assign(m, 0.0);
+    L[l].sn.assign(m, 0.0);
+    L[l].g.assign(m + 1, 0.0);
+    L[l].its = 0;
+    L[l].done = L[l].arnoldi = false;
+  }
+  norms(true, all);
+  norms(false, all);
+  for (GmresLane& G : L) {
+    if (G.bnorm == 0.0) {
+      EWBEM_HIP_CHECK(hipMemsetAsync(G.x, 0, N * sizeof(cd), st));
+      G.relres = 0.0;
+      G.done = true;
+      continue;
+    }
+    G.relres = G.rnorm / G.bnorm;
+    if (!(G.relres > tol)) G.done = true;
+  }
+  std::vector<int> act, ends;
+  for (;;) {
+    // systems starting a cycle
+    for (GmresLane& G : L) {
+      if (G.done || G.arnoldi) continue;
+      if (G.its >= c->so.maxit) {
+        G.done = true;
+        continue;
+      }
+      launch_axpby(cd{1.0 / G.rnorm, 0.0}, G.r, cd{0.0, 0.0}, G.V, N, st);
+      std::fill(G.g.begin(), G.g.end(), 0.0);
+      G.g[0] = G.rnorm;
+      G.j = 0;
+      G.arnoldi = true;
+    }
+    act.clear();
+    for (int l = 0; l < nb; ++l)
+      if (L[l].arnoldi) act.push_back(l);
+    if (act.empty()) break;
+    // one Arnoldi step of each: w = A M^{-1} v_j, Gram-Schmidt twice, |w|
+    const int na = (int)act.size();
+    for (int i = 0; i < na; ++i) precond_apply(c, L[act[i]].V + (size_t)L[act[i]].j * N, Z + (size_t)i * N);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+    apply_tree_multi(c, Z, W, na);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+    for (int i = 0; i < na; ++i) {
+      GmresLane& G = L[act[i]];
+      cd* w = W + (size_t)i * N;
+      cd* hd2 = G.hd + (m + 2);
+      cd* nd = G.hd + 2 * (m + 2);
+      launch_dots(G.V, N, G.j + 1, w, N, c->d_hpart.p, G.hd, st);
+      launch_gemv_sub(G.V, N, G.j + 1, G.hd, w, N, st);
+      launch_dots(G.V, N, G.j + 1, w, N, c->d_hpart.p, hd2, st);
+      launch_gemv_sub(G.V, N, G.j + 1, hd2, w, N, st);
+      launch_dots(w, N, 1, w, N, c->d_hpart.p, nd, st);
+      EWBEM_HIP_CHECK(hipMemcpyAsync(&hb[(size_t)act[i] * hs], G.hd, (2 * (m + 2) + 1) * sizeof(cd),
+                                     hipMemcpyDeviceToHost, st));
+    }
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    c->acc.t_matvec_ms += ev.elapsed();
+    c->acc.matvec_bytes_total += c->matvec_bytes + (na - 1) * c->matvec_rhs_bytes;
+    c->acc.matvecs_timed += 1;
+    ends.clear();
+    for (int i = 0; i < na; ++i) {
+      GmresLane& G = L[act[i]];
+      const cd* h = &hb[(size_t)act[i] * hs];
+      const int j = G.j;
+      auto Hc = [&](int row) -> std::complex<double>& { return G.H[(size_t)j * (m + 1) + row]; };
+      ++G.its;
+      const double hn = std::sqrt(std::max(0.0, h[2 * (m + 2)].x));
+      for (int q = 0; q <= j; ++q) Hc(q) = std::complex<double>(h[q].x + h[m + 2 + q].x, h[q].y + h[m + 2 + q].y);
+      Hc(j + 1) = hn;
+      for (int q = 0; q < j; ++q) {
+        std::complex<double>& a = Hc(q);
+        std::complex<double>& b = Hc(q + 1);
+        const std::complex<double> t = std::conj(G.cs[q]) * a + std::conj(G.sn[q]) * b;
+        b = -G.sn[q] * a + G.cs[q] * b;
+        a = t;
+      }
+      const std::complex<double> a = Hc(j);
+      const double den = std::sqrt(std::norm(a) + hn * hn);
+      if (den == 0.0) {
+        G.cs[j] = 1.0;
+        G.sn[j] = 0.0;
+      } else {
+        G.cs[j] = a / den;
+        G.sn[j] = hn / den;
+      }
+      Hc(j) = den;
+      Hc(j + 1) = 0.0;
+      G.g[j + 1] = -G.sn[j] * G.g[j];
+      G.g[j] = std::conj(G.cs[j]) * G.g[j];
+      const double est = std::abs(G.g[j + 1]) / G.bnorm;
+      // the normalised vector goes into the basis (w itself when hn = 0)
+      if (hn > 0.0 && j + 1 <= m)
+        launch_axpby(cd{1.0 / hn, 0.0}, W + (size_t)i * N, cd{0.0, 0.0}, G.V + (size_t)(j + 1) * N, N, st);
+      G.j = j + 1;
+      if (est <= tol || hn == 0.0 || G.j >= m || G.its >= c->so.maxit) ends.push_back(act[i]);
+    }
+    if (ends.empty()) continue;
+    // cycle ends: x += M^{-1} V y, then the true residuals in one matvec
+    const int ne = (int)ends.size();
+    std::vector<std::vector<cd>> yd(ne);
+    for (int e = 0; e < ne; ++e) {
+      GmresLane& G = L[ends[e]];
+      const int j = G.j;
+      std::vector<std::complex<double>> y(j);
+      for (int i = j - 1; i >= 0; --i) {
+        std::complex<double> sacc = G.g[i];
+        for (int q = i + 1; q < j; ++q) sacc -= G.H[(size_t)q * (m + 1) + i] * y[q];
+        y[i] = sacc / G.H[(size_t)i * (m + 1) + i];
+      }
+      yd[e].resize(j);
+      for (int i = 0; i < j; ++i) yd[e][i] = cd{y[i].real(), y[i].imag()};
+      cd* u = W + (size_t)e * N;
+      cd* z = Z + (size_t)e * N;
+      EWBEM_HIP_CHECK(hipMemcpyAsync(G.hd, yd[e].data(), j * sizeof(cd), hipMemcpyHostToDevice, st));
+      launch_gemv_acc(G.V, N, j, G.hd, cd{0.0, 0.0}, u, N, st);
+      precond_apply(c, u, z);
+      launch_axpby(cd{1.0, 0.0}, z, cd{1.0, 0.0}, G.x, N, st);
+      EWBEM_HIP_CHECK(hipMemcpyAsync(z, G.x, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+    }
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+    apply_tree_multi(c, Z, W, ne);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+    for (int e = 0; e < ne; ++e) {
+      GmresLane& G = L[ends[e]];
+      EWBEM_HIP_CHECK(hipMemcpyAsync(G.r, W + (size_t)e * N, N * sizeof(cd), hipMemcpyDeviceToDevice, st));
+      launch_axpby(cd{1.0, 0.0}, G.b, cd{-1.0, 0.0}, G.r, N, st);
+    }
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    c->acc.t_matvec_ms += ev.elapsed();
+    c->acc.matvec_bytes_total += c->matvec_bytes + (ne - 1) * c->matvec_rhs_bytes;
+    c->acc.matvecs_timed += 1;
+    norms(false, ends);
+    for (int l : ends) {
+      GmresLane& G = L[l];
+      G.relres = G.rnorm / G.bnorm;
+      G.arnoldi = false;
+      if (!(G.relres > tol) || G.j == 0) G.done = true;
+    }
+  }
+}
+
 // Sec. 4.2: x0 = X R^{-1} Q^H b with Y = A X = Q R (X: the last K solutions,
 // newest first); columns with |R_jj| < 1e-12 |R_00| are dropped.  Also
 // returns r0 = b - Y s without another matvec.
@@ -1375,9 +1562,9 @@ const cd* learned_guess(ewbem_ctx* c, int k) {
   return c->d_lx.p;
 }
 
-// Solve frequency k into d_x (tree order); x0 (caller order, device) optional.
-int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
-  if (c->assembled_k != k) assemble_k(c, k);
+// The initial guess of frequency k into d_x and its residual into d_r (b in
+// d_b, the operator assembled); x0 (caller order, device) optional.
+void guess_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
   hipStream_t st = c->stream;
   const long long N = 3LL * c->nt;
   const auto tg = Clock::now();
@@ -1414,11 +1601,13 @@ int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
   const double bn = dev_norm(c, c->d_b.p);
   c->acc.guess_resid_sum += bn > 0 ? dev_norm(c, c->d_r.p) / bn : 0.0;
   c->acc.t_guess_ms += ms_since(tg);
-  const auto ts = Clock::now();
-  int its = 0;
-  bool conv = true;
-  const double rel = gmres(c, c->d_x.p, c->d_r.p, its, conv);
-  c->acc.t_gmres_ms += ms_since(ts);
+}
+
+// After GMRES on frequency k (solution in d_x): statistics, extrapolation
+// history and the spectrum.
+void finish_k(ewbem_ctx* c, int k, int its, double rel) {
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
   c->acc.n_solves += 1;
   c->acc.iters_total += its;
   c->acc.iters_max = std::max(c->acc.iters_max, its);
@@ -1427,6 +1616,18 @@ int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
   if (c->so.guess == EWBEM_GUESS_LEARNED && c->lm.ok) push_coords(c, c->d_x.p, k);
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_spec.p + (size_t)k * N, c->d_x.p, N * sizeof(cd),
                                  hipMemcpyDeviceToDevice, st));
+}
+
+// Solve frequency k into d_x (tree order); x0 (caller order, device) optional.
+int solve_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
+  if (c->assembled_k != k) assemble_k(c, k);
+  guess_k(c, k, x0);
+  const auto ts = Clock::now();
+  int its = 0;
+  bool conv = true;
+  const double rel = gmres(c, c->d_x.p, c->d_r.p, its, conv);
+  c->acc.t_gmres_ms += ms_since(ts);
+  finish_k(c, k, its, rel);
   return conv ? EWBEM_OK : EWBEM_ENOCONV;
 }
 
@@ -1499,12 +1700,14 @@ int frequency_loop(ewbem_ctx* c) {
 // ---- several loads (same history) through one frequency loop
 
 // What differs between the loads of a multi-load run: the traction, its
-// off-diagonal sums for every frequency, the extrapolation history and where
-// the spectrum goes (tree order, N_f/2 + 1 rows of N).
+// off-diagonal sums for every frequency, the extrapolation history, the
+// current right-hand side, iterate and residual, and where the spectrum goes
+// (tree order, N_f/2 + 1 rows of N).
 struct LoadRun {
   DevBuf<double> t0;
   DevBuf<cd> rhs_part;
   DevBuf<cd> hist_sol;
+  DevBuf<cd> b, x, r;
   std::vector<int> hist_slot, hist_kidx;
   int hist_n = 0;
   cd* spec = nullptr;
@@ -1521,30 +1724,56 @@ void swap_load(ewbem_ctx* c, LoadRun& L) {
   swap_buf(c->d_t0, L.t0);
   swap_buf(c->d_rhs_part, L.rhs_part);
   swap_buf(c->d_hist_sol, L.hist_sol);
+  swap_buf(c->d_b, L.b);
+  swap_buf(c->d_x, L.x);
+  swap_buf(c->d_r, L.r);
   std::swap(c->hist_slot, L.hist_slot);
   std::swap(c->hist_kidx, L.hist_kidx);
   std::swap(c->hist_n, L.hist_n);
 }
 
+// A load's state in the context for one scope.
+struct LoadIn {
+  ewbem_ctx* c;
+  LoadRun& L;
+  LoadIn(ewbem_ctx* c_, LoadRun& L_) : c(c_), L(L_) { swap_load(c, L); }
+  ~LoadIn() { swap_load(c, L); }
+  LoadIn(const LoadIn&) = delete;
+  LoadIn& operator=(const LoadIn&) = delete;
+};
+
 // Every frequency once for all loads: the operator, preconditioner and self
-// terms are assembled once per frequency and each load's right-hand side,
-// guess and GMRES follow.  A load's solutions match those of
-// frequency_loop for that load alone on the same operators.
+// terms are assembled once per frequency; each load's right-hand side and
+// extrapolated guess follow, and the loads' GMRES run in lock-step groups of
+// up to four, their matvecs as one multi-right-hand-side product.  A load's
+// solutions equal those of frequency_loop for that load alone on the same
+// operators.
 int multi_load_loop(ewbem_ctx* c, std::vector<LoadRun>& loads) {
   const long long N = 3LL * c->nt;
   const int nk = c->n_f / 2 + 1;
+  const int n = (int)loads.size();
   hipStream_t st = c->stream;
   const DevGeom g = dev_geom(c);
   const int ncap = std::max(1, c->so.sem_k);
+  const int m = c->so.restart;
+  const int hs = 2 * (m + 2) + 2;
+  const int gmax = std::min(n, HMV_MAXRHS);
+  DevBuf<cd> Vm, Zm, Wm, hm;
+  Vm.reserve((size_t)gmax * (m + 1) * N);
+  Zm.reserve((size_t)HMV_MAXRHS * N);
+  Wm.reserve((size_t)HMV_MAXRHS * N);
+  hm.reserve((size_t)gmax * hs);
   {
     EventPair ev;
     const auto t0 = Clock::now();
     EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
     for (LoadRun& L : loads) {
       L.hist_sol.reserve((size_t)ncap * N);
-      swap_load(c, L);
+      L.b.reserve(N);
+      L.x.reserve(N);
+      L.r.reserve(N);
+      LoadIn in(c, L);
       rhs_precompute(c, g, 0, nk);
-      swap_load(c, L);
     }
     EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -1554,25 +1783,39 @@ int multi_load_loop(ewbem_ctx* c, std::vector<LoadRun>& loads) {
   const int saved_guess = c->so.guess;
   if (c->so.guess == EWBEM_GUESS_LEARNED) c->so.guess = EWBEM_GUESS_SEM;  // no per-load coordinate rings
   int rc = EWBEM_OK;
+  std::vector<GmresLane> lanes;
   try {
     for (int k = 0; k < nk; ++k)
-      for (size_t l = 0; l < loads.size(); ++l) {
-        LoadRun& L = loads[l];
-        swap_load(c, L);
-        try {
+      for (int g0 = 0; g0 < n; g0 += HMV_MAXRHS) {
+        const int g1 = std::min(n, g0 + HMV_MAXRHS);
+        for (int l = g0; l < g1; ++l) {
+          LoadIn in(c, loads[l]);
           if (c->assembled_k != k)
             assemble_k(c, k);  // b of this load too
           else
             rhs_finish_k(c, k);
-          const int r = solve_k(c, k, nullptr);
-          if (r != EWBEM_OK) rc = r;
-          EWBEM_HIP_CHECK(hipMemcpyAsync(L.spec + (size_t)k * N, c->d_x.p, N * sizeof(cd),
-                                         hipMemcpyDeviceToDevice, st));
-        } catch (...) {
-          swap_load(c, L);
-          throw;
+          guess_k(c, k, nullptr);
         }
-        swap_load(c, L);
+        lanes.assign(g1 - g0, GmresLane{});
+        for (int l = g0; l < g1; ++l) {
+          GmresLane& G = lanes[l - g0];
+          G.b = loads[l].b.p;
+          G.x = loads[l].x.p;
+          G.r = loads[l].r.p;
+          G.V = Vm.p + (size_t)(l - g0) * (m + 1) * N;
+          G.hd = hm.p + (size_t)(l - g0) * hs;
+        }
+        const auto ts = Clock::now();
+        gmres_multi(c, lanes, Zm.p, Wm.p);
+        c->acc.t_gmres_ms += ms_since(ts);
+        for (int l = g0; l < g1; ++l) {
+          const GmresLane& G = lanes[l - g0];
+          LoadIn in(c, loads[l]);
+          finish_k(c, k, G.its, G.relres);
+          if (!(G.relres <= c->so.tol)) rc = EWBEM_ENOCONV;
+          EWBEM_HIP_CHECK(hipMemcpyAsync(loads[l].spec + (size_t)k * N, c->d_x.p, N * sizeof(cd),
+                                         hipMemcpyDeviceToDevice, st));
+        }
       }
   } catch (...) {
     c->so.guess = saved_guess;
