@@ -26,54 +26,65 @@ __device__ __forceinline__ double wsum64(double v) {
 // ldz, ldp, ldy): every factor and near-block entry is loaded once and
 // multiplied against the NR vectors.  Phase 1 takes NC factor columns per
 // wavefront (a tuning choice).
+// Columns per pass: with several right-hand sides the NC x NR accumulators
+// would crowd the registers (and the occupancy), so a task's columns are
+// taken in passes of NCS, the x slice being re-read from cache each pass.
+template <int NR, int NC>
+constexpr int far_vt_pass_cols() {
+  return NR == 1 ? NC : (NR == 2 ? (NC < 4 ? NC : 4) : 2);
+}
+
 template <typename TS, int NR, int NC>
 __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks, int ntask,
                                                 const cd* __restrict__ x, long long ldx, cd* __restrict__ z,
                                                 long long ldz) {
+  constexpr int NCS = far_vt_pass_cols<NR, NC>();
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= ntask) return;
   const VtTask T = tasks[t];
   const TS* __restrict__ V = (const TS*)T.V;
   const cd* __restrict__ xs = x + T.x0;
-  cd a[NC][NR];
-#pragma unroll
-  for (int k = 0; k < NC; ++k)
-#pragma unroll
-    for (int q = 0; q < NR; ++q) a[k][q] = mk(0.0);
   const int C = T.C;
   const int nc = T.ncol;
-  // columns past ncol read column 0 again (in bounds) and are discarded
-  const TS* __restrict__ Vc[NC];
+  for (int k0 = 0; k0 < NC && k0 < nc; k0 += NCS) {
+    cd a[NCS][NR];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) Vc[k] = V + (size_t)(nc > k ? k : 0) * C;
-  for (int c = lane; c < C; c += 64) {
-    cd v[NC];
+    for (int k = 0; k < NCS; ++k)
 #pragma unroll
-    for (int k = 0; k < NC; ++k) v[k] = to_cd(Vc[k][c]);
+      for (int q = 0; q < NR; ++q) a[k][q] = mk(0.0);
+    // columns past ncol read column 0 again (in bounds) and are discarded
+    const TS* __restrict__ Vc[NCS];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const cd xv = xs[c + q * ldx];
+    for (int k = 0; k < NCS; ++k) Vc[k] = V + (size_t)(nc > k0 + k ? k0 + k : 0) * C;
+    for (int c = lane; c < C; c += 64) {
+      cd v[NCS];
 #pragma unroll
-      for (int k = 0; k < NC; ++k) a[k][q] += v[k] * xv;
+      for (int k = 0; k < NCS; ++k) v[k] = to_cd(Vc[k][c]);
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const cd xv = xs[c + q * ldx];
+#pragma unroll
+        for (int k = 0; k < NCS; ++k) a[k][q] += v[k] * xv;
+      }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < NC; ++k)
+    for (int k = 0; k < NCS; ++k)
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      a[k][q].x = wsum64(a[k][q].x);
-      a[k][q].y = wsum64(a[k][q].y);
-    }
-  // every lane holds the sums; lane 0 stores them (no lane-indexed select,
-  // which the compiler would place in scratch memory)
-  if (lane == 0) {
+      for (int q = 0; q < NR; ++q) {
+        a[k][q].x = wsum64(a[k][q].x);
+        a[k][q].y = wsum64(a[k][q].y);
+      }
+    // every lane holds the sums; lane 0 stores them (no lane-indexed select,
+    // which the compiler would place in scratch memory)
+    if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      cd* zz = z + T.zidx + q * ldz;
+      for (int q = 0; q < NR; ++q) {
+        cd* zz = z + T.zidx + q * ldz + k0;
 #pragma unroll
-      for (int k = 0; k < NC; ++k)
-        if (nc > k) zz[k] = a[k][q];
+        for (int k = 0; k < NCS; ++k)
+          if (nc > k0 + k) zz[k] = a[k][q];
+      }
     }
   }
 }
@@ -143,7 +154,10 @@ __global__ __launch_bounds__(256) void k_hmv(const RowTask* __restrict__ tasks, 
   const RowTask T = tasks[blockIdx.x];
   const int rows_pad = (T.rows + 63) & ~63;
   const int G = 256 / rows_pad;
-  const int r = threadIdx.x % rows_pad, g = threadIdx.x / rows_pad;
+  // rows_pad is a multiple of 64, so a wavefront's threads share g: made
+  // explicit, it lets every x load of the panel loop be one uniform load
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / rows_pad);
+  const int r = threadIdx.x - g * rows_pad;
   __shared__ cd red[NR][256];
   cd acc[NR];
 #pragma unroll
