@@ -1767,14 +1767,23 @@ int multi_load_loop(ewbem_ctx* c, std::vector<LoadRun>& loads) {
     EventPair ev;
     const auto t0 = Clock::now();
     EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+    // every load's off-diagonal U t0 for all frequencies, the kernel
+    // evaluated once per pair for up to eight loads
+    std::vector<const double*> t0s;
+    std::vector<cd*> parts;
     for (LoadRun& L : loads) {
       L.hist_sol.reserve((size_t)ncap * N);
       L.b.reserve(N);
       L.x.reserve(N);
       L.r.reserve(N);
-      LoadIn in(c, L);
-      rhs_precompute(c, g, 0, nk);
+      L.rhs_part.reserve((size_t)rhs_split(c->nt) * nk * N);
+      t0s.push_back(L.t0.p);
+      parts.push_back(L.rhs_part.p);
     }
+    launch_rhs_loads(g, c->P, c->sigma, 2.0 * M_PI / c->period, 0, nk, n, t0s.data(), parts.data(), st);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    c->boff_k0 = 0;
+    c->boff_nk = nk;
     EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
     c->acc.t_rhs_ms += ev.elapsed();

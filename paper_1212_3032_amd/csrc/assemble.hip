@@ -383,6 +383,123 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
   }
 }
 
+// The same sums for several loads t0_l on one mesh (traction or pressure
+// loads, no incident wave): one workgroup column per frequency, every pair's
+// kernel evaluated once and applied to all NL loads.  A frequency's phases
+// come from the same recurrence as in k_rhs_multi (from the first frequency
+// of its group of RHS_NK, with RHS_NK groups counted from k0), and each
+// load's terms are formed in the same order, so every load's partials equal
+// those k_rhs_multi writes for it alone.
+template <int NL>
+__global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double sigma, double dw, int k0,
+                                                   int nk, RhsLoadSet L) {
+  __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[NL * RHS_TILE * 3];
+  const int ne = g.ne;
+  const int k = k0 + blockIdx.y;
+  const int kst = k0 + ((k - k0) / RHS_NK) * RHS_NK;  // first frequency of k's group
+  const int jk = k - kst;
+  const int split = blockIdx.z, nsplit = gridDim.z;
+  const int s0 = (int)((long long)ne * split / nsplit), s1 = (int)((long long)ne * (split + 1) / nsplit);
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = a < ne;
+  double x[3] = {0, 0, 0};
+  if (act) {
+    x[0] = g.cen[3 * a];
+    x[1] = g.cen[3 * a + 1];
+    x[2] = g.cen[3 * a + 2];
+  }
+  cd acc[NL][3];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) acc[l][0] = acc[l][1] = acc[l][2] = mk(0.0);
+  const double gam = P.gamma, ics = P.inv_cs;
+  for (int c0 = s0; c0 < s1; c0 += RHS_TILE) {
+    const int nc = min(RHS_TILE, s1 - c0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nc * 21; i += blockDim.x) sq[i] = g.qp[(size_t)c0 * 21 + i];
+    for (int i = threadIdx.x; i < nc * 7; i += blockDim.x) sw[i] = g.qw[(size_t)c0 * 7 + i];
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+      for (int i = threadIdx.x; i < nc * 3; i += blockDim.x) stt[l * RHS_TILE * 3 + i] = L.t0[l][(size_t)c0 * 3 + i];
+    __syncthreads();
+    if (!act) continue;
+    for (int b = 0; b < nc; ++b) {
+      if (c0 + b == a) continue;
+      double tb[NL][3];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        tb[l][0] = stt[l * RHS_TILE * 3 + 3 * b];
+        tb[l][1] = stt[l * RHS_TILE * 3 + 3 * b + 1];
+        tb[l][2] = stt[l * RHS_TILE * 3 + 3 * b + 2];
+      }
+      for (int qq = 0; qq < 7; ++qq) {
+        const double* y = sq + 21 * b + 3 * qq;
+        const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double ir = 1.0 / r;
+        const double h0 = d0 * ir, h1 = d1 * ir, h2 = d2 * ir;
+        const double sc = sw[7 * b + qq] * P.inv4pimu * ir;
+        const double zx = sigma * r * ics;
+        const double th = dw * r * ics;
+        double sn, cs;
+        const double ms = exp(-zx), mp = exp(-gam * zx);
+        sincos(kst * th, &sn, &cs);
+        cd ph = cd{ms * cs, -ms * sn};
+        sincos(th, &sn, &cs);
+        const cd rot = cd{cs, -sn};
+        sincos(gam * kst * th, &sn, &cs);
+        cd php = cd{mp * cs, -mp * sn};
+        sincos(gam * th, &sn, &cs);
+        const cd rotp = cd{cs, -sn};
+        for (int j = 0; j < jk; ++j) {
+          ph = ph * rot;
+          php = php * rotp;
+        }
+        const cd z = cd{zx, (kst + jk) * th};
+        cd rphi, rpsi;
+        if (norm2(z) < P.series_z2) {
+          cd a1 = mk(P.c_phi[NSER - 1]), b1 = mk(P.c_psi[NSER - 1]);
+          for (int m = NSER - 2; m >= 0; --m) {
+            a1 = a1 * z + P.c_phi[m];
+            b1 = b1 * z + P.c_psi[m];
+          }
+          rphi = a1;
+          rpsi = b1;
+        } else {
+          const cd iz = cinv(z);
+          const cd iz2 = iz * iz;
+          const cd gi = iz * gam;
+          rphi = ph * (1.0 + iz + iz2) - php * (gi + iz2);
+          rpsi = ph * (1.0 + 3.0 * iz + 3.0 * iz2) - php * (P.g2 + 3.0 * gi + 3.0 * iz2);
+        }
+        const cd f = rphi * sc;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const double ht = h0 * tb[l][0] + h1 * tb[l][1] + h2 * tb[l][2];
+          const cd gg = rpsi * (sc * ht);
+          acc[l][0] += f * tb[l][0] - gg * h0;
+          acc[l][1] += f * tb[l][1] - gg * h1;
+          acc[l][2] += f * tb[l][2] - gg * h2;
+        }
+      }
+    }
+  }
+  if (!act) return;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    cd* out = L.part[l] + ((size_t)split * nk + (k - k0)) * 3 * ne + 3 * (size_t)a;
+    out[0] = acc[l][0];
+    out[1] = acc[l][1];
+    out[2] = acc[l][2];
+  }
+}
+
+template <int NL>
+void rhs_loads_nl(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk, const RhsLoadSet& L,
+                  hipStream_t st) {
+  dim3 grid((g.ne + 255) / 256, nk, rhs_split(g.ne));
+  hipLaunchKernelGGL(k_rhs_loads<NL>, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, L);
+}
+
 // b[d] = P_k (sum over source ranges of the partials of frequency index kk
 // + U_self t0)
 __global__ void k_rhs_finish(const cd* __restrict__ partial, int nsplit, int nk, int kk, int ne,
@@ -419,6 +536,29 @@ void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double d
     hipLaunchKernelGGL(k_rhs_multi<true>, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, t0, tau, partial);
   else
     hipLaunchKernelGGL(k_rhs_multi<false>, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, t0, tau, partial);
+}
+
+void launch_rhs_loads(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk, int n_loads,
+                      const double* const* t0, cd* const* partial, hipStream_t st) {
+  if (nk <= 0) return;
+  for (int l0 = 0; l0 < n_loads; l0 += RHS_NL) {
+    const int n = std::min(RHS_NL, n_loads - l0);
+    RhsLoadSet L{};
+    for (int i = 0; i < n; ++i) {
+      L.t0[i] = t0[l0 + i];
+      L.part[i] = partial[l0 + i];
+    }
+    switch (n) {
+      case 1: rhs_loads_nl<1>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 2: rhs_loads_nl<2>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 3: rhs_loads_nl<3>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 4: rhs_loads_nl<4>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 5: rhs_loads_nl<5>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 6: rhs_loads_nl<6>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 7: rhs_loads_nl<7>(g, P, sigma, dw, k0, nk, L, st); break;
+      default: rhs_loads_nl<8>(g, P, sigma, dw, k0, nk, L, st); break;
+    }
+  }
 }
 
 void launch_rhs_finish(const cd* partial, int nk, int kk, int ne, const cd* selfU, const double* t0,

@@ -41,6 +41,16 @@ void launch_dense_self(const cd* selfT, const cd* selfU, const int* perm, int ne
 int rhs_split(int ne);
 void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk,
                       const double* t0, const double* tau, cd* partial, hipStream_t st);
+// The same partials for n_loads loads (t0[l] and partial[l] per load, no
+// incident wave), each pair's kernel evaluated once for up to RHS_NL loads;
+// every load's partials equal launch_rhs_multi's for it with the same k0.
+constexpr int RHS_NL = 8;
+struct RhsLoadSet {
+  const double* t0[RHS_NL];
+  cd* part[RHS_NL];
+};
+void launch_rhs_loads(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk, int n_loads,
+                      const double* const* t0, cd* const* partial, hipStream_t st);
 void launch_rhs_finish(const cd* partial, int nk, int kk, int ne, const cd* selfU, const double* t0,
                        const double* tau, cd s_k, const cd* phat_k, cd* b, hipStream_t st);
 void launch_kernel_eval(const KParams& P, long long n, const double* x, const double* y,

@@ -1,14 +1,21 @@
 """Several loads through one frequency loop (ewbem_solve_transient_loads):
 each frequency's operator, self terms and preconditioner are assembled once
-for all loads, each load's right-hand side and extrapolated guess follow,
-and the loads' GMRES run in lock-step groups of up to four whose matvecs are
-one multi-right-hand-side product.  The operators are those a lone transient
-builds (the same warm-started ACA sequence over k = 0..N_f/2), and the
-multi-right-hand-side matvec sums every column in the order the single one
-does, so every load's transient and spectrum must equal, bit for bit, those
-of a fresh context solving that load alone -- also when the loads of a group
-converge after different numbers of iterations, and with a group of one
-(five loads).  Matvec autotuning is off here so that both runs take the
+for all loads, the loads' off-diagonal U t0 come from one pass that
+evaluates every pair's kernel once for up to eight loads, each load's guess
+follows, and the loads' GMRES run in lock-step groups of up to four whose
+matvecs are one multi-right-hand-side product.
+
+The operators are those a lone transient builds (the same warm-started ACA
+sequence over k = 0..N_f/2), and the multi-right-hand-side matvec sums every
+column in the order the single one does.  The multi-load right-hand-side
+kernel forms each load's terms in the single-load kernel's order, but the
+compiler fuses their products into FMAs in its own way, so b agrees to
+rounding (about 1e-16 relative), not bit for bit.  Hence: every load's
+transient and spectrum agree with a fresh context's lone solve to 1e-10
+relative (rounding carried through GMRES, far below its 1e-8 tolerance),
+with the same GMRES iteration counts to within 1% -- also when the loads of
+a group converge after different numbers of iterations, and with a group of
+one (five loads).  Matvec autotuning is off here so that both runs take the
 same task shapes (its candidates agree to 1e-12, not bitwise).
 """
 
@@ -29,7 +36,11 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _ctx(E, xyz, tri, kind, load, pressure):
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _ctx(E, xyz, tri, kind, load, pressure, **solver):
     c = E.Context(0)
     c.set_mesh(xyz, tri, exterior=True)
     c.set_material(1.0, 1.0, 0.25)
@@ -43,7 +54,9 @@ def _ctx(E, xyz, tri, kind, load, pressure):
         c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-6, autotune=0)
     else:
         c.set_operator(kind=E.OP_DENSE, autotune=0)
-    c.set_solver(tol=1e-8, guess=E.GUESS_SEM)
+    so = dict(tol=1e-8, guess=E.GUESS_SEM)
+    so.update(solver)
+    c.set_solver(**so)
     return c
 
 
@@ -82,12 +95,13 @@ def test_loads_equal_lone_transients(kind, pressure, sub, n_loads):
     _say(f"  lone iterations {lone_it} ({sum(lone_it)}), together {st['iters_total']} "
          f"in {st['n_solves']} solves")
     assert st["n_solves"] == len(loads) * nk
-    assert st["iters_total"] == sum(lone_it)
+    assert abs(st["iters_total"] - sum(lone_it)) <= 0.01 * sum(lone_it)
     U = u.cpu().numpy().reshape(len(loads), -1)
     S = s.cpu().numpy().reshape(len(loads), -1)
-    for l in range(len(loads)):
-        assert np.array_equal(U[l], lone_u[l]), l
-        assert np.array_equal(S[l], lone_s[l]), l
+    eu = max(_rel(U[l], lone_u[l]) for l in range(len(loads)))
+    es = max(_rel(S[l], lone_s[l]) for l in range(len(loads)))
+    _say(f"  largest relative difference to the lone solves: transients {eu:.1e}, spectra {es:.1e}")
+    assert eu < 1e-10 and es < 1e-10
 
     # the context's own load is untouched: its transient (on operators
     # rebuilt by a second pass, warm ACA) agrees to the solver tolerance
@@ -112,3 +126,43 @@ def test_loads_equal_lone_transients(kind, pressure, sub, n_loads):
     _say(f"  own load at k = 5 after another multi-load run: relative difference {e:.1e}")
     assert e < 1e-5
     c.close()
+
+
+@pytest.mark.parametrize("restart,maxit,tol", [(6, 400, 1e-8), (100, 12, 1e-12)])
+def test_loads_restarts_and_iteration_cap(restart, maxit, tol):
+    """Short restart cycles (the loads of a group restart at different
+    steps, so cycle ends, true residuals and new cycles interleave with other
+    loads' Arnoldi steps) and an iteration cap that no load meets (every solve
+    stops unconverged): still the lone solves to rounding."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    dev = torch.device("cuda:0")
+    xyz, tri = icosphere(3)
+    N = 3 * len(tri)
+    rng = np.random.default_rng(77)
+    loads = np.array([sh_pressure(xyz, tri, rng)[0] for _ in range(4)])
+    so = dict(restart=restart, maxit=maxit, tol=tol)
+    lone, its, res = [], [], []
+    for l in range(len(loads)):
+        c = _ctx(E, xyz, tri, "hmat", loads[l], True, **so)
+        u = torch.zeros(NF * N, dtype=torch.float64, device=dev)
+        st = c.solve_transient(u, allow_noconv=True)
+        lone.append(u.cpu().numpy())
+        its.append(st["iters_total"])
+        res.append(st["resid_max"])
+        c.close()
+    c = _ctx(E, xyz, tri, "hmat", loads[0], True, **so)
+    u = torch.zeros(len(loads) * NF * N, dtype=torch.float64, device=dev)
+    st = c.solve_transient_loads(loads, u, pressures=True, allow_noconv=True)
+    c.close()
+    _say(f"restart {restart}, maxit {maxit}, tol {tol:.0e}: lone iterations {its}, largest final residuals "
+         f"{max(res):.2e} / together {st['iters_total']}, {st['resid_max']:.2e}")
+    assert abs(st["iters_total"] - sum(its)) <= 0.01 * sum(its)
+    if maxit < 100:
+        assert st["iters_total"] == sum(its) == len(loads) * (NF // 2 + 1) * maxit
+        assert st["iters_max"] == maxit and st["resid_max"] > tol
+        assert abs(st["resid_max"] - max(res)) <= 1e-6 * max(res)
+    U = u.cpu().numpy().reshape(len(loads), -1)
+    e = max(_rel(U[l], lone[l]) for l in range(len(loads)))
+    _say(f"  largest relative difference to the lone solves {e:.1e}")
+    assert e < 1e-10
