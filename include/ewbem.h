@@ -290,11 +290,11 @@ int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats*
  * and serve all loads, each with its own right-hand side, extrapolation
  * history and GMRES; the right-hand sides of up to eight loads share one
  * kernel evaluation per element pair, and the loads' GMRES run in lock-step
- * groups of four whose matvecs read the operator once for the group.  Each
+ * groups of up to eight whose matvecs read the operator once for the group.  Each
  * load's result is that of ewbem_solve_transient with that load on the same
  * operators, to rounding.  Memory: per load 16 (N_f/2+1) N bytes of
  * off-diagonal sums (times 4 from 4,096 elements on), the extrapolation
- * history and three vectors; per group four Krylov bases of restart + 1
+ * history and three vectors; per group eight Krylov bases of restart + 1
  * vectors.  loads: host,
  * n_loads x nt x 3 tractions (pressure 0) or n_loads x nt pressures
  * (pressure 1), caller order.  u: device, n_loads x n_f x N doubles (load-

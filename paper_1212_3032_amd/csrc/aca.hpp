@@ -176,6 +176,6 @@ void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, l
                 const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st);
 void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, long long ldp, int nrhs, cd* y,
                        long long ldy, hipStream_t st);
-constexpr int HMV_MAXRHS = 4;
+constexpr int HMV_MAXRHS = 8;  // right-hand sides of one multi-right-hand-side matvec
 
 }  // namespace ewbem

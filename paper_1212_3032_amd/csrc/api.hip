@@ -931,7 +931,7 @@ void apply_tree(ewbem_ctx* c, const cd* x, cd* y, EventPair* ev) {
   c->acc.matvecs += 1;
 }
 
-// Y(:, j) = A X(:, j) for j < nrhs <= 4, columns N apart (tree order): the
+// Y(:, j) = A X(:, j) for j < nrhs <= HMV_MAXRHS (8), columns N apart (tree order): the
 // operator is read once for all of them.
 void apply_tree_multi(ewbem_ctx* c, const cd* X, cd* Y, int nrhs) {
   hipStream_t st = c->stream;
@@ -1236,13 +1236,13 @@ double gmres(ewbem_ctx* c, cd* x, cd* r, int& iters_out, bool& converged) {
   return relres;
 }
 
-// The same GMRES for up to four systems A x_l = b_l on one operator, in
+// The same GMRES for up to eight systems A x_l = b_l on one operator, in
 // lock-step: each step's preconditioned vectors of the systems still
 // iterating go through one multi-right-hand-side matvec (the operator read
 // once for all), and one host synchronisation serves all their Arnoldi
 // coefficients.  Per system the arithmetic is that of gmres() in the same
 // order, so each result equals a lone solve's.  Vm: nb x (m+1) x N Krylov
-// bases; Z, W: 4 x N staging; small: nb x (2 (m+2) + 2) coefficients.
+// bases; Z, W: nb x N staging; small: nb x (2 (m+2) + 2) coefficients.
 struct GmresLane {
   cd* b = nullptr;
   cd* x = nullptr;
@@ -1261,7 +1261,7 @@ void gmres_multi(ewbem_ctx* c, std::vector<GmresLane>& L, cd* Z, cd* W) {
   const int m = c->so.restart;
   const double tol = c->so.tol;
   const int nb = (int)L.size();
-  if (nb < 1 || nb > HMV_MAXRHS) fail(EWBEM_EINVAL, "internal: 1 to 4 systems per lock-step GMRES");
+  if (nb < 1 || nb > HMV_MAXRHS) fail(EWBEM_EINVAL, "internal: 1 to 8 systems per lock-step GMRES");
   const int hs = 2 * (m + 2) + 2;
   std::vector<cd> hb((size_t)nb * hs);
   EventPair ev;
@@ -1436,7 +1436,7 @@ void sem_guess(ewbem_ctx* c, cd* x, cd* r, const cd* extra = nullptr) {
   cd* Y = c->d_Y.p;
   cd* Q = c->d_V.p;  // GMRES basis as scratch
   // Y(:, j) = A X(:, j): the columns are copied into the order of Y, then the
-  // operator is applied to up to four at once
+  // operator is applied to up to eight at once
   for (int j = 0; j < K; ++j)
     EWBEM_HIP_CHECK(hipMemcpyAsync(Q + (size_t)j * N, c->d_hist_sol.p + (size_t)c->hist_slot[j] * N,
                                    N * sizeof(cd), hipMemcpyDeviceToDevice, st));
@@ -1745,7 +1745,7 @@ struct LoadIn {
 // Every frequency once for all loads: the operator, preconditioner and self
 // terms are assembled once per frequency; each load's right-hand side and
 // extrapolated guess follow, and the loads' GMRES run in lock-step groups of
-// up to four, their matvecs as one multi-right-hand-side product.  A load's
+// up to eight, their matvecs as one multi-right-hand-side product.  A load's
 // solutions equal those of frequency_loop for that load alone on the same
 // operators.
 int multi_load_loop(ewbem_ctx* c, std::vector<LoadRun>& loads) {

@@ -107,7 +107,11 @@ void far_vt_nc(const VtTask* tasks, int ntask, int store_c64, const cd* x, long 
     case 2: far_vt_nr<2, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
     case 3: far_vt_nr<3, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
     case 4: far_vt_nr<4, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
-    default: throw ApiError(-1, "matvec: 1 to 4 right-hand sides");
+    case 5: far_vt_nr<5, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 6: far_vt_nr<6, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 7: far_vt_nr<7, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    case 8: far_vt_nr<8, NC>(tasks, ntask, store_c64, x, ldx, z, ldz, st); break;
+    default: throw ApiError(-1, "matvec: 1 to 8 right-hand sides");
   }
 }
 
@@ -195,7 +199,11 @@ void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, l
     case 2: hipLaunchKernelGGL(k_hmv<2>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
     case 3: hipLaunchKernelGGL(k_hmv<3>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
     case 4: hipLaunchKernelGGL(k_hmv<4>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
-    default: throw ApiError(-1, "matvec: 1 to 4 right-hand sides");
+    case 5: hipLaunchKernelGGL(k_hmv<5>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    case 6: hipLaunchKernelGGL(k_hmv<6>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    case 7: hipLaunchKernelGGL(k_hmv<7>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    case 8: hipLaunchKernelGGL(k_hmv<8>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;
+    default: throw ApiError(-1, "matvec: 1 to 8 right-hand sides");
   }
 }
 

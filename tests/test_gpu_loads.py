@@ -2,7 +2,7 @@
 each frequency's operator, self terms and preconditioner are assembled once
 for all loads, the loads' off-diagonal U t0 come from one pass that
 evaluates every pair's kernel once for up to eight loads, each load's guess
-follows, and the loads' GMRES run in lock-step groups of up to four whose
+follows, and the loads' GMRES run in lock-step groups of up to eight whose
 matvecs are one multi-right-hand-side product.
 
 The operators are those a lone transient builds (the same warm-started ACA
@@ -15,7 +15,7 @@ transient and spectrum agree with a fresh context's lone solve to 1e-10
 relative (rounding carried through GMRES, far below its 1e-8 tolerance),
 with the same GMRES iteration counts to within 1% -- also when the loads of
 a group converge after different numbers of iterations, and with a group of
-one (five loads).  Matvec autotuning is off here so that both runs take the
+one (nine loads: groups of eight and one).  Matvec autotuning is off here so that both runs take the
 same task shapes (its candidates agree to 1e-12, not bitwise).
 """
 
@@ -60,7 +60,7 @@ def _ctx(E, xyz, tri, kind, load, pressure, **solver):
     return c
 
 
-@pytest.mark.parametrize("kind,pressure,sub,n_loads", [("hmat", True, 3, 5), ("dense", False, 2, 3)])
+@pytest.mark.parametrize("kind,pressure,sub,n_loads", [("hmat", True, 3, 9), ("dense", False, 2, 3)])
 def test_loads_equal_lone_transients(kind, pressure, sub, n_loads):
     import torch
     from paper_1212_3032_amd import ewbem as E
