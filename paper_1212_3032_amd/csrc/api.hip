@@ -272,7 +272,7 @@ void ensure_structure(ewbem_ctx* c) {
   std::vector<int> perm = build_tree(c->nv, c->xyz.data(), c->nt, c->tri.data(), c->op.leaf_size,
                                      c->part.clusters);
   build_geometry(c->nv, c->xyz.data(), c->nt, c->tri.data(), c->exterior, perm, c->hg);
-  build_partition(c->op.kind == EWBEM_OP_DENSE ? 0.0 : c->op.eta_adm, c->part);
+  build_partition(c->op.kind == EWBEM_OP_DENSE ? 0.0 : c->op.eta_adm, c->part, ACA_MAXM);
   // near-block layout (each block column-major, ld = 3 m) and the position
   // of every element's self block inside its diagonal near block
   c->near_h.clear();
@@ -298,7 +298,8 @@ void ensure_structure(ewbem_ctx* c) {
   for (const BlockPair& bp : c->part.far) {
     const Cluster& r = c->part.clusters[bp.row];
     const Cluster& s = c->part.clusters[bp.col];
-    if (r.size() > ACA_MAXM) fail(EWBEM_EINVAL, "far block with more than 16384 row elements");
+    if (r.size() > ACA_MAXM || s.size() > ACA_MAXM)
+      fail(EWBEM_EINVAL, "internal: far block with more than 16384 elements on a side");
     FarBlk fb{};
     fb.r0 = r.begin;
     fb.m = r.size();

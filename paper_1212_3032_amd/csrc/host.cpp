@@ -184,7 +184,7 @@ static double bbox_dist(const Cluster& a, const Cluster& b) {
   return std::sqrt(s);
 }
 
-void build_partition(double eta, Partition& p) {
+void build_partition(double eta, Partition& p, int max_far) {
   p.near.clear();
   p.far.clear();
   p.leaves.clear();
@@ -197,7 +197,11 @@ void build_partition(double eta, Partition& p) {
     const Cluster& cs = p.clusters[s];
     if (eta > 0) {
       double d = bbox_dist(ct, cs);
-      if (std::min(bbox_diam(ct), bbox_diam(cs)) <= eta * d) {
+      // an admissible pair larger than max_far elements on a side is split
+      // further: its child pairs are admissible too (their boxes are no
+      // larger and no closer)
+      if (std::min(bbox_diam(ct), bbox_diam(cs)) <= eta * d &&
+          ((ct.size() <= max_far && cs.size() <= max_far) || (ct.leaf() && cs.leaf()))) {
         p.far.push_back({t, s});
         return;
       }

@@ -59,7 +59,9 @@ std::vector<int> build_tree(int nv, const double* xyz, int nt, const int32_t* tr
 
 // Block partition: (tau, sigma) is admissible (low rank) when
 // min(diam tau, diam sigma) <= eta * dist(tau, sigma) with bounding-box
-// diameters and distances; eta <= 0 makes every block near (dense).
-void build_partition(double eta, Partition& p);
+// diameters and distances; eta <= 0 makes every block near (dense).  An
+// admissible pair with more than max_far elements on a side is split into
+// its child pairs (admissible as well) until both sides fit.
+void build_partition(double eta, Partition& p, int max_far);
 
 }  // namespace ewbem

@@ -1,8 +1,9 @@
 """The 12-cavity scattering scene (spherical cavities at seeded,
 non-overlapping centres in a 20 x 20 x 20 box, hit by a plane S-wave with a
 Ricker wavelet), at icosphere level 1 so that the oracle's dense LU is cheap:
-N = 12 x 80 x 3 = 2,880 unknowns.  The full-size scene (level 5, 737,280
-unknowns) runs the same code with larger clusters.
+N = 12 x 80 x 3 = 2,880 unknowns.  Larger levels run the same code with
+larger clusters (level 4, 184,320 unknowns, is the largest that fits one GPU;
+level 5's partition is checked on the host).
 
 Tolerances: H-matrix solves 30 x ACA tol against dense LU (the ACA bound);
 the point-source manufactured solution at levels 1-3 (N = 2,880 to 46,080)

@@ -201,3 +201,31 @@ def test_product_and_oracle_share_no_code():
             assert "oracle" not in open(os.path.join(root, f), errors="ignore").read().lower(), f
     assert "paper_1212_3032_amd" not in imports(os.path.join(ROOT, "synth"))
     assert "oracle" not in imports(os.path.join(ROOT, "synth"))
+
+
+def test_scene_full_size_partition_splits_large_admissible_pairs():
+    """The twelve-cavity scene at level 5 (245,760 elements): admissible pairs
+    of whole cavities exceed the far-block side limit of 16,384 elements and
+    are split into admissible child pairs.  The blocks still cover every
+    element pair exactly once (for every leaf, the column ranges of the
+    blocks whose rows contain it tile 0..N_e), and no far block exceeds the
+    limit on either side."""
+    d = config_inputs(5, sub=5)
+    c = ewbem.Context(device=-1)
+    c.set_mesh(d["xyz"], d["tri"], exterior=True)
+    c.set_operator(kind=ewbem.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-4)
+    perm, near, far = c.partition()
+    ne = len(d["tri"])
+    assert ne == 245760
+    blocks = np.concatenate([near, far]).astype(np.int64)
+    area = ((blocks[:, 1] - blocks[:, 0]) * (blocks[:, 3] - blocks[:, 2])).sum()
+    assert area == ne * ne
+    assert (far[:, 1] - far[:, 0]).max() <= 16384 and (far[:, 3] - far[:, 2]).max() <= 16384
+    rows, inv = np.unique(blocks[:, :2], axis=0, return_inverse=True)
+    cols = [blocks[inv.ravel() == g][:, 2:] for g in range(len(rows))]
+    leaves = np.unique(near[:, :2], axis=0)
+    assert leaves[0, 0] == 0 and leaves[-1, 1] == ne and (leaves[1:, 0] == leaves[:-1, 1]).all()
+    for a, b in leaves:
+        iv = np.concatenate([cols[g] for g in np.nonzero((rows[:, 0] <= a) & (rows[:, 1] >= b))[0]])
+        iv = iv[np.argsort(iv[:, 0])]
+        assert iv[0, 0] == 0 and iv[-1, 1] == ne and (iv[1:, 0] == iv[:-1, 1]).all()
