@@ -1851,12 +1851,18 @@ std::vector<LoadRun> make_load_runs(ewbem_ctx* c, int n, const double* loads, bo
   const std::vector<double> saved = c->load_caller;
   const bool saved_p = c->load_is_pressure;
   std::vector<LoadRun> runs(n);
-  for (int i = 0; i < n; ++i) {
-    c->load_caller.assign(loads + per * i, loads + per * (i + 1));
-    c->load_is_pressure = pressure;
-    runs[i].t0.upload(tree_load(c), c->stream);
-    EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));  // the host vector is a temporary
-    runs[i].spec = spec_base + (size_t)i * nk * N;
+  try {
+    for (int i = 0; i < n; ++i) {
+      c->load_caller.assign(loads + per * i, loads + per * (i + 1));
+      c->load_is_pressure = pressure;
+      runs[i].t0.upload(tree_load(c), c->stream);
+      EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));  // the host vector is a temporary
+      runs[i].spec = spec_base + (size_t)i * nk * N;
+    }
+  } catch (...) {
+    c->load_caller = saved;
+    c->load_is_pressure = saved_p;
+    throw;
   }
   c->load_caller = saved;
   c->load_is_pressure = saved_p;
