@@ -385,19 +385,16 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
 
 // The same sums for several loads t0_l on one mesh (traction or pressure
 // loads, no incident wave): one workgroup column per frequency, every pair's
-// kernel evaluated once and applied to all NL loads.  A frequency's phases
-// come from the same recurrence as in k_rhs_multi (from the first frequency
-// of its group of RHS_NK, with RHS_NK groups counted from k0), and each
-// load's terms are formed in the same order, so every load's partials equal
-// those k_rhs_multi writes for it alone.
+// kernel evaluated once and applied to all NL loads.  With one frequency per
+// pass the phases exp(-i Im(s) r / c) are evaluated directly (no rotation
+// recurrence to share), so a load's partials agree with k_rhs_multi's to
+// rounding.
 template <int NL>
 __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double sigma, double dw, int k0,
                                                    int nk, RhsLoadSet L) {
   __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[NL * RHS_TILE * 3];
   const int ne = g.ne;
   const int k = k0 + blockIdx.y;
-  const int kst = k0 + ((k - k0) / RHS_NK) * RHS_NK;  // first frequency of k's group
-  const int jk = k - kst;
   const int split = blockIdx.z, nsplit = gridDim.z;
   const int s0 = (int)((long long)ne * split / nsplit), s1 = (int)((long long)ne * (split + 1) / nsplit);
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -439,22 +436,14 @@ __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double 
         const double h0 = d0 * ir, h1 = d1 * ir, h2 = d2 * ir;
         const double sc = sw[7 * b + qq] * P.inv4pimu * ir;
         const double zx = sigma * r * ics;
-        const double th = dw * r * ics;
+        const double zy = k * dw * r * ics;  // Im z_s at s_k
         double sn, cs;
         const double ms = exp(-zx), mp = exp(-gam * zx);
-        sincos(kst * th, &sn, &cs);
-        cd ph = cd{ms * cs, -ms * sn};
-        sincos(th, &sn, &cs);
-        const cd rot = cd{cs, -sn};
-        sincos(gam * kst * th, &sn, &cs);
-        cd php = cd{mp * cs, -mp * sn};
-        sincos(gam * th, &sn, &cs);
-        const cd rotp = cd{cs, -sn};
-        for (int j = 0; j < jk; ++j) {
-          ph = ph * rot;
-          php = php * rotp;
-        }
-        const cd z = cd{zx, (kst + jk) * th};
+        sincos(zy, &sn, &cs);
+        const cd ph = cd{ms * cs, -ms * sn};
+        sincos(gam * zy, &sn, &cs);
+        const cd php = cd{mp * cs, -mp * sn};
+        const cd z = cd{zx, zy};
         cd rphi, rpsi;
         if (norm2(z) < P.series_z2) {
           cd a1 = mk(P.c_phi[NSER - 1]), b1 = mk(P.c_psi[NSER - 1]);

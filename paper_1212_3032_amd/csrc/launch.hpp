@@ -43,7 +43,7 @@ void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double d
                       const double* t0, const double* tau, cd* partial, hipStream_t st);
 // The same partials for n_loads loads (t0[l] and partial[l] per load, no
 // incident wave), each pair's kernel evaluated once for up to RHS_NL loads;
-// every load's partials equal launch_rhs_multi's for it with the same k0.
+// every load's partials agree with launch_rhs_multi's for it to rounding.
 constexpr int RHS_NL = 8;
 struct RhsLoadSet {
   const double* t0[RHS_NL];
