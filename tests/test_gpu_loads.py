@@ -8,15 +8,15 @@ matvecs are one multi-right-hand-side product.
 The operators are those a lone transient builds (the same warm-started ACA
 sequence over k = 0..N_f/2), and the multi-right-hand-side matvec sums every
 column in the order the single one does.  The multi-load right-hand-side
-kernel forms each load's terms in the single-load kernel's order, but the
-compiler fuses their products into FMAs in its own way, so b agrees to
-rounding (about 1e-16 relative), not bit for bit.  Hence: every load's
-transient and spectrum agree with a fresh context's lone solve to 1e-10
-relative (rounding carried through GMRES, far below its 1e-8 tolerance),
-with the same GMRES iteration counts to within 1% -- also when the loads of
-a group converge after different numbers of iterations, and with a group of
-one (nine loads: groups of eight and one).  Matvec autotuning is off here so that both runs take the
-same task shapes (its candidates agree to 1e-12, not bitwise).
+kernel evaluates each frequency's phases directly where the single-load one
+advances them by a rotation, so b agrees to rounding (about 1e-16
+relative), not bit for bit.  Hence: every load's transient and spectrum
+agree with a fresh context's lone solve to 1e-10 relative (rounding carried
+through GMRES, far below its 1e-8 tolerance), with the same GMRES iteration
+counts to within 1% -- also when the loads of a group converge after
+different numbers of iterations, and with a group of one (nine loads:
+groups of eight and one).  Matvec autotuning is off here so that both runs
+take the same task shapes (its candidates agree to 1e-12, not bitwise).
 """
 
 import sys
