@@ -893,6 +893,9 @@ void build_matvec(ewbem_ctx* c) {
         const Seg& S = flat[q];
         const long long span = ((long long)(S.ncols - 1) * S.ld + T.rows);
         if (S.ncols < 1 || S.ld < T.rows) fail(EWBEM_EINVAL, "internal: segment shape");
+        // the matvec addresses a panel with 32-bit byte offsets
+        if ((long long)S.ncols * S.ld * ((S.flags & SEG_C64) ? 8 : 16) >= (1LL << 32))
+          fail(EWBEM_EINVAL, "internal: panel of 4 GiB or more");
         if (S.flags & SEG_FROM_Z) {
           if (S.src < 0 || S.src + S.ncols > ztot || !store_ok(S.A, span * es))
             fail(EWBEM_EINVAL, "internal: far segment out of range");

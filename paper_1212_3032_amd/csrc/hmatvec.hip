@@ -126,26 +126,68 @@ void launch_far_vt(const VtTask* tasks, int ntask, int cols_per_wave, int store_
   }
 }
 
+// One entry of a panel through a buffer resource: counted by the vector
+// memory counter only (a flat load would also hold every wait on the scalar
+// x loads), and bounded by the resource's size.
+template <typename TS>
+__device__ __forceinline__ cd panel_load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  if constexpr (sizeof(TS) == 16) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    const double2 d = __builtin_bit_cast(double2, v);
+    return cd{d.x, d.y};
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    const float2 f = __builtin_bit_cast(float2, v);
+    return cd{(double)f.x, (double)f.y};
+  }
+}
+
+// acc[q] += sum_c A[c, r] src[c + q lds] over the columns c = g, g + G, ...
+// of a column-major panel (ld rows; its span below 4 GiB, checked on the
+// host).  Four columns per step; the next step's four entries are loaded
+// before this step's products, so their latency overlaps the arithmetic
+// (the products are summed in column order either way).
 template <typename TS, int NR>
 __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __restrict__ src, long long lds,
                                           int ld, int ncols, int r, int g, int G, cd (&acc)[NR]) {
+  const unsigned span = (unsigned)(((size_t)(ncols - 1) * ld + ld) * sizeof(TS));
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)A, 0, span, 0x00020000);
+  const unsigned es = sizeof(TS);
+  const unsigned stride = (unsigned)G * (unsigned)ld * es;
   int c = g;
-  for (; c + 3 * G < ncols; c += 4 * G) {
-    const cd a0 = to_cd(A[(size_t)c * ld + r]);
-    const cd a1 = to_cd(A[(size_t)(c + G) * ld + r]);
-    const cd a2 = to_cd(A[(size_t)(c + 2 * G) * ld + r]);
-    const cd a3 = to_cd(A[(size_t)(c + 3 * G) * ld + r]);
+  unsigned off = ((unsigned)c * (unsigned)ld + (unsigned)r) * es;
+  // one step: load the next four entries into nxt, then the products of the
+  // current four in cur; the two register sets alternate, so no copy has to
+  // wait for a load.  The loads are unconditional (no branch for the wait
+  // counts to merge): past the panel's span a buffer load returns zero, and
+  // those values are not used.
+  auto step = [&](cd (&cur)[4], cd (&nxt)[4]) -> bool {
+    const int cn = c + 4 * G;
+    const unsigned offn = off + 4 * stride;
+    const bool more = cn + 3 * G < ncols;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) nxt[i] = panel_load<TS>(rs, offn + i * stride);
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const cd* sq = src + q * lds;
-      acc[q] += a0 * sq[c];
-      acc[q] += a1 * sq[c + G];
-      acc[q] += a2 * sq[c + 2 * G];
-      acc[q] += a3 * sq[c + 3 * G];
+      acc[q] += cur[0] * sq[c];
+      acc[q] += cur[1] * sq[c + G];
+      acc[q] += cur[2] * sq[c + 2 * G];
+      acc[q] += cur[3] * sq[c + 3 * G];
+    }
+    c = cn;
+    off = offn;
+    return more;
+  };
+  if (c + 3 * G < ncols) {
+    cd a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = panel_load<TS>(rs, off + i * stride);
+    while (step(a, b) && step(b, a)) {
     }
   }
-  for (; c < ncols; c += G) {
-    const cd a0 = to_cd(A[(size_t)c * ld + r]);
+  for (; c < ncols; c += G, off += stride) {
+    const cd a0 = panel_load<TS>(rs, off);
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] += a0 * src[c + q * lds];
   }
