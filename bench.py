@@ -166,6 +166,7 @@ def run_gpu(args, store, pipeline=0):
     tot["matvec_shapes"] = {"cols_per_wave": info["mv_cols"], "task_div": info["mv_task_div"],
                             "tuned": info["mv_tuned"], "tuned_ms": info["mv_tune_best_ms"],
                             "default_ms": info["mv_tune_default_ms"]}
+    tot["u_last"] = u.cpu().numpy()  # the last timed transient (untimed copy)
     ctx.close()
     return d, N, elapsed, tot
 
@@ -268,8 +269,9 @@ def learned_workload(args):
     cp.set_load_pressure(loads[held[0]], d["history"])
     cp.solve_transient(u)  # warmup: the learned context was warmed by its training solves
     res = {}
+    plain_u = {}  # held-out transients of the plain FP64 pass, for the error of the other
     for name, c in (("plain_fp64", cp), ("learned_fp32", cl)):
-        tot = dict(its=0, solves=0, resid=0.0, guess=0.0, learned=0, t=0.0, t_gmres=0.0)
+        tot = dict(its=0, solves=0, resid=0.0, guess=0.0, learned=0, t=0.0, t_gmres=0.0, err=0.0)
         for i in held:
             c.set_load_pressure(loads[i], d["history"])
             torch.cuda.synchronize()
@@ -283,12 +285,18 @@ def learned_workload(args):
             tot["guess"] += st["guess_resid_sum"]
             tot["learned"] += st["guess_learned"]
             tot["t_gmres"] += st["t_gmres_ms"]
+            if name == "plain_fp64":
+                plain_u[i] = u.clone()
+            else:
+                tot["err"] = max(tot["err"], (torch.linalg.norm(u - plain_u[i]) / torch.linalg.norm(plain_u[i])).item())
             print(f"# {name} load {i}: {st['iters_total']} its, guess residual sum "
                   f"{st['guess_resid_sum']:.3e}", file=sys.stderr, flush=True)
         res[name] = {"value": tot["solves"] / tot["t"], "gmres_iters_per_solve": tot["its"] / tot["solves"],
                      "resid_max": tot["resid"], "guess_resid_mean": tot["guess"] / tot["solves"],
                      "learned_guesses": tot["learned"], "gmres_ms_per_solve": tot["t_gmres"] / tot["solves"],
                      "ms_per_step": 1000.0 * tot["t"] / len(held)}
+        if name != "plain_fp64":
+            res[name]["transient_rel_l2_vs_fp64_max"] = tot["err"]
     cl.close()
     cp.close()
     lf, pf = res["learned_fp32"], res["plain_fp64"]
@@ -583,6 +591,7 @@ def main():
     if args.copy_probe:
         copy_probe()
     d, N, elapsed, st = run_gpu(args, args.store)
+    u_ref = st.pop("u_last")
     solves = st["n_solves"]
     value = solves / elapsed
     ms_step = 1000.0 * elapsed / args.steps
@@ -645,16 +654,20 @@ def main():
         out["roofline"]["frac_of_stream_read_probe"] = mv_gbs / rp
     if args.c64_variant and args.store == "c128":
         _, _, el2, st2 = run_gpu(args, "c64")
+        u2 = st2.pop("u_last")
         out["c64_factors"] = {
             "value": st2["n_solves"] / el2,
             "matvec_GBps": st2["matvec_bytes_total"] / (st2["t_matvec_ms"] / 1000.0) / 1e9,
             "gmres_iters_per_solve": st2["iters_total"] / max(1, st2["n_solves"]),
             "resid_max": st2["resid_max"],
+            "transient_rel_l2_vs_fp64": float(np.linalg.norm(u2 - u_ref) / np.linalg.norm(u_ref)),
         }
     if args.pipeline_variant:
         _, _, el3, st3 = run_gpu(args, args.store, pipeline=1)
+        u3 = st3.pop("u_last")
         out["pipelined"] = {
             "value": st3["n_solves"] / el3,
+            "transient_rel_l2_vs_sequential": float(np.linalg.norm(u3 - u_ref) / np.linalg.norm(u_ref)),
             "matvec_GBps": st3["matvec_bytes_total"] / (st3["t_matvec_ms"] / 1000.0) / 1e9,
             "gmres_iters_per_solve": st3["iters_total"] / max(1, st3["n_solves"]),
         }
