@@ -56,6 +56,9 @@ def parse():
                          "against one transient per load")
     ap.add_argument("--wave", type=int, default=6,
                     help="batch12 workload: problems alive and solved concurrently at once")
+    ap.add_argument("--fp64-reference", action="store_true",
+                    help="batch12 and scene workloads: also solve every problem with complex128 factors "
+                         "(untimed) and report the complex64 results' relative L2 error against them")
     ap.add_argument("--n-loads", type=int, default=8,
                     help="loads workload: loads solved through one frequency loop")
     ap.add_argument("--train-cases", type=int, default=8,
@@ -403,10 +406,10 @@ def batch12_workload(args):
     probs = config_inputs(3, sub=args.sub)["problems"]
     dev = torch.device("cuda:0")
 
-    def make(d, st=None):
+    def make(d, st=None, store=E.STORE_C64):
         c = E.Context(0, stream=None if st is None else st.cuda_stream)
         E.setup_from_inputs(c, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5,
-                                          far_store=E.STORE_C64),
+                                          far_store=store),
                             solver=dict(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF))
         return c
 
@@ -438,10 +441,13 @@ def batch12_workload(args):
     t = time.perf_counter()
     bat_solves = bat_its = 0
     resid = 0.0
+    u_bat = {}
     for w in waves:
         streams = [torch.cuda.Stream() for _ in w]
         ctxs = [make(probs[i], st) for i, st in zip(w, streams)]
-        st = E.batch_solve_transient(ctxs, [out(probs[i]) for i in w], per_launch=16)
+        for i in w:
+            u_bat[i] = out(probs[i])
+        st = E.batch_solve_transient(ctxs, [u_bat[i] for i in w], per_launch=16)
         torch.cuda.synchronize()
         free, total = torch.cuda.mem_get_info()
         for c in ctxs:
@@ -452,6 +458,17 @@ def batch12_workload(args):
         print(f"# wave {[probs[i]['name'] for i in w]}: {st['iters_total']} its; device memory in use "
               f"before closing {(total - free) / 1e9:.0f} GB", file=sys.stderr, flush=True)
     t_bat = time.perf_counter() - t
+    err64 = None
+    if args.fp64_reference:
+        err64 = 0.0
+        for i, d in enumerate(probs):
+            c = make(d, store=E.STORE_C128)
+            ref = out(d)
+            c.solve_transient(ref)
+            c.close()
+            e = (torch.linalg.norm(u_bat[i] - ref) / torch.linalg.norm(ref)).item()
+            err64 = max(err64, e)
+            print(f"# {d['name']}: complex64 transient vs complex128 {e:.2e}", file=sys.stderr, flush=True)
     n_dofs = [3 * len(d["tri"]) for d in probs]
     print(json.dumps({
         "metric": "freq-solves/s, twelve uneven cavities (complex64 factors, 1e-6 residual)",
@@ -464,7 +481,8 @@ def batch12_workload(args):
         "one_at_a_time": {"value": seq_solves / t_seq, "ms": 1000.0 * t_seq,
                           "gmres_iters_per_solve": seq_its / seq_solves},
         "concurrent": {"value": bat_solves / t_bat, "ms": 1000.0 * t_bat,
-                       "gmres_iters_per_solve": bat_its / bat_solves, "resid_max": resid},
+                       "gmres_iters_per_solve": bat_its / bat_solves, "resid_max": resid,
+                       "transient_rel_l2_vs_fp64_max": err64},
         "speedup_concurrent": (bat_solves / t_bat) / (seq_solves / t_seq),
     }), flush=True)
 
@@ -506,6 +524,21 @@ def scene_workload(args):
     el = time.perf_counter() - t
     info = c.info()
     c.close()
+    err64 = None
+    if args.fp64_reference:
+        c = E.Context(0)
+        c.set_mesh(d["xyz"], d["tri"], exterior=True)
+        c.set_material(m["rho"], m["mu"], m["nu"])
+        c.set_time(d["period"], d["n_f"], d["sigma"], d["window"])
+        c.set_load_incident_s([1.0, 0.0, 0.0], [0.0, 0.0, 1.0], 0.5, 13.0)
+        c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-4, far_store=E.STORE_C128)
+        c.set_solver(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF)
+        ref = torch.zeros_like(u)
+        for _ in range(args.warmup + args.steps):  # the same sequence of warm-started passes
+            c.solve_transient(ref)
+        c.close()
+        err64 = (torch.linalg.norm(u - ref) / torch.linalg.norm(ref)).item()
+        print(f"# complex64 transient vs complex128 {err64:.2e}", file=sys.stderr, flush=True)
     n = tot["n_solves"]
     mv_s = tot["t_matvec_ms"] / 1000.0
     print(json.dumps({
@@ -517,6 +550,7 @@ def scene_workload(args):
                    "period": d["period"], "sigma": d["sigma"], "aca_tol": 1e-4, "gmres_tol": 1e-6,
                    "far_blocks": info["n_far"], "near_blocks": info["n_near"]},
         "gmres_iters_per_solve": tot["iters_total"] / n, "resid_max": tot["resid_max"],
+        "transient_rel_l2_vs_fp64": err64,
         "matvec_GBps": tot["matvec_bytes_total"] / mv_s / 1e9 if mv_s > 0 else None,
         "stored_operator_GB": tot["stored_bytes"] / 1e9, "rank_max": tot["rank_max"],
         "phases_ms_per_step": {"assembly_ms": tot["t_assemble_ms"] / args.steps,
