@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--aca-reuse", type=int, choices=[0, 1], default=None,
                     help="start each frequency's ACA from the previous pivots (library default if unset)")
     ap.add_argument("--cpu-rows", type=int, default=48)
-    ap.add_argument("--workload", choices=["cavity", "rod-table1", "learned", "batch12", "scene", "loads"],
+    ap.add_argument("--workload", choices=["cavity", "rod-table1", "learned", "batch12", "scene", "loads", "scene-waves"],
                     default="cavity",
                     help="cavity: the frequency-solve benchmark (default); rod-table1: the "
                          "three damping / extrapolation cases of the paper's Table 1 on its "
@@ -53,7 +53,8 @@ def parse():
                          "concurrently against one at a time; scene: twelve cavities in one "
                          "mesh scattering a plane S-wave (level 3 unless --sub); loads: the "
                          "cavity under --n-loads pressure loads through one frequency loop "
-                         "against one transient per load")
+                         "against one transient per load; scene-waves: the scene under --n-loads "
+                         "incident S-waves of different directions, the same comparison")
     ap.add_argument("--wave", type=int, default=6,
                     help="batch12 workload: problems alive and solved concurrently at once")
     ap.add_argument("--fp64-reference", action="store_true",
@@ -391,6 +392,73 @@ def loads_workload(args):
     }), flush=True)
 
 
+def scene_waves_workload(args):
+    """The twelve-cavity scene (level 3 unless --sub) under --n-loads plane
+    S-waves: seeded random directions with random normal polarisations, the
+    scene's Ricker wavelet; complex64 factors at ACA 1e-4, GMRES 1e-6.  One
+    transient per wave against all waves through one frequency loop, both on
+    one context after a warm-up transient."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    from synth import config_inputs
+
+    sub = 3 if args.sub is None else args.sub
+    d = config_inputs(5, sub=sub)
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(2012)
+    dirs = rng.standard_normal((args.n_loads, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pols = rng.standard_normal((args.n_loads, 3))
+    pols -= (pols * dirs).sum(axis=1, keepdims=True) * dirs
+    pols /= np.linalg.norm(pols, axis=1, keepdims=True)
+    c = E.Context(0)
+    c.set_mesh(d["xyz"], d["tri"], exterior=True)
+    m = d["material"]
+    c.set_material(m["rho"], m["mu"], m["nu"])
+    c.set_time(d["period"], d["n_f"], d["sigma"], d["window"])
+    c.set_load_incident_s([1.0, 0.0, 0.0], [0.0, 0.0, 1.0], 0.5, 13.0)
+    c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-4, far_store=E.STORE_C64)
+    c.set_solver(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF)
+    N, n_f = 3 * len(d["tri"]), d["n_f"]
+    u1 = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
+    c.solve_transient(u1)  # warm-up
+    seq = dict(t=0.0, solves=0, its=0)
+    for l in range(args.n_loads):
+        c.set_load_incident_s(dirs[l], pols[l], 0.5, 13.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = c.solve_transient(u1)
+        torch.cuda.synchronize()
+        seq["t"] += time.perf_counter() - t
+        seq["solves"] += st["n_solves"]
+        seq["its"] += st["iters_total"]
+        print(f"# one at a time, wave {l}: {st['iters_total']} its", file=sys.stderr, flush=True)
+    u = torch.zeros(args.n_loads * n_f * N, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = c.solve_transient_incident_loads(dirs, pols, u)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t
+    c.close()
+    same = (torch.linalg.norm(u[(args.n_loads - 1) * n_f * N:] - u1) / torch.linalg.norm(u1)).item()
+    v, pv = st["n_solves"] / t_multi, seq["solves"] / seq["t"]
+    print(f"# {args.n_loads} waves together: {st['iters_total']} its, {t_multi:.2f} s; one at a time "
+          f"{seq['its']} its, {seq['t']:.2f} s; last wave's transients differ by {same:.1e}",
+          file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "freq-solves/s, twelve-cavity scene under several incident waves (complex64 factors, 1e-6 residual)",
+        "value": v, "unit": "freq-solves/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": 1000.0 * t_multi,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+c64-factors",
+        "data": "synthetic",
+        "config": {"workload": d["name"].replace("sub5", f"sub{sub}") + f" ({args.n_loads} incident waves)",
+                   "n_dof": N, "n_f": n_f, "n_waves": args.n_loads, "aca_tol": 1e-4, "gmres_tol": 1e-6},
+        "together": {"seconds": t_multi, "solves": st["n_solves"], "gmres_iters": st["iters_total"],
+                     "assemble_ms": st["t_assemble_ms"], "gmres_ms": st["t_gmres_ms"]},
+        "one_at_a_time": {"value": pv, "seconds": seq["t"], "solves": seq["solves"], "gmres_iters": seq["its"]},
+        "speedup": v / pv, "last_wave_rel_diff": same,
+    }), flush=True)
+
+
 def batch12_workload(args):
     """Twelve independent cavities (spheres and ellipsoids with semi-axes in
     [0.5, 2], icosphere levels 3-5, seeded pressure amplitudes; N_f = 128,
@@ -621,6 +689,9 @@ def main():
         return
     if args.workload == "loads":
         loads_workload(args)
+        return
+    if args.workload == "scene-waves":
+        scene_waves_workload(args)
         return
     if args.copy_probe:
         copy_probe()

@@ -306,6 +306,22 @@ int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats*
 int ewbem_solve_transient_loads(ewbem_ctx* ctx, int32_t n_loads, const double* loads, int32_t pressure,
                                 double* u, ewbem_z* spec, ewbem_stats* stats);
 
+/* Several incident plane S-waves on one mesh: the scattered field of each
+ * wave of unit direction dirs[3l..3l+2] and polarisation pols[3l..3l+2]
+ * (normalised here; each polarisation normal to its direction), all with
+ * the wavelet of the context's current incident wave
+ * (ewbem_set_load_incident_s), as that call defines the load (Sec. 2.1's
+ * equation for the scattered field).  Every frequency is assembled once for
+ * all waves, as in ewbem_solve_transient_loads; the right-hand sides of up
+ * to four waves share one kernel evaluation per element pair.  dirs, pols:
+ * host, n_loads x 3.  u, spec and the results as for
+ * ewbem_solve_transient_loads: each wave's result is that of
+ * ewbem_solve_transient with that wave, to rounding.  ESTATE without mesh,
+ * time grid and an incident wave; EINVAL for a zero or non-normal
+ * polarisation. */
+int ewbem_solve_transient_incident_loads(ewbem_ctx* ctx, int32_t n_loads, const double* dirs,
+                                         const double* pols, double* u, ewbem_z* spec, ewbem_stats* stats);
+
 /* Several problems at once (one context each, all distinct): up to
  * per_launch of them run concurrently from host threads, each with its
  * whole frequency loop on its own context's stream (contexts created on the

@@ -319,23 +319,34 @@ void ensure_structure(ewbem_ctx* c) {
   c->assembled_k = -1;
 }
 
+// The plane S-wave along unit d polarised along unit q, per element in tree
+// order: the frequency-independent factor g of the scattered-field load
+//   t_sc(s) = s F(s) exp(-s tau) g,  g = (mu / c_s)(q (d.n) + d (q.n))
+// (the negated traction of the plane wave on a surface of normal n), and the
+// arrival delay tau = d.x / c_s at each collocation point.
+void incident_factors(const ewbem_ctx* c, const double* d, const double* q, std::vector<double>& g0,
+                      std::vector<double>& tau) {
+  const HostGeom& g = c->hg;
+  const double cs = std::sqrt(c->mu / c->rho), f = c->mu / cs;
+  g0.assign(3 * (size_t)c->nt, 0.0);
+  tau.assign(c->nt, 0.0);
+  for (int t = 0; t < c->nt; ++t) {
+    const double* n = &g.nrm[3 * (size_t)t];
+    const double dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+    const double qn = q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+    for (int k = 0; k < 3; ++k) g0[3 * (size_t)t + k] = f * (q[k] * dn + d[k] * qn);
+    tau[t] = (d[0] * g.cen[3 * (size_t)t] + d[1] * g.cen[3 * (size_t)t + 1] + d[2] * g.cen[3 * (size_t)t + 2]) / cs;
+  }
+}
+
 std::vector<double> tree_load(ewbem_ctx* c) {
-  // traction per element in tree order; for the incident S-wave, the
-  // frequency-independent factor g of the scattered-field load
-  //   t_sc(s) = s F(s) exp(-s dir.x / c_s) g,  g = (mu / c_s)(pol (dir.n) + dir (pol.n))
-  // (the negated traction of the plane wave on a surface of normal n)
+  // traction per element in tree order; for the incident S-wave, the factor
+  // g of incident_factors
   const HostGeom& g = c->hg;
   std::vector<double> t0(3 * (size_t)c->nt);
   if (c->load_incident) {
-    const double cs = std::sqrt(c->mu / c->rho), f = c->mu / cs;
-    const double* d = c->inc_dir;
-    const double* q = c->inc_pol;
-    for (int t = 0; t < c->nt; ++t) {
-      const double* n = &g.nrm[3 * (size_t)t];
-      const double dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
-      const double qn = q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
-      for (int k = 0; k < 3; ++k) t0[3 * (size_t)t + k] = f * (q[k] * dn + d[k] * qn);
-    }
+    std::vector<double> tau;
+    incident_factors(c, c->inc_dir, c->inc_pol, t0, tau);
     return t0;
   }
   for (int t = 0; t < c->nt; ++t) {
@@ -407,12 +418,10 @@ void ensure_device(ewbem_ctx* c) {
   c->d_t0.upload(t0, st);
   if (c->load_incident) {
     // arrival delay of the plane wave at each collocation point
-    const double cs = std::sqrt(c->mu / c->rho);
-    std::vector<double> tau(c->nt);
-    for (int t = 0; t < c->nt; ++t)
-      tau[t] = (c->inc_dir[0] * g.cen[3 * (size_t)t] + c->inc_dir[1] * g.cen[3 * (size_t)t + 1] +
-                c->inc_dir[2] * g.cen[3 * (size_t)t + 2]) / cs;
+    std::vector<double> g0, tau;
+    incident_factors(c, c->inc_dir, c->inc_pol, g0, tau);
     c->d_tau.upload(tau, st);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // tau is a temporary
   }
   if (!c->bc_caller.empty()) {
     std::vector<int> bct(c->nt);
@@ -1709,6 +1718,7 @@ int frequency_loop(ewbem_ctx* c) {
 // (tree order, N_f/2 + 1 rows of N).
 struct LoadRun {
   DevBuf<double> t0;
+  DevBuf<double> tau;  // incident waves: arrival delay per element
   DevBuf<cd> rhs_part;
   DevBuf<cd> hist_sol;
   DevBuf<cd> b, x, r;
@@ -1726,6 +1736,7 @@ void swap_buf(DevBuf<T>& a, DevBuf<T>& b) {
 // Exchange a load's state with the context's (twice restores it).
 void swap_load(ewbem_ctx* c, LoadRun& L) {
   swap_buf(c->d_t0, L.t0);
+  if (c->load_incident) swap_buf(c->d_tau, L.tau);
   swap_buf(c->d_rhs_part, L.rhs_part);
   swap_buf(c->d_hist_sol, L.hist_sol);
   swap_buf(c->d_b, L.b);
@@ -1773,7 +1784,7 @@ int multi_load_loop(ewbem_ctx* c, std::vector<LoadRun>& loads) {
     EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
     // every load's off-diagonal U t0 for all frequencies, the kernel
     // evaluated once per pair for up to eight loads
-    std::vector<const double*> t0s;
+    std::vector<const double*> t0s, taus;
     std::vector<cd*> parts;
     for (LoadRun& L : loads) {
       L.hist_sol.reserve((size_t)ncap * N);
@@ -1782,9 +1793,11 @@ int multi_load_loop(ewbem_ctx* c, std::vector<LoadRun>& loads) {
       L.r.reserve(N);
       L.rhs_part.reserve((size_t)rhs_split(c->nt) * nk * N);
       t0s.push_back(L.t0.p);
+      taus.push_back(L.tau.p);
       parts.push_back(L.rhs_part.p);
     }
-    launch_rhs_loads(g, c->P, c->sigma, 2.0 * M_PI / c->period, 0, nk, n, t0s.data(), parts.data(), st);
+    launch_rhs_loads(g, c->P, c->sigma, 2.0 * M_PI / c->period, 0, nk, n, t0s.data(),
+                     c->load_incident ? taus.data() : nullptr, parts.data(), st);
     EWBEM_HIP_CHECK(hipGetLastError());
     c->boff_k0 = 0;
     c->boff_nk = nk;
@@ -1870,6 +1883,52 @@ std::vector<LoadRun> make_load_runs(ewbem_ctx* c, int n, const double* loads, bo
   c->load_caller = saved;
   c->load_is_pressure = saved_p;
   return runs;
+}
+
+// One LoadRun per incident plane S-wave (unit direction dirs[3i], unit
+// polarisation pols[3i], normal to each other): its factor g and arrival
+// delays, spectra at spec_base.
+std::vector<LoadRun> make_incident_runs(ewbem_ctx* c, int n, const double* dirs, const double* pols,
+                                        cd* spec_base) {
+  const long long N = 3LL * c->nt;
+  const int nk = c->n_f / 2 + 1;
+  std::vector<LoadRun> runs(n);
+  std::vector<double> g0, tau;
+  for (int i = 0; i < n; ++i) {
+    incident_factors(c, dirs + 3 * i, pols + 3 * i, g0, tau);
+    runs[i].t0.upload(g0, c->stream);
+    runs[i].tau.upload(tau, c->stream);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));  // the host vectors are reused
+    runs[i].spec = spec_base + (size_t)i * nk * N;
+  }
+  return runs;
+}
+
+void begin_stats(ewbem_ctx* c);
+void end_stats(ewbem_ctx* c, ewbem_stats* out);
+
+// The loads' frequency loop, then each load's inverse transform into u (and
+// its spectrum in caller order into spec, if given); sp holds the spectra.
+int run_loads(ewbem_ctx* ctx, std::vector<LoadRun>& runs, const cd* sp, double* u, ewbem_z* spec,
+              ewbem_stats* stats) {
+  const long long N = 3LL * ctx->nt;
+  const int nk = ctx->n_f / 2 + 1;
+  const int rc = multi_load_loop(ctx, runs);
+  const auto tp = Clock::now();
+  for (size_t l = 0; l < runs.size(); ++l) {
+    const cd* sl = sp + l * nk * N;
+    launch_mft_inverse(sl, N, ctx->n_f, ctx->period, ctx->sigma, ctx->window, ctx->d_perm.p,
+                       u + l * ctx->n_f * N, ctx->stream);
+    if (spec)
+      for (int k = 0; k < nk; ++k)
+        launch_permute(sl + (size_t)k * N, ctx->d_perm.p, ctx->nt, 0, (cd*)spec + (l * nk + k) * N, ctx->stream);
+  }
+  EWBEM_HIP_CHECK(hipGetLastError());
+  EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  ctx->acc.t_post_ms += ms_since(tp);
+  end_stats(ctx, stats);
+  if (rc != EWBEM_OK) ctx->err = "GMRES did not reach the tolerance within maxit at some frequency";
+  return rc;
 }
 
 int guard(ewbem_ctx* ctx, const std::function<int()>& f) {
@@ -2612,28 +2671,44 @@ int ewbem_solve_transient_loads(ewbem_ctx* ctx, int32_t n_loads, const double* l
     if (!finite_all(loads, per * n_loads)) fail(EWBEM_EINVAL, "solve_transient_loads: non-finite load values");
     begin_stats(ctx);
     ensure_device(ctx);
-    const long long N = 3LL * ctx->nt;
-    const int nk = ctx->n_f / 2 + 1;
     DevBuf<cd> sp;
-    sp.reserve((size_t)n_loads * nk * N);
+    sp.reserve((size_t)n_loads * (ctx->n_f / 2 + 1) * 3 * ctx->nt);
     std::vector<LoadRun> runs = make_load_runs(ctx, n_loads, loads, pressure == 1, sp.p);
-    const int rc = multi_load_loop(ctx, runs);
-    const auto tp = Clock::now();
+    return run_loads(ctx, runs, sp.p, u, spec, stats);
+  });
+}
+
+int ewbem_solve_transient_incident_loads(ewbem_ctx* ctx, int32_t n_loads, const double* dirs, const double* pols,
+                                         double* u, ewbem_z* spec, ewbem_stats* stats) {
+  return guard(ctx, [&] {
+    if (n_loads < 1 || !dirs || !pols || !u)
+      fail(EWBEM_EINVAL, "solve_transient_incident_loads: need n_loads >= 1, directions, polarisations and u");
+    if (!ctx->have_mesh || !ctx->have_time || !ctx->have_load || !ctx->load_incident)
+      fail(EWBEM_ESTATE, "solve_transient_incident_loads: set the mesh, time grid and an incident wave (its "
+                         "wavelet is used) first");
+    if (!finite_all(dirs, 3 * (size_t)n_loads) || !finite_all(pols, 3 * (size_t)n_loads))
+      fail(EWBEM_EINVAL, "solve_transient_incident_loads: non-finite direction or polarisation");
+    std::vector<double> dd(3 * (size_t)n_loads), pp(3 * (size_t)n_loads);
     for (int l = 0; l < n_loads; ++l) {
-      const cd* sl = sp.p + (size_t)l * nk * N;
-      launch_mft_inverse(sl, N, ctx->n_f, ctx->period, ctx->sigma, ctx->window, ctx->d_perm.p,
-                         u + (size_t)l * ctx->n_f * N, ctx->stream);
-      if (spec)
-        for (int k = 0; k < nk; ++k)
-          launch_permute(sl + (size_t)k * N, ctx->d_perm.p, ctx->nt, 0, (cd*)spec + ((size_t)l * nk + k) * N,
-                         ctx->stream);
+      const double* d = dirs + 3 * l;
+      const double* q = pols + 3 * l;
+      const double nd = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double np = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+      if (!(nd > 0) || !(np > 0)) fail(EWBEM_EINVAL, "incident wave: zero direction or polarisation");
+      double dp = 0;
+      for (int k = 0; k < 3; ++k) {
+        dd[3 * l + k] = d[k] / nd;
+        pp[3 * l + k] = q[k] / np;
+        dp += dd[3 * l + k] * pp[3 * l + k];
+      }
+      if (std::fabs(dp) > 1e-9) fail(EWBEM_EINVAL, "incident S-wave: polarisation must be normal to the direction");
     }
-    EWBEM_HIP_CHECK(hipGetLastError());
-    EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    ctx->acc.t_post_ms += ms_since(tp);
-    end_stats(ctx, stats);
-    if (rc != EWBEM_OK) ctx->err = "GMRES did not reach the tolerance within maxit at some frequency";
-    return rc;
+    begin_stats(ctx);
+    ensure_device(ctx);
+    DevBuf<cd> sp;
+    sp.reserve((size_t)n_loads * (ctx->n_f / 2 + 1) * 3 * ctx->nt);
+    std::vector<LoadRun> runs = make_incident_runs(ctx, n_loads, dd.data(), pp.data(), sp.p);
+    return run_loads(ctx, runs, sp.p, u, spec, stats);
   });
 }
 

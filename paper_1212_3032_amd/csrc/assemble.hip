@@ -383,16 +383,17 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
   }
 }
 
-// The same sums for several loads t0_l on one mesh (traction or pressure
-// loads, no incident wave): one workgroup column per frequency, every pair's
-// kernel evaluated once and applied to all NL loads.  With one frequency per
-// pass the phases exp(-i Im(s) r / c) are evaluated directly (no rotation
-// recurrence to share), so a load's partials agree with k_rhs_multi's to
-// rounding.
-template <int NL>
+// The same sums for several loads t0_l on one mesh: one workgroup column
+// per frequency, every pair's kernel evaluated once and applied to all NL
+// loads.  With one frequency per pass the phases exp(-i Im(s) r / c) are
+// evaluated directly (no rotation recurrence to share), so a load's
+// partials agree with k_rhs_multi's to rounding.  INC: incident waves, each
+// load's source element weighted by its own exp(-s_k tau_l), as in
+// k_rhs_multi<true>.
+template <int NL, bool INC>
 __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double sigma, double dw, int k0,
                                                    int nk, RhsLoadSet L) {
-  __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[NL * RHS_TILE * 3];
+  __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[NL * RHS_TILE * 3], stau[INC ? NL * RHS_TILE : 1];
   const int ne = g.ne;
   const int k = k0 + blockIdx.y;
   const int split = blockIdx.z, nsplit = gridDim.z;
@@ -417,6 +418,10 @@ __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double 
 #pragma unroll
     for (int l = 0; l < NL; ++l)
       for (int i = threadIdx.x; i < nc * 3; i += blockDim.x) stt[l * RHS_TILE * 3 + i] = L.t0[l][(size_t)c0 * 3 + i];
+    if (INC)
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        for (int i = threadIdx.x; i < nc; i += blockDim.x) stau[l * RHS_TILE + i] = L.tau[l][c0 + i];
     __syncthreads();
     if (!act) continue;
     for (int b = 0; b < nc; ++b) {
@@ -427,6 +432,18 @@ __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double 
         tb[l][0] = stt[l * RHS_TILE * 3 + 3 * b];
         tb[l][1] = stt[l * RHS_TILE * 3 + 3 * b + 1];
         tb[l][2] = stt[l * RHS_TILE * 3 + 3 * b + 2];
+      }
+      // incident waves: the source's load at s_k, exp(-s_k tau_l)
+      cd sp[INC ? NL : 1];
+      if (INC) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          double sn, cs;
+          const double ta = stau[l * RHS_TILE + b];
+          sincos(k * dw * ta, &sn, &cs);
+          const double m = exp(-sigma * ta);
+          sp[l] = cd{m * cs, -m * sn};
+        }
       }
       for (int qq = 0; qq < 7; ++qq) {
         const double* y = sq + 21 * b + 3 * qq;
@@ -464,10 +481,14 @@ __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double 
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
           const double ht = h0 * tb[l][0] + h1 * tb[l][1] + h2 * tb[l][2];
-          const cd gg = rpsi * (sc * ht);
-          acc[l][0] += f * tb[l][0] - gg * h0;
-          acc[l][1] += f * tb[l][1] - gg * h1;
-          acc[l][2] += f * tb[l][2] - gg * h2;
+          cd fl = f, gg = rpsi * (sc * ht);
+          if (INC) {
+            fl = fl * sp[l];
+            gg = gg * sp[l];
+          }
+          acc[l][0] += fl * tb[l][0] - gg * h0;
+          acc[l][1] += fl * tb[l][1] - gg * h1;
+          acc[l][2] += fl * tb[l][2] - gg * h2;
         }
       }
     }
@@ -482,11 +503,11 @@ __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double 
   }
 }
 
-template <int NL>
+template <int NL, bool INC>
 void rhs_loads_nl(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk, const RhsLoadSet& L,
                   hipStream_t st) {
   dim3 grid((g.ne + 255) / 256, nk, rhs_split(g.ne));
-  hipLaunchKernelGGL(k_rhs_loads<NL>, grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, L);
+  hipLaunchKernelGGL((k_rhs_loads<NL, INC>), grid, dim3(256), 0, st, g, P, sigma, dw, k0, nk, L);
 }
 
 // b[d] = P_k (sum over source ranges of the partials of frequency index kk
@@ -528,24 +549,35 @@ void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double d
 }
 
 void launch_rhs_loads(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk, int n_loads,
-                      const double* const* t0, cd* const* partial, hipStream_t st) {
+                      const double* const* t0, const double* const* tau, cd* const* partial, hipStream_t st) {
   if (nk <= 0) return;
-  for (int l0 = 0; l0 < n_loads; l0 += RHS_NL) {
-    const int n = std::min(RHS_NL, n_loads - l0);
+  const int per = tau ? RHS_NL_INC : RHS_NL;
+  for (int l0 = 0; l0 < n_loads; l0 += per) {
+    const int n = std::min(per, n_loads - l0);
     RhsLoadSet L{};
     for (int i = 0; i < n; ++i) {
       L.t0[i] = t0[l0 + i];
+      L.tau[i] = tau ? tau[l0 + i] : nullptr;
       L.part[i] = partial[l0 + i];
     }
+    if (tau) {
+      switch (n) {
+        case 1: rhs_loads_nl<1, true>(g, P, sigma, dw, k0, nk, L, st); break;
+        case 2: rhs_loads_nl<2, true>(g, P, sigma, dw, k0, nk, L, st); break;
+        case 3: rhs_loads_nl<3, true>(g, P, sigma, dw, k0, nk, L, st); break;
+        default: rhs_loads_nl<4, true>(g, P, sigma, dw, k0, nk, L, st); break;
+      }
+      continue;
+    }
     switch (n) {
-      case 1: rhs_loads_nl<1>(g, P, sigma, dw, k0, nk, L, st); break;
-      case 2: rhs_loads_nl<2>(g, P, sigma, dw, k0, nk, L, st); break;
-      case 3: rhs_loads_nl<3>(g, P, sigma, dw, k0, nk, L, st); break;
-      case 4: rhs_loads_nl<4>(g, P, sigma, dw, k0, nk, L, st); break;
-      case 5: rhs_loads_nl<5>(g, P, sigma, dw, k0, nk, L, st); break;
-      case 6: rhs_loads_nl<6>(g, P, sigma, dw, k0, nk, L, st); break;
-      case 7: rhs_loads_nl<7>(g, P, sigma, dw, k0, nk, L, st); break;
-      default: rhs_loads_nl<8>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 1: rhs_loads_nl<1, false>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 2: rhs_loads_nl<2, false>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 3: rhs_loads_nl<3, false>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 4: rhs_loads_nl<4, false>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 5: rhs_loads_nl<5, false>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 6: rhs_loads_nl<6, false>(g, P, sigma, dw, k0, nk, L, st); break;
+      case 7: rhs_loads_nl<7, false>(g, P, sigma, dw, k0, nk, L, st); break;
+      default: rhs_loads_nl<8, false>(g, P, sigma, dw, k0, nk, L, st); break;
     }
   }
 }

@@ -41,16 +41,20 @@ void launch_dense_self(const cd* selfT, const cd* selfU, const int* perm, int ne
 int rhs_split(int ne);
 void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk,
                       const double* t0, const double* tau, cd* partial, hipStream_t st);
-// The same partials for n_loads loads (t0[l] and partial[l] per load, no
-// incident wave), each pair's kernel evaluated once for up to RHS_NL loads;
-// every load's partials agree with launch_rhs_multi's for it to rounding.
+// The same partials for n_loads loads (t0[l] and partial[l] per load; with
+// tau, tau[l] per load: incident waves, as for launch_rhs_multi), each
+// pair's kernel evaluated once for up to RHS_NL loads (RHS_NL_INC with
+// tau); every load's partials agree with launch_rhs_multi's for it to
+// rounding.
 constexpr int RHS_NL = 8;
+constexpr int RHS_NL_INC = 4;
 struct RhsLoadSet {
   const double* t0[RHS_NL];
+  const double* tau[RHS_NL];
   cd* part[RHS_NL];
 };
 void launch_rhs_loads(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk, int n_loads,
-                      const double* const* t0, cd* const* partial, hipStream_t st);
+                      const double* const* t0, const double* const* tau, cd* const* partial, hipStream_t st);
 void launch_rhs_finish(const cd* partial, int nk, int kk, int ne, const cd* selfU, const double* t0,
                        const double* tau, cd s_k, const cd* phat_k, cd* b, hipStream_t st);
 void launch_kernel_eval(const KParams& P, long long n, const double* x, const double* y,

@@ -29,6 +29,7 @@ EXPORTED = [
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
     "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_solve_transient_loads",
+    "ewbem_solve_transient_incident_loads",
     "ewbem_batch_solve_transient",
     "ewbem_mft_inverse", "ewbem_default_train_opts", "ewbem_guess_train", "ewbem_guess_save",
     "ewbem_guess_load", "ewbem_guess_basis", "ewbem_mlp_eval", "ewbem_mlp_train",
@@ -126,6 +127,7 @@ def lib():
         "ewbem_solve_frequency": (C.c_int, [P, I32, P, P, C.POINTER(Stats)]),
         "ewbem_solve_transient": (C.c_int, [P, P, P, C.POINTER(Stats)]),
         "ewbem_solve_transient_loads": (C.c_int, [P, I32, P, I32, P, P, C.POINTER(Stats)]),
+        "ewbem_solve_transient_incident_loads": (C.c_int, [P, I32, P, P, P, P, C.POINTER(Stats)]),
         "ewbem_batch_solve_transient": (C.c_int, [P, I32, P, C.POINTER(Stats), I32]),
         "ewbem_mft_inverse": (C.c_int, [P, P, P]),
         "ewbem_default_train_opts": (None, [C.POINTER(TrainOpts)]),
@@ -371,6 +373,25 @@ class Context:
         st = Stats()
         rc = self._L.ewbem_solve_transient_loads(self.h, n, pa, 1 if pressures else 0,
                                                  _dev_ptr(u, "torch.float64", n * self.n_f * N), ps, C.byref(st))
+        if not (allow_noconv and rc == ENOCONV):
+            self._check(rc)
+        return st.as_dict()
+
+    def solve_transient_incident_loads(self, dirs, pols, u, spec=None, allow_noconv=False):
+        """Several incident plane S-waves (n x 3 directions and polarisations)
+        with the current incident wave's wavelet, through one frequency
+        loop: u a device float64 tensor of n x n_f x N."""
+        N = 3 * self.nt
+        a, pa = _host(dirs, np.float64)
+        b, pb = _host(pols, np.float64)
+        if a.size % 3 != 0 or a.size == 0 or b.size != a.size:
+            raise ValueError("dirs and pols must both hold n x 3 values")
+        n = a.size // 3
+        ps = _dev_ptr(spec, "torch.complex128", n * (self.n_f // 2 + 1) * N) if spec is not None else None
+        st = Stats()
+        rc = self._L.ewbem_solve_transient_incident_loads(self.h, n, pa, pb,
+                                                          _dev_ptr(u, "torch.float64", n * self.n_f * N), ps,
+                                                          C.byref(st))
         if not (allow_noconv and rc == ENOCONV):
             self._check(rc)
         return st.as_dict()

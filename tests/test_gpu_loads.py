@@ -194,3 +194,99 @@ def test_loads_match_oracle():
         e = _rel(U[l].ravel(), ref["u"].ravel())
         _say(f"load {l}: relative L2 error against the oracle {e:.2e}")
         assert e < 1e-6
+
+
+def _waves(rng, n):
+    """n random unit directions, each with a random unit polarisation normal
+    to it."""
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    q = rng.standard_normal((n, 3))
+    q -= (q * d).sum(axis=1, keepdims=True) * d
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return d, q
+
+
+def _inc_ctx(E, xyz, tri, kind, d, q):
+    c = E.Context(0)
+    c.set_mesh(xyz, tri, exterior=True)
+    c.set_material(1.0, 1.0, 0.25)
+    c.set_time(PERIOD, NF, 6.0 / PERIOD, 1)
+    c.set_load_incident_s(d, q, 0.5, 2.0)
+    if kind == "hmat":
+        c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-6, autotune=0)
+    else:
+        c.set_operator(kind=E.OP_DENSE, autotune=0)
+    c.set_solver(tol=1e-8, guess=E.GUESS_SEM)
+    return c
+
+
+@pytest.mark.parametrize("kind,sub,n_waves", [("hmat", 3, 5), ("dense", 2, 3)])
+def test_incident_loads_equal_lone_transients(kind, sub, n_waves):
+    """Several incident plane S-waves (random directions and polarisations,
+    the Ricker wavelet of the context's own wave) through one frequency
+    loop: each wave's transient and spectrum as a fresh context's lone solve
+    of that wave, to rounding (1e-10 relative), with the same iteration
+    counts to 1%.  Five waves give right-hand-side passes of four and one."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    dev = torch.device("cuda:0")
+    xyz, tri = icosphere(sub)
+    N = 3 * len(tri)
+    nk = NF // 2 + 1
+    dirs, pols = _waves(np.random.default_rng(400 + sub), n_waves + 1)
+    lone_u, lone_s, its = [], [], []
+    for l in range(n_waves):
+        c = _inc_ctx(E, xyz, tri, kind, dirs[l], pols[l])
+        u = torch.zeros(NF * N, dtype=torch.float64, device=dev)
+        s = torch.zeros(nk * N, dtype=torch.complex128, device=dev)
+        its.append(c.solve_transient(u, s)["iters_total"])
+        lone_u.append(u.cpu().numpy())
+        lone_s.append(s.cpu().numpy())
+        c.close()
+    c = _inc_ctx(E, xyz, tri, kind, dirs[-1], pols[-1])  # the context's own wave is another one
+    u = torch.zeros(n_waves * NF * N, dtype=torch.float64, device=dev)
+    s = torch.zeros(n_waves * nk * N, dtype=torch.complex128, device=dev)
+    st = c.solve_transient_incident_loads(dirs[:n_waves], pols[:n_waves], u, s)
+    own = torch.zeros(NF * N, dtype=torch.float64, device=dev)
+    c.solve_transient(own)
+    c.close()
+    ref = _inc_ctx(E, xyz, tri, kind, dirs[-1], pols[-1])
+    own_ref = torch.zeros(NF * N, dtype=torch.float64, device=dev)
+    ref.solve_transient(own_ref)
+    ref.close()
+    U = u.cpu().numpy().reshape(n_waves, -1)
+    S = s.cpu().numpy().reshape(n_waves, -1)
+    eu = max(_rel(U[l], lone_u[l]) for l in range(n_waves))
+    es = max(_rel(S[l], lone_s[l]) for l in range(n_waves))
+    eo = (torch.linalg.norm(own - own_ref) / torch.linalg.norm(own_ref)).item()
+    _say(f"{kind}, {n_waves} incident waves, sub {sub}: lone iterations {its} ({sum(its)}), together "
+         f"{st['iters_total']}; largest difference: transients {eu:.1e}, spectra {es:.1e}; own wave after {eo:.1e}")
+    assert st["n_solves"] == n_waves * nk
+    assert abs(st["iters_total"] - sum(its)) <= 0.01 * sum(its)
+    assert eu < 1e-10 and es < 1e-10
+    assert eo < 1e-5
+
+
+def test_incident_loads_match_oracle():
+    """Two incident waves on the level-1 cavity (dense, GMRES tol 1e-8)
+    against the oracle's scattered-field transient of each (dense LU per
+    frequency, direct inverse DFT): within the FP64 bar of 1e-6."""
+    import torch
+    from oracle import solve as osolve
+    from paper_1212_3032_amd import ewbem as E
+    from synth import ricker_history
+    xyz, tri = icosphere(1)
+    N = 3 * len(tri)
+    dirs, pols = _waves(np.random.default_rng(9), 2)
+    c = _inc_ctx(E, xyz, tri, "dense", dirs[0], pols[0])
+    u = torch.zeros(2 * NF * N, dtype=torch.float64, device="cuda:0")
+    c.solve_transient_incident_loads(dirs, pols, u)
+    c.close()
+    U = u.cpu().numpy().reshape(2, NF, N)
+    for l in range(2):
+        ref = osolve.transient_incident_s(xyz, tri, dict(rho=1.0, mu=1.0, nu=0.25), PERIOD, NF, 6.0 / PERIOD, 1,
+                                          dirs[l], pols[l], ricker_history(NF, PERIOD, 0.5, 2.0))
+        e = _rel(U[l].ravel(), ref["u"].ravel())
+        _say(f"incident wave {l}: relative L2 error against the oracle {e:.2e}")
+        assert e < 1e-6

@@ -127,6 +127,13 @@ def test_gpu_calls_refused_on_host_context():
     assert L.ewbem_solve_transient_loads(c.h, 0, pp, 1, None, None, None) == ewbem.EINVAL
     assert L.ewbem_solve_transient_loads(c.h, 1, pp, 1, None, None, None) == ewbem.EINVAL
     assert L.ewbem_solve_transient_loads(c.h, 1, pp, 2, None, None, None) == ewbem.EINVAL
+    # the incident-wave entry: arguments, then the context's load kind
+    dq = np.array([1.0, 0.0, 0.0, 0.0, 0.0, 1.0])
+    pd = dq.ctypes.data_as(ctypes.c_void_p)
+    assert L.ewbem_solve_transient_incident_loads(c.h, 0, pd, pd, None, None, None) == ewbem.EINVAL
+    assert L.ewbem_solve_transient_incident_loads(c.h, 1, pd, pd, None, None, None) == ewbem.EINVAL
+    u_fake = ctypes.c_void_p(16)  # never touched: the pressure load is refused first
+    assert L.ewbem_solve_transient_incident_loads(c.h, 1, pd, pd, u_fake, None, None) == ewbem.ESTATE
 
 
 def _model_blob(n_dof, r, dims, rng, magic=b"EWBGUESS", version=1):
