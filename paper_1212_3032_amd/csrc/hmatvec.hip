@@ -142,14 +142,16 @@ __device__ __forceinline__ cd panel_load(__amdgpu_buffer_rsrc_t rs, unsigned off
   }
 }
 
-// acc[q] += sum_c A[c, r] src[c + q lds] over the columns c = g, g + G, ...
-// of a column-major panel (ld rows; its span below 4 GiB, checked on the
-// host).  Four columns per step; the next step's four entries are loaded
+// acc[q] += sum_c A[c, r] x(c, q) over the columns c = g, g + G, ... of a
+// column-major panel (ld rows; its span below 4 GiB, checked on the host),
+// with x(c, q) = src[c + q lds], or, with XL, src[c NR + q] (a slice staged
+// in LDS).  Four columns per step; the next step's four entries are loaded
 // before this step's products, so their latency overlaps the arithmetic
 // (the products are summed in column order either way).
-template <typename TS, int NR>
+template <typename TS, int NR, bool XL = false>
 __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __restrict__ src, long long lds,
                                           int ld, int ncols, int r, int g, int G, cd (&acc)[NR]) {
+  auto xv = [&](int c, int q) -> cd { return XL ? src[c * NR + q] : src[c + q * lds]; };
   const unsigned span = (unsigned)(((size_t)(ncols - 1) * ld + ld) * sizeof(TS));
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)A, 0, span, 0x00020000);
   const unsigned es = sizeof(TS);
@@ -169,11 +171,10 @@ __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __
     for (int i = 0; i < 4; ++i) nxt[i] = panel_load<TS>(rs, offn + i * stride);
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const cd* sq = src + q * lds;
-      acc[q] += cur[0] * sq[c];
-      acc[q] += cur[1] * sq[c + G];
-      acc[q] += cur[2] * sq[c + 2 * G];
-      acc[q] += cur[3] * sq[c + 3 * G];
+      acc[q] += cur[0] * xv(c, q);
+      acc[q] += cur[1] * xv(c + G, q);
+      acc[q] += cur[2] * xv(c + 2 * G, q);
+      acc[q] += cur[3] * xv(c + 3 * G, q);
     }
     c = cn;
     off = offn;
@@ -189,9 +190,14 @@ __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __
   for (; c < ncols; c += G, off += stride) {
     const cd a0 = panel_load<TS>(rs, off);
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] += a0 * src[c + q * lds];
+    for (int q = 0; q < NR; ++q) acc[q] += a0 * xv(c, q);
   }
 }
+
+// Columns of x staged in LDS per pass, for four or more right-hand sides
+// (their x loads would otherwise be NR scalar loads per column, which miss
+// the small scalar cache when many waves read different segments).
+constexpr int HMV_XCH = 64;
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_hmv(const RowTask* __restrict__ tasks, const Seg* __restrict__ segs,
@@ -208,7 +214,34 @@ __global__ __launch_bounds__(256) void k_hmv(const RowTask* __restrict__ tasks, 
   cd acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = mk(0.0);
-  if (g < G && r < T.rows) {
+  const bool active = g < G && r < T.rows;
+  if constexpr (NR >= 4) {
+    // x in chunks of HMV_XCH columns through LDS; every thread takes part in
+    // the staging and reaches every barrier (segments and chunks are the
+    // same for the whole workgroup)
+    __shared__ cd xs[HMV_XCH * NR];
+    for (int s = T.s0; s < T.s1; ++s) {
+      const Seg S = segs[s];
+      const bool fz = (S.flags & SEG_FROM_Z) != 0;
+      const cd* src = (fz ? z : x) + S.src;
+      const long long lds = fz ? ldz : ldx;
+      for (int c0 = 0; c0 < S.ncols; c0 += HMV_XCH) {
+        const int nch = min(HMV_XCH, S.ncols - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nch * NR; i += blockDim.x) {
+          const int q = i / nch, cc = i - q * nch;
+          xs[cc * NR + q] = src[c0 + cc + q * lds];
+        }
+        __syncthreads();
+        if (active) {
+          if (S.flags & SEG_C64)
+            panel_dot<cf, NR, true>((const cf*)S.A + (size_t)c0 * S.ld, xs, 0, S.ld, nch, r, g, G, acc);
+          else
+            panel_dot<cd, NR, true>((const cd*)S.A + (size_t)c0 * S.ld, xs, 0, S.ld, nch, r, g, G, acc);
+        }
+      }
+    }
+  } else if (active) {
     for (int s = T.s0; s < T.s1; ++s) {
       const Seg S = segs[s];
       const bool fz = (S.flags & SEG_FROM_Z) != 0;
