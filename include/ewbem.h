@@ -290,19 +290,19 @@ int ewbem_solve_transient(ewbem_ctx* ctx, double* u, ewbem_z* spec, ewbem_stats*
  * and serve all loads, each with its own right-hand side, extrapolation
  * history and GMRES; the right-hand sides of up to eight loads share one
  * kernel evaluation per element pair, and the loads' GMRES run in lock-step
- * groups of up to eight whose matvecs read the operator once for the group.  Each
- * load's result is that of ewbem_solve_transient with that load on the same
- * operators, to rounding.  Memory: per load 16 (N_f/2+1) N bytes of
- * off-diagonal sums (times 4 from 4,096 elements on), the extrapolation
- * history and three vectors; per group eight Krylov bases of restart + 1
- * vectors.  loads: host,
- * n_loads x nt x 3 tractions (pressure 0) or n_loads x nt pressures
- * (pressure 1), caller order.  u: device, n_loads x n_f x N doubles (load-
- * major, each as in ewbem_solve_transient); spec: device, n_loads x
- * (N_f/2+1) x N complex, or NULL.  The learned guess is not used here (the
- * extrapolation alone).  The context's own load is unchanged.  ESTATE
- * without mesh, time grid and a traction or pressure load; ENOCONV as for
- * ewbem_solve_transient. */
+ * groups of up to eight whose matvecs read the operator once for the
+ * group.  Each load's result is that of ewbem_solve_transient with that load
+ * on the same operators, to rounding.
+ * loads: host, n_loads x nt x 3 tractions (pressure 0) or n_loads x nt
+ * pressures (pressure 1), caller order.  u: device, n_loads x n_f x N
+ * doubles (load-major, each as in ewbem_solve_transient); spec: device,
+ * n_loads x (N_f/2+1) x N complex, or NULL.
+ * Memory: per load 16 (N_f/2+1) N bytes of off-diagonal sums (times 4 from
+ * 4,096 elements on), the extrapolation history and three vectors; per
+ * group up to eight Krylov bases of restart + 1 vectors.
+ * The learned guess is not used here (the extrapolation alone).  The
+ * context's own load is unchanged.  ESTATE without mesh, time grid and a
+ * traction or pressure load; ENOCONV as for ewbem_solve_transient. */
 int ewbem_solve_transient_loads(ewbem_ctx* ctx, int32_t n_loads, const double* loads, int32_t pressure,
                                 double* u, ewbem_z* spec, ewbem_stats* stats);
 
