@@ -138,6 +138,10 @@ typedef struct {
                               squared norm inside the reduced basis */
   double train_loss_first; /* ewbem_guess_train: mean squared error of the network on */
   double train_loss_last;  /*   its samples before the first and after the last step */
+  int64_t aca_core_blocks[5]; /* warm starts by the size class of the core eliminated (complex
+                                 entries of A(I, J), held in LDS unless stated): [0] at most
+                                 2,304, [1] 4,480, [2] 8,960, [3] larger or over 128 rows
+                                 (global memory), [4] at most 64 rows and 1,024 entries */
 } ewbem_stats;
 
 /* Training of the learned initial guess (ewbem_guess_train). */
@@ -235,7 +239,22 @@ int ewbem_set_load_mixed(ewbem_ctx* ctx, const int32_t* bc, const double* values
 int ewbem_set_load_incident_s(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
                               double t0);
 
+/* The fast operator for A_k (Sec. 4.1 accelerates the matvec with a fast
+ * method and names hierarchical matrices as an alternative to its
+ * precorrected FFT; this library builds the hierarchical matrix: cluster
+ * tree, admissibility min(diam) <= eta_adm dist, ACA far blocks, dense near
+ * blocks).  opts (host) is copied (ewbem_default_op_opts gives the
+ * defaults).  EINVAL for NULL or a field out of its documented range (the
+ * context is then unchanged).  The tree, partition and device state are
+ * rebuilt at the next assembly. */
 int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* opts);
+/* The iterative solver (Sec. 5: GMRES with a block-diagonal
+ * preconditioner, stopped at a relative residual; Sec. 4.2: the initial
+ * guess by extrapolation from the previous frequencies' solutions, eqs.
+ * a0, lsem, a0-solution).  opts (host) is copied
+ * (ewbem_default_solver_opts gives the defaults).  EINVAL for NULL or a
+ * field out of its documented range (the context is then unchanged).  The
+ * solver's device buffers are resized at the next solve. */
 int ewbem_set_solver(ewbem_ctx* ctx, const ewbem_solver_opts* opts);
 
 /* Sizes of the discretisation, cluster tree and block partition (host). */
@@ -322,7 +341,9 @@ int ewbem_solve_transient_loads(ewbem_ctx* ctx, int32_t n_loads, const double* l
 int ewbem_solve_transient_incident_loads(ewbem_ctx* ctx, int32_t n_loads, const double* dirs,
                                          const double* pols, double* u, ewbem_z* spec, ewbem_stats* stats);
 
-/* Several problems at once (one context each, all distinct): up to
+/* An addition to the method (the paper solves one problem at a time; each
+ * problem's own path is Sec. 2.2-4 as in ewbem_solve_transient).
+ * Several problems at once (one context each, all distinct): up to
  * per_launch of them run concurrently from host threads, each with its
  * whole frequency loop on its own context's stream (contexts created on the
  * same stream serialise).  u_out[i] (device, n_f x 3 nt of context i) as in

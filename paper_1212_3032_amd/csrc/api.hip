@@ -531,6 +531,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     tv += ntv;
   }
   const int nw = (int)wb.size();
+  int n_lu_count[5] = {0, 0, 0, 0, 0};
   if (er > INT32_MAX / 2 || ec > INT32_MAX / 2 || tu > INT32_MAX / 2 || tv > INT32_MAX / 2 || pqn > INT32_MAX / 2)
     fail(EWBEM_EINVAL, "warm start larger than its index range");
   AcaWork W0{c->d_far.p, c->d_acast.p, c->d_acaplan.p, c->d_used.p, nullptr, nullptr, c->d_plist.p, c->d_nlist.p};
@@ -577,6 +578,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
         }
       }
     c->d_wslu.upload(lu_list, st);
+    for (int cls = 0; cls < 5; ++cls) n_lu_count[cls] = n_lu[cls];
     WsArgs A{c->d_wsb.p, nw, c->d_wsoff.p, c->d_wsoff.p + (nw + 1), c->d_wsoff.p + 2 * (nw + 1),
              c->d_wsoff.p + 3 * (nw + 1), (int)er, (int)ec, (int)tu, (int)tv, c->d_cross.p, c->d_wspq.p,
              c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p, {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4]}};
@@ -585,6 +587,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
   if (count_starts) {
     c->acc.aca_warm_blocks += nw;
     c->acc.aca_cold_blocks += (long long)cold.size();
+    for (int cls = 0; cls < 5; ++cls) c->acc.aca_core_blocks[cls] += n_lu_count[cls];
   }
   // the active list: every block still ACA_ACTIVE after its start
   EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, 0, 1, st));
@@ -2646,6 +2649,7 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
       a.matvecs_timed += b.matvecs_timed;
       a.aca_warm_blocks += b.aca_warm_blocks;
       a.aca_cold_blocks += b.aca_cold_blocks;
+      for (int cls = 0; cls < 5; ++cls) a.aca_core_blocks[cls] += b.aca_core_blocks[cls];
       a.guess_learned += b.guess_learned;
     }
     *stats = a;

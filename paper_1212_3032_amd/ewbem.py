@@ -64,10 +64,12 @@ class Stats(C.Structure):
                 ("matvecs_timed", C.c_int32), ("pad0", C.c_int32),
                 ("aca_warm_blocks", C.c_int64), ("aca_cold_blocks", C.c_int64),
                 ("guess_learned", C.c_int64), ("pod_energy", C.c_double),
-                ("train_loss_first", C.c_double), ("train_loss_last", C.c_double)]
+                ("train_loss_first", C.c_double), ("train_loss_last", C.c_double),
+                ("aca_core_blocks", C.c_int64 * 5)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: (list(getattr(self, f)) if f == "aca_core_blocks" else getattr(self, f))
+                for f, _ in self._fields_}
 
 
 class TrainOpts(C.Structure):

@@ -3,6 +3,12 @@ configuration bench.py times), on outputs the oracle can compute one by one:
 sampled rows of the operator's action and of the right-hand side, the true
 residual of the solution on sampled rows, and the transient against the
 cavity's closed form.  Also the failure paths the host can force.
+
+Bounds: the operator's action and the solution's residual on sampled rows
+within 10 x the ACA tolerance relative to the largest entry (the ACA sets
+this bound, not the arithmetic; measured 0.1 to 2.9 x tol); the right-hand
+side, summed directly, to 1e-12; complex64 far factors against complex128
+to 1e-4 (the reduced-precision bar).
 """
 
 import sys
@@ -71,7 +77,7 @@ def test_sampled_rows_of_apply_rhs_and_residual(setup, k):
     bg = b.cpu().numpy()
     e_rhs = np.abs(bg[idx] - b_ref).max() / np.abs(b_ref).max()
     _say(f"  e_apply={e_apply:.2e} e_rhs={e_rhs:.2e}")
-    assert e_apply < 30 * ACA_TOL
+    assert e_apply < 10 * ACA_TOL
     assert e_rhs < 1e-12
     a = torch.zeros(N, dtype=torch.complex128, device=dev)
     st = c.solve_frequency(k, a)
@@ -79,8 +85,73 @@ def test_sampled_rows_of_apply_rhs_and_residual(setup, k):
     e_res = np.abs(r).max() / np.abs(bg).max()
     _say(f"  solve: its={st['iters_total']} resid={st['resid_max']:.2e} dense-row resid={e_res:.2e}")
     assert st["resid_max"] <= 1e-6
-    assert e_res < 30 * ACA_TOL
+    assert e_res < 10 * ACA_TOL
     c.close()
+
+
+def test_warm_sequence_sampled_rows(setup):
+    """The launch sequence the benchmark times: one context assembling
+    consecutive frequencies with the ACA warm-started from the previous
+    frequency's pivots (k = 56..64, where ranks and cores are largest).
+    After each frequency the operator's action on sampled rows is checked
+    against the oracle's rows, and every size class of the warm start's core
+    elimination (LDS classes and the global-memory class for cores over 128
+    rows or 8,960 entries) must have run over the sequence."""
+    torch, E, d, g, mat, elems = setup
+    dev = torch.device("cuda:0")
+    N = 3 * g["ne"]
+    s_k = mft.freq_grid(d["period"], d["n_f"], d["sigma"])
+    idx = (3 * elems[:, None] + np.arange(3)[None, :]).reshape(-1)
+    rng = np.random.default_rng(56)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    xd = torch.tensor(x, device=dev)
+    y = torch.zeros(N, dtype=torch.complex128, device=dev)
+    c = _ctx(E, d)
+    classes = np.zeros(5, np.int64)
+    worst = 0.0
+    for k in range(56, 65):
+        st = c.assemble(k)
+        classes += np.array(st["aca_core_blocks"])
+        if k > 56:
+            assert st["aca_warm_blocks"] > 0.9 * st["n_far"]
+        if k % 2 == 0:
+            c.apply(xd, y)
+            rows = bem.assemble_rows(g, s_k[k], mat, elems, which=("T",))
+            y_ref = rows["T"] @ x
+            e = np.abs(y.cpu().numpy()[idx] - y_ref).max() / np.abs(y_ref).max()
+            worst = max(worst, e)
+            _say(f"warm sequence k={k}: warm {st['aca_warm_blocks']} cold {st['aca_cold_blocks']} "
+                 f"rank max {st['rank_max']} apply err {e:.2e} ({e / ACA_TOL:.2f} tol)")
+    c.close()
+    _say(f"  core eliminations by size class: {classes.tolist()}")
+    assert worst < 10 * ACA_TOL
+    assert classes[2] > 0 and classes[3] > 0 and classes[0] > 0
+
+
+def test_complex64_factors_match_complex128(setup):
+    """Reduced precision at full size: the transient with complex64 far
+    factors (FP64 Arnoldi and residuals) against the complex128 one on the
+    same configuration; the spec bar for reduced precision is 1e-4
+    relative L2 against FP64."""
+    torch, E, d, g, mat, _ = setup
+    dev = torch.device("cuda:0")
+    N = 3 * g["ne"]
+    out = {}
+    for store in (E.STORE_C128, E.STORE_C64):
+        c = E.Context(0)
+        E.setup_from_inputs(c, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=ACA_TOL,
+                                          far_store=store),
+                            solver=dict(tol=1e-6, guess=E.GUESS_SEM))
+        u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+        _say(f"fullsize transient, far store {'c64' if store else 'c128'}")
+        st = c.solve_transient(u)
+        c.close()
+        out[store] = u.cpu().numpy()
+        _say(f"  its={st['iters_total']} resid_max={st['resid_max']:.2e}")
+        assert st["resid_max"] <= 1e-6
+    e = np.linalg.norm(out[E.STORE_C64] - out[E.STORE_C128]) / np.linalg.norm(out[E.STORE_C128])
+    _say(f"  complex64 vs complex128 transient: {e:.3e}")
+    assert e < 1e-4
 
 
 def test_transient_matches_closed_form(setup):

@@ -411,3 +411,33 @@ def test_long_window_stays_accurate(torch_dev, E, mat):
     _say(f"  solves={st['n_solves']} err={err:.3e} late-window err={late:.3e}")
     assert st["n_solves"] == 129
     assert err < 0.06 and late < 0.06
+
+
+def test_long_window_matches_oracle(torch_dev, E):
+    """Sec. 5.1 (long-time behaviour) against the oracle: a window four times
+    the cavity workload's (T = 32, N_f = 256, 129 solves, sigma = 6/T, Hann)
+    on the level-1 cavity, dense operator, GMRES tol 1e-10 from the
+    extrapolated guess; the transient at every element and time step within
+    1e-6 relative L2 of the oracle's LU transient (the FP64 bar)."""
+    torch, dev = torch_dev
+    d = config_inputs(1, sub=1)
+    d["period"], d["n_f"] = 32.0, 256
+    d["sigma"] = 6.0 / d["period"]
+    d["history"] = ramp_history(d["n_f"], d["period"], d["t_rise"])
+    N = 3 * len(d["tri"])
+    _say("long window vs oracle: oracle transient (129 LU solves)")
+    ref = osolve.transient(d["xyz"], d["tri"], d["material"], d["period"], d["n_f"], d["sigma"],
+                           d["window"], d["pressure"], d["history"])
+    c = _ctx(E, d, op=dict(kind=E.OP_DENSE), solver=dict(tol=1e-10, guess=E.GUESS_SEM))
+    u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+    spec = torch.zeros((d["n_f"] // 2 + 1) * N, dtype=torch.complex128, device=dev)
+    st = c.solve_transient(u, spec)
+    c.close()
+    got = u.cpu().numpy().reshape(d["n_f"], N)
+    err = _l2(got, ref["u"])
+    late = np.abs(got[-64:] - ref["u"][-64:]).max() / np.abs(ref["u"]).max()
+    e_spec = _l2(spec.cpu().numpy().reshape(-1, N), ref["spec"])
+    _say(f"  solves={st['n_solves']} its={st['iters_total']} transient err={err:.3e} "
+         f"last-quarter err={late:.3e} spectrum err={e_spec:.3e}")
+    assert st["n_solves"] == 129
+    assert err < 1e-6 and late < 1e-6 and e_spec < 1e-6

@@ -124,3 +124,31 @@ def test_sem_drops_dependent_columns():
     x0 = sem.sem_guess(lambda M: A @ M, X, b)
     assert np.linalg.norm(x0 - 0.5 * x) < 1e-10 * np.linalg.norm(x)
     assert np.array_equal(sem.sem_guess(lambda M: A @ M, X[:, :0], b), np.zeros_like(b))
+
+
+def test_quadratic_extrapolation_exact_on_quadratics():
+    # Lagrange extrapolation through the three previous equispaced samples
+    # reproduces any vector sequence quadratic in k, and on a cubic it
+    # leaves exactly the third difference (6 c for c k^3).  The shorter
+    # histories are the constant and linear extrapolations.
+    rng = np.random.default_rng(11)
+    c0, c1, c2, c3 = (rng.standard_normal(17) + 1j * rng.standard_normal(17) for _ in range(4))
+    for k in (3, 7, 40):
+        quad = lambda j: c0 + c1 * j + c2 * j * j
+        hist = [quad(k - 1), quad(k - 2), quad(k - 3)]
+        x = sem.quadratic_extrapolation(hist)
+        assert np.linalg.norm(x - quad(k)) <= 1e-12 * np.linalg.norm(quad(k))
+        cub = lambda j: quad(j) + c3 * j ** 3
+        x = sem.quadratic_extrapolation([cub(k - 1), cub(k - 2), cub(k - 3)])
+        assert np.linalg.norm((cub(k) - x) - 6.0 * c3) <= 1e-9 * np.linalg.norm(cub(k))
+        lin = lambda j: c0 + c1 * j
+        x = sem.quadratic_extrapolation([lin(k - 1), lin(k - 2)])
+        assert np.linalg.norm(x - lin(k)) <= 1e-12 * np.linalg.norm(lin(k))
+        x = sem.quadratic_extrapolation([quad(k - 1), quad(k - 2)])
+        assert np.linalg.norm((quad(k) - x) - 2.0 * c2) <= 1e-10 * np.linalg.norm(quad(k))
+        assert np.array_equal(sem.quadratic_extrapolation([c0]), c0)
+    assert sem.quadratic_extrapolation([]) is None
+    # a planted mistake in the coefficients (2 a1 - a2, the linear rule on
+    # three samples) is caught by the quadratic case
+    bad = 2.0 * quad(39) - quad(38)
+    assert np.linalg.norm(bad - quad(40)) > 1e-3 * np.linalg.norm(quad(40))
