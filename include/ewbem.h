@@ -158,7 +158,10 @@ typedef struct {
   int32_t augment;     /* virtual cases per case: random complex combinations of the
                           cases' coordinate sequences (exact, the solution being
                           linear in the load), 0..64 (default 4) */
-  int32_t pad;
+  int32_t unit_snapshots; /* 1: the basis is the POD of the snapshots scaled to unit
+                             norm, so every frequency counts alike (default); 0: of the
+                             raw snapshots, which the large low-frequency solutions
+                             dominate */
 } ewbem_train_opts;
 
 typedef struct {

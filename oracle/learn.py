@@ -5,7 +5,10 @@ takes one more column, a network's prediction of the next frequency's
 solution.  What is defined here, plainly and in float64:
 
 * proper orthogonal decomposition: the basis is the r leading left singular
-  vectors of the snapshot matrix (numpy's SVD);
+  vectors of the snapshot matrix (numpy's SVD), optionally of the snapshots
+  scaled to unit norm;
+* the learned column: the quadratic extrapolation of the last three
+  solutions plus the network's correction mapped through the basis;
 * reduced coordinates c = Phi^H a, and the samples: input
   [Re c1, Im c1, Re c2, Im c2, Re c3, Im c3] / nu followed by f and f^2,
   target [Re e, Im e] / nu with e = c_k - (3 c1 - 3 c2 + c3), where
@@ -136,10 +139,15 @@ def adam(params, grad_fn, steps, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 # ---- reduced coordinates and samples
 
-def pod_basis(S, r):
+def pod_basis(S, r, unit=False):
     """The r leading left singular vectors of S (N x M) and the fraction of
-    |S|_F^2 they capture."""
-    U, sv, _ = np.linalg.svd(np.asarray(S), full_matrices=False)
+    |S|_F^2 they capture; with ``unit`` those of S with every nonzero column
+    scaled to unit norm (each snapshot weighted alike)."""
+    S = np.asarray(S)
+    if unit:
+        n = np.linalg.norm(S, axis=0)
+        S = S / np.where(n > 0, n, 1.0)[None, :]
+    U, sv, _ = np.linalg.svd(S, full_matrices=False)
     e = sv ** 2
     return U[:, :r], float(e[:r].sum() / e.sum()) if e.sum() > 0 else 1.0
 
@@ -164,3 +172,13 @@ def compose(c1, c2, c3, nu, y):
     """Predicted coordinates: 3 c1 - 3 c2 + c3 + nu (y_re + i y_im)."""
     r = len(c1)
     return 3 * np.asarray(c1) - 3 * np.asarray(c2) + np.asarray(c3) + nu * (y[:r] + 1j * y[r:])
+
+
+def learned_column(a1, a2, a3, Phi, nu, y):
+    """The learned column of the extrapolation: the quadratic extrapolation
+    of the last three solutions plus the network's correction in the basis,
+    3 a1 - 3 a2 + a3 + Phi nu (y_re + i y_im).  With c_j = Phi^H a_j its
+    coordinates are compose(c1, c2, c3, nu, y), and its part outside the
+    basis is that of the extrapolation."""
+    r = Phi.shape[1]
+    return 3 * np.asarray(a1) - 3 * np.asarray(a2) + np.asarray(a3) + Phi @ (nu * (y[:r] + 1j * y[r:]))

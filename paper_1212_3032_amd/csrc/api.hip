@@ -1557,7 +1557,12 @@ void push_coords(ewbem_ctx* c, const cd* a, int k) {
 }
 
 // The network's guess at frequency k (tree order, in d_lx), or null when the
-// coordinates of k-1, k-2 and k-3 are not all in the ring.
+// coordinates of k-1, k-2 and k-3 are not all in the ring.  With the three
+// previous solutions in the extrapolation history the guess is their
+// quadratic extrapolation 3 a1 - 3 a2 + a3 plus the network's correction in
+// the basis, Phi nu y: its coordinates are the prediction and its part
+// outside the basis is the extrapolation's.  Otherwise it is Phi times the
+// predicted coordinates alone.
 const cd* learned_guess(ewbem_ctx* c, int k) {
   if (k < 3 || c->lc_kidx.size() < 3 || c->lc_kidx[0] != k - 1 || c->lc_kidx[1] != k - 2 ||
       c->lc_kidx[2] != k - 3)
@@ -1571,9 +1576,22 @@ const cd* learned_guess(ewbem_ctx* c, int k) {
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_lkf.p, &kf, sizeof(float), hipMemcpyHostToDevice, st));
   launch_learn_samples(c->d_lcoef.p, r, c->d_lidx.p, c->d_lkf.p, 1, c->d_lfeat.p, nullptr, c->d_lnu.p, st);
   mlp_forward(c->lm.shape, c->d_lp.p, 1, c->d_lfeat.p, c->d_lact.p, c->d_lpre.p, c->d_ly.p, st);
-  launch_learn_compose(c->d_lcoef.p, r, c->d_lidx.p, c->d_lnu.p, c->d_ly.p, c->d_lpred.p, st);
-  launch_gemv_acc(c->d_phi.p, N, r, c->d_lpred.p, cd{0.0, 0.0}, c->d_lx.p, N, st);
-  EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // idx and kf live on this frame
+  const bool full = c->hist_kidx.size() >= 3 && c->hist_kidx[0] == k - 1 && c->hist_kidx[1] == k - 2 &&
+                    c->hist_kidx[2] == k - 3;
+  launch_learn_compose(c->d_lcoef.p, r, c->d_lidx.p, c->d_lnu.p, c->d_ly.p, full ? 0 : 1, c->d_lpred.p, st);
+  std::vector<cd> cx(std::max(1, c->so.sem_k), cd{0, 0});
+  if (full) {
+    const int ncap = (int)cx.size();
+    cx[c->hist_slot[0]] = cd{3, 0};
+    cx[c->hist_slot[1]] = cd{-3, 0};
+    cx[c->hist_slot[2]] = cd{1, 0};
+    EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p, cx.data(), ncap * sizeof(cd), hipMemcpyHostToDevice, st));
+    launch_gemv_acc(c->d_hist_sol.p, N, ncap, c->d_small.p, cd{0.0, 0.0}, c->d_lx.p, N, st);
+    launch_gemv_acc(c->d_phi.p, N, r, c->d_lpred.p, cd{1.0, 0.0}, c->d_lx.p, N, st);
+  } else {
+    launch_gemv_acc(c->d_phi.p, N, r, c->d_lpred.p, cd{0.0, 0.0}, c->d_lx.p, N, st);
+  }
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // idx, kf and cx live on this frame
   c->acc.guess_learned += 1;
   return c->d_lx.p;
 }
@@ -2728,6 +2746,7 @@ void ewbem_default_train_opts(ewbem_train_opts* o) {
   o->load_kind = 0;
   o->seed = 1;
   o->augment = 4;
+  o->unit_snapshots = 1;
 }
 
 int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, const ewbem_train_opts* o,
@@ -2737,7 +2756,7 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     if (o->n_modes < 1 || o->n_modes > 1024 || o->hidden < 1 || o->hidden > 4096 || o->n_hidden < 0 ||
         o->n_hidden > 8 || o->epochs < 0 || o->epochs > 1000000 || !(o->lr > 0) || !std::isfinite(o->lr) ||
         o->power_iters < 0 || o->power_iters > 10 || (o->load_kind != 0 && o->load_kind != 1) ||
-        o->augment < 0 || o->augment > 64)
+        o->augment < 0 || o->augment > 64 || (o->unit_snapshots != 0 && o->unit_snapshots != 1))
       fail(EWBEM_EINVAL, "guess_train: options out of range");
     if (!ctx->have_mesh || !ctx->have_time || !ctx->have_load)
       fail(EWBEM_ESTATE, "guess_train: set the mesh, time grid and a load (its history is used) first");
@@ -2777,11 +2796,21 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     // reduced basis and every snapshot's coordinates
     DevBuf<cd> phi, coef, part;
     phi.reserve((size_t)N * r);
+    // unit-norm snapshots weight every frequency alike; the raw ones are
+    // dominated by the low frequencies, whose solutions are orders of
+    // magnitude larger
+    DevBuf<double> snorm;
+    if (o->unit_snapshots) {
+      snorm.reserve(M);
+      launch_col_norms(S.p, N, M, N, snorm.p, st);
+      launch_col_scale(S.p, N, M, N, snorm.p, 1, st);
+    }
     const int l = std::min(M, r + 16);
     const double energy = pod_basis(ctx, S.p, N, M, r, l, o->power_iters, o->seed, phi.p);
     coef.reserve((size_t)M * r);
     part.reserve((size_t)dots_chunks(N) * r);
     for (int m = 0; m < M; ++m) launch_dots(phi.p, N, r, S.p + (size_t)m * N, N, part.p, coef.p + (size_t)m * r, st);
+    if (o->unit_snapshots) launch_col_scale(coef.p, r, M, r, snorm.p, 0, st);  // the raw snapshots' coordinates
     S.release();
     // the solutions depend linearly on the load, so any combination of the
     // cases' coordinate sequences is the sequence of the combined load:

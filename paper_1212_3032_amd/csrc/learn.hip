@@ -203,12 +203,18 @@ __global__ __launch_bounds__(64) void k_learn_samples(const cd* __restrict__ coe
 
 // out = 3 c1 - 3 c2 + c3 + nu (y_re + i y_im).
 __global__ void k_learn_compose(const cd* __restrict__ coef, int r, const int* __restrict__ idx,
-                                const double* __restrict__ nu, const float* __restrict__ y, cd* __restrict__ out) {
+                                const double* __restrict__ nu, const float* __restrict__ y, int base,
+                                cd* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= r) return;
-  const cd a = coef[(size_t)idx[0] * r + j], b = coef[(size_t)idx[1] * r + j], c = coef[(size_t)idx[2] * r + j];
   const double v = nu[0];
-  out[j] = (3.0 * a - 3.0 * b + c) + cd{v * (double)y[j], v * (double)y[r + j]};
+  const cd corr{v * (double)y[j], v * (double)y[r + j]};
+  if (!base) {
+    out[j] = corr;
+    return;
+  }
+  const cd a = coef[(size_t)idx[0] * r + j], b = coef[(size_t)idx[1] * r + j], c = coef[(size_t)idx[2] * r + j];
+  out[j] = (3.0 * a - 3.0 * b + c) + corr;
 }
 
 }  // namespace
@@ -347,9 +353,10 @@ void launch_learn_samples(const cd* coef, int r, const int* idx, const float* kf
   hipLaunchKernelGGL(k_learn_samples, dim3(n), dim3(64), 0, st, coef, r, idx, kf, n, X, T, nu);
 }
 
-void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, cd* out,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_learn_compose, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, coef, r, idx, nu, y, out);
+void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, int base,
+                          cd* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_learn_compose, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, coef, r, idx, nu, y, base,
+                     out);
 }
 
 }  // namespace ewbem

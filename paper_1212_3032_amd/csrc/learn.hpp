@@ -84,9 +84,10 @@ void launch_adam(float* p, const float* g, float* m, float* v, long long n, cons
 // with f = kf[s].  T and nu may be null.
 void launch_learn_samples(const cd* coef, int r, const int* idx, const float* kf, int n, float* X, float* T,
                           double* nu, hipStream_t st);
-// out (r) = 3 c1 - 3 c2 + c3 + nu (y[0..r) + i y[r..2r)) for the rows idx[0..2].
-void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, cd* out,
-                          hipStream_t st);
+// out (r) = 3 c1 - 3 c2 + c3 + nu (y[0..r) + i y[r..2r)) for the rows idx[0..2]
+// (base = 1), or only the correction nu (y[0..r) + i y[r..2r)) (base = 0).
+void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, int base,
+                          cd* out, hipStream_t st);
 
 // ---- host helpers (small dense matrices, row-major)
 

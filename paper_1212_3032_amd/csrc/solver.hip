@@ -50,6 +50,41 @@ int dots_chunks(long long n) {
   return (int)c;
 }
 
+// nrm[c] = |V(:, c)|_2 for c < ncols: one 256-thread workgroup per column,
+// fixed summation order
+__global__ __launch_bounds__(256) void k_col_norms(const cd* __restrict__ V, long long ld, long long n,
+                                                   double* __restrict__ nrm) {
+  const cd* __restrict__ v = V + (size_t)blockIdx.x * ld;
+  double acc = 0.0;
+  for (long long r = threadIdx.x; r < n; r += 256) acc += v[r].x * v[r].x + v[r].y * v[r].y;
+  __shared__ double sp[4];
+  acc = wsumv(acc);
+  if ((threadIdx.x & 63) == 0) sp[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) nrm[blockIdx.x] = sqrt(sp[0] + sp[1] + sp[2] + sp[3]);
+}
+
+// V(:, c) *= f[c] (inv = 0) or / f[c] (inv = 1; a zero f leaves the column)
+__global__ void k_col_scale(cd* __restrict__ V, long long ld, long long n, const double* __restrict__ f,
+                            int inv) {
+  const double g = f[blockIdx.y];
+  const double a = inv ? (g > 0.0 ? 1.0 / g : 1.0) : g;
+  cd* __restrict__ v = V + (size_t)blockIdx.y * ld;
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long long)gridDim.x * blockDim.x)
+    v[r] = cd{a * v[r].x, a * v[r].y};
+}
+
+void launch_col_norms(const cd* V, long long ld, int ncols, long long n, double* nrm, hipStream_t st) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_col_norms, dim3(ncols), dim3(256), 0, st, V, ld, n, nrm);
+}
+
+void launch_col_scale(cd* V, long long ld, int ncols, long long n, const double* f, int inv, hipStream_t st) {
+  if (ncols <= 0 || n <= 0) return;
+  const long long bx = std::min<long long>((n + 255) / 256, 64);
+  hipLaunchKernelGGL(k_col_scale, dim3((unsigned)bx, ncols), dim3(256), 0, st, V, ld, n, f, inv);
+}
+
 void launch_dots(const cd* V, long long ld, int ncols, const cd* w, long long n, cd* partial,
                  cd* out, hipStream_t st) {
   if (ncols <= 0) return;

@@ -11,6 +11,9 @@ int dots_chunks(long long n);
 // out[c] = sum_r conj(V[r + c ld]) w[r], c < ncols (partial: ncols*dots_chunks(n))
 void launch_dots(const cd* V, long long ld, int ncols, const cd* w, long long n, cd* partial,
                  cd* out, hipStream_t st);
+// nrm[c] = |V(:, c)|_2; V(:, c) *= f[c] (inv: /= f[c], zero f leaves it)
+void launch_col_norms(const cd* V, long long ld, int ncols, long long n, double* nrm, hipStream_t st);
+void launch_col_scale(cd* V, long long ld, int ncols, long long n, const double* f, int inv, hipStream_t st);
 void launch_gemv_sub(const cd* V, long long ld, int ncols, const cd* h, cd* w, long long n,
                      hipStream_t st);
 void launch_gemv_acc(const cd* V, long long ld, int ncols, const cd* h, cd beta, cd* out, long long n,

@@ -76,7 +76,7 @@ class TrainOpts(C.Structure):
     _fields_ = [("n_modes", C.c_int32), ("hidden", C.c_int32), ("n_hidden", C.c_int32),
                 ("epochs", C.c_int32), ("lr", C.c_double), ("power_iters", C.c_int32),
                 ("load_kind", C.c_int32), ("seed", C.c_uint64), ("augment", C.c_int32),
-                ("pad", C.c_int32)]
+                ("unit_snapshots", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -98,7 +98,7 @@ def test_scene_aca_histories(sub):
 
 
 def test_scene_history_spread_is_the_window_amplification():
-    """Two transients of the level-2 scene (11,520 unknowns, T = 32,
+    """Two transients of the level-3 scene (46,080 unknowns, T = 32,
     N_f = 256, sigma = 8/T) whose operators come from different ACA
     histories (warm-started vs from scratch at every frequency, ACA 1e-4).
     Sec. 3.1: the de-damping factor exp(sigma t) of the inverse transform
@@ -110,18 +110,21 @@ def test_scene_history_spread_is_the_window_amplification():
     import torch
     from paper_1212_3032_amd import ewbem as E
     dev = torch.device("cuda:0")
-    d = config_inputs(5, sub=2)
+    d = config_inputs(5, sub=3)
     N = 3 * len(d["tri"])
     n_f, T, sig = d["n_f"], d["period"], d["sigma"]
     assert (n_f, T) == (256, 32.0) and abs(sig * T - 8.0) < 1e-12
     us = []
     for reuse in (1, 0):
         c = _ctx(E, d, reuse)
-        c.set_solver(tol=1e-8, guess=E.GUESS_SEM)
+        # the workload's solver (1e-6); the level-2 mesh has under one
+        # element per shear wavelength at the top frequencies, where GMRES
+        # stalls, so the scene is taken at level 3
+        c.set_solver(tol=1e-6, guess=E.GUESS_SEM)
         u = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
         st = c.solve_transient(u)
         c.close()
-        _say(f"scene level 2 transient, aca_reuse={reuse}: its {st['iters_total']} "
+        _say(f"scene level 3 transient, aca_reuse={reuse}: its {st['iters_total']} "
              f"resid max {st['resid_max']:.1e}")
         us.append(u.cpu().numpy().reshape(n_f, N))
     t = np.arange(n_f) * (T / n_f)

@@ -124,7 +124,8 @@ def test_mlp_train_matches_oracle_adam(env):
 # ---- the guess on the spherical cavity under spherical-harmonic pressures
 
 SUB, NF, PERIOD = 3, 64, 8.0
-N_TRAIN, N_HELD = 16, 4
+N_TRAIN, N_HELD = 48, 4
+R = 128
 
 
 def _setup(E, xyz, tri, guess, p0):
@@ -146,7 +147,7 @@ def trained(env):
     loads = np.array([sh_pressure(xyz, tri, rng)[0] for _ in range(N_TRAIN + N_HELD)])
     c = _setup(E, xyz, tri, E.GUESS_LEARNED, loads[0])
     _say(f"training on {N_TRAIN} cases, sub {SUB}, N_f {NF}")
-    st = c.guess_train(loads[:N_TRAIN], pressures=True, n_modes=48, epochs=1500)
+    st = c.guess_train(loads[:N_TRAIN], pressures=True, n_modes=R, epochs=1500)
     _say(f"  pod energy {st['pod_energy']:.8f}, loss {st['train_loss_first']:.3e} -> "
          f"{st['train_loss_last']:.3e}, {st['n_solves']} solves, {st['iters_total']} iterations")
     return dict(ctx=c, loads=loads, xyz=xyz, tri=tri, stats=st)
@@ -172,7 +173,9 @@ def test_basis_is_orthonormal_and_near_optimal(env, trained):
         ref.solve_transient(u, spec)
         S[:, i * nk:(i + 1) * nk] = spec.cpu().numpy().reshape(nk, N).T
     ref.close()
-    _, e_opt = OL.pod_basis(S, r)
+    # the basis is that of the unit-norm snapshots (every frequency alike)
+    _, e_opt = OL.pod_basis(S, r, unit=True)
+    S = S / np.linalg.norm(S, axis=0)[None, :]
     res = np.linalg.norm(S - Phi @ (Phi.conj().T @ S)) ** 2 / np.linalg.norm(S) ** 2
     e_stat = trained["stats"]["pod_energy"]
     _say(f"basis r={r}: residual energy {res:.3e} (optimal {1 - e_opt:.3e}); reported energy {e_stat:.10f}")
@@ -238,11 +241,12 @@ def test_save_load_round_trip(env, trained):
 
 def test_learned_column_ceiling(env, trained):
     """What any prediction in the basis could gain: replace the in-basis part
-    of the extrapolated guess by the exact solution's coordinates.  The
-    operator weights the out-of-basis part of the guess error (fine spatial
-    detail) heavily, so even exact coordinates lower the guess residual by
-    at most a few times on training loads and by well under 2x on held-out
-    ones -- the measured reason the network's column gains little here."""
+    of the extrapolated guess by the exact solution's coordinates.  On the
+    sphere the response to one harmonic Y_lm spans two fixed fields (normal
+    and tangential), so 48 degree-6 loads excite about 2 x 49 directions:
+    with r = 128 modes of the unit-norm snapshots exact coordinates lower the
+    held-out guess residual 3.4-6x (at r = 64 only 1.1-1.9x, which capped the
+    first version of the guess)."""
     torch, dev, E = env
     c, loads = trained["ctx"], trained["loads"]
     N = 3 * len(trained["tri"])
@@ -259,7 +263,7 @@ def test_learned_column_ceiling(env, trained):
         return y
 
     ratios = {}
-    for case in (0, N_TRAIN):
+    for case in (0, N_TRAIN, N_TRAIN + 1, N_TRAIN + 2):
         d.set_load_pressure(loads[case], ramp_history(NF, PERIOD, 0.05))
         sols, rs, rr = [], [], []
         for k in range(NF // 2 + 1):
@@ -277,9 +281,11 @@ def test_learned_column_ceiling(env, trained):
                 rs.append(float(torch.linalg.norm(b - A(xs)) / bn))
                 rr.append(float(torch.linalg.norm(b - A(xr)) / bn))
             sols.append(a)
-        ratios[case] = np.mean(rr) / np.mean(rs)
+        ratios[case] = np.mean(rs) / np.mean(rr)
         _say(f"case {case} ({'training' if case < N_TRAIN else 'held-out'}): mean guess residual "
-             f"extrapolation {np.mean(rs):.2e}, with exact in-basis part {np.mean(rr):.2e}")
+             f"extrapolation {np.mean(rs):.2e}, with exact in-basis part {np.mean(rr):.2e} "
+             f"({ratios[case]:.2f}x lower)")
     d.close()
-    assert ratios[0] < 1.0 and ratios[N_TRAIN] < 1.0
-    assert ratios[N_TRAIN] > 0.5
+    held = [ratios[N_TRAIN + i] for i in range(3)]
+    assert ratios[0] > 3.0
+    assert min(held) > 2.5 and np.mean(held) > 3.0

@@ -152,7 +152,7 @@ def test_learned_model_format_on_host_context():
     rng = np.random.default_rng(1)
     o = ewbem.default_train_opts()
     assert (o.n_modes, o.hidden, o.n_hidden, o.epochs, o.lr, o.power_iters, o.load_kind, o.seed,
-            o.augment, o.pad) == (64, 256, 3, 2000, 1e-3, 2, 0, 1, 4, 0)
+            o.augment, o.unit_snapshots) == (64, 256, 3, 2000, 1e-3, 2, 0, 1, 4, 1)
     with pytest.raises(ewbem.EwbemError) as e:
         c.guess_save()  # no model yet
     assert e.value.status == ewbem.ESTATE

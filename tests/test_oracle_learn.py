@@ -120,6 +120,49 @@ def test_pod_basis_is_eckart_young():
         assert e == pytest.approx((sv[:r] ** 2).sum() / (sv ** 2).sum(), rel=1e-12)
 
 
+def test_pod_basis_of_unit_snapshots():
+    """Scaling snapshots does not change the unit-norm basis (its projector),
+    the unit-norm basis of unit-norm snapshots is the plain one, and with
+    snapshots of very different sizes the unit weighting keeps directions
+    the plain basis drops."""
+    rng = np.random.default_rng(9)
+    N, M = 50, 30
+    S = rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))
+    proj = lambda P: P @ P.conj().T
+    P1, e1 = OL.pod_basis(S, 7, unit=True)
+    P2, e2 = OL.pod_basis(S * (10.0 ** rng.uniform(-6, 6, M))[None, :], 7, unit=True)
+    assert np.abs(proj(P1) - proj(P2)).max() < 1e-9 and e1 == pytest.approx(e2, rel=1e-10)
+    Su = S / np.linalg.norm(S, axis=0)[None, :]
+    P3, e3 = OL.pod_basis(Su, 7)
+    assert np.abs(proj(P1) - proj(P3)).max() < 1e-9 and e1 == pytest.approx(e3, rel=1e-12)
+    # one large snapshot among small orthogonal ones: the plain basis of rank 1
+    # is that snapshot; the unit basis weights all alike
+    Q, _ = np.linalg.qr(rng.standard_normal((N, 4)))
+    T = Q * np.array([1e6, 1.0, 1.0, 1.0])[None, :]
+    Pp, _ = OL.pod_basis(T, 1)
+    assert abs(abs(Pp[:, 0] @ Q[:, 0]) - 1) < 1e-12
+    Pu, eu = OL.pod_basis(T, 3, unit=True)
+    assert eu == pytest.approx(0.75, rel=1e-12)
+
+
+def test_learned_column_has_the_predicted_coordinates():
+    """The column's coordinates are the composed prediction and its part
+    outside the basis is the quadratic extrapolation's."""
+    rng = np.random.default_rng(10)
+    N, r = 40, 6
+    Phi, _ = np.linalg.qr(rng.standard_normal((N, r)) + 1j * rng.standard_normal((N, r)))
+    a1, a2, a3 = (rng.standard_normal(N) + 1j * rng.standard_normal(N) for _ in range(3))
+    y = rng.standard_normal(2 * r)
+    nu = 0.37
+    x = OL.learned_column(a1, a2, a3, Phi, nu, y)
+    c = [Phi.conj().T @ a for a in (a1, a2, a3)]
+    assert np.abs(Phi.conj().T @ x - OL.compose(c[0], c[1], c[2], nu, y)).max() < 1e-12
+    out = lambda v: v - Phi @ (Phi.conj().T @ v)
+    assert np.abs(out(x) - out(3 * a1 - 3 * a2 + a3)).max() < 1e-12
+    # a zero correction gives the extrapolation itself
+    assert np.abs(OL.learned_column(a1, a2, a3, Phi, nu, np.zeros(2 * r)) - (3 * a1 - 3 * a2 + a3)).max() < 1e-13
+
+
 def test_samples_of_a_quadratic_sequence_have_zero_target():
     rng = np.random.default_rng(4)
     r = 9
