@@ -428,6 +428,23 @@ int ewbem_mlp_train(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, float
                     const float* x, const float* target, int32_t epochs, double lr, double* loss_first,
                     double* loss_last);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as ewbem_mlp_eval, with the same arguments and results, that
+ * allocates nothing.  Its activations, pre-activations, output gradient,
+ * backward work area and loss partials live in one statically sized array
+ * of 32 MiB per GPU (held from the first context on that GPU until the
+ * process ends), so it needs 2 batch sum(hidden widths) + [target] (batch
+ * dims[L] + 256 x 2) + [grad] 2 batch max(width) floats, each part rounded
+ * up to 256 bytes, within 32 MiB; larger requests return EINVAL before any
+ * work is enqueued.  Every call on a GPU shares that array and leaves its
+ * contents behind (nothing there needs clearing: each call writes before it
+ * reads), so calls that overlap on one GPU (several host threads, or
+ * several streams in flight) race and must be serialised by the caller. */
+int ewbem_mlp_eval_noalloc(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, const float* params,
+                           int64_t batch, const float* x, const float* target, float* y, float* grad,
+                           double* loss);
+
 /* Sec. 3.3 (inverse): u(n dt) = Re{exp(sigma n dt) sum_k W_k a_k
  * exp(2 pi i n k / N_f)} with a_{N_f-k} = conj(a_k).  spec: device,
  * (N_f/2+1) x N complex (caller order); u: device, N_f x N doubles. */

@@ -11,6 +11,7 @@
 #include <thread>
 #include <atomic>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -2177,6 +2178,47 @@ size_t model_bytes(const LearnedModel& m, long long N) {
 
 }  // namespace
 
+// ---- the allocation-free network evaluation's scratch
+//
+// One statically sized array per GPU, holding the activations, the
+// pre-activations, the output gradient, the backward pass's work area and
+// the loss partials of ewbem_mlp_eval_noalloc.  In host code its name is
+// not a device address: every use goes through the address that
+// hipGetSymbolAddress returned for the device (kept in g_scratch_addr).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The scratch array's address on `device` (which must be current), looked
+// up once per device.  Null when the lookup fails.
+void* scratch_addr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_addr[device] = ptr;
+  }
+  return g_scratch_addr[device];
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
 extern "C" {
 
 void ewbem_default_op_opts(ewbem_op_opts* o) {
@@ -2222,6 +2264,10 @@ int ewbem_create(ewbem_ctx** out, int32_t device, void* hip_stream) {
       return EWBEM_ESTATE;
     }
     if (hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return EWBEM_EHIP;
+    }
+    if (!scratch_addr(device)) {
       delete c;
       return EWBEM_EHIP;
     }
@@ -3032,6 +3078,63 @@ int ewbem_mlp_eval(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, const 
         work.reserve(2 * (size_t)s.max_width() * batch);
         mlp_backward(s, params, batch, x, act.p, pre.p, dY.p, work.p, grad, st);
       }
+    }
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    return EWBEM_OK;
+  });
+}
+
+int ewbem_mlp_eval_noalloc(ewbem_ctx* ctx, int32_t n_layers, const int32_t* dims, const float* params,
+                           int64_t batch, const float* x, const float* target, float* y, float* grad,
+                           double* loss) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    const MlpShape s = mlp_shape(n_layers, dims);
+    if (batch < 0 || batch > (1LL << 24)) fail(EWBEM_EINVAL, "mlp_eval_noalloc: batch out of range");
+    if (!params || (batch > 0 && (!x || !y))) fail(EWBEM_EINVAL, "mlp_eval_noalloc: null array");
+    if (batch > 0 && grad && !target) fail(EWBEM_EINVAL, "mlp_eval_noalloc: the gradient needs a target");
+    // the same buffers as ewbem_mlp_eval, carved from the scratch array
+    const int dL = s.dims[n_layers];
+    const long long nout = batch * dL;
+    const int nb = loss_blocks(nout);
+    const size_t b_act = round256(sizeof(float) * std::max<size_t>(1, s.hidden_sum() * batch));
+    const size_t b_dy = round256(sizeof(float) * std::max<long long>(1, nout));
+    const size_t b_work = round256(sizeof(float) * 2 * (size_t)s.max_width() * batch);
+    const size_t b_part = round256(sizeof(double) * nb);
+    const size_t need = 2 * b_act + (target ? b_dy + b_part : 0) + (target && grad ? b_work : 0);
+    if (need > kScratchBytes)
+      fail(EWBEM_EINVAL, "mlp_eval_noalloc: batch x widths need " + std::to_string(need) +
+                             " bytes of scratch, more than its " + std::to_string(kScratchBytes));
+    void* base = scratch_addr(ctx->device);
+    if (!base) fail(EWBEM_EHIP, "mlp_eval_noalloc: no scratch address on this device");
+    if (loss) *loss = 0.0;
+    hipStream_t st = ctx->stream;
+    const size_t np = s.n_params();
+    if (batch == 0) {
+      if (grad)
+        hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)std::min<size_t>((np + 255) / 256, 1024)), dim3(256), 0, st,
+                           grad, (long long)np);
+      EWBEM_HIP_CHECK(hipGetLastError());
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      return EWBEM_OK;
+    }
+    unsigned char* p = (unsigned char*)base;
+    float* act = (float*)p;
+    float* pre = (float*)(p + b_act);
+    float* dY = (float*)(p + 2 * b_act);
+    double* part = (double*)(p + 2 * b_act + b_dy);
+    float* work = (float*)(p + 2 * b_act + b_dy + b_part);
+    mlp_forward(s, params, batch, x, act, pre, y, st);
+    if (target) {
+      launch_mlp_loss(y, target, nout, (float)(2.0 / (double)nout), dY, part, st);
+      double h[256];
+      EWBEM_HIP_CHECK(hipMemcpyAsync(h, part, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      double sum = 0.0;
+      for (int i = 0; i < nb; ++i) sum += h[i];
+      if (loss) *loss = sum / (double)nout;
+      if (grad) mlp_backward(s, params, batch, x, act, pre, dY, work, grad, st);
     }
     EWBEM_HIP_CHECK(hipGetLastError());
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));

@@ -32,7 +32,7 @@ EXPORTED = [
     "ewbem_solve_transient_incident_loads",
     "ewbem_batch_solve_transient",
     "ewbem_mft_inverse", "ewbem_default_train_opts", "ewbem_guess_train", "ewbem_guess_save",
-    "ewbem_guess_load", "ewbem_guess_basis", "ewbem_mlp_eval", "ewbem_mlp_train",
+    "ewbem_guess_load", "ewbem_guess_basis", "ewbem_mlp_eval", "ewbem_mlp_eval_noalloc", "ewbem_mlp_train",
 ]
 
 
@@ -138,6 +138,7 @@ def lib():
         "ewbem_guess_load": (C.c_int, [P, P, C.c_size_t]),
         "ewbem_guess_basis": (C.c_int, [P, C.POINTER(I32), P]),
         "ewbem_mlp_eval": (C.c_int, [P, I32, P, P, I64, P, P, P, P, C.POINTER(D)]),
+        "ewbem_mlp_eval_noalloc": (C.c_int, [P, I32, P, P, I64, P, P, P, P, C.POINTER(D)]),
         "ewbem_mlp_train": (C.c_int, [P, I32, P, P, I64, P, P, I32, D, C.POINTER(D), C.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
@@ -435,15 +436,17 @@ class Context:
                 self.h, C.byref(r), _dev_ptr(phi, "torch.complex128", 3 * self.nt * r.value)))
         return r.value
 
-    def mlp_eval(self, dims, params, x, y, target=None, grad=None):
+    def mlp_eval(self, dims, params, x, y, target=None, grad=None, noalloc=False):
         """The network's kernels on device float32 tensors; returns the loss
-        (0 without a target)."""
+        (0 without a target).  noalloc: through ewbem_mlp_eval_noalloc (no
+        device allocation; its buffers in the library's static scratch)."""
         d, pd = _host(dims, np.int32)
         L = d.size - 1
         batch = x.numel() // int(d[0]) if int(d[0]) > 0 else 0
         np_ = sum(int(d[l + 1]) * int(d[l]) + int(d[l + 1]) for l in range(L))
         loss = C.c_double(0.0)
-        self._check(self._L.ewbem_mlp_eval(
+        fn = self._L.ewbem_mlp_eval_noalloc if noalloc else self._L.ewbem_mlp_eval
+        self._check(fn(
             self.h, L, pd, _dev_ptr(params, "torch.float32", np_), batch,
             _dev_ptr(x, "torch.float32", batch * int(d[0])) if batch else None,
             _dev_ptr(target, "torch.float32", batch * int(d[-1])) if target is not None else None,
