@@ -9,6 +9,15 @@ three previous solutions, GMRES runs to a 1e-6 relative residual; then the
 windowed, de-damped inverse transform gives the time response.  Inputs are
 resident on the GPU before the timed region.
 
+The default line also carries, each timed on its own after the main steps:
+``quad_variant``, the same transient with the plain quadratic
+extrapolation 3 a1 - 3 a2 + a3 as the initial guess; and ``learned_fp32``,
+the headline comparison on the same geometry under spherical-harmonic
+pressures: held-out loads solved by plain FP64 (complex128 factors,
+least-squares extrapolation) and by the learned guess with complex64 far
+factors (FP64 Arnoldi and residuals), the guess trained (untimed) on
+--learned-train other loads.
+
 Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
 """
 
@@ -40,6 +49,17 @@ def parse():
     ap.add_argument("--c64-variant", action="store_true",
                     help="also time the complex64-factor variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant-steps", type=int, default=1,
+                    help="cavity workload: transients timed with the plain quadratic extrapolation "
+                         "3 a1 - 3 a2 + a3 after the least-squares one (Sec. 4.2, K = 3), on the "
+                         "same context (0: skip)")
+    ap.add_argument("--learned-train", type=int, default=8,
+                    help="cavity workload: training loads of the learned + FP32 comparison "
+                         "(spherical-harmonic pressures on the same geometry; 0: skip)")
+    ap.add_argument("--learned-held", type=int, default=1,
+                    help="cavity workload: held-out loads timed in each leg of that comparison")
+    ap.add_argument("--learned-modes", type=int, default=128,
+                    help="reduced coordinates of the learned guess")
     ap.add_argument("--aca-reuse", type=int, choices=[0, 1], default=None,
                     help="start each frequency's ACA from the previous pivots (library default if unset)")
     ap.add_argument("--cpu-rows", type=int, default=48)
@@ -60,6 +80,18 @@ def parse():
     ap.add_argument("--fp64-reference", action="store_true",
                     help="batch12 and scene workloads: also solve every problem with complex128 factors "
                          "(untimed) and report the complex64 results' relative L2 error against them")
+    ap.add_argument("--total-field", action="store_true",
+                    help="scene workload: the total-field formulation of the incident wave "
+                         "(right-hand side u_inc itself, O(N) per frequency; outputs the total "
+                         "displacement) instead of the scattered one (O(N^2) sum U t_sc)")
+    ap.add_argument("--aca-batch-mb", type=int, default=0,
+                    help="scene workload: approximate the far blocks in batches of about this many "
+                         "MiB of complex128 work area, converting each to complex64 as it "
+                         "finishes (0: all at once)")
+    ap.add_argument("--per-frequency", action="store_true",
+                    help="scene workload: drive the frequency loop from here (one solve per "
+                         "frequency, a progress line each, then the inverse transform) instead "
+                         "of one library call per transient; the default at level 5")
     ap.add_argument("--n-loads", type=int, default=8,
                     help="loads workload: loads solved through one frequency loop")
     ap.add_argument("--train-cases", type=int, default=8,
@@ -125,7 +157,10 @@ def traffic_from_profiles(bytes_per_launch):
         return None
 
 
-def run_gpu(args, store, pipeline=0):
+def run_gpu(args, store, pipeline=0, guess=None, after=None):
+    """Time --steps transients of the level-5 cavity on one context after
+    --warmup; ``after(ctx, d, u)`` runs on the same (warm) context before it
+    is closed and its result is returned as the fifth value."""
     import torch
     from paper_1212_3032_amd import ewbem as E
     from synth import config_inputs
@@ -138,7 +173,8 @@ def run_gpu(args, store, pipeline=0):
         op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5,
                 far_store=E.STORE_C64 if store == "c64" else E.STORE_C128,
                 **({} if args.aca_reuse is None else {"aca_reuse": args.aca_reuse})),
-        solver=dict(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF, pipeline=pipeline))
+        solver=dict(tol=1e-6, guess=E.GUESS_SEM if guess is None else guess, sem_k=3,
+                    precond=E.PREC_LEAF, pipeline=pipeline))
     N = 3 * len(d["tri"])
     n_f = d["n_f"]
     u = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
@@ -171,8 +207,9 @@ def run_gpu(args, store, pipeline=0):
                             "tuned": info["mv_tuned"], "tuned_ms": info["mv_tune_best_ms"],
                             "default_ms": info["mv_tune_default_ms"]}
     tot["u_last"] = u.cpu().numpy()  # the last timed transient (untimed copy)
+    extra = after(ctx, d, u) if after is not None else None
     ctx.close()
-    return d, N, elapsed, tot
+    return d, N, elapsed, tot, extra
 
 
 def rod_table1(args):
@@ -265,7 +302,7 @@ def learned_workload(args):
     u = torch.zeros(n_f * N, dtype=torch.float64, device=dev)
     cl = make(E.STORE_C64, E.GUESS_LEARNED)
     t = time.perf_counter()
-    tr = cl.guess_train(loads[[d["train"][i] for i in range(n_tr)]], pressures=True)
+    tr = cl.guess_train(loads[[d["train"][i] for i in range(n_tr)]], pressures=True, n_modes=args.learned_modes)
     t_train = time.perf_counter() - t
     print(f"# trained on {n_tr} loads in {t_train:.1f} s: pod energy {tr['pod_energy']:.8f}, "
           f"loss {tr['train_loss_first']:.3e} -> {tr['train_loss_last']:.3e}", file=sys.stderr, flush=True)
@@ -310,7 +347,7 @@ def learned_workload(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+c64-factors+bf16-net", "data": "synthetic",
         "config": {"workload": d["name"] + " (held-out loads)", "n_dof": N, "n_f": n_f,
                    "train_loads": n_tr, "held_out_loads": [int(i) for i in held], "gmres_tol": 1e-6,
-                   "aca_tol": 1e-5, "n_modes": 64, "network": "3 x 256 GELU, bf16 products"},
+                   "aca_tol": 1e-5, "n_modes": args.learned_modes, "network": "3 x 256 GELU, bf16 products"},
         "plain_fp64": pf, "learned_fp32": lf, "speedup_vs_plain": lf["value"] / pf["value"],
         "training": {"seconds": t_train, "solves": tr["n_solves"], "pod_energy": tr["pod_energy"],
                      "loss_first": tr["train_loss_first"], "loss_last": tr["train_loss_last"]},
@@ -566,25 +603,51 @@ def scene_workload(args):
     from synth import config_inputs
 
     sub = 3 if args.sub is None else args.sub
+    per_freq = args.per_frequency or sub >= 5
     d = config_inputs(5, sub=sub)
     dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
     c = E.Context(0)
     c.set_mesh(d["xyz"], d["tri"], exterior=True)
     m = d["material"]
     c.set_material(m["rho"], m["mu"], m["nu"])
     c.set_time(d["period"], d["n_f"], d["sigma"], d["window"])
-    c.set_load_incident_s([1.0, 0.0, 0.0], [0.0, 0.0, 1.0], 0.5, 13.0)
-    c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-4, far_store=E.STORE_C64)
+    c.set_load_incident_s([1.0, 0.0, 0.0], [0.0, 0.0, 1.0], 0.5, 13.0, total=args.total_field)
+    c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-4, far_store=E.STORE_C64,
+                   aca_batch_mb=args.aca_batch_mb)
     c.set_solver(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF)
     N = 3 * len(d["tri"])
+    info0 = c.info()
+    print(f"# scene level {sub}: {N} unknowns, {info0['n_near']} near / {info0['n_far']} far blocks, "
+          f"near field {16 * info0['near_entries'] / 1e9:.1f} GB (set-up {time.perf_counter() - t_setup:.1f} s)",
+          file=sys.stderr, flush=True)
     u = torch.zeros(d["n_f"] * N, dtype=torch.float64, device=dev)
+    nk = d["n_f"] // 2 + 1
+
+    def one_transient():
+        if not per_freq:
+            return c.solve_transient(u)
+        spec = torch.zeros(nk * N, dtype=torch.complex128, device=dev)
+        tot = None
+        t0 = time.perf_counter()
+        for k in range(nk):
+            st = c.solve_frequency(k, spec[k * N:(k + 1) * N])
+            tot = st if tot is None else {q: (max(tot[q], v) if q in ("resid_max", "iters_max", "rank_max")
+                                              else v if q in ("matvec_bytes", "stored_bytes", "n_near", "n_far",
+                                                              "rank_sum") else tot[q] + v) for q, v in st.items()}
+            print(f"# k={k}: {st['iters_total']} its, resid {st['resid_max']:.1e}, rank max {st['rank_max']}, "
+                  f"stored {st['stored_bytes'] / 1e9:.1f} GB, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+        c.mft_inverse(spec, u)
+        return tot
+
     for _ in range(args.warmup):
-        c.solve_transient(u)
+        one_transient()
     torch.cuda.synchronize()
     t = time.perf_counter()
     tot = None
     for _ in range(args.steps):
-        st = c.solve_transient(u)
+        st = one_transient()
         tot = st if tot is None else {k: (max(tot[k], v) if k in ("resid_max", "iters_max", "rank_max")
                                           else v if k in ("matvec_bytes", "stored_bytes", "n_near", "n_far",
                                                           "rank_sum") else tot[k] + v) for k, v in st.items()}
@@ -598,7 +661,7 @@ def scene_workload(args):
         c.set_mesh(d["xyz"], d["tri"], exterior=True)
         c.set_material(m["rho"], m["mu"], m["nu"])
         c.set_time(d["period"], d["n_f"], d["sigma"], d["window"])
-        c.set_load_incident_s([1.0, 0.0, 0.0], [0.0, 0.0, 1.0], 0.5, 13.0)
+        c.set_load_incident_s([1.0, 0.0, 0.0], [0.0, 0.0, 1.0], 0.5, 13.0, total=args.total_field)
         c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-4, far_store=E.STORE_C128)
         c.set_solver(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF)
         ref = torch.zeros_like(u)
@@ -616,7 +679,9 @@ def scene_workload(args):
         "vs_baseline": None, "dtype": "f64+c64-factors", "data": "synthetic",
         "config": {"workload": d["name"].replace("sub5", f"sub{sub}"), "n_dof": N, "n_f": d["n_f"],
                    "period": d["period"], "sigma": d["sigma"], "aca_tol": 1e-4, "gmres_tol": 1e-6,
-                   "far_blocks": info["n_far"], "near_blocks": info["n_near"]},
+                   "far_blocks": info["n_far"], "near_blocks": info["n_near"],
+                   "formulation": "total field (b = u_inc)" if args.total_field else "scattered field (b = U t_sc)",
+                   "aca_batch_mb": args.aca_batch_mb, "driven_per_frequency": per_freq},
         "gmres_iters_per_solve": tot["iters_total"] / n, "resid_max": tot["resid_max"],
         "transient_rel_l2_vs_fp64": err64,
         "matvec_GBps": tot["matvec_bytes_total"] / mv_s / 1e9 if mv_s > 0 else None,
@@ -669,6 +734,119 @@ def cpu_baseline(args):
     }
 
 
+def time_transients(ctx, u, n, ref=None):
+    """n transients on ctx (its current load), each bracketed by device
+    synchronisations; totals, and the largest relative L2 difference of the
+    transient from ref[i] when given."""
+    import torch
+    tot = dict(t=0.0, solves=0, its=0, resid=0.0, guess=0.0, learned=0, gmres=0.0, err=0.0, u=[])
+    for i in range(n):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = ctx.solve_transient(u)
+        torch.cuda.synchronize()
+        tot["t"] += time.perf_counter() - t
+        tot["solves"] += st["n_solves"]
+        tot["its"] += st["iters_total"]
+        tot["resid"] = max(tot["resid"], st["resid_max"])
+        tot["guess"] += st["guess_resid_sum"]
+        tot["learned"] += st["guess_learned"]
+        tot["gmres"] += st["t_gmres_ms"]
+        if ref is not None:
+            tot["err"] = max(tot["err"], (torch.linalg.norm(u - ref[i]) / torch.linalg.norm(ref[i])).item())
+        tot["u"].append(u.clone())
+    return tot
+
+
+def leg_summary(tot, n):
+    return {"value": tot["solves"] / tot["t"], "unit": "freq-solves/s", "transients": n,
+            "ms_per_transient": 1000.0 * tot["t"] / max(1, n),
+            "gmres_iters_per_solve": tot["its"] / max(1, tot["solves"]),
+            "guess_resid_mean": tot["guess"] / max(1, tot["solves"]), "resid_max": tot["resid"],
+            "gmres_ms_per_solve": tot["gmres"] / max(1, tot["solves"])}
+
+
+def cavity_variants(args, held_loads):
+    """Runs on the main context after its timed steps: the quadratic
+    extrapolation variant, then the plain FP64 leg of the learned
+    comparison on held-out spherical-harmonic loads."""
+    from paper_1212_3032_amd import ewbem as E
+
+    def after(ctx, d, u):
+        out = {}
+        if args.variant_steps > 0:
+            ctx.set_solver(tol=1e-6, guess=E.GUESS_QUAD, sem_k=3, precond=E.PREC_LEAF)
+            tot = time_transients(ctx, u, args.variant_steps)
+            out["quad"] = leg_summary(tot, args.variant_steps)
+            print(f"# quadratic extrapolation: {tot['its']} its over {tot['solves']} solves",
+                  file=sys.stderr, flush=True)
+        if held_loads is not None:
+            loads, hist = held_loads
+            ctx.set_solver(tol=1e-6, guess=E.GUESS_SEM, sem_k=3, precond=E.PREC_LEAF)
+            tot = dict(t=0.0, solves=0, its=0, resid=0.0, guess=0.0, learned=0, gmres=0.0, err=0.0, u=[])
+            for p in loads:
+                ctx.set_load_pressure(p, hist)
+                t1 = time_transients(ctx, u, 1)
+                for k in ("t", "solves", "its", "guess", "learned", "gmres"):
+                    tot[k] += t1[k]
+                tot["resid"] = max(tot["resid"], t1["resid"])
+                tot["u"] += t1["u"]
+            out["plain_held"] = tot
+            print(f"# plain FP64 on held-out loads: {tot['its']} its over {tot['solves']} solves",
+                  file=sys.stderr, flush=True)
+        return out
+    return after
+
+
+def learned_leg(args, d4, held, plain):
+    """The learned + FP32 leg: complex64 far factors (FP64 Arnoldi and
+    residuals) and the trained guess, on the held-out loads the plain leg
+    solved; training (untimed) on the first --learned-train loads."""
+    from paper_1212_3032_amd import ewbem as E
+    import torch
+
+    N, n_f = 3 * len(d4["tri"]), d4["n_f"]
+    c = E.Context(0)
+    c.set_mesh(d4["xyz"], d4["tri"], exterior=True)
+    m = d4["material"]
+    c.set_material(m["rho"], m["mu"], m["nu"])
+    c.set_time(d4["period"], n_f, d4["sigma"], d4["window"])
+    c.set_load_pressure(d4["loads"][held[0]], d4["history"])
+    c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-5, far_store=E.STORE_C64)
+    c.set_solver(tol=1e-6, guess=E.GUESS_LEARNED, sem_k=3, precond=E.PREC_LEAF)
+    tr_ids = d4["train"][:args.learned_train]
+    t = time.perf_counter()
+    tr = c.guess_train(d4["loads"][tr_ids], pressures=True, n_modes=args.learned_modes)
+    t_train = time.perf_counter() - t
+    print(f"# learned guess trained on {len(tr_ids)} loads in {t_train:.1f} s", file=sys.stderr, flush=True)
+    u = torch.zeros(n_f * N, dtype=torch.float64, device="cuda:0")
+    tot = dict(t=0.0, solves=0, its=0, resid=0.0, guess=0.0, learned=0, gmres=0.0, err=0.0, u=[])
+    for j, i in enumerate(held):
+        c.set_load_pressure(d4["loads"][i], d4["history"])
+        t1 = time_transients(c, u, 1, ref=[plain["u"][j]])
+        for k in ("t", "solves", "its", "guess", "learned", "gmres"):
+            tot[k] += t1[k]
+        tot["resid"] = max(tot["resid"], t1["resid"])
+        tot["err"] = max(tot["err"], t1["err"])
+    c.close()
+    pl = leg_summary(plain, len(held))
+    le = leg_summary(tot, len(held))
+    le["learned_guesses"] = tot["learned"]
+    le["transient_rel_l2_vs_fp64_max"] = tot["err"]
+    print(f"# learned + FP32 on held-out loads: {tot['its']} its over {tot['solves']} solves, "
+          f"transient vs FP64 {tot['err']:.2e}", file=sys.stderr, flush=True)
+    return {
+        "workload": d4["name"].replace("sub5", f"sub{args.sub}") if args.sub else d4["name"],
+        "held_out_loads": [int(i) for i in held], "train_loads": [int(i) for i in tr_ids],
+        "plain_fp64": dict(pl, guess="LS extrapolation K=3", far_store="c128"),
+        "learned_fp32": dict(le, guess="learned column + LS extrapolation K=3", far_store="c64",
+                             n_modes=args.learned_modes, network="3 x 256 GELU, bf16 products"),
+        "speedup_vs_plain": le["value"] / pl["value"],
+        "training": {"seconds": t_train, "solves": tr["n_solves"], "pod_energy": tr["pod_energy"],
+                     "loss_first": tr["train_loss_first"], "loss_last": tr["train_loss_last"]},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -695,7 +873,14 @@ def main():
         return
     if args.copy_probe:
         copy_probe()
-    d, N, elapsed, st = run_gpu(args, args.store)
+    d4 = held = None
+    if args.learned_train > 0 and args.learned_held > 0:
+        from synth import config_inputs
+        d4 = config_inputs(4, sub=args.sub)
+        held = d4["held_out"][:args.learned_held]
+    d, N, elapsed, st, var = run_gpu(
+        args, args.store,
+        after=cavity_variants(args, None if d4 is None else ([d4["loads"][i] for i in held], d4["history"])))
     u_ref = st.pop("u_last")
     solves = st["n_solves"]
     value = solves / elapsed
@@ -730,7 +915,8 @@ def main():
         "config": {
             "workload": d["name"], "n_dof": N, "n_elements": len(d["tri"]), "n_f": d["n_f"],
             "freq_solves_per_step": solves // args.steps, "sigma": d["sigma"], "period": d["period"],
-            "leaf": 64, "eta_adm": 1.0, "aca_tol": 1e-5, "gmres_tol": 1e-6, "guess": "LS-SEM K=3",
+            "leaf": 64, "eta_adm": 1.0, "aca_tol": 1e-5, "gmres_tol": 1e-6,
+            "guess": "least-squares extrapolation over the 3 previous solutions (Sec. 4.2)",
             "precond": "leaf block-diagonal", "far_store": args.store, "arith": "complex128",
             "aca_block_starts_per_frequency": {"warm": st["aca_warm_blocks"] / max(1, solves),
                                                "cold": st["aca_cold_blocks"] / max(1, solves)},
@@ -758,7 +944,7 @@ def main():
         out["roofline"]["stream_read_probe_GBps"] = rp
         out["roofline"]["frac_of_stream_read_probe"] = mv_gbs / rp
     if args.c64_variant and args.store == "c128":
-        _, _, el2, st2 = run_gpu(args, "c64")
+        _, _, el2, st2, _ = run_gpu(args, "c64")
         u2 = st2.pop("u_last")
         out["c64_factors"] = {
             "value": st2["n_solves"] / el2,
@@ -768,7 +954,7 @@ def main():
             "transient_rel_l2_vs_fp64": float(np.linalg.norm(u2 - u_ref) / np.linalg.norm(u_ref)),
         }
     if args.pipeline_variant:
-        _, _, el3, st3 = run_gpu(args, args.store, pipeline=1)
+        _, _, el3, st3, _ = run_gpu(args, args.store, pipeline=1)
         u3 = st3.pop("u_last")
         out["pipelined"] = {
             "value": st3["n_solves"] / el3,
@@ -776,6 +962,11 @@ def main():
             "matvec_GBps": st3["matvec_bytes_total"] / (st3["t_matvec_ms"] / 1000.0) / 1e9,
             "gmres_iters_per_solve": st3["iters_total"] / max(1, st3["n_solves"]),
         }
+    if "quad" in var:
+        out["quad_variant"] = dict(var["quad"], guess="quadratic extrapolation 3 a1 - 3 a2 + a3 (no operator "
+                                                      "products; inside the span of the least-squares one)")
+    if "plain_held" in var:
+        out["learned_fp32"] = learned_leg(args, d4, held, var["plain_held"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

@@ -89,6 +89,14 @@ typedef struct {
                          columns per phase-1 wavefront, and phase-2 tasks of 1/2048, 1/4096
                          or 1/8192 of all panel columns -- and keep the fastest; 0: 4 and
                          1/4096 (default 1).  The shapes change the summation order only. */
+  int32_t aca_batch_mb; /* with far_store C64: 0 approximates every far block at once in
+                           complex128 and then converts them (default); > 0 takes the far
+                           blocks in index order in batches whose complex128 factors and
+                           warm-start work areas need about this many MiB, converting each
+                           batch to complex64 as it finishes and reusing its work area, so
+                           the complex128 copy never exists for all blocks at once (the
+                           meshes whose complex128 far field would not fit).  The factors are
+                           the same; only the memory differs.  Not with the pipeline. */
 } ewbem_op_opts;
 
 typedef struct {
@@ -162,6 +170,14 @@ typedef struct {
                              norm, so every frequency counts alike (default); 0: of the
                              raw snapshots, which the large low-frequency solutions
                              dominate */
+  int32_t lsq_map;     /* 1: the prediction's base is a least-squares map per frequency
+                          from the three previous coordinate vectors to the next, fitted
+                          over the training loads (regularised, dual form), and the
+                          network learns to correct its leave-one-out errors (default);
+                          0: the base is the quadratic extrapolation 3 c1 - 3 c2 + c3 */
+  int32_t pad;
+  double lsq_reg;      /* the map's regularisation: lam = lsq_reg tr(G) / n with G the
+                          n x n Gram matrix of the training histories, (0, 1) (default 1e-8) */
 } ewbem_train_opts;
 
 typedef struct {
@@ -241,6 +257,20 @@ int ewbem_set_load_mixed(ewbem_ctx* ctx, const int32_t* bc, const double* values
  * any earlier load. */
 int ewbem_set_load_incident_s(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
                               double t0);
+
+/* The same plane S-wave in the total-field formulation: with traction-free
+ * cavities the total displacement u = u_sc + u_inc solves the integral
+ * equation of Sec. 2.1 with the incident displacement as the right-hand
+ * side, (c + T) u = u_inc, because u_inc, regular inside every cavity,
+ * satisfies T u_inc - U t_inc = (1 - c) u_inc there (Somigliana's identity
+ * for the cavities' interior).  b is then u_inc at the collocation points:
+ * O(N) per frequency instead of the O(N^2) sum U t_sc.  The unknowns and
+ * every output are the total displacement.  The two formulations agree in
+ * the limit of refinement, not element by element.  Arguments and errors as
+ * for ewbem_set_load_incident_s; ewbem_solve_transient_incident_loads
+ * takes the scattered formulation only (ESTATE after this call). */
+int ewbem_set_load_incident_s_total(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
+                                    double t0);
 
 /* The fast operator for A_k (Sec. 4.1 accelerates the matvec with a fast
  * method and names hierarchical matrices as an alternative to its
@@ -394,13 +424,17 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
 int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, const ewbem_train_opts* opts,
                       ewbem_stats* stats);
 
-/* Serialise the model (basis in caller order, network) into buf (host).
- * buf = NULL: *len receives the size.  EINVAL if *len is too small (then
- * *len is the size needed); ESTATE without a model.  Layout: 8 bytes
- * "EWBGUESS"; int32 version 1, N, r, L; int32 widths dims[0..L]; fp64 pod
- * energy, first and last training loss; fp32 parameters (per layer W_l row-
- * major dims[l+1] x dims[l], then b_l); complex128 basis N x r column-major.
- * All little-endian, no padding. */
+/* Serialise the model (basis in caller order, network, least-squares map)
+ * into buf (host).  buf = NULL: *len receives the size.  EINVAL if *len is
+ * too small (then *len is the size needed); ESTATE without a model.  Layout:
+ * 8 bytes "EWBGUESS"; int32 version 2, N, r, L; int32 widths dims[0..L];
+ * fp64 pod energy, first and last training loss; fp32 parameters (per layer
+ * W_l row-major dims[l+1] x dims[l], then b_l); complex128 basis N x r
+ * column-major; int32 n (training loads of the map, 0 for none) and K (the
+ * frequency count N_f/2 + 1 it was fitted for, 0 for none); complex128 X_k
+ * (3r x n, column-major) for k = 3..K-1, then W_k (r x n) for k = 3..K-1.
+ * All little-endian, no padding.  ewbem_guess_load also reads version 1,
+ * which ends after the basis (no map). */
 int ewbem_guess_save(const ewbem_ctx* ctx, void* buf, size_t* len);
 
 /* Load a model written by ewbem_guess_save (host buffer of len bytes) for

@@ -166,6 +166,18 @@ def incident_s_load(geom, s, mat, direction, polarisation):
     return (-np.einsum("eij,ej->ei", S, geom["n"])).reshape(-1)
 
 
+def incident_s_total_rhs(geom, s, mat, direction, polarisation):
+    """Total-field right-hand side of a plane S-wave on traction-free
+    cavities, for a unit wavelet spectrum: the incident displacement
+    pol exp(-s d.x / c_s) at each element's centroid, flattened to 3 N_e.
+    The total displacement u = u_sc + u_inc then solves T u = u_inc (T with
+    its free term), because u_inc, regular inside the cavities, satisfies
+    T u_inc - U t_inc = u_inc there (Somigliana's identity for the
+    cavities' interior with the normal reversed)."""
+    from .closed_form import plane_s_wave
+    return plane_s_wave(geom["cen"], s, mat, direction, polarisation).reshape(-1)
+
+
 def mixed_system(T, U, bc, given):
     """Sec. 2.1, eq. Aa_b: the boundary conditions move the known boundary
     values to the right-hand side of T u = U t.  For an element with a given

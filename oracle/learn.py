@@ -9,6 +9,9 @@ solution.  What is defined here, plainly and in float64:
   scaled to unit norm;
 * the learned column: the quadratic extrapolation of the last three
   solutions plus the network's correction mapped through the basis;
+* a regularised least-squares map per frequency from the three previous
+  coordinate vectors to the next (dual form over the training cases), with
+  its leave-one-out residuals;
 * reduced coordinates c = Phi^H a, and the samples: input
   [Re c1, Im c1, Re c2, Im c2, Re c3, Im c3] / nu followed by f and f^2,
   target [Re e, Im e] / nu with e = c_k - (3 c1 - 3 c2 + c3), where
@@ -152,9 +155,10 @@ def pod_basis(S, r, unit=False):
     return U[:, :r], float(e[:r].sum() / e.sum()) if e.sum() > 0 else 1.0
 
 
-def sample(c1, c2, c3, f, c0=None):
+def sample(c1, c2, c3, f, c0=None, base=None):
     """Network input (6 r + 2), target (2 r, or None) and nu from the
-    coordinates at k-1, k-2, k-3 (and k)."""
+    coordinates at k-1, k-2, k-3 (and k).  The target is the correction to
+    ``base`` (default: the quadratic extrapolation 3 c1 - 3 c2 + c3)."""
     c1, c2, c3 = (np.asarray(c, dtype=complex) for c in (c1, c2, c3))
     nu = float(np.linalg.norm(c1))
     if nu == 0.0:
@@ -163,22 +167,61 @@ def sample(c1, c2, c3, f, c0=None):
     x = np.concatenate([x, [f, f * f]])
     t = None
     if c0 is not None:
-        e = np.asarray(c0, dtype=complex) - (3 * c1 - 3 * c2 + c3)
+        b = (3 * c1 - 3 * c2 + c3) if base is None else np.asarray(base, dtype=complex)
+        e = np.asarray(c0, dtype=complex) - b
         t = np.concatenate([e.real, e.imag]) / nu
     return x, t, nu
 
 
-def compose(c1, c2, c3, nu, y):
-    """Predicted coordinates: 3 c1 - 3 c2 + c3 + nu (y_re + i y_im)."""
+# ---- the linear part of the prediction: a regularised least-squares map per
+# frequency from the three previous coordinate vectors to the next
+
+def ridge_fit(C, k, eps=1e-8):
+    """C: coordinates of the training cases, shape (n_cases, n_k, r).  For
+    frequency k >= 3 the history of case i is h_i = [c_{k-1}; c_{k-2};
+    c_{k-3}] (3 r) and its target y_i = c_k.  The map y = W X^H h minimises
+    sum_i |y_i - W X^H h_i|^2 + lam |W|^2-type penalty in its dual form:
+    with X = [h_1 .. h_n] (3 r x n), Y = [y_1 .. y_n] (r x n),
+    G = X^H X and lam = eps tr(G) / n, A = (G + lam I)^{-1} and W = Y A.
+    Returns X, W and diag(A)."""
+    C = np.asarray(C, dtype=complex)
+    X = np.concatenate([C[:, k - 1, :], C[:, k - 2, :], C[:, k - 3, :]], axis=1).T
+    Y = C[:, k, :].T
+    G = X.conj().T @ X
+    n = G.shape[0]
+    lam = eps * np.trace(G).real / n
+    A = np.linalg.inv(G + lam * np.eye(n))
+    return X, Y @ A, np.diag(A).copy()
+
+
+def ridge_predict(X, W, h):
+    """Prediction W X^H h for the history h = [c_{k-1}; c_{k-2}; c_{k-3}]."""
+    return W @ (X.conj().T @ np.asarray(h, dtype=complex))
+
+
+def ridge_loo(W, adiag):
+    """Leave-one-out residuals of the dual fit: y_i minus the prediction of a
+    fit without case i, which is column i of W divided by A_ii (the
+    Sherman-Morrison identity for the kernel form)."""
+    return W / np.asarray(adiag)[None, :]
+
+
+def compose(c1, c2, c3, nu, y, base=None):
+    """Predicted coordinates: base + nu (y_re + i y_im), base defaulting to
+    the quadratic extrapolation 3 c1 - 3 c2 + c3."""
     r = len(c1)
-    return 3 * np.asarray(c1) - 3 * np.asarray(c2) + np.asarray(c3) + nu * (y[:r] + 1j * y[r:])
+    b = (3 * np.asarray(c1) - 3 * np.asarray(c2) + np.asarray(c3)) if base is None else np.asarray(base)
+    return b + nu * (y[:r] + 1j * y[r:])
 
 
-def learned_column(a1, a2, a3, Phi, nu, y):
+def learned_column(a1, a2, a3, Phi, nu, y, base=None):
     """The learned column of the extrapolation: the quadratic extrapolation
-    of the last three solutions plus the network's correction in the basis,
-    3 a1 - 3 a2 + a3 + Phi nu (y_re + i y_im).  With c_j = Phi^H a_j its
-    coordinates are compose(c1, c2, c3, nu, y), and its part outside the
-    basis is that of the extrapolation."""
-    r = Phi.shape[1]
-    return 3 * np.asarray(a1) - 3 * np.asarray(a2) + np.asarray(a3) + Phi @ (nu * (y[:r] + 1j * y[r:]))
+    of the last three solutions with its coordinates replaced by the
+    prediction, 3 a1 - 3 a2 + a3 + Phi (p - (3 c1 - 3 c2 + c3)) where
+    p = compose(c1, c2, c3, nu, y, base) and c_j = Phi^H a_j.  Its part
+    outside the basis is that of the extrapolation."""
+    a1, a2, a3 = (np.asarray(a) for a in (a1, a2, a3))
+    c = [Phi.conj().T @ a for a in (a1, a2, a3)]
+    q = 3 * c[0] - 3 * c[1] + c[2]
+    p = compose(c[0], c[1], c[2], nu, y, base)
+    return 3 * a1 - 3 * a2 + a3 + Phi @ (p - q)

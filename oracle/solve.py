@@ -74,3 +74,21 @@ def transient_incident_s(xyz, tri, mat_params, period, n_f, sigma, window_kind, 
         spec[k] = np.linalg.solve(T, phat[k] * (U @ t_sc))
     u = mft.inverse(spec, period, sigma, window_kind)
     return dict(s=s_k, phat=phat, spec=spec, u=u, geom=geom, mat=mat)
+
+
+def transient_incident_s_total(xyz, tri, mat_params, period, n_f, sigma, window_kind, direction,
+                               polarisation, history, self_order=24):
+    """Total displacement on traction-free cavities under the same plane
+    S-wave, total-field formulation: b_k = F_k u_inc(x_i, s_k), A_k = T(s_k).
+
+    Returns dict(s, phat, spec (N_f/2+1, N), u (N_f, N))."""
+    mat = material(**mat_params)
+    geom = bem.geometry(xyz, tri, exterior=True)
+    s_k = mft.freq_grid(period, n_f, sigma)
+    phat = mft.load_spectrum(history, period, sigma)
+    spec = np.zeros((len(s_k), 3 * geom["ne"]), np.complex128)
+    for k, s in enumerate(s_k):
+        T, _ = bem.assemble_dense(geom, s, mat, self_order=self_order)
+        spec[k] = np.linalg.solve(T, phat[k] * bem.incident_s_total_rhs(geom, s, mat, direction, polarisation))
+    u = mft.inverse(spec, period, sigma, window_kind)
+    return dict(s=s_k, phat=phat, spec=spec, u=u, geom=geom, mat=mat)

@@ -691,6 +691,24 @@ __global__ void k_to_c64(const FarBlk* __restrict__ blks, const int* __restrict_
   for (long long i = threadIdx.x; i < nvv; i += blockDim.x) Vo[i] = to_cf(B.V[i]);
 }
 
+// The same conversion for the blocks ids[0..n) into per-block destinations.
+__global__ void k_to_c64_ptr(const FarBlk* __restrict__ blks, const int* __restrict__ ids,
+                             const int* __restrict__ rank, cf* const* __restrict__ up, cf* const* __restrict__ vp) {
+  const int b = ids[blockIdx.x];
+  const FarBlk B = blks[b];
+  const int k = rank[b];
+  const long long nu = 3LL * B.m * k, nvv = 3LL * B.n * k;
+  cf* Uo = up[blockIdx.x];
+  cf* Vo = vp[blockIdx.x];
+  for (long long i = threadIdx.x; i < nu; i += blockDim.x) Uo[i] = to_cf(B.U[i]);
+  for (long long i = threadIdx.x; i < nvv; i += blockDim.x) Vo[i] = to_cf(B.V[i]);
+}
+
+void launch_to_c64_ptr(const FarBlk* blks, const int* ids, int n, const int* rank, cf* const* up, cf* const* vp,
+                       hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_to_c64_ptr, dim3(n), dim3(256), 0, st, blks, ids, rank, up, vp);
+}
+
 void launch_to_c64(const FarBlk* blks, int nblk, const int* rank, const long long* uo,
                    const long long* vo, cf* out, hipStream_t st) {
   if (nblk > 0) hipLaunchKernelGGL(k_to_c64, dim3(nblk), dim3(256), 0, st, blks, rank, uo, vo, out);

@@ -87,6 +87,10 @@ void launch_aca_step(const AcaLists& L, const AcaWork& W, const DevGeom& g, cons
 void launch_aca_finish(const int* ids, int n, const AcaState* st, int* rank, int* status, hipStream_t s);
 void launch_to_c64(const FarBlk* blks, int nblk, const int* rank, const long long* uo,
                    const long long* vo, cf* out, hipStream_t st);
+// The blocks ids[0..n): factors to complex64 at up[i], vp[i] (device arrays
+// of device pointers).
+void launch_to_c64_ptr(const FarBlk* blks, const int* ids, int n, const int* rank, cf* const* up, cf* const* vp,
+                       hipStream_t st);
 
 // ---- Warm start from the previous frequency's pivots.
 // A block whose previous approximation accepted pivots in row elements
@@ -130,7 +134,17 @@ constexpr int WS_LDS_MID = 4480;
 constexpr int WS_LDS_LARGE = 8960;
 constexpr int WS_CH = 8;             // substitution terms solved together in registers (coefficient padding)
 constexpr int WS_LU_NR_LDS = 2;     // LDS classes hold cores of at most 128 rows
-void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s);
+// Side streams and events on which launch_ws runs independent kernels
+// concurrently (the row and column evaluations; the five core-elimination
+// size classes; the U and V substitutions); null streams: everything on s.
+constexpr int WS_SIDE = 4;
+struct WsStreams {
+  hipStream_t side[WS_SIDE] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork[3] = {nullptr, nullptr, nullptr};        // recorded on s
+  hipEvent_t done[3][WS_SIDE] = {};                        // recorded on the side streams
+};
+void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s,
+               const WsStreams* ss = nullptr);
 
 // ---- H-matrix matvec
 // Phase 1 task: z[zidx + j] = sum_c V[c, j] x[x0 + c] for j < ncol, with V

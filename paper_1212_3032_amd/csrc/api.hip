@@ -99,6 +99,11 @@ struct LearnedModel {
   std::vector<float> params;               // flat fp32 parameters
   std::vector<std::complex<double>> phi;   // basis, N x r column-major, caller dof order
   double energy = 0, loss0 = 0, loss1 = 0;  // training snapshots' energy in the basis; fit losses
+  // the least-squares map of each frequency k = 3 .. rk - 1 over rn training
+  // loads (rn = 0: none): X_k (3 r x rn) and W_k (r x rn), column-major,
+  // frequency after frequency; the prediction is W_k X_k^H [c1; c2; c3]
+  int rn = 0, rk = 0;
+  std::vector<std::complex<double>> rx, rw;
 };
 }  // namespace
 
@@ -121,6 +126,7 @@ struct ewbem_ctx {
   bool load_is_pressure = false;
   // plane S-wave incident load: u_inc = pol f(t - dir . x / c_s), f Ricker
   bool load_incident = false;
+  bool inc_total = false;  // total-field formulation: b = u_inc, the unknown is u_sc + u_inc
   double inc_dir[3] = {1, 0, 0}, inc_pol[3] = {0, 0, 1}, inc_fc = 0, inc_t0 = 0;
   std::vector<int> bc_caller;       // empty: every element has a given traction
   std::vector<double> load_caller;  // t0 (nt*3) or p (nt), caller order
@@ -154,12 +160,20 @@ struct ewbem_ctx {
   DevBuf<cd> d_wsf[2];
   int fslot = 0;
   hipStream_t astream = nullptr;  // the overlapped ACA's stream (library-owned)
+  WsStreams ws_streams;           // the warm start's side streams and events (library-owned)
   // one buffer per capacity-retry round of the current frequency; all stay
   // alive until the next frequency is assembled (blocks retried in an
   // earlier round keep pointing into their round's buffer)
   std::vector<std::unique_ptr<DevBuf<cd>>> d_retry[2];
   DevBuf<cf> d_f32;
   DevBuf<long long> d_uo, d_vo;
+  // streamed complex64 store (op.aca_batch_mb > 0): chunks filled in block
+  // order as the batches finish; block b's factors at u32_h[b], v32_h[b]
+  std::vector<std::unique_ptr<DevBuf<cf>>> d_f32s;
+  std::vector<cf*> u32_h, v32_h;
+  bool streamed = false;  // the factors in use came from a streamed run
+  DevBuf<int> d_batch_ids;
+  DevBuf<cf*> d_u32p, d_v32p;
   DevBuf<int> d_rank, d_status;
   // lock-step ACA: per-block state, used-row bits, active lists and scans
   DevBuf<AcaState> d_acast;
@@ -208,6 +222,7 @@ struct ewbem_ctx {
   LearnedModel lm;
   bool lm_dev = false;  // device copies of lm current
   DevBuf<cd> d_phi, d_lcoef, d_lpred, d_lx;
+  DevBuf<cd> d_rx, d_rw, d_lh, d_lz, d_lbase;  // least-squares map and its inference buffers
   DevBuf<float> d_lp, d_lfeat, d_lact, d_lpre, d_ly, d_lkf;
   DevBuf<int> d_lidx;
   DevBuf<double> d_lnu;
@@ -377,6 +392,16 @@ void learned_upload(ewbem_ctx* c) {
     }
   c->d_phi.upload(ph, st);
   c->d_lp.upload(m.params, st);
+  if (m.rn > 0) {
+    std::vector<cd> rx(m.rx.size()), rw(m.rw.size());
+    for (size_t i = 0; i < rx.size(); ++i) rx[i] = cd{m.rx[i].real(), m.rx[i].imag()};
+    for (size_t i = 0; i < rw.size(); ++i) rw[i] = cd{m.rw[i].real(), m.rw[i].imag()};
+    c->d_rx.upload(rx, st);
+    c->d_rw.upload(rw, st);
+    c->d_lh.reserve(3 * (size_t)r);
+    c->d_lz.reserve(m.rn);
+    c->d_lbase.reserve(r);
+  }
   const int L = m.shape.n_layers();
   c->d_lcoef.reserve(3 * (size_t)r);
   c->d_lpred.reserve(r);
@@ -388,7 +413,7 @@ void learned_upload(ewbem_ctx* c) {
   c->d_lkf.reserve(1);
   c->d_lidx.reserve(4);
   c->d_lnu.reserve(1);
-  c->d_hpart.reserve((size_t)dots_chunks(N) * r);
+  c->d_hpart.reserve((size_t)dots_chunks(N) * std::max(r, m.rn));
   c->lc_slot.clear();
   c->lc_kidx.clear();
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -407,6 +432,13 @@ void ensure_device(ewbem_ctx* c) {
   }
   EWBEM_HIP_CHECK(hipSetDevice(c->device));
   if (!c->astream) EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking));
+  if (!c->ws_streams.side[0]) {
+    WsStreams& w = c->ws_streams;
+    for (hipEvent_t& e : w.fork) EWBEM_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& row : w.done)
+      for (hipEvent_t& e : row) EWBEM_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (hipStream_t& q : w.side) EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+  }
   hipStream_t st = c->stream;
   const HostGeom& g = c->hg;
   c->d_cen.upload(g.cen, st);
@@ -583,7 +615,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     WsArgs A{c->d_wsb.p, nw, c->d_wsoff.p, c->d_wsoff.p + (nw + 1), c->d_wsoff.p + 2 * (nw + 1),
              c->d_wsoff.p + 3 * (nw + 1), (int)er, (int)ec, (int)tu, (int)tv, c->d_cross.p, c->d_wspq.p,
              c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p, {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4]}};
-    launch_ws(A, W0, g, c->P, c->op.aca_tol, st);
+    launch_ws(A, W0, g, c->P, c->op.aca_tol, st, &c->ws_streams);
   }
   if (count_starts) {
     c->acc.aca_warm_blocks += nw;
@@ -628,7 +660,10 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
   launch_aca_finish(c->d_aca_ids.p, n, c->d_acast.p, c->d_rank.p, c->d_status.p, st);
 }
 
-// Far factors of every block into factor slot ``slot`` on stream st.
+// Far factors of every block into factor slot ``slot`` on stream st.  With
+// op.aca_batch_mb > 0 the blocks go in batches through one complex128 work
+// area, each batch converted into the streamed complex64 store as it
+// finishes.
 void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipStream_t st, int slot) {
   const int nf = (int)c->far_h.size();
   if (nf == 0) return;
@@ -663,20 +698,62 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipS
     want = ((want + 2) / 3) * 3;
     kcap[b] = std::max(3, std::min({want, full, ACA_KMAX}));
   }
-  // main layout (the previous frequency's retry buffers are no longer used)
-  c->d_retry[slot].clear();
-  long long total = 0, words = 0;
-  for (int b = 0; b < nf; ++b) total += (long long)(3 * c->far_h[b].m + 3 * c->far_h[b].n) * kcap[b];
+  // batches of blocks (one batch of all unless streamed)
+  const bool streamed = c->op.aca_batch_mb > 0 && c->op.far_store == EWBEM_STORE_C64;
+  std::vector<std::vector<int>> batches(1);
+  if (streamed) {
+    const double budget = (double)c->op.aca_batch_mb * 1048576.0;
+    double acc = 0;
+    for (int b = 0; b < nf; ++b) {
+      const FarBlk& f = c->far_h[b];
+      const double nr = c->nlist_h[2 * b], nc = c->nlist_h[2 * b + 1];
+      const double rc = 3.0 * std::min(nr, nc);
+      const double need = 16.0 * (3.0 * (f.m + f.n) * kcap[b] + 9.0 * (nr * f.n + nc * f.m + nr * nc) +
+                                  2.0 * (rc + 8) * rc);
+      if (!batches.back().empty() && acc + need > budget) {
+        batches.emplace_back();
+        acc = 0;
+      }
+      batches.back().push_back(b);
+      acc += need;
+    }
+  } else {
+    batches[0].resize(nf);
+    for (int b = 0; b < nf; ++b) batches[0][b] = b;
+  }
+  c->streamed = streamed;
+  if (streamed) {
+    c->u32_h.assign(nf, nullptr);
+    c->v32_h.assign(nf, nullptr);
+  }
+  size_t chunk_i = 0, chunk_used = 0;  // fill position in the streamed store
+  auto store_alloc = [&](size_t n) -> cf* {
+    constexpr size_t kChunk = size_t(1) << 29;  // 4 GiB of complex64 entries
+    while (true) {
+      if (chunk_i < c->d_f32s.size() && chunk_used + n <= c->d_f32s[chunk_i]->n) {
+        cf* p = c->d_f32s[chunk_i]->p + chunk_used;
+        chunk_used += n;
+        return p;
+      }
+      if (chunk_i < c->d_f32s.size() && chunk_used > 0) {  // next chunk
+        ++chunk_i;
+        chunk_used = 0;
+        continue;
+      }
+      if (chunk_i >= c->d_f32s.size()) {
+        c->d_f32s.emplace_back(new DevBuf<cf>());
+        c->d_f32s.back()->reserve(std::max(n, kChunk));
+      } else {
+        // an existing, empty chunk too small for this block: a larger one in its place
+        c->d_f32s[chunk_i]->reserve(n);
+      }
+    }
+  };
   DevBuf<cd>& ws = c->d_wsf[slot];
-  ws.reserve_grow(total);
-  long long off = 0;
+  c->d_retry[slot].clear();
+  long long words = 0;
   for (int b = 0; b < nf; ++b) {
     FarBlk& f = c->far_h[b];
-    f.kcap = kcap[b];
-    f.U = ws.p + off;
-    off += 3LL * f.m * kcap[b];
-    f.V = ws.p + off;
-    off += 3LL * f.n * kcap[b];
     if (words > INT32_MAX - 1024) fail(EWBEM_EINVAL, "too many far blocks");
     f.bitoff = (int)words;
     words += (f.m + 31) / 32;
@@ -684,56 +761,92 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipS
   c->d_used.reserve(words);
   c->d_acast.reserve(nf);
   c->d_acaplan.reserve(nf);
-  c->d_far.upload(c->far_h, st);
   c->d_rank.reserve(nf);
   c->d_status.reserve(nf);
-  std::vector<int> all(nf);
-  for (int b = 0; b < nf; ++b) all[b] = b;
-  EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-  aca_lockstep(c, g, all, warm, true, st);
-  EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
-  EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
-  EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
-  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
-  aca_ms += ev.elapsed();
-  // retries for blocks that ran out of capacity, in a separate buffer
-  for (int round = 0; round < 8; ++round) {
-    std::vector<int> over;
-    for (int b = 0; b < nf; ++b)
-      if (c->status_h[b] != 0) over.push_back(b);
-    if (over.empty()) break;
-    long long tot2 = 0;
-    for (int b : over) {
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const std::vector<int>& ids = batches[bi];
+    // main layout (the previous batch's or frequency's retry buffers are no
+    // longer used)
+    c->d_retry[slot].clear();
+    long long total = 0;
+    for (int b : ids) total += (long long)(3 * c->far_h[b].m + 3 * c->far_h[b].n) * kcap[b];
+    if (streamed)
+      ws.reserve(std::max<long long>(total, 1));
+    else
+      ws.reserve_grow(total);
+    long long off = 0;
+    for (int b : ids) {
       FarBlk& f = c->far_h[b];
-      const int full = 3 * std::min(f.m, f.n) + 2;
-      if (f.kcap >= std::min(full, ACA_KMAX))
-        fail(EWBEM_EINVAL, "ACA rank exceeds the per-block limit of 1024");
-      f.kcap = std::min({full, ACA_KMAX, 2 * f.kcap + 6});
-      tot2 += (long long)(3 * f.m + 3 * f.n) * f.kcap;
-    }
-    c->d_retry[slot].emplace_back(new DevBuf<cd>());
-    DevBuf<cd>& buf = *c->d_retry[slot].back();
-    buf.reserve(tot2);
-    long long o2 = 0;
-    for (int b : over) {
-      FarBlk& f = c->far_h[b];
-      f.U = buf.p + o2;
-      o2 += 3LL * f.m * f.kcap;
-      f.V = buf.p + o2;
-      o2 += 3LL * f.n * f.kcap;
+      f.kcap = kcap[b];
+      f.U = ws.p + off;
+      off += 3LL * f.m * kcap[b];
+      f.V = ws.p + off;
+      off += 3LL * f.n * kcap[b];
     }
     c->d_far.upload(c->far_h, st);
     EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-    aca_lockstep(c, g, over, false, false, st);
+    aca_lockstep(c, g, ids, warm, true, st);
     EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
     aca_ms += ev.elapsed();
-  }
-  for (int b = 0; b < nf; ++b) {
-    if (c->status_h[b] != 0) fail(EWBEM_EINVAL, "ACA did not converge within its capacity");
-    c->kcap_prev[b] = c->far_h[b].kcap;
+    // retries for blocks that ran out of capacity, in a separate buffer
+    for (int round = 0; round < 8; ++round) {
+      std::vector<int> over;
+      for (int b : ids)
+        if (c->status_h[b] != 0) over.push_back(b);
+      if (over.empty()) break;
+      long long tot2 = 0;
+      for (int b : over) {
+        FarBlk& f = c->far_h[b];
+        const int full = 3 * std::min(f.m, f.n) + 2;
+        if (f.kcap >= std::min(full, ACA_KMAX))
+          fail(EWBEM_EINVAL, "ACA rank exceeds the per-block limit of 1024");
+        f.kcap = std::min({full, ACA_KMAX, 2 * f.kcap + 6});
+        tot2 += (long long)(3 * f.m + 3 * f.n) * f.kcap;
+      }
+      c->d_retry[slot].emplace_back(new DevBuf<cd>());
+      DevBuf<cd>& buf = *c->d_retry[slot].back();
+      buf.reserve(tot2);
+      long long o2 = 0;
+      for (int b : over) {
+        FarBlk& f = c->far_h[b];
+        f.U = buf.p + o2;
+        o2 += 3LL * f.m * f.kcap;
+        f.V = buf.p + o2;
+        o2 += 3LL * f.n * f.kcap;
+      }
+      c->d_far.upload(c->far_h, st);
+      EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
+      aca_lockstep(c, g, over, false, false, st);
+      EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
+      EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+      EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      aca_ms += ev.elapsed();
+    }
+    for (int b : ids) {
+      if (c->status_h[b] != 0) fail(EWBEM_EINVAL, "ACA did not converge within its capacity");
+      if (c->rank_h[b] < 0 || c->rank_h[b] > c->far_h[b].kcap) fail(EWBEM_EINVAL, "internal: rank outside capacity");
+      c->kcap_prev[b] = c->far_h[b].kcap;
+    }
+    if (streamed) {
+      // this batch into the complex64 store, before its work area is reused
+      std::vector<cf*> up(ids.size()), vp(ids.size());
+      for (size_t i = 0; i < ids.size(); ++i) {
+        const FarBlk& f = c->far_h[ids[i]];
+        const int k = c->rank_h[ids[i]];
+        up[i] = c->u32_h[ids[i]] = store_alloc(std::max<size_t>(1, 3 * (size_t)f.m * k));
+        vp[i] = c->v32_h[ids[i]] = store_alloc(std::max<size_t>(1, 3 * (size_t)f.n * k));
+      }
+      c->d_batch_ids.upload(ids, st);
+      c->d_u32p.upload(up, st);
+      c->d_v32p.upload(vp, st);
+      launch_to_c64_ptr(c->d_far.p, c->d_batch_ids.p, (int)ids.size(), c->d_rank.p, c->d_u32p.p, c->d_v32p.p, st);
+      EWBEM_HIP_CHECK(hipGetLastError());
+      EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // up, vp and the work area
+    }
   }
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->nlist_h.data(), c->d_nlist.p, 2 * (size_t)nf * sizeof(int),
                                  hipMemcpyDeviceToHost, st));
@@ -749,7 +862,25 @@ bool in_alloc(const void* p, long long n_bytes, const void* base, size_t base_by
   return base && a >= b && n_bytes >= 0 && a + n_bytes <= b + base_bytes;
 }
 
+// The streamed store's chunk holding [p, p + n).
+bool in_f32_chunks(const ewbem_ctx* c, const void* p, long long n_bytes) {
+  for (const auto& ch : c->d_f32s)
+    if (in_alloc(p, n_bytes, ch->p, ch->n * sizeof(cf))) return true;
+  return false;
+}
+
 void check_far_ranges(ewbem_ctx* c) {
+  if (c->streamed) {  // the complex128 pointers are stale: check the complex64 store
+    for (size_t b = 0; b < c->far_h.size(); ++b) {
+      const FarBlk& f = c->far_h[b];
+      const long long k = c->rank_h[b];
+      if (k < 0 || k > f.kcap) fail(EWBEM_EINVAL, "internal: rank outside capacity");
+      if (!in_f32_chunks(c, c->u32_h[b], 3LL * f.m * std::max(1LL, k) * (long long)sizeof(cf)) ||
+          !in_f32_chunks(c, c->v32_h[b], 3LL * f.n * std::max(1LL, k) * (long long)sizeof(cf)))
+        fail(EWBEM_EINVAL, "internal: streamed factor range outside its chunk");
+    }
+    return;
+  }
   for (size_t b = 0; b < c->far_h.size(); ++b) {
     const FarBlk& f = c->far_h[b];
     const long long nu = 3LL * f.m * f.kcap * (long long)sizeof(cd), nv = 3LL * f.n * f.kcap * (long long)sizeof(cd);
@@ -785,7 +916,10 @@ void build_matvec(ewbem_ctx* c) {
   }
   c->z_len = std::max<long long>(1, zoff[nf]);
   c->d_z.reserve_grow((size_t)HMV_MAXRHS * c->z_len);
-  if (c64) {
+  const bool streamed = c64 && c->streamed;  // factors already in the streamed store
+  auto u32 = [&](int b) -> const cf* { return streamed ? c->u32_h[b] : c->d_f32.p + uo[b]; };
+  auto v32 = [&](int b) -> const cf* { return streamed ? c->v32_h[b] : c->d_f32.p + vo[b]; };
+  if (c64 && !streamed) {
     c->d_f32.reserve_grow(std::max<long long>(1, f32tot));
     c->d_uo.upload(uo, st);
     c->d_vo.upload(vo, st);
@@ -799,7 +933,7 @@ void build_matvec(ewbem_ctx* c) {
     const int k = c->rank_h[b], C = 3 * f.n;
     for (int l0 = 0; l0 < k; l0 += vc) {
       VtTask t{};
-      t.V = c64 ? (const void*)(c->d_f32.p + vo[b] + (size_t)l0 * C) : (const void*)(f.V + (size_t)l0 * C);
+      t.V = c64 ? (const void*)(v32(b) + (size_t)l0 * C) : (const void*)(f.V + (size_t)l0 * C);
       t.zidx = zoff[b] + l0;
       t.C = C;
       t.x0 = 3 * f.c0;
@@ -839,7 +973,7 @@ void build_matvec(ewbem_ctx* c) {
       const Cluster& L = c->part.clusters[leaves[li]];
       Seg s{};
       const size_t roff = 3 * (size_t)(L.begin - f.r0);
-      s.A = c64 ? (const void*)(c->d_f32.p + uo[b] + roff) : (const void*)(f.U + roff);
+      s.A = c64 ? (const void*)(u32(b) + roff) : (const void*)(f.U + roff);
       s.src = zoff[b];
       s.ld = 3 * f.m;
       s.ncols = k;
@@ -886,6 +1020,7 @@ void build_matvec(ewbem_ctx* c) {
   {
     const long long ztot = zoff[nf];
     auto store_ok = [&](const void* p, long long bytes) {
+      if (streamed) return in_f32_chunks(c, p, bytes);
       if (c64) return in_alloc(p, bytes, c->d_f32.p, c->d_f32.n * sizeof(cf));
       bool ok = in_alloc(p, bytes, c->d_wsf[c->fslot].p, c->d_wsf[c->fslot].n * sizeof(cd));
       for (const auto& r : c->d_retry[c->fslot]) ok = ok || in_alloc(p, bytes, r->p, r->n * sizeof(cd));
@@ -1020,6 +1155,11 @@ void precond_apply(ewbem_ctx* c, const cd* v, cd* z) {
 
 // Off-diagonal U(s_k) t0 for frequencies k0 .. k0+nk-1 in one batched pass.
 void rhs_precompute(ewbem_ctx* c, const DevGeom& g, int k0, int nk) {
+  if (c->inc_total) {  // b is the incident displacement itself: no sums
+    c->boff_k0 = k0;
+    c->boff_nk = nk;
+    return;
+  }
   const size_t need = (size_t)rhs_split(c->nt) * nk * 3 * (size_t)c->nt;
   c->d_rhs_part.reserve(need);
   launch_rhs_multi(g, c->P, c->sigma, 2.0 * M_PI / c->period, k0, nk, c->d_t0.p,
@@ -1033,6 +1173,10 @@ double dev_norm(ewbem_ctx* c, const cd* v);
 // b_k of the current load from its off-diagonal sums (d_rhs_part) and the
 // self elements' U of the assembled frequency.
 void rhs_finish_k(ewbem_ctx* c, int k) {
+  if (c->inc_total) {
+    launch_rhs_total(c->d_tau.p, c->inc_pol, s_of_k(c, k), c->d_phat.p + k, c->nt, c->d_b.p, c->stream);
+    return;
+  }
   launch_rhs_finish(c->d_rhs_part.p, c->boff_nk, k - c->boff_k0, c->nt, c->d_selfU.p, c->d_t0.p,
                     c->load_incident ? c->d_tau.p : nullptr, s_of_k(c, k), c->d_phat.p + k, c->d_b.p, c->stream);
 }
@@ -1575,11 +1719,24 @@ const cd* learned_guess(ewbem_ctx* c, int k) {
   const float kf = (float)k / (float)(c->n_f / 2);
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_lidx.p, idx, sizeof(idx), hipMemcpyHostToDevice, st));
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_lkf.p, &kf, sizeof(float), hipMemcpyHostToDevice, st));
-  launch_learn_samples(c->d_lcoef.p, r, c->d_lidx.p, c->d_lkf.p, 1, c->d_lfeat.p, nullptr, c->d_lnu.p, st);
+  launch_learn_samples(c->d_lcoef.p, nullptr, r, c->d_lidx.p, c->d_lkf.p, 1, c->d_lfeat.p, nullptr, c->d_lnu.p, st);
   mlp_forward(c->lm.shape, c->d_lp.p, 1, c->d_lfeat.p, c->d_lact.p, c->d_lpre.p, c->d_ly.p, st);
+  // the least-squares map's prediction W_k X_k^H [c1; c2; c3] as the base
+  // the network corrects (when the model has one for this frequency grid)
+  const cd* bp = nullptr;
+  const LearnedModel& m = c->lm;
+  if (m.rn > 0 && m.rk == c->n_f / 2 + 1 && k < m.rk) {
+    const size_t xs = 3 * (size_t)r * m.rn, wsz = (size_t)r * m.rn;
+    for (int j = 0; j < 3; ++j)
+      EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_lh.p + (size_t)j * r, c->d_lcoef.p + (size_t)idx[j] * r, r * sizeof(cd),
+                                     hipMemcpyDeviceToDevice, st));
+    launch_dots(c->d_rx.p + (size_t)(k - 3) * xs, 3 * r, m.rn, c->d_lh.p, 3 * r, c->d_hpart.p, c->d_lz.p, st);
+    launch_gemv_acc(c->d_rw.p + (size_t)(k - 3) * wsz, r, m.rn, c->d_lz.p, cd{0.0, 0.0}, c->d_lbase.p, r, st);
+    bp = c->d_lbase.p;
+  }
   const bool full = c->hist_kidx.size() >= 3 && c->hist_kidx[0] == k - 1 && c->hist_kidx[1] == k - 2 &&
                     c->hist_kidx[2] == k - 3;
-  launch_learn_compose(c->d_lcoef.p, r, c->d_lidx.p, c->d_lnu.p, c->d_ly.p, full ? 0 : 1, c->d_lpred.p, st);
+  launch_learn_compose(c->d_lcoef.p, r, c->d_lidx.p, c->d_lnu.p, c->d_ly.p, bp, full ? 1 : 0, c->d_lpred.p, st);
   std::vector<cd> cx(std::max(1, c->so.sem_k), cd{0, 0});
   if (full) {
     const int ncap = (int)cx.size();
@@ -1690,6 +1847,8 @@ int frequency_loop(ewbem_ctx* c) {
   // the far factors of k + 1 are approximated on the library's second
   // stream by a second host thread, into the factor slot the matvec of k
   // does not read; the rest of k + 1's assembly follows the solve
+  if (c->so.pipeline && c->op.aca_batch_mb > 0)
+    fail(EWBEM_EINVAL, "the pipeline needs the whole complex128 far field (aca_batch_mb = 0)");
   const bool pipe = c->so.pipeline && !c->far_h.empty();
   for (int k = 0; k < nk; ++k) {
     if (!pipe || k + 1 == nk) {
@@ -2170,10 +2329,11 @@ MlpShape mlp_shape(int n_layers, const int32_t* dims) {
 // then fp64 energy, loss0, loss1, then the fp32 parameters, then the basis
 // (n_dof x r complex128, column-major, caller dof order).
 constexpr char kModelMagic[8] = {'E', 'W', 'B', 'G', 'U', 'E', 'S', 'S'};
-constexpr int32_t kModelVersion = 1;
+constexpr int32_t kModelVersion = 2;  // 1: without the least-squares map (still read)
 
 size_t model_bytes(const LearnedModel& m, long long N) {
-  return 8 + 4 * (4 + m.shape.dims.size()) + 3 * 8 + 4 * m.params.size() + 16 * (size_t)N * m.r;
+  return 8 + 4 * (4 + m.shape.dims.size()) + 3 * 8 + 4 * m.params.size() + 16 * (size_t)N * m.r + 8 +
+         16 * (m.rx.size() + m.rw.size());
 }
 
 }  // namespace
@@ -2286,6 +2446,18 @@ void ewbem_destroy(ewbem_ctx* ctx) {
       (void)hipStreamDestroy(ctx->astream);
       ctx->astream = nullptr;
     }
+    WsStreams& w = ctx->ws_streams;
+    for (hipStream_t& q : w.side)
+      if (q) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+        q = nullptr;
+      }
+    for (hipEvent_t& e : w.fork)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& row : w.done)
+      for (hipEvent_t& e : row)
+        if (e) (void)hipEventDestroy(e);
   }
   delete ctx;
 }
@@ -2380,6 +2552,7 @@ static int set_load(ewbem_ctx* ctx, const double* v, size_t nv_, const double* h
     ctx->history.assign(history, history + ctx->n_f);
     ctx->load_is_pressure = pressure;
     ctx->load_incident = false;
+    ctx->inc_total = false;
     ctx->have_load = true;
     ctx->device_ok = false;
     ctx->assembled_k = -1;
@@ -2406,8 +2579,8 @@ int ewbem_set_load_mixed(ewbem_ctx* ctx, const int32_t* bc, const double* values
   return set_load(ctx, values, 3 * (size_t)ctx->nt, history, false, bc);
 }
 
-int ewbem_set_load_incident_s(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
-                              double t0) {
+static int set_incident(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc, double t0,
+                        bool total) {
   return guard(ctx, [&] {
     if (!ctx->have_mesh || !ctx->have_time) fail(EWBEM_ESTATE, "load: set the mesh and time grid first");
     if (!dir || !pol) fail(EWBEM_EINVAL, "incident wave: null direction or polarisation");
@@ -2440,11 +2613,22 @@ int ewbem_set_load_incident_s(ewbem_ctx* ctx, const double* dir, const double* p
     ctx->load_caller.clear();
     ctx->load_is_pressure = false;
     ctx->load_incident = true;
+    ctx->inc_total = total;
     ctx->have_load = true;
     ctx->device_ok = false;
     ctx->assembled_k = -1;
     return EWBEM_OK;
   });
+}
+
+int ewbem_set_load_incident_s(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
+                              double t0) {
+  return set_incident(ctx, dir, pol, ricker_fc, t0, false);
+}
+
+int ewbem_set_load_incident_s_total(ewbem_ctx* ctx, const double* dir, const double* pol, double ricker_fc,
+                                    double t0) {
+  return set_incident(ctx, dir, pol, ricker_fc, t0, true);
 }
 
 int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
@@ -2454,7 +2638,8 @@ int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
         !(o->eta_adm > 0) || !(o->aca_tol > 0 && o->aca_tol < 1) ||
         (o->far_store != EWBEM_STORE_C128 && o->far_store != EWBEM_STORE_C64) || o->self_order < 4 ||
         o->self_order > MAX_SELF_ORDER || (o->aca_reuse != 0 && o->aca_reuse != 1) ||
-        (o->autotune != 0 && o->autotune != 1))
+        (o->autotune != 0 && o->autotune != 1) || o->aca_batch_mb < 0 ||
+        (o->aca_batch_mb > 0 && (o->far_store != EWBEM_STORE_C64 || o->kind != EWBEM_OP_HMAT)))
       fail(EWBEM_EINVAL, "operator options out of range");
     ctx->op = *o;
     ctx->structure_ok = false;
@@ -2751,6 +2936,9 @@ int ewbem_solve_transient_incident_loads(ewbem_ctx* ctx, int32_t n_loads, const 
   return guard(ctx, [&] {
     if (n_loads < 1 || !dirs || !pols || !u)
       fail(EWBEM_EINVAL, "solve_transient_incident_loads: need n_loads >= 1, directions, polarisations and u");
+    if (ctx->inc_total)
+      fail(EWBEM_ESTATE, "solve_transient_incident_loads: the scattered-field formulation only "
+                         "(set the wave with ewbem_set_load_incident_s)");
     if (!ctx->have_mesh || !ctx->have_time || !ctx->have_load || !ctx->load_incident)
       fail(EWBEM_ESTATE, "solve_transient_incident_loads: set the mesh, time grid and an incident wave (its "
                          "wavelet is used) first");
@@ -2793,6 +2981,8 @@ void ewbem_default_train_opts(ewbem_train_opts* o) {
   o->seed = 1;
   o->augment = 4;
   o->unit_snapshots = 1;
+  o->lsq_map = 1;
+  o->lsq_reg = 1e-8;
 }
 
 int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, const ewbem_train_opts* o,
@@ -2802,7 +2992,8 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     if (o->n_modes < 1 || o->n_modes > 1024 || o->hidden < 1 || o->hidden > 4096 || o->n_hidden < 0 ||
         o->n_hidden > 8 || o->epochs < 0 || o->epochs > 1000000 || !(o->lr > 0) || !std::isfinite(o->lr) ||
         o->power_iters < 0 || o->power_iters > 10 || (o->load_kind != 0 && o->load_kind != 1) ||
-        o->augment < 0 || o->augment > 64 || (o->unit_snapshots != 0 && o->unit_snapshots != 1))
+        o->augment < 0 || o->augment > 64 || (o->unit_snapshots != 0 && o->unit_snapshots != 1) ||
+        (o->lsq_map != 0 && o->lsq_map != 1) || !(o->lsq_reg > 0 && o->lsq_reg < 1))
       fail(EWBEM_EINVAL, "guess_train: options out of range");
     if (!ctx->have_mesh || !ctx->have_time || !ctx->have_load)
       fail(EWBEM_ESTATE, "guess_train: set the mesh, time grid and a load (its history is used) first");
@@ -2858,15 +3049,54 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     for (int m = 0; m < M; ++m) launch_dots(phi.p, N, r, S.p + (size_t)m * N, N, part.p, coef.p + (size_t)m * r, st);
     if (o->unit_snapshots) launch_col_scale(coef.p, r, M, r, snorm.p, 0, st);  // the raw snapshots' coordinates
     S.release();
+    // the least-squares map of each frequency over the training loads
+    // (small dense algebra on the host: an n_cases x n_cases Gram matrix per
+    // frequency), and its leave-one-out predictions, the base the network
+    // learns to correct: for a load outside the fit the map's error is what
+    // the leave-one-out residuals sample
+    std::vector<zc> rxh, rwh;
+    int rn = 0;
+    DevBuf<cd> base;
+    if (o->lsq_map && n_cases >= 2) {
+      const std::vector<zc> C = to_host(ctx, coef.p, (size_t)M * r);
+      std::vector<cd> bh((size_t)M * r, cd{0.0, 0.0});
+      std::vector<zc> X((size_t)3 * r * n_cases), Y((size_t)r * n_cases), W;
+      std::vector<double> ad;
+      for (int k = 3; k < nk; ++k) {
+        for (int i = 0; i < n_cases; ++i)
+          for (int j = 0; j < r; ++j) {
+            const size_t b = (size_t)i * nk;
+            X[(size_t)i * 3 * r + j] = C[(b + k - 1) * r + j];
+            X[(size_t)i * 3 * r + r + j] = C[(b + k - 2) * r + j];
+            X[(size_t)i * 3 * r + 2 * r + j] = C[(b + k - 3) * r + j];
+            Y[(size_t)i * r + j] = C[(b + k) * r + j];
+          }
+        if (!ridge_dual(X, Y, 3 * r, r, n_cases, o->lsq_reg, W, ad))
+          fail(EWBEM_EINVAL, "guess training: the training loads' histories are degenerate at some frequency");
+        rxh.insert(rxh.end(), X.begin(), X.end());
+        rwh.insert(rwh.end(), W.begin(), W.end());
+        for (int i = 0; i < n_cases; ++i)
+          for (int j = 0; j < r; ++j) {
+            const zc v = Y[(size_t)i * r + j] - W[(size_t)i * r + j] / ad[i];
+            bh[((size_t)i * nk + k) * r + j] = cd{v.real(), v.imag()};
+          }
+      }
+      rn = n_cases;
+      base.upload(bh, st);
+    }
     // the solutions depend linearly on the load, so any combination of the
     // cases' coordinate sequences is the sequence of the combined load:
     // augment virtual cases with complex Gaussian weights
     const int n_virt = o->augment * n_cases;
     const int n_all = n_cases + n_virt;
     if (n_virt > 0) {
-      DevBuf<cd> tab, wv;
+      DevBuf<cd> tab, tabb, wv;
       tab.reserve((size_t)n_all * nk * r);
       EWBEM_HIP_CHECK(hipMemcpyAsync(tab.p, coef.p, (size_t)M * r * sizeof(cd), hipMemcpyDeviceToDevice, st));
+      if (rn > 0) {
+        tabb.reserve((size_t)n_all * nk * r);
+        EWBEM_HIP_CHECK(hipMemcpyAsync(tabb.p, base.p, (size_t)M * r * sizeof(cd), hipMemcpyDeviceToDevice, st));
+      }
       std::mt19937_64 rng(o->seed * 0x2545f4914f6cdd1dULL + 7);
       std::normal_distribution<double> nd(0.0, std::sqrt(0.5 / n_cases));
       std::vector<zc> w((size_t)n_virt * n_cases);
@@ -2874,12 +3104,22 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
       wv.reserve(w.size());
       to_device(ctx, w, wv.p);
       const long long blk = (long long)nk * r;  // one case's coordinate sequence
-      for (int v = 0; v < n_virt; ++v)
+      for (int v = 0; v < n_virt; ++v) {
         launch_gemv_acc(tab.p, blk, n_cases, wv.p + (size_t)v * n_cases, cd{0.0, 0.0},
                         tab.p + (size_t)(n_cases + v) * blk, blk, st);
+        // the virtual case's base: the same combination of the leave-one-out
+        // predictions
+        if (rn > 0)
+          launch_gemv_acc(tabb.p, blk, n_cases, wv.p + (size_t)v * n_cases, cd{0.0, 0.0},
+                          tabb.p + (size_t)(n_cases + v) * blk, blk, st);
+      }
       EWBEM_HIP_CHECK(hipStreamSynchronize(st));
       std::swap(coef.p, tab.p);
       std::swap(coef.n, tab.n);
+      if (rn > 0) {
+        std::swap(base.p, tabb.p);
+        std::swap(base.n, tabb.n);
+      }
     }
     // samples: k = 3 .. N_f/2 of every case
     std::vector<int> idx;
@@ -2901,7 +3141,7 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     d_kf.upload(kf, st);
     X.reserve((size_t)ns * shape.dims[0]);
     T.reserve((size_t)ns * 2 * r);
-    launch_learn_samples(coef.p, r, d_idx.p, d_kf.p, ns, X.p, T.p, nullptr, st);
+    launch_learn_samples(coef.p, rn > 0 ? base.p : nullptr, r, d_idx.p, d_kf.p, ns, X.p, T.p, nullptr, st);
     // initial weights N(0, 1 / fan-in); the last layer starts at zero, so the
     // untrained network returns the quadratic extrapolation
     std::vector<float> p0(shape.n_params(), 0.f);
@@ -2930,6 +3170,10 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     m.r = r;
     m.shape = shape;
     m.energy = energy;
+    m.rn = rn;
+    m.rk = rn > 0 ? nk : 0;
+    m.rx = std::move(rxh);
+    m.rw = std::move(rwh);
     ctx->lm = std::move(m);
     ctx->lm_dev = false;
     end_stats(ctx, stats);
@@ -2975,6 +3219,10 @@ int ewbem_guess_save(const ewbem_ctx* cctx, void* buf, size_t* len) {
     put(f, sizeof(f));
     put(m.params.data(), 4 * m.params.size());
     put(m.phi.data(), 16 * m.phi.size());
+    const int32_t rh[2] = {m.rn, m.rk};
+    put(rh, sizeof(rh));
+    put(m.rx.data(), 16 * m.rx.size());
+    put(m.rw.data(), 16 * m.rw.size());
     *len = need;
     return EWBEM_OK;
   });
@@ -2996,7 +3244,7 @@ int ewbem_guess_load(ewbem_ctx* ctx, const void* buf, size_t len) {
     if (std::memcmp(magic, kModelMagic, 8) != 0) fail(EWBEM_EINVAL, "guess_load: not a model");
     int32_t hdr[4];
     get(hdr, sizeof(hdr));
-    if (hdr[0] != kModelVersion) fail(EWBEM_EINVAL, "guess_load: unknown model version");
+    if (hdr[0] != 1 && hdr[0] != kModelVersion) fail(EWBEM_EINVAL, "guess_load: unknown model version");
     const long long N = 3LL * ctx->nt;
     if (hdr[1] != N) fail(EWBEM_EINVAL, "guess_load: the model belongs to a mesh with another number of unknowns");
     const int r = hdr[2];
@@ -3014,6 +3262,26 @@ int ewbem_guess_load(ewbem_ctx* ctx, const void* buf, size_t len) {
     get(m.params.data(), 4 * m.params.size());
     m.phi.resize((size_t)N * r);
     get(m.phi.data(), 16 * m.phi.size());
+    if (hdr[0] >= 2) {
+      int32_t rh[2];
+      get(rh, sizeof(rh));
+      if (rh[0] < 0 || rh[0] > 65535 || (rh[0] > 0 && (rh[1] < 4 || rh[1] > 65535)) || (rh[0] == 0 && rh[1] != 0))
+        fail(EWBEM_EINVAL, "guess_load: bad least-squares map header");
+      m.rn = rh[0];
+      m.rk = rh[1];
+      if (m.rn > 0) {
+        const size_t nkk = (size_t)(m.rk - 3);
+        const size_t want = 16 * nkk * (size_t)m.rn * 4 * (size_t)r;
+        if ((size_t)(end - p) < want) fail(EWBEM_EINVAL, "guess_load: truncated model");
+        m.rx.resize(nkk * 3 * (size_t)r * m.rn);
+        m.rw.resize(nkk * (size_t)r * m.rn);
+        get(m.rx.data(), 16 * m.rx.size());
+        get(m.rw.data(), 16 * m.rw.size());
+        if (!finite_all((const double*)m.rx.data(), 2 * m.rx.size()) ||
+            !finite_all((const double*)m.rw.data(), 2 * m.rw.size()))
+          fail(EWBEM_EINVAL, "guess_load: non-finite least-squares map");
+      }
+    }
     if (p != end) fail(EWBEM_EINVAL, "guess_load: trailing bytes");
     for (float v : m.params)
       if (!std::isfinite(v)) fail(EWBEM_EINVAL, "guess_load: non-finite parameters");

@@ -536,6 +536,28 @@ __global__ void k_rhs_finish(const cd* __restrict__ partial, int nsplit, int nk,
   }
 }
 
+// Total-field load of a plane S-wave on traction-free cavities: b = the
+// incident displacement at each collocation point,
+// b[3e + i] = F_k exp(-s_k tau_e) pol_i.
+__global__ void k_rhs_total(const double* __restrict__ tau, double q0, double q1, double q2, cd s_k,
+                            const cd* __restrict__ phat_k, int ne, cd* __restrict__ b) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= 3 * ne) return;
+  const int e = d / 3, i = d - 3 * e;
+  double sn, cs;
+  sincos(s_k.y * tau[e], &sn, &cs);
+  const double m = exp(-s_k.x * tau[e]);
+  const double q = i == 0 ? q0 : (i == 1 ? q1 : q2);
+  b[d] = cd{m * cs, -m * sn} * phat_k[0] * q;
+}
+
+void launch_rhs_total(const double* tau, const double* pol, cd s_k, const cd* phat_k, int ne, cd* b,
+                      hipStream_t st) {
+  if (ne <= 0) return;
+  hipLaunchKernelGGL(k_rhs_total, dim3((3 * ne + 255) / 256), dim3(256), 0, st, tau, pol[0], pol[1], pol[2], s_k,
+                     phat_k, ne, b);
+}
+
 int rhs_split(int ne) { return ne >= 4096 ? 4 : 1; }
 
 void launch_rhs_multi(const DevGeom& g, const KParams& P, double sigma, double dw, int k0, int nk,

@@ -57,6 +57,10 @@ void launch_rhs_loads(const DevGeom& g, const KParams& P, double sigma, double d
                       const double* const* t0, const double* const* tau, cd* const* partial, hipStream_t st);
 void launch_rhs_finish(const cd* partial, int nk, int kk, int ne, const cd* selfU, const double* t0,
                        const double* tau, cd s_k, const cd* phat_k, cd* b, hipStream_t st);
+// b = F_k exp(-s_k tau_e) pol at every collocation point (the incident
+// displacement: total-field load of a plane wave; pol on the host)
+void launch_rhs_total(const double* tau, const double* pol, cd s_k, const cd* phat_k, int ne, cd* b,
+                      hipStream_t st);
 void launch_kernel_eval(const KParams& P, long long n, const double* x, const double* y,
                         const double* nrm, cd* U, cd* T, hipStream_t st);
 

@@ -162,9 +162,10 @@ __device__ inline double wave_sum(double v) {
 }
 
 // One wave per sample.
-__global__ __launch_bounds__(64) void k_learn_samples(const cd* __restrict__ coef, int r, const int* __restrict__ idx,
-                                                     const float* __restrict__ kf, int n, float* __restrict__ X,
-                                                     float* __restrict__ T, double* __restrict__ nu) {
+__global__ __launch_bounds__(64) void k_learn_samples(const cd* __restrict__ coef, const cd* __restrict__ base, int r,
+                                                     const int* __restrict__ idx, const float* __restrict__ kf, int n,
+                                                     float* __restrict__ X, float* __restrict__ T,
+                                                     double* __restrict__ nu) {
   const int s = blockIdx.x, lane = threadIdx.x;
   if (s >= n) return;
   const cd* c1 = coef + (size_t)idx[4 * s] * r;
@@ -188,8 +189,9 @@ __global__ __launch_bounds__(64) void k_learn_samples(const cd* __restrict__ coe
     x[5 * r + j] = (float)(c.y * iv);
     if (T && i0 >= 0) {
       const cd t0 = coef[(size_t)i0 * r + j];
-      // extrapolation residual: c_k - (3 c_{k-1} - 3 c_{k-2} + c_{k-3})
-      const cd e = t0 - (3.0 * a - 3.0 * b + c);
+      // residual of the base prediction: the table's row for the target's
+      // snapshot, else the extrapolation 3 c_{k-1} - 3 c_{k-2} + c_{k-3}
+      const cd e = t0 - (base ? base[(size_t)i0 * r + j] : 3.0 * a - 3.0 * b + c);
       T[(size_t)s * 2 * r + j] = (float)(e.x * iv);
       T[(size_t)s * 2 * r + r + j] = (float)(e.y * iv);
     }
@@ -201,20 +203,19 @@ __global__ __launch_bounds__(64) void k_learn_samples(const cd* __restrict__ coe
   }
 }
 
-// out = 3 c1 - 3 c2 + c3 + nu (y_re + i y_im).
+// p = (bp ? bp : 3 c1 - 3 c2 + c3) + nu (y_re + i y_im), the predicted
+// coordinates; out = p (rel = 0) or p - (3 c1 - 3 c2 + c3) (rel = 1).
 __global__ void k_learn_compose(const cd* __restrict__ coef, int r, const int* __restrict__ idx,
-                                const double* __restrict__ nu, const float* __restrict__ y, int base,
-                                cd* __restrict__ out) {
+                                const double* __restrict__ nu, const float* __restrict__ y,
+                                const cd* __restrict__ bp, int rel, cd* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= r) return;
   const double v = nu[0];
   const cd corr{v * (double)y[j], v * (double)y[r + j]};
-  if (!base) {
-    out[j] = corr;
-    return;
-  }
   const cd a = coef[(size_t)idx[0] * r + j], b = coef[(size_t)idx[1] * r + j], c = coef[(size_t)idx[2] * r + j];
-  out[j] = (3.0 * a - 3.0 * b + c) + corr;
+  const cd q = 3.0 * a - 3.0 * b + c;
+  const cd p = (bp ? bp[j] : q) + corr;
+  out[j] = rel ? p - q : p;
 }
 
 }  // namespace
@@ -347,16 +348,16 @@ void launch_adam(float* p, const float* g, float* m, float* v, long long n, cons
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n, a);
 }
 
-void launch_learn_samples(const cd* coef, int r, const int* idx, const float* kf, int n, float* X, float* T,
-                          double* nu, hipStream_t st) {
+void launch_learn_samples(const cd* coef, const cd* base, int r, const int* idx, const float* kf, int n, float* X,
+                          float* T, double* nu, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_learn_samples, dim3(n), dim3(64), 0, st, coef, r, idx, kf, n, X, T, nu);
+  hipLaunchKernelGGL(k_learn_samples, dim3(n), dim3(64), 0, st, coef, base, r, idx, kf, n, X, T, nu);
 }
 
-void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, int base,
-                          cd* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_learn_compose, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, coef, r, idx, nu, y, base,
-                     out);
+void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, const cd* bp,
+                          int rel, cd* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_learn_compose, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, st, coef, r, idx, nu, y, bp,
+                     rel, out);
 }
 
 }  // namespace ewbem

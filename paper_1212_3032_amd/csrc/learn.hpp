@@ -80,14 +80,15 @@ void launch_adam(float* p, const float* g, float* m, float* v, long long n, cons
 // Sample s uses rows idx[4s .. 4s+2] as the solutions at k-1, k-2, k-3 and
 // row idx[4s+3] (or -1) as the target at k.  With nu = |c_{k-1}| (1 if 0):
 //   X row (6 r + 2): [Re c1, Im c1, Re c2, Im c2, Re c3, Im c3] / nu, f, f^2
-//   T row (2 r):     [Re e, Im e] / nu,  e = c_k - (3 c1 - 3 c2 + c3)
-// with f = kf[s].  T and nu may be null.
-void launch_learn_samples(const cd* coef, int r, const int* idx, const float* kf, int n, float* X, float* T,
-                          double* nu, hipStream_t st);
-// out (r) = 3 c1 - 3 c2 + c3 + nu (y[0..r) + i y[r..2r)) for the rows idx[0..2]
-// (base = 1), or only the correction nu (y[0..r) + i y[r..2r)) (base = 0).
-void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, int base,
-                          cd* out, hipStream_t st);
+//   T row (2 r):     [Re e, Im e] / nu,  e = c_k - base_k
+// with f = kf[s] and base_k row idx[4s+3] of ``base`` (same layout as coef),
+// or 3 c1 - 3 c2 + c3 when base is null.  T and nu may be null.
+void launch_learn_samples(const cd* coef, const cd* base, int r, const int* idx, const float* kf, int n, float* X,
+                          float* T, double* nu, hipStream_t st);
+// p (r) = (bp ? bp : 3 c1 - 3 c2 + c3) + nu (y[0..r) + i y[r..2r)) for the
+// rows idx[0..2] of coef; out = p (rel = 0) or p - (3 c1 - 3 c2 + c3) (rel = 1).
+void launch_learn_compose(const cd* coef, int r, const int* idx, const double* nu, const float* y, const cd* bp,
+                          int rel, cd* out, hipStream_t st);
 
 // ---- host helpers (small dense matrices, row-major)
 
@@ -96,6 +97,12 @@ void launch_learn_compose(const cd* coef, int r, const int* idx, const double* n
 bool cholesky(std::vector<std::complex<double>>& A, int n);
 // Inverse of the upper-triangular L^H of a Cholesky factor (upper triangular).
 std::vector<std::complex<double>> inverse_lh(const std::vector<std::complex<double>>& L, int n);
+// The least-squares map of one frequency in its dual form: X (d x n) and Y
+// (r x n), both column-major; A = (X^H X + lam I)^{-1} with
+// lam = eps tr(X^H X) / n; W = Y A (r x n, column-major) and adiag = diag(A).
+// False if the Gram matrix is zero or does not factor.
+bool ridge_dual(const std::vector<std::complex<double>>& X, const std::vector<std::complex<double>>& Y, int d,
+                int r, int n, double eps, std::vector<std::complex<double>>& W, std::vector<double>& adiag);
 // Eigen-decomposition of a Hermitian n x n matrix by cyclic Jacobi
 // rotations: eigenvalues in descending order, eigenvectors as the columns of
 // V (row-major n x n).

@@ -1,6 +1,7 @@
 // Host helpers of the learned initial guess: the small dense factorisations
 // of the randomized range finder (Cholesky-QR and the final Hermitian
-// eigenproblem of the sketch).
+// eigenproblem of the sketch) and of the per-frequency least-squares map
+// (an n x n Gram matrix per frequency, n the training loads).
 #include "learn.hpp"
 
 #include <algorithm>
@@ -98,6 +99,44 @@ void herm_eig(std::vector<zc> A, int n, std::vector<double>& w, std::vector<zc>&
     for (int i = 0; i < n; ++i) Vs[(size_t)i * n + c] = V[(size_t)i * n + ord[c]];
   }
   V.swap(Vs);
+}
+
+bool ridge_dual(const std::vector<zc>& X, const std::vector<zc>& Y, int d, int r, int n, double eps,
+                std::vector<zc>& W, std::vector<double>& adiag) {
+  // G = X^H X (row-major n x n), columns of X contiguous
+  std::vector<zc> G((size_t)n * n);
+  double tr = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      zc acc = 0.0;
+      for (int q = 0; q < d; ++q) acc += std::conj(X[(size_t)i * d + q]) * X[(size_t)j * d + q];
+      G[(size_t)i * n + j] = acc;
+      G[(size_t)j * n + i] = std::conj(acc);
+    }
+  for (int i = 0; i < n; ++i) tr += G[(size_t)i * n + i].real();
+  if (!(tr > 0)) return false;
+  const double lam = eps * tr / n;
+  for (int i = 0; i < n; ++i) G[(size_t)i * n + i] += lam;
+  if (!cholesky(G, n)) return false;
+  // A = (L L^H)^{-1} = R R^H with R = (L^H)^{-1} upper triangular
+  const std::vector<zc> R = inverse_lh(G, n);
+  std::vector<zc> A((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      zc acc = 0.0;
+      for (int q = std::max(i, j); q < n; ++q) acc += R[(size_t)i * n + q] * std::conj(R[(size_t)j * n + q]);
+      A[(size_t)i * n + j] = acc;
+    }
+  W.assign((size_t)r * n, 0.0);
+  adiag.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    adiag[j] = A[(size_t)j * n + j].real();
+    for (int q = 0; q < n; ++q) {
+      const zc a = A[(size_t)q * n + j];
+      for (int i = 0; i < r; ++i) W[(size_t)j * r + i] += Y[(size_t)q * r + i] * a;
+    }
+  }
+  return true;
 }
 
 }  // namespace ewbem

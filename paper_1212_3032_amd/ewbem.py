@@ -24,7 +24,7 @@ EXPORTED = [
     "ewbem_default_op_opts", "ewbem_default_solver_opts", "ewbem_create", "ewbem_destroy",
     "ewbem_last_error", "ewbem_set_mesh", "ewbem_set_material", "ewbem_set_time",
     "ewbem_set_load_traction", "ewbem_set_load_pressure", "ewbem_set_load_mixed",
-    "ewbem_set_load_incident_s",
+    "ewbem_set_load_incident_s", "ewbem_set_load_incident_s_total",
     "ewbem_set_operator",
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
@@ -43,7 +43,7 @@ class Z(C.Structure):
 class OpOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("leaf_size", C.c_int32), ("eta_adm", C.c_double),
                 ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32),
-                ("aca_reuse", C.c_int32), ("autotune", C.c_int32)]
+                ("aca_reuse", C.c_int32), ("autotune", C.c_int32), ("aca_batch_mb", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
@@ -76,7 +76,8 @@ class TrainOpts(C.Structure):
     _fields_ = [("n_modes", C.c_int32), ("hidden", C.c_int32), ("n_hidden", C.c_int32),
                 ("epochs", C.c_int32), ("lr", C.c_double), ("power_iters", C.c_int32),
                 ("load_kind", C.c_int32), ("seed", C.c_uint64), ("augment", C.c_int32),
-                ("unit_snapshots", C.c_int32)]
+                ("unit_snapshots", C.c_int32), ("lsq_map", C.c_int32), ("pad", C.c_int32),
+                ("lsq_reg", C.c_double)]
 
 
 class Info(C.Structure):
@@ -116,6 +117,7 @@ def lib():
         "ewbem_set_load_pressure": (C.c_int, [P, P, P]),
         "ewbem_set_load_mixed": (C.c_int, [P, P, P, P]),
         "ewbem_set_load_incident_s": (C.c_int, [P, P, P, D, D]),
+        "ewbem_set_load_incident_s_total": (C.c_int, [P, P, P, D, D]),
         "ewbem_set_operator": (C.c_int, [P, C.POINTER(OpOpts)]),
         "ewbem_set_solver": (C.c_int, [P, C.POINTER(SolverOpts)]),
         "ewbem_info": (C.c_int, [P, C.POINTER(Info)]),
@@ -275,15 +277,17 @@ class Context:
             raise ValueError("bc must have nt entries, values 3 nt, history n_f")
         self._check(self._L.ewbem_set_load_mixed(self.h, pb, pv, ph))
 
-    def set_load_incident_s(self, direction, polarisation, ricker_fc, t0):
+    def set_load_incident_s(self, direction, polarisation, ricker_fc, t0, total=False):
         """Plane S-wave u_inc = pol f(t - dir.x / c_s), f a Ricker wavelet of
         centre frequency ricker_fc peaking at t0; outputs are the scattered
-        displacement."""
+        displacement, or with ``total`` (the total-field formulation, whose
+        right-hand side is u_inc itself) the total displacement."""
         d, pd = _host(direction, np.float64)
         q, pq = _host(polarisation, np.float64)
         if d.shape != (3,) or q.shape != (3,):
             raise ValueError("direction and polarisation must have 3 entries")
-        self._check(self._L.ewbem_set_load_incident_s(self.h, pd, pq, float(ricker_fc), float(t0)))
+        fn = self._L.ewbem_set_load_incident_s_total if total else self._L.ewbem_set_load_incident_s
+        self._check(fn(self.h, pd, pq, float(ricker_fc), float(t0)))
 
     def set_operator(self, **kw):
         o = default_op_opts(**kw)

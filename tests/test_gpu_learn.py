@@ -175,12 +175,48 @@ def test_basis_is_orthonormal_and_near_optimal(env, trained):
     ref.close()
     # the basis is that of the unit-norm snapshots (every frequency alike)
     _, e_opt = OL.pod_basis(S, r, unit=True)
+    S0 = S
     S = S / np.linalg.norm(S, axis=0)[None, :]
     res = np.linalg.norm(S - Phi @ (Phi.conj().T @ S)) ** 2 / np.linalg.norm(S) ** 2
     e_stat = trained["stats"]["pod_energy"]
     _say(f"basis r={r}: residual energy {res:.3e} (optimal {1 - e_opt:.3e}); reported energy {e_stat:.10f}")
     assert res <= 1.1 * (1 - e_opt) + 1e-12
     assert abs((1 - res) - e_stat) < 1e-8
+    # the least-squares map in the saved model against the oracle's
+    # coordinates of the same loads (their solves differ by the GMRES
+    # tolerance, 1e-6): X_k holds the histories, and W_k (X_k^H X_k + lam I)
+    # returns the targets c_k (lam = 1e-8 tr / n, the fit's definition)
+    rn, rk, Xs, Ws = _model_map(c.guess_save(), N)
+    assert rn == N_TRAIN and rk == nk
+    Co = (Phi.conj().T @ S0).T.reshape(N_TRAIN, nk, r)
+    ex = ey = 0.0
+    for k in range(3, nk):
+        Xo = np.concatenate([Co[:, k - 1], Co[:, k - 2], Co[:, k - 3]], axis=1).T
+        X, W = Xs[k - 3], Ws[k - 3]
+        ex = max(ex, np.linalg.norm(X - Xo) / np.linalg.norm(Xo))
+        G = X.conj().T @ X
+        Yr = W @ (G + 1e-8 * np.trace(G).real / rn * np.eye(rn))
+        ey = max(ey, np.linalg.norm(Yr - Co[:, k].T) / np.linalg.norm(Co[:, k]))
+    _say(f"least-squares map: histories vs oracle {ex:.1e}, W (G + lam I) vs targets {ey:.1e}")
+    assert ex < 1e-4 and ey < 1e-4
+
+
+def _model_map(blob, N):
+    """(n, K, [X_k], [W_k]) of a saved model (format version 2)."""
+    import struct
+    v, n_dof, r, L = struct.unpack_from("<4i", blob, 8)
+    assert v == 2 and n_dof == N
+    o = 24 + 4 * (L + 1) + 24
+    dims = struct.unpack_from(f"<{L + 1}i", blob, 24)
+    o += 4 * sum(dims[l + 1] * dims[l] + dims[l + 1] for l in range(L))
+    o += 16 * N * r
+    rn, rk = struct.unpack_from("<2i", blob, o)
+    o += 8
+    nkk = rk - 3
+    X = np.frombuffer(blob, "<c16", nkk * 3 * r * rn, o).reshape(nkk, rn, 3 * r).transpose(0, 2, 1)
+    o += 16 * nkk * 3 * r * rn
+    W = np.frombuffer(blob, "<c16", nkk * r * rn, o).reshape(nkk, rn, r).transpose(0, 2, 1)
+    return rn, rk, list(X), list(W)
 
 
 def test_learned_guess_on_held_out_loads(env, trained):

@@ -86,12 +86,12 @@ def test_scene_point_sources_manufactured(scene):
     (Sec. 2.1's integral equation holds for any exact solution).  The
     traction is complex at a complex frequency, so its real and imaginary
     parts are solved as two loads.  Discretisation error: 4.2-4.4% for the
-    oracle's dense solve at level 1; it must shrink at levels 2 and 3
-    (N = 11,520 and 46,080)."""
+    oracle's dense solve at level 1; it must shrink at levels 2, 3 and 4
+    (N = 11,520, 46,080 and 184,320)."""
     torch, dev, E, _ = scene
     mat = K.material(1.0, 1.0, 0.25)
     errs = {}
-    for sub in (1, 2, 3):
+    for sub in (1, 2, 3, 4):
         d = config_inputs(5, sub=sub)
         g = bem.geometry(d["xyz"], d["tri"], exterior=True)
         N = 3 * g["ne"]
@@ -126,6 +126,9 @@ def test_scene_point_sources_manufactured(scene):
             errs[sub].append(e)
             _say(f"scene level {sub} (N = {N}) k={k}: point sources, error against the exact field {e:.3e}")
         c.close()
+    # first-order convergence per frequency (measured ratios 0.33-0.37, 0.44-0.47,
+    # 0.58-0.62 from level to level)
     assert max(errs[1]) < 0.06
-    assert max(errs[2]) < 0.7 * min(errs[1])
-    assert max(errs[3]) < 0.7 * min(errs[2])
+    for sub in (2, 3, 4):
+        for j in range(2):
+            assert errs[sub][j] < 0.7 * errs[sub - 1][j]

@@ -136,14 +136,18 @@ def test_gpu_calls_refused_on_host_context():
     assert L.ewbem_solve_transient_incident_loads(c.h, 1, pd, pd, u_fake, None, None) == ewbem.ESTATE
 
 
-def _model_blob(n_dof, r, dims, rng, magic=b"EWBGUESS", version=1):
+def _model_blob(n_dof, r, dims, rng, magic=b"EWBGUESS", version=2, rn=0, rk=0):
     import struct
     n_p = sum(dims[l + 1] * dims[l] + dims[l + 1] for l in range(len(dims) - 1))
     head = magic + struct.pack("<4i", version, n_dof, r, len(dims) - 1) + struct.pack(f"<{len(dims)}i", *dims)
     head += struct.pack("<3d", 0.99, 1e-2, 1e-4)
     p = rng.standard_normal(n_p).astype("<f4").tobytes()
     phi = (rng.standard_normal(n_dof * r) + 1j * rng.standard_normal(n_dof * r)).astype("<c16").tobytes()
-    return head + p + phi
+    if version == 1:
+        return head + p + phi
+    nmap = max(0, rk - 3) * max(0, rn) * 4 * r
+    tab = (rng.standard_normal(nmap) + 1j * rng.standard_normal(nmap)).astype("<c16").tobytes()
+    return head + p + phi + struct.pack("<2i", rn, rk) + tab
 
 
 def test_learned_model_format_on_host_context():
@@ -152,19 +156,26 @@ def test_learned_model_format_on_host_context():
     rng = np.random.default_rng(1)
     o = ewbem.default_train_opts()
     assert (o.n_modes, o.hidden, o.n_hidden, o.epochs, o.lr, o.power_iters, o.load_kind, o.seed,
-            o.augment, o.unit_snapshots) == (64, 256, 3, 2000, 1e-3, 2, 0, 1, 4, 1)
+            o.augment, o.unit_snapshots, o.lsq_map) == (64, 256, 3, 2000, 1e-3, 2, 0, 1, 4, 1, 1)
     with pytest.raises(ewbem.EwbemError) as e:
         c.guess_save()  # no model yet
     assert e.value.status == ewbem.ESTATE
     r = 5
     dims = [6 * r + 2, 16, 16, 2 * r]
-    blob = _model_blob(N, r, dims, rng)
+    import struct
+    # version 1 (no least-squares map) loads and is saved as version 2 with
+    # an empty map
+    v1 = _model_blob(N, r, dims, rng, version=1)
+    c.guess_load(v1)
+    assert c.guess_save() == v1[:8] + struct.pack("<i", 2) + v1[12:] + struct.pack("<2i", 0, 0)
+    blob = _model_blob(N, r, dims, rng, rn=3, rk=7)
     c.guess_load(blob)
     assert c.guess_save() == blob  # a byte-exact round trip
     assert c.guess_basis() == r
     bad = [blob[:-1], blob + b"\0", b"X" + blob[1:], _model_blob(N + 3, r, dims, rng),
-           _model_blob(N, r, [6 * r + 1, 16, 2 * r], rng), _model_blob(N, r, dims, rng, version=2),
-           _model_blob(N, r, [6 * r + 2], rng)]
+           _model_blob(N, r, [6 * r + 1, 16, 2 * r], rng), _model_blob(N, r, dims, rng, version=3),
+           _model_blob(N, r, [6 * r + 2], rng), _model_blob(N, r, dims, rng, rn=3, rk=3),
+           _model_blob(N, r, dims, rng, rn=0, rk=5), _model_blob(N, r, dims, rng, rn=-1, rk=5)]
     for b in bad:
         with pytest.raises(ewbem.EwbemError) as e:
             c.guess_load(b)

@@ -9,7 +9,12 @@
     convention are right);
   * manufactured solution: a solid ball (interior problem, Sec. 2.1) loaded
     by the scattered-field traction of the wave, -sigma_inc n, has the exact
-    solution -u_inc on its surface; the oracle's BEM converges to it.
+    solution -u_inc on its surface; the oracle's BEM converges to it;
+  * the total-field formulation: the identity it rests on, T u_inc - U t_inc
+    = u_inc on a cavity's surface (u_inc regular inside it), holds to the
+    discretisation error and converges; and the total-field solution equals
+    the scattered one plus u_inc in the limit (their difference shrinks
+    under refinement).
 """
 
 import numpy as np
@@ -85,3 +90,37 @@ def test_interior_ball_reproduces_minus_the_incident_wave(mat):
     # level 1 then level 2, for both directions
     assert max(errs[2:]) < 0.06
     assert errs[2] < 0.7 * errs[0] and errs[3] < 0.7 * errs[1]
+
+
+def test_interior_identity_behind_the_total_field(mat):
+    """T u_inc - U t_inc = u_inc for the cavity (T with its free term 1/2):
+    Somigliana's identity inside the cavity, where the plane wave is
+    regular.  A sign error in either term, or a free term of 1, breaks it."""
+    s = 0.75 + 3.0j
+    errs, bad = [], []
+    for sub in (1, 2):
+        d, q = DIRS[1]
+        xyz, tri = icosphere(sub)
+        g = bem.geometry(xyz, tri, exterior=True)
+        T, U = bem.assemble_dense(g, s, mat)
+        v = bem.incident_s_total_rhs(g, s, mat, d, q)
+        t_inc = -bem.incident_s_load(g, s, mat, d, q)   # the wave's own traction (n out of the solid)
+        errs.append(np.linalg.norm(T @ v - U @ t_inc - v) / np.linalg.norm(v))
+        bad.append(np.linalg.norm(T @ v + U @ t_inc - v) / np.linalg.norm(v))
+    assert errs[1] < 0.05 and errs[1] < 0.6 * errs[0]
+    assert min(bad) > 0.3
+
+
+def test_total_field_converges_to_scattered_plus_incident(mat):
+    s = 0.75 + 2.0j
+    diffs = []
+    for sub in (1, 2):
+        d, q = DIRS[0]
+        xyz, tri = icosphere(sub)
+        g = bem.geometry(xyz, tri, exterior=True)
+        T, U = bem.assemble_dense(g, s, mat)
+        u_tot = np.linalg.solve(T, bem.incident_s_total_rhs(g, s, mat, d, q))
+        u_sc = np.linalg.solve(T, U @ bem.incident_s_load(g, s, mat, d, q))
+        u_inc = bem.incident_s_total_rhs(g, s, mat, d, q)
+        diffs.append(np.linalg.norm(u_tot - u_sc - u_inc) / np.linalg.norm(u_tot))
+    assert diffs[1] < 0.05 and diffs[1] < 0.6 * diffs[0]

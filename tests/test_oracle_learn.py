@@ -161,6 +161,11 @@ def test_learned_column_has_the_predicted_coordinates():
     assert np.abs(out(x) - out(3 * a1 - 3 * a2 + a3)).max() < 1e-12
     # a zero correction gives the extrapolation itself
     assert np.abs(OL.learned_column(a1, a2, a3, Phi, nu, np.zeros(2 * r)) - (3 * a1 - 3 * a2 + a3)).max() < 1e-13
+    # with a base prediction the coordinates are base + nu y, the outside part unchanged
+    base = rng.standard_normal(r) + 1j * rng.standard_normal(r)
+    xb = OL.learned_column(a1, a2, a3, Phi, nu, y, base=base)
+    assert np.abs(Phi.conj().T @ xb - (base + nu * (y[:r] + 1j * y[r:]))).max() < 1e-12
+    assert np.abs(out(xb) - out(3 * a1 - 3 * a2 + a3)).max() < 1e-12
 
 
 def test_samples_of_a_quadratic_sequence_have_zero_target():
@@ -184,3 +189,53 @@ def test_samples_of_a_quadratic_sequence_have_zero_target():
     # a zero history has nu = 1 and a zero input
     x, _, nu = OL.sample(np.zeros(r), np.zeros(r), np.zeros(r), 0.25)
     assert nu == 1.0 and np.all(x[:-2] == 0)
+
+
+def _cases(rng, n, nk, r):
+    return rng.standard_normal((n, nk, r)) + 1j * rng.standard_normal((n, nk, r))
+
+
+def test_ridge_recovers_an_exact_linear_recurrence():
+    """Coordinates that follow c_k = M_k [c_{k-1}; c_{k-2}; c_{k-3}] exactly,
+    with more cases than history entries, give back M_k on a new history."""
+    rng = np.random.default_rng(11)
+    n, nk, r, k = 40, 6, 4, 5
+    C = _cases(rng, n, nk, r)
+    M = (rng.standard_normal((r, 3 * r)) + 1j * rng.standard_normal((r, 3 * r))) / 4
+    C[:, k, :] = (M @ np.concatenate([C[:, k - 1], C[:, k - 2], C[:, k - 3]], axis=1).T).T
+    # (more cases than entries make the dual Gram matrix singular, so the
+    # regularisation sets the accuracy: bias ~ eps, rounding ~ 1e-16 / eps)
+    X, W, ad = OL.ridge_fit(C, k, eps=1e-10)
+    h = rng.standard_normal(3 * r) + 1j * rng.standard_normal(3 * r)
+    assert np.abs(OL.ridge_predict(X, W, h) - M @ h).max() < 1e-5 * np.abs(M @ h).max()
+
+
+def test_ridge_interpolates_and_combines_training_cases():
+    """With fewer cases than history entries the fit reproduces each
+    training target, and a combination of training histories is mapped to
+    the same combination of their targets (the solution is linear in the
+    load, so this is what a combined load needs)."""
+    rng = np.random.default_rng(12)
+    n, nk, r, k = 7, 5, 6, 4
+    C = _cases(rng, n, nk, r)
+    X, W, ad = OL.ridge_fit(C, k, eps=1e-12)
+    for i in range(n):
+        assert np.abs(OL.ridge_predict(X, W, X[:, i]) - C[i, k]).max() < 1e-9
+    w = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    assert np.abs(OL.ridge_predict(X, W, X @ w) - C[:, k, :].T @ w).max() < 1e-8
+
+
+def test_ridge_leave_one_out_matches_refitting():
+    rng = np.random.default_rng(13)
+    n, nk, r, k = 9, 5, 3, 3
+    C = _cases(rng, n, nk, r)
+    X, W, ad = OL.ridge_fit(C, k, eps=1e-3)
+    R = OL.ridge_loo(W, ad)
+    G = X.conj().T @ X
+    lam = 1e-3 * np.trace(G).real / n
+    for i in range(n):
+        keep = [j for j in range(n) if j != i]
+        Xi, Yi = X[:, keep], C[keep, k, :].T
+        Wi = Yi @ np.linalg.inv(Xi.conj().T @ Xi + lam * np.eye(n - 1))
+        ref = C[i, k] - Wi @ (Xi.conj().T @ X[:, i])
+        assert np.abs(R[:, i] - ref).max() < 1e-10 * np.abs(ref).max()
