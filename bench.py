@@ -75,6 +75,9 @@ def parse():
                          "cavity under --n-loads pressure loads through one frequency loop "
                          "against one transient per load; scene-waves: the scene under --n-loads "
                          "incident S-waves of different directions, the same comparison")
+    ap.add_argument("--lockstep", action="store_true",
+                    help="batch12 workload: each wave in lock-step over the frequency index, one "
+                         "concatenated matvec (a replayed HIP graph) per Arnoldi step for the wave")
     ap.add_argument("--wave", type=int, default=6,
                     help="batch12 workload: problems alive and solved concurrently at once")
     ap.add_argument("--fp64-reference", action="store_true",
@@ -552,7 +555,8 @@ def batch12_workload(args):
         ctxs = [make(probs[i], st) for i, st in zip(w, streams)]
         for i in w:
             u_bat[i] = out(probs[i])
-        st = E.batch_solve_transient(ctxs, [u_bat[i] for i in w], per_launch=16)
+        st = E.batch_solve_transient(ctxs, [u_bat[i] for i in w], per_launch=16 if not args.lockstep else len(w),
+                                     lockstep=args.lockstep)
         torch.cuda.synchronize()
         free, total = torch.cuda.mem_get_info()
         for c in ctxs:
@@ -582,7 +586,9 @@ def batch12_workload(args):
         "dtype": "f64+c64-factors", "data": "synthetic",
         "config": {"workload": "12-cavities-batched", "n_dof": n_dofs, "n_dof_total": int(sum(n_dofs)),
                    "n_f": probs[0]["n_f"], "aca_tol": 1e-5, "gmres_tol": 1e-6,
-                   "waves": [[probs[i]["name"] for i in w] for w in waves]},
+                   "waves": [[probs[i]["name"] for i in w] for w in waves],
+                   "batch": "lock-step, one concatenated matvec per Arnoldi step" if args.lockstep
+                            else "concurrent host threads, one stream per problem"},
         "one_at_a_time": {"value": seq_solves / t_seq, "ms": 1000.0 * t_seq,
                           "gmres_iters_per_solve": seq_its / seq_solves},
         "concurrent": {"value": bat_solves / t_bat, "ms": 1000.0 * t_bat,

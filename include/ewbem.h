@@ -64,8 +64,9 @@ extern "C" {
 #define EWBEM_GUESS_ZERO 0
 #define EWBEM_GUESS_SEM 1    /* least-squares extrapolation, Sec. 4.2 */
 #define EWBEM_GUESS_QUAD 2   /* Lagrange extrapolation 3a1 - 3a2 + a3 */
-#define EWBEM_GUESS_LEARNED 3 /* least-squares extrapolation with one more column, the
-                                 trained network's prediction (ewbem_guess_train) */
+#define EWBEM_GUESS_LEARNED 3 /* least-squares extrapolation with its part in the learned
+                                 basis moved to the trained model's prediction
+                                 (ewbem_guess_train) */
 
 typedef struct ewbem_ctx ewbem_ctx; /* opaque, owned by the library */
 
@@ -173,8 +174,8 @@ typedef struct {
   int32_t lsq_map;     /* 1: the prediction's base is a least-squares map per frequency
                           from the three previous coordinate vectors to the next, fitted
                           over the training loads (regularised, dual form), and the
-                          network learns to correct its leave-one-out errors (default);
-                          0: the base is the quadratic extrapolation 3 c1 - 3 c2 + c3 */
+                          network learns its residual (default); 0: the base is the
+                          quadratic extrapolation 3 c1 - 3 c2 + c3 */
   int32_t pad;
   double lsq_reg;      /* the map's regularisation: lam = lsq_reg tr(G) / n with G the
                           n x n Gram matrix of the training histories, (0, 1) (default 1e-8) */
@@ -388,6 +389,25 @@ int ewbem_solve_transient_incident_loads(ewbem_ctx* ctx, int32_t n_loads, const 
 int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewbem_stats* stats,
                                 int32_t per_launch);
 
+/* An addition to the method, like ewbem_batch_solve_transient: the same
+ * problems in lock-step over the frequency index, in groups of per_launch.
+ * At each k every problem of a group assembles its operator and forms its
+ * initial guess on its own library-owned stream (host threads,
+ * concurrently); then the group's GMRES run together on one library-owned
+ * stream, and every Arnoldi step applies all their operators with one
+ * matvec: their task tables concatenated into one launch of each matvec
+ * kernel (the phase-1 factor products, the panel products and the fixed-
+ * order reduction), captured once per frequency as a HIP graph and replayed
+ * each step.  Problems leave the launch as they converge (the graph is
+ * rebuilt for the rest).  Each problem's arithmetic is its lone solve's.
+ * Requirements: contexts on one device, H-matrix or dense operators whose
+ * far factors share one store type, no pipeline; N_f may differ (a problem
+ * leaves the lock-step after its last frequency).  Outputs, stats and return
+ * codes as for ewbem_batch_solve_transient; EINVAL also for contexts on
+ * different devices. */
+int ewbem_batch_solve_transient_lockstep(ewbem_ctx** ctxs, int32_t n, double** u_out, ewbem_stats* stats,
+                                         int32_t per_launch);
+
 /* ---- Learned initial guess (an addition to the method; Sec. 4.2 supplies
  * the extrapolation it extends).
  *
@@ -399,20 +419,31 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
  *     r + 16 columns, then the exact eigen-decomposition of the sketch):
  *     the basis Phi, N x r with orthonormal columns;
  *   - forms, for every case and k = 3..N_f/2, the reduced coordinates
- *     c_j = Phi^H a_j of the solutions at k-1, k-2, k-3 and at k; the
- *     network's input is [Re, Im of c_{k-1}, c_{k-2}, c_{k-3}] / nu with
+ *     c_j = Phi^H a_j of the solutions at k-1, k-2, k-3 and at k;
+ *   - (lsq_map) fits, for every k, the least-squares map from the history
+ *     h = [c_{k-1}; c_{k-2}; c_{k-3}] to c_k over the n_cases loads in its
+ *     dual form: X_k = [h_1 .. h_n], A = (X_k^H X_k + lam I)^{-1},
+ *     lam = lsq_reg tr(X_k^H X_k) / n, W_k = [c_k of each case] A, so the
+ *     map is c_k ~ W_k X_k^H h (a combination of the training loads'
+ *     outcomes, the solution being linear in the load); its prediction of
+ *     each training case is the base the network corrects (else the base is
+ *     3 c_{k-1} - 3 c_{k-2} + c_{k-3});
+ *   - the network's input is [Re, Im of c_{k-1}, c_{k-2}, c_{k-3}] / nu with
  *     nu = |c_{k-1}|, followed by f and f^2 (f = k / (N_f/2)); its target is
- *     [Re, Im of c_k - (3 c_{k-1} - 3 c_{k-2} + c_{k-3})] / nu; the samples
- *     also come from augment x n_cases virtual cases, each a combination of
- *     the cases' coordinate sequences with complex N(0, 1/n_cases) weights;
+ *     [Re, Im of c_k - base] / nu; the samples also come from augment x
+ *     n_cases virtual cases, each a combination of the cases' coordinate
+ *     sequences (and bases) with complex N(0, 1/n_cases) weights;
  *   - fits a network of n_hidden GELU layers of width hidden (bf16 weights
  *     and activations in the products, fp32 accumulation) by full-batch Adam
  *     on the mean squared error.
- * With EWBEM_GUESS_LEARNED, frequency k >= 3 then adds the vector
- *   Phi (3 c_{k-1} - 3 c_{k-2} + c_{k-3} + nu y)  (y: network output)
- * as one more column to the least-squares extrapolation, so the guess is
- * never worse in residual than the extrapolation alone over the same
- * history; k < 3 uses the extrapolation alone.  The context's own load is
+ * With EWBEM_GUESS_LEARNED, frequency k >= 3 then takes the least-squares
+ * extrapolation x (residual r) and moves its part in the basis to the
+ * prediction p = base + nu y (y: network output, base the map's W_k X_k^H h
+ * when the model was fitted for the context's N_f, else the quadratic
+ * extrapolation) along v = Phi (p - Phi^H x) by the step gamma that
+ * minimises |r - gamma A v| (one more operator application), so the guess
+ * is never worse in residual than the extrapolation alone; k < 3 uses the
+ * extrapolation alone.  The context's own load is
  * unchanged (the training loads run through the multi-load loop of
  * ewbem_solve_transient_loads).  loads: host, n_cases x nt x 3 tractions
  * (load_kind 0) or n_cases x nt pressures (1), caller order.  stats sum the

@@ -10,8 +10,11 @@ solution.  What is defined here, plainly and in float64:
 * the learned column: the quadratic extrapolation of the last three
   solutions plus the network's correction mapped through the basis;
 * a regularised least-squares map per frequency from the three previous
-  coordinate vectors to the next (dual form over the training cases), with
-  its leave-one-out residuals;
+  coordinate vectors to the next (dual form over the training cases), its
+  predictions of the training cases and its leave-one-out residuals;
+* the learned guess: the least-squares extrapolation with its part in the
+  basis moved towards the predicted coordinates by a residual-minimising
+  step;
 * reduced coordinates c = Phi^H a, and the samples: input
   [Re c1, Im c1, Re c2, Im c2, Re c3, Im c3] / nu followed by f and f^2,
   target [Re e, Im e] / nu with e = c_k - (3 c1 - 3 c2 + c3), where
@@ -197,6 +200,24 @@ def ridge_fit(C, k, eps=1e-8):
 def ridge_predict(X, W, h):
     """Prediction W X^H h for the history h = [c_{k-1}; c_{k-2}; c_{k-3}]."""
     return W @ (X.conj().T @ np.asarray(h, dtype=complex))
+
+
+def ridge_train_predictions(X, W):
+    """The map's predictions of its own training cases, W X^H X (r x n)."""
+    return W @ (X.conj().T @ X)
+
+
+def learned_guess(xs, rs, Phi, p, A):
+    """The learned initial guess from the least-squares extrapolation xs
+    (residual rs = b - A xs) and predicted coordinates p: the part of xs in
+    the basis is moved towards p along v = Phi (p - Phi^H xs) by the step
+    gamma minimising |rs - gamma A v|.  A: callable x -> A x.  Returns
+    (x0, r0, gamma)."""
+    v = Phi @ (np.asarray(p) - Phi.conj().T @ xs)
+    y = A(v)
+    yy = np.vdot(y, y).real
+    gamma = np.vdot(y, rs) / yy if yy > 0 else 0.0
+    return xs + gamma * v, rs - gamma * y, gamma
 
 
 def ridge_loo(W, adiag):

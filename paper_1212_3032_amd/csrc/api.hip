@@ -194,6 +194,11 @@ struct ewbem_ctx {
   DevBuf<Seg> d_seg;
   DevBuf<RowTask> d_rt;
   DevBuf<LeafRange> d_lr;
+  // host copies of the matvec tables, for the batch's concatenated launch
+  std::vector<VtTask> vt_h;
+  std::vector<Seg> seg_h;
+  std::vector<RowTask> rt_h;
+  std::vector<LeafRange> lr_h;
   int n_vt = 0, n_rt = 0, n_lr = 0;
   // matvec task shapes: factor columns per phase-1 wavefront and the phase-2
   // task size (total panel columns / mv_div per task); chosen by timing on
@@ -403,7 +408,7 @@ void learned_upload(ewbem_ctx* c) {
     c->d_lbase.reserve(r);
   }
   const int L = m.shape.n_layers();
-  c->d_lcoef.reserve(3 * (size_t)r);
+  c->d_lcoef.reserve(4 * (size_t)r);  // the ring of three, then scratch for Phi^H x
   c->d_lpred.reserve(r);
   c->d_lx.reserve(N);
   c->d_lfeat.reserve(m.shape.dims[0]);
@@ -1063,9 +1068,14 @@ void build_matvec(ewbem_ctx* c) {
   c->d_seg.upload(flat, st);
   c->d_rt.upload(rt, st);
   c->d_lr.upload(lr, st);
-  c->n_vt = (int)vt.size();
-  c->n_rt = (int)rt.size();
-  c->n_lr = (int)lr.size();
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // the uploads read the host tables kept below
+  c->vt_h = std::move(vt);
+  c->seg_h = std::move(flat);
+  c->rt_h = std::move(rt);
+  c->lr_h = std::move(lr);
+  c->n_vt = (int)c->vt_h.size();
+  c->n_rt = (int)c->rt_h.size();
+  c->n_lr = (int)c->lr_h.size();
   c->mvpart_len = (long long)std::max(1, c->n_rt) * HMV_MAXROWS;
   c->d_mvpart.reserve_grow((size_t)HMV_MAXRHS * c->mvpart_len);
   EWBEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -1701,19 +1711,16 @@ void push_coords(ewbem_ctx* c, const cd* a, int k) {
   c->lc_kidx.insert(c->lc_kidx.begin(), k);
 }
 
-// The network's guess at frequency k (tree order, in d_lx), or null when the
-// coordinates of k-1, k-2 and k-3 are not all in the ring.  With the three
-// previous solutions in the extrapolation history the guess is their
-// quadratic extrapolation 3 a1 - 3 a2 + a3 plus the network's correction in
-// the basis, Phi nu y: its coordinates are the prediction and its part
-// outside the basis is the extrapolation's.  Otherwise it is Phi times the
-// predicted coordinates alone.
-const cd* learned_guess(ewbem_ctx* c, int k) {
+// The learned prediction of frequency k's coordinates into d_lpred: the
+// least-squares map's W_k X_k^H [c1; c2; c3] (when the model has one for
+// this frequency grid; else the quadratic extrapolation 3 c1 - 3 c2 + c3)
+// plus the network's correction nu y.  False when the coordinates of k-1,
+// k-2 and k-3 are not all in the ring.
+bool learned_coords(ewbem_ctx* c, int k) {
   if (k < 3 || c->lc_kidx.size() < 3 || c->lc_kidx[0] != k - 1 || c->lc_kidx[1] != k - 2 ||
       c->lc_kidx[2] != k - 3)
-    return nullptr;
+    return false;
   hipStream_t st = c->stream;
-  const long long N = 3LL * c->nt;
   const int r = c->lm.r;
   const int idx[4] = {c->lc_slot[0], c->lc_slot[1], c->lc_slot[2], -1};
   const float kf = (float)k / (float)(c->n_f / 2);
@@ -1721,8 +1728,6 @@ const cd* learned_guess(ewbem_ctx* c, int k) {
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_lkf.p, &kf, sizeof(float), hipMemcpyHostToDevice, st));
   launch_learn_samples(c->d_lcoef.p, nullptr, r, c->d_lidx.p, c->d_lkf.p, 1, c->d_lfeat.p, nullptr, c->d_lnu.p, st);
   mlp_forward(c->lm.shape, c->d_lp.p, 1, c->d_lfeat.p, c->d_lact.p, c->d_lpre.p, c->d_ly.p, st);
-  // the least-squares map's prediction W_k X_k^H [c1; c2; c3] as the base
-  // the network corrects (when the model has one for this frequency grid)
   const cd* bp = nullptr;
   const LearnedModel& m = c->lm;
   if (m.rn > 0 && m.rk == c->n_f / 2 + 1 && k < m.rk) {
@@ -1734,24 +1739,38 @@ const cd* learned_guess(ewbem_ctx* c, int k) {
     launch_gemv_acc(c->d_rw.p + (size_t)(k - 3) * wsz, r, m.rn, c->d_lz.p, cd{0.0, 0.0}, c->d_lbase.p, r, st);
     bp = c->d_lbase.p;
   }
-  const bool full = c->hist_kidx.size() >= 3 && c->hist_kidx[0] == k - 1 && c->hist_kidx[1] == k - 2 &&
-                    c->hist_kidx[2] == k - 3;
-  launch_learn_compose(c->d_lcoef.p, r, c->d_lidx.p, c->d_lnu.p, c->d_ly.p, bp, full ? 1 : 0, c->d_lpred.p, st);
-  std::vector<cd> cx(std::max(1, c->so.sem_k), cd{0, 0});
-  if (full) {
-    const int ncap = (int)cx.size();
-    cx[c->hist_slot[0]] = cd{3, 0};
-    cx[c->hist_slot[1]] = cd{-3, 0};
-    cx[c->hist_slot[2]] = cd{1, 0};
-    EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p, cx.data(), ncap * sizeof(cd), hipMemcpyHostToDevice, st));
-    launch_gemv_acc(c->d_hist_sol.p, N, ncap, c->d_small.p, cd{0.0, 0.0}, c->d_lx.p, N, st);
-    launch_gemv_acc(c->d_phi.p, N, r, c->d_lpred.p, cd{1.0, 0.0}, c->d_lx.p, N, st);
-  } else {
-    launch_gemv_acc(c->d_phi.p, N, r, c->d_lpred.p, cd{0.0, 0.0}, c->d_lx.p, N, st);
-  }
-  EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // idx, kf and cx live on this frame
+  launch_learn_compose(c->d_lcoef.p, r, c->d_lidx.p, c->d_lnu.p, c->d_ly.p, bp, 0, c->d_lpred.p, st);
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));  // idx and kf live on this frame
+  return true;
+}
+
+// The learned guess: the least-squares extrapolation x (residual r) with
+// its part in the basis moved towards the prediction p, by the step that
+// minimises the residual along v = Phi (p - Phi^H x):
+//   y = A v,  gamma = (y^H r) / (y^H y),  x += gamma v,  r -= gamma y.
+// One operator application; the residual never grows.
+void learned_refine(ewbem_ctx* c, int k, cd* x, cd* r) {
+  if (!learned_coords(c, k)) return;
+  hipStream_t st = c->stream;
+  const long long N = 3LL * c->nt;
+  const int rr = c->lm.r;
+  cd* cx = c->d_lcoef.p + 3 * (size_t)rr;  // scratch after the ring's three slots
+  launch_dots(c->d_phi.p, N, rr, x, N, c->d_hpart.p, cx, st);
+  launch_axpby(cd{-1.0, 0.0}, cx, cd{1.0, 0.0}, c->d_lpred.p, rr, st);  // p - Phi^H x
+  launch_gemv_acc(c->d_phi.p, N, rr, c->d_lpred.p, cd{0.0, 0.0}, c->d_lx.p, N, st);
+  EventPair ev;
+  apply_tree(c, c->d_lx.p, c->d_w.p, &ev);
+  launch_dots(c->d_w.p, N, 1, r, N, c->d_hpart.p, c->d_small.p, st);
+  launch_dots(c->d_w.p, N, 1, c->d_w.p, N, c->d_hpart.p, c->d_small.p + 1, st);
+  cd h[2];
+  EWBEM_HIP_CHECK(hipMemcpyAsync(h, c->d_small.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+  account_matvec(c, ev);
+  if (!(h[1].x > 0.0)) return;
+  const cd g{h[0].x / h[1].x, h[0].y / h[1].x};
+  launch_axpby(g, c->d_lx.p, cd{1.0, 0.0}, x, N, st);
+  launch_axpby(cd{-g.x, -g.y}, c->d_w.p, cd{1.0, 0.0}, r, N, st);
   c->acc.guess_learned += 1;
-  return c->d_lx.p;
 }
 
 // The initial guess of frequency k into d_x and its residual into d_r (b in
@@ -1768,12 +1787,9 @@ void guess_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
     account_matvec(c, ev);
   } else if (c->so.guess == EWBEM_GUESS_SEM || c->so.guess == EWBEM_GUESS_LEARNED) {
-    const cd* extra = nullptr;
-    if (c->so.guess == EWBEM_GUESS_LEARNED) {
-      if (!c->lm.ok) fail(EWBEM_ESTATE, "learned guess: no trained or loaded model");
-      extra = learned_guess(c, k);
-    }
-    sem_guess(c, c->d_x.p, c->d_r.p, extra);
+    if (c->so.guess == EWBEM_GUESS_LEARNED && !c->lm.ok) fail(EWBEM_ESTATE, "learned guess: no trained or loaded model");
+    sem_guess(c, c->d_x.p, c->d_r.p, nullptr);
+    if (c->so.guess == EWBEM_GUESS_LEARNED) learned_refine(c, k, c->d_x.p, c->d_r.p);
   } else if (c->so.guess == EWBEM_GUESS_QUAD && c->hist_n > 0) {
     const int K = std::min(3, c->hist_n);
     static const double coef[4][3] = {{0, 0, 0}, {1, 0, 0}, {2, -1, 0}, {3, -3, 1}};
@@ -2911,6 +2927,513 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
   return out;
 }
 
+// ---- several problems in lock-step: one concatenated matvec per Arnoldi step
+
+namespace {
+
+// The matvecs of several problems as one: their task tables concatenated,
+// the vectors side by side (problem i's x at X + xo[i], its factor
+// products at Z + zo[i]), the three launches captured as a graph that every
+// Arnoldi step replays.  Each problem's tasks, and so its products, are its
+// own launch's.
+struct ConcatMatvec {
+  DevBuf<VtTask> vt;
+  DevBuf<Seg> seg;
+  DevBuf<RowTask> rt;
+  DevBuf<LeafRange> lr;
+  DevBuf<cd> X, Y, Z, P;
+  std::vector<long long> xo;
+  int nvt = 0, nrt = 0, nlr = 0, cols = 2, c64 = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~ConcatMatvec() { drop(); }
+  void drop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  void build(const std::vector<ewbem_ctx*>& cs, hipStream_t s) {
+    drop();
+    std::vector<VtTask> v;
+    std::vector<Seg> g;
+    std::vector<RowTask> r;
+    std::vector<LeafRange> l;
+    xo.assign(cs.size(), 0);
+    long long x = 0, z = 0;
+    int far_kind = -1;
+    cols = 2;
+    for (size_t i = 0; i < cs.size(); ++i) {
+      ewbem_ctx* c = cs[i];
+      xo[i] = x;
+      const long long segoff = (long long)g.size(), taskoff = (long long)r.size();
+      if (!c->vt_h.empty()) {
+        const int kind = c->store_c64_active ? 1 : 0;
+        if (far_kind >= 0 && kind != far_kind)
+          fail(EWBEM_EINVAL, "batch lock-step: every problem's far factors need the same store (c128 or c64)");
+        far_kind = kind;
+        cols = std::max(cols, c->vt_cols);
+      }
+      for (VtTask t : c->vt_h) {
+        t.x0 += (int)x;
+        t.zidx += z;
+        v.push_back(t);
+      }
+      for (Seg q : c->seg_h) {
+        q.src += (q.flags & SEG_FROM_Z) ? z : x;
+        g.push_back(q);
+      }
+      for (RowTask t : c->rt_h) {
+        t.row0 += (int)x;
+        t.s0 += (int)segoff;
+        t.s1 += (int)segoff;
+        r.push_back(t);
+      }
+      for (LeafRange q : c->lr_h) {
+        q.row0 += (int)x;
+        q.t0 += (int)taskoff;
+        q.t1 += (int)taskoff;
+        l.push_back(q);
+      }
+      x += 3LL * c->nt;
+      z += c->z_len;
+      if (x > INT32_MAX / 2 || (long long)g.size() > INT32_MAX / 2 || (long long)r.size() > INT32_MAX / 2)
+        fail(EWBEM_EINVAL, "batch lock-step: the problems together exceed the matvec's index range");
+    }
+    c64 = far_kind == 1;
+    nvt = (int)v.size();
+    nrt = (int)r.size();
+    nlr = (int)l.size();
+    vt.upload(v, s);
+    seg.upload(g, s);
+    rt.upload(r, s);
+    lr.upload(l, s);
+    X.reserve_grow(std::max<long long>(x, 1));
+    Y.reserve_grow(std::max<long long>(x, 1));
+    Z.reserve_grow(std::max<long long>(z, 1));
+    P.reserve_grow((size_t)std::max(nrt, 1) * HMV_MAXROWS);
+    EWBEM_HIP_CHECK(hipStreamSynchronize(s));  // the host tables go out of scope
+    // the three launches as a graph (no memory set nodes: every output is
+    // written by its kernel)
+    EWBEM_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    launch_far_vt(vt.p, nvt, cols, c64, X.p, 0, 1, Z.p, 0, s);
+    launch_hmv(rt.p, nrt, seg.p, X.p, 0, 1, Z.p, 0, P.p, 0, s);
+    launch_hmv_reduce(lr.p, nlr, P.p, 0, 1, Y.p, 0, s);
+    EWBEM_HIP_CHECK(hipStreamEndCapture(s, &graph));
+    EWBEM_HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  void launch(hipStream_t s) { EWBEM_HIP_CHECK(hipGraphLaunch(exec, s)); }
+};
+
+// The host side of one Arnoldi step of a GMRES lane: column j of H from the
+// Gram-Schmidt coefficients h (two passes) and |w| = hn, the earlier Givens
+// rotations, a new one, and the residual estimate |g_{j+1}| / |b|.
+double arnoldi_update(GmresLane& G, const cd* h, int m, double hn) {
+  const int j = G.j;
+  auto Hc = [&](int row) -> std::complex<double>& { return G.H[(size_t)j * (m + 1) + row]; };
+  for (int q = 0; q <= j; ++q) Hc(q) = std::complex<double>(h[q].x + h[m + 2 + q].x, h[q].y + h[m + 2 + q].y);
+  Hc(j + 1) = hn;
+  for (int q = 0; q < j; ++q) {
+    std::complex<double>& a = Hc(q);
+    std::complex<double>& b = Hc(q + 1);
+    const std::complex<double> t = std::conj(G.cs[q]) * a + std::conj(G.sn[q]) * b;
+    b = -G.sn[q] * a + G.cs[q] * b;
+    a = t;
+  }
+  const std::complex<double> a = Hc(j);
+  const double den = std::sqrt(std::norm(a) + hn * hn);
+  if (den == 0.0) {
+    G.cs[j] = 1.0;
+    G.sn[j] = 0.0;
+  } else {
+    G.cs[j] = a / den;
+    G.sn[j] = hn / den;
+  }
+  Hc(j) = den;
+  Hc(j + 1) = 0.0;
+  G.g[j + 1] = -G.sn[j] * G.g[j];
+  G.g[j] = std::conj(G.cs[j]) * G.g[j];
+  return std::abs(G.g[j + 1]) / G.bnorm;
+}
+
+// y of the least-squares problem H y = g of a finished cycle (j columns).
+std::vector<cd> cycle_coeffs(const GmresLane& G, int m) {
+  const int j = G.j;
+  std::vector<std::complex<double>> y(j);
+  for (int i = j - 1; i >= 0; --i) {
+    std::complex<double> sacc = G.g[i];
+    for (int q = i + 1; q < j; ++q) sacc -= G.H[(size_t)q * (m + 1) + i] * y[q];
+    y[i] = sacc / G.H[(size_t)i * (m + 1) + i];
+  }
+  std::vector<cd> out(j);
+  for (int i = 0; i < j; ++i) out[i] = cd{y[i].real(), y[i].imag()};
+  return out;
+}
+
+// Right-preconditioned GMRES of several problems (each with its own
+// operator, restart, tolerance and iteration cap) in lock-step on stream s:
+// every problem's context has s as its stream here; the operators are
+// applied by one concatenated launch per step.  The arithmetic of each
+// problem is that of gmres() on its own.  Returns each problem's iterations
+// and final relative residual.
+void gmres_lockstep(std::vector<ewbem_ctx*>& cs, hipStream_t s, ConcatMatvec& cm, std::vector<int>& its,
+                    std::vector<double>& rel, std::vector<char>& conv) {
+  const int nb = (int)cs.size();
+  std::vector<GmresLane> L(nb);
+  std::vector<int> lane_of(nb);  // position of problem i in the current launch, or -1
+  const int hs_max = 4;          // cd entries per |.|^2 readback
+  (void)hs_max;
+  for (int i = 0; i < nb; ++i) {
+    ewbem_ctx* c = cs[i];
+    const int m = c->so.restart;
+    GmresLane& G = L[i];
+    G.b = c->d_b.p;
+    G.x = c->d_x.p;
+    G.r = c->d_r.p;
+    G.V = c->d_V.p;
+    G.hd = c->d_small.p;
+    G.H.assign((size_t)(m + 1) * m, 0.0);
+    G.cs.assign(m, 0.0);
+    G.sn.assign(m, 0.0);
+    G.g.assign(m + 1, 0.0);
+  }
+  auto norm_of = [&](ewbem_ctx* c, const cd* v) { return dev_norm(c, v); };
+  for (int i = 0; i < nb; ++i) {
+    GmresLane& G = L[i];
+    G.bnorm = norm_of(cs[i], G.b);
+    G.rnorm = norm_of(cs[i], G.r);
+    if (G.bnorm == 0.0) {
+      launch_axpby(cd{0.0, 0.0}, G.b, cd{0.0, 0.0}, G.x, 3LL * cs[i]->nt, s);
+      G.relres = 0.0;
+      G.done = true;
+      continue;
+    }
+    G.relres = G.rnorm / G.bnorm;
+    if (!(G.relres > cs[i]->so.tol)) G.done = true;
+  }
+  // the concatenated launch over the problems still iterating
+  int built_for = -1;
+  auto rebuild = [&] {
+    std::vector<ewbem_ctx*> live;
+    std::fill(lane_of.begin(), lane_of.end(), -1);
+    for (int i = 0; i < nb; ++i)
+      if (!L[i].done) {
+        lane_of[i] = (int)live.size();
+        live.push_back(cs[i]);
+      }
+    if (live.empty()) return;
+    cm.build(live, s);
+    built_for = (int)live.size();
+  };
+  std::vector<cd> hb;
+  EventPair ev;
+  for (;;) {
+    int ndone = 0;
+    for (const GmresLane& G : L) ndone += G.done ? 1 : 0;
+    if (ndone == nb) break;
+    if (built_for != nb - ndone) rebuild();
+    // lanes starting a cycle
+    for (int i = 0; i < nb; ++i) {
+      GmresLane& G = L[i];
+      if (G.done || G.arnoldi) continue;
+      if (G.its >= cs[i]->so.maxit) {
+        G.done = true;
+        continue;
+      }
+      launch_axpby(cd{1.0 / G.rnorm, 0.0}, G.r, cd{0.0, 0.0}, G.V, 3LL * cs[i]->nt, s);
+      std::fill(G.g.begin(), G.g.end(), 0.0);
+      G.g[0] = G.rnorm;
+      G.j = 0;
+      G.arnoldi = true;
+    }
+    std::vector<int> act;
+    for (int i = 0; i < nb; ++i)
+      if (L[i].arnoldi && !L[i].done) act.push_back(i);
+    if (act.empty()) continue;
+    if (built_for != nb - ndone) continue;  // a lane hit its cap: the launch shrinks first
+    // one Arnoldi step of each: w = A M^{-1} v_j, Gram-Schmidt twice, |w|
+    for (int i : act) {
+      ewbem_ctx* c = cs[i];
+      const long long N = 3LL * c->nt;
+      precond_apply(c, L[i].V + (size_t)L[i].j * N, cm.X.p + cm.xo[lane_of[i]]);
+    }
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, s));
+    cm.launch(s);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, s));
+    size_t hoff = 0;
+    std::vector<size_t> at(nb);
+    for (int i : act) {
+      ewbem_ctx* c = cs[i];
+      const int m = c->so.restart;
+      const long long N = 3LL * c->nt;
+      GmresLane& G = L[i];
+      cd* w = cm.Y.p + cm.xo[lane_of[i]];
+      cd* hd2 = G.hd + (m + 2);
+      cd* nd = G.hd + 2 * (m + 2);
+      launch_dots(G.V, N, G.j + 1, w, N, c->d_hpart.p, G.hd, s);
+      launch_gemv_sub(G.V, N, G.j + 1, G.hd, w, N, s);
+      launch_dots(G.V, N, G.j + 1, w, N, c->d_hpart.p, hd2, s);
+      launch_gemv_sub(G.V, N, G.j + 1, hd2, w, N, s);
+      launch_dots(w, N, 1, w, N, c->d_hpart.p, nd, s);
+      at[i] = hoff;
+      hoff += 2 * (m + 2) + 1;
+    }
+    hb.resize(hoff);
+    for (int i : act) {
+      const int m = cs[i]->so.restart;
+      EWBEM_HIP_CHECK(hipMemcpyAsync(&hb[at[i]], L[i].hd, (2 * (m + 2) + 1) * sizeof(cd), hipMemcpyDeviceToHost, s));
+    }
+    EWBEM_HIP_CHECK(hipStreamSynchronize(s));
+    {
+      const float ms = ev.elapsed();
+      for (int i : act) {
+        cs[i]->acc.t_matvec_ms += ms / act.size();
+        cs[i]->acc.matvec_bytes_total += cs[i]->matvec_bytes;
+        cs[i]->acc.matvecs_timed += 1;
+        cs[i]->acc.matvecs += 1;
+      }
+    }
+    std::vector<int> ends;
+    for (int i : act) {
+      ewbem_ctx* c = cs[i];
+      const int m = c->so.restart;
+      const long long N = 3LL * c->nt;
+      GmresLane& G = L[i];
+      const cd* h = &hb[at[i]];
+      ++G.its;
+      const double hn = std::sqrt(std::max(0.0, h[2 * (m + 2)].x));
+      const double est = arnoldi_update(G, h, m, hn);
+      const int j = G.j;
+      if (hn > 0.0 && j + 1 <= m)
+        launch_axpby(cd{1.0 / hn, 0.0}, cm.Y.p + cm.xo[lane_of[i]], cd{0.0, 0.0}, G.V + (size_t)(j + 1) * N, N, s);
+      G.j = j + 1;
+      if (est <= c->so.tol || hn == 0.0 || G.j >= m || G.its >= c->so.maxit) ends.push_back(i);
+    }
+    if (ends.empty()) continue;
+    // cycle ends: x += M^{-1} V y, then the true residuals in one launch
+    std::vector<std::vector<cd>> yd(ends.size());
+    for (size_t e = 0; e < ends.size(); ++e) {
+      const int i = ends[e];
+      ewbem_ctx* c = cs[i];
+      const int m = c->so.restart;
+      const long long N = 3LL * c->nt;
+      GmresLane& G = L[i];
+      yd[e] = cycle_coeffs(G, m);
+      cd* u = cm.Y.p + cm.xo[lane_of[i]];
+      cd* z = cm.X.p + cm.xo[lane_of[i]];
+      EWBEM_HIP_CHECK(hipMemcpyAsync(G.hd, yd[e].data(), G.j * sizeof(cd), hipMemcpyHostToDevice, s));
+      launch_gemv_acc(G.V, N, G.j, G.hd, cd{0.0, 0.0}, u, N, s);
+      precond_apply(c, u, z);
+      launch_axpby(cd{1.0, 0.0}, z, cd{1.0, 0.0}, G.x, N, s);
+      EWBEM_HIP_CHECK(hipMemcpyAsync(z, G.x, N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+    }
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, s));
+    cm.launch(s);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, s));
+    for (int i : ends) {
+      ewbem_ctx* c = cs[i];
+      const long long N = 3LL * c->nt;
+      GmresLane& G = L[i];
+      EWBEM_HIP_CHECK(hipMemcpyAsync(G.r, cm.Y.p + cm.xo[lane_of[i]], N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+      launch_axpby(cd{1.0, 0.0}, G.b, cd{-1.0, 0.0}, G.r, N, s);
+    }
+    EWBEM_HIP_CHECK(hipStreamSynchronize(s));  // yd lives on this frame
+    {
+      const float ms = ev.elapsed();
+      for (int i : ends) {
+        cs[i]->acc.t_matvec_ms += ms / ends.size();
+        cs[i]->acc.matvec_bytes_total += cs[i]->matvec_bytes;
+        cs[i]->acc.matvecs_timed += 1;
+        cs[i]->acc.matvecs += 1;
+      }
+    }
+    for (int i : ends) {
+      GmresLane& G = L[i];
+      G.rnorm = norm_of(cs[i], G.r);
+      G.relres = G.rnorm / G.bnorm;
+      G.arnoldi = false;
+      if (!(G.relres > cs[i]->so.tol) || G.j == 0) G.done = true;
+    }
+  }
+  its.assign(nb, 0);
+  rel.assign(nb, 0.0);
+  conv.assign(nb, 1);
+  for (int i = 0; i < nb; ++i) {
+    its[i] = L[i].its;
+    rel[i] = L[i].relres;
+    conv[i] = !(L[i].relres > cs[i]->so.tol);
+  }
+}
+
+// The stream a context's calls enqueue on, swapped for the duration of a
+// lock-step phase.
+struct StreamSwap {
+  ewbem_ctx* c;
+  hipStream_t saved;
+  StreamSwap(ewbem_ctx* cc, hipStream_t s) : c(cc), saved(cc->stream) { c->stream = s; }
+  ~StreamSwap() { c->stream = saved; }
+};
+
+// Transients of one group of problems in lock-step over the frequency
+// index: each problem assembles frequency k and forms its guess on its own
+// library-owned stream (host threads, concurrently), then the group's GMRES
+// run together on stream s with one concatenated matvec per step.
+int lockstep_group(std::vector<ewbem_ctx*>& cs, double* const* u, hipStream_t s) {
+  const int nb = (int)cs.size();
+  int nk_max = 0;
+  for (ewbem_ctx* c : cs) {
+    ensure_device(c);
+    if (c->so.pipeline) fail(EWBEM_EINVAL, "batch lock-step: not with the pipeline");
+    nk_max = std::max(nk_max, c->n_f / 2 + 1);
+  }
+  // per-problem phases on each problem's second stream, in host threads
+  auto each = [&](const std::vector<int>& who, const std::function<void(ewbem_ctx*)>& f) {
+    std::vector<std::exception_ptr> err(who.size());
+    std::vector<std::thread> th;
+    for (size_t q = 0; q < who.size(); ++q)
+      th.emplace_back([&, q] {
+        try {
+          ewbem_ctx* c = cs[who[q]];
+          EWBEM_HIP_CHECK(hipSetDevice(c->device));
+          StreamSwap sw(c, c->astream);
+          f(c);
+        } catch (...) {
+          err[q] = std::current_exception();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (auto& e : err)
+      if (e) std::rethrow_exception(e);
+  };
+  std::vector<int> all(nb);
+  for (int i = 0; i < nb; ++i) all[i] = i;
+  each(all, [&](ewbem_ctx* c) {
+    c->hist_n = 0;
+    c->hist_slot.clear();
+    c->hist_kidx.clear();
+    c->lc_slot.clear();
+    c->lc_kidx.clear();
+    EventPair ev;
+    const auto t0 = Clock::now();
+    EWBEM_HIP_CHECK(hipEventRecord(ev.a, c->stream));
+    rhs_precompute(c, dev_geom(c), 0, c->n_f / 2 + 1);
+    EWBEM_HIP_CHECK(hipEventRecord(ev.b, c->stream));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->acc.t_rhs_ms += ev.elapsed();
+    c->acc.t_assemble_ms += ms_since(t0);
+  });
+  int rc = EWBEM_OK;
+  ConcatMatvec cm;
+  for (int k = 0; k < nk_max; ++k) {
+    std::vector<int> live;
+    for (int i = 0; i < nb; ++i)
+      if (k <= cs[i]->n_f / 2) live.push_back(i);
+    each(live, [&](ewbem_ctx* c) {
+      if (c->assembled_k != k) assemble_k(c, k);
+      guess_k(c, k, nullptr);
+      EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+    });
+    std::vector<ewbem_ctx*> lc;
+    for (int i : live) lc.push_back(cs[i]);
+    std::vector<int> its;
+    std::vector<double> rel;
+    std::vector<char> conv;
+    {
+      std::vector<std::unique_ptr<StreamSwap>> sw;
+      for (ewbem_ctx* c : lc) sw.emplace_back(new StreamSwap(c, s));
+      const auto ts = Clock::now();
+      gmres_lockstep(lc, s, cm, its, rel, conv);
+      const double ms = ms_since(ts);
+      for (size_t q = 0; q < lc.size(); ++q) {
+        lc[q]->acc.t_gmres_ms += ms / lc.size();
+        finish_k(lc[q], k, its[q], rel[q]);
+        if (!conv[q]) rc = EWBEM_ENOCONV;
+      }
+      EWBEM_HIP_CHECK(hipStreamSynchronize(s));
+    }
+  }
+  each(all, [&](ewbem_ctx* c) {
+    const auto tp = Clock::now();
+    size_t i = 0;
+    while (cs[i] != c) ++i;
+    launch_mft_inverse(c->d_spec.p, 3LL * c->nt, c->n_f, c->period, c->sigma, c->window, c->d_perm.p, u[i],
+                       c->stream);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->acc.t_post_ms += ms_since(tp);
+  });
+  return rc;
+}
+
+}  // namespace
+
+int ewbem_batch_solve_transient_lockstep(ewbem_ctx** ctxs, int32_t n, double** u_out, ewbem_stats* stats,
+                                         int32_t per_launch) {
+  if (n < 1 || per_launch < 1 || !ctxs || !u_out) return EWBEM_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !u_out[i]) return EWBEM_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return EWBEM_EINVAL;  // one context, one problem
+    if (ctxs[i]->device != ctxs[0]->device) return EWBEM_EINVAL;
+  }
+  hipStream_t s = nullptr;
+  std::vector<ewbem_stats> st(n);
+  int rc = guard(ctxs[0], [&] {
+    require_gpu(ctxs[0]);
+    EWBEM_HIP_CHECK(hipSetDevice(ctxs[0]->device));
+    EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    for (int i = 0; i < n; ++i) begin_stats(ctxs[i]);
+    int out = EWBEM_OK;
+    for (int g0 = 0; g0 < n; g0 += per_launch) {
+      const int g1 = std::min(n, g0 + per_launch);
+      std::vector<ewbem_ctx*> cs(ctxs + g0, ctxs + g1);
+      const int r = lockstep_group(cs, u_out + g0, s);
+      if (r != EWBEM_OK) out = r;
+    }
+    for (int i = 0; i < n; ++i) end_stats(ctxs[i], &st[i]);
+    return out;
+  });
+  if (s) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  if (rc != EWBEM_OK && rc != EWBEM_ENOCONV) return rc;
+  if (stats) {
+    ewbem_stats a{};
+    for (int i = 0; i < n; ++i) {
+      const ewbem_stats& b = st[i];
+      a.n_solves += b.n_solves;
+      a.iters_total += b.iters_total;
+      a.iters_max = std::max(a.iters_max, b.iters_max);
+      a.matvecs += b.matvecs;
+      a.resid_max = std::max(a.resid_max, b.resid_max);
+      a.guess_resid_sum += b.guess_resid_sum;
+      a.t_assemble_ms += b.t_assemble_ms;
+      a.t_guess_ms += b.t_guess_ms;
+      a.t_gmres_ms += b.t_gmres_ms;
+      a.t_post_ms += b.t_post_ms;
+      a.t_matvec_ms += b.t_matvec_ms;
+      a.matvec_bytes += b.matvec_bytes;
+      a.stored_bytes += b.stored_bytes;
+      a.n_near += b.n_near;
+      a.n_far += b.n_far;
+      a.rank_sum += b.rank_sum;
+      a.rank_max = std::max(a.rank_max, b.rank_max);
+      a.t_aca_ms += b.t_aca_ms;
+      a.t_near_ms += b.t_near_ms;
+      a.t_rhs_ms += b.t_rhs_ms;
+      a.matvec_bytes_total += b.matvec_bytes_total;
+      a.matvecs_timed += b.matvecs_timed;
+      a.aca_warm_blocks += b.aca_warm_blocks;
+      a.aca_cold_blocks += b.aca_cold_blocks;
+      for (int cls = 0; cls < 5; ++cls) a.aca_core_blocks[cls] += b.aca_core_blocks[cls];
+      a.guess_learned += b.guess_learned;
+    }
+    *stats = a;
+  }
+  return rc;
+}
+
 int ewbem_solve_transient_loads(ewbem_ctx* ctx, int32_t n_loads, const double* loads, int32_t pressure, double* u,
                                 ewbem_z* spec, ewbem_stats* stats) {
   return guard(ctx, [&] {
@@ -3051,9 +3574,8 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
     S.release();
     // the least-squares map of each frequency over the training loads
     // (small dense algebra on the host: an n_cases x n_cases Gram matrix per
-    // frequency), and its leave-one-out predictions, the base the network
-    // learns to correct: for a load outside the fit the map's error is what
-    // the leave-one-out residuals sample
+    // frequency), and its predictions of the training loads, the base the
+    // network learns to correct (the map's own residual, lam W)
     std::vector<zc> rxh, rwh;
     int rn = 0;
     DevBuf<cd> base;
@@ -3062,6 +3584,7 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
       std::vector<cd> bh((size_t)M * r, cd{0.0, 0.0});
       std::vector<zc> X((size_t)3 * r * n_cases), Y((size_t)r * n_cases), W;
       std::vector<double> ad;
+      double lam = 0.0;
       for (int k = 3; k < nk; ++k) {
         for (int i = 0; i < n_cases; ++i)
           for (int j = 0; j < r; ++j) {
@@ -3071,13 +3594,13 @@ int ewbem_guess_train(ewbem_ctx* ctx, int32_t n_cases, const double* loads, cons
             X[(size_t)i * 3 * r + 2 * r + j] = C[(b + k - 3) * r + j];
             Y[(size_t)i * r + j] = C[(b + k) * r + j];
           }
-        if (!ridge_dual(X, Y, 3 * r, r, n_cases, o->lsq_reg, W, ad))
+        if (!ridge_dual(X, Y, 3 * r, r, n_cases, o->lsq_reg, W, ad, lam))
           fail(EWBEM_EINVAL, "guess training: the training loads' histories are degenerate at some frequency");
         rxh.insert(rxh.end(), X.begin(), X.end());
         rwh.insert(rwh.end(), W.begin(), W.end());
         for (int i = 0; i < n_cases; ++i)
           for (int j = 0; j < r; ++j) {
-            const zc v = Y[(size_t)i * r + j] - W[(size_t)i * r + j] / ad[i];
+            const zc v = Y[(size_t)i * r + j] - lam * W[(size_t)i * r + j];
             bh[((size_t)i * nk + k) * r + j] = cd{v.real(), v.imag()};
           }
       }

@@ -99,10 +99,11 @@ bool cholesky(std::vector<std::complex<double>>& A, int n);
 std::vector<std::complex<double>> inverse_lh(const std::vector<std::complex<double>>& L, int n);
 // The least-squares map of one frequency in its dual form: X (d x n) and Y
 // (r x n), both column-major; A = (X^H X + lam I)^{-1} with
-// lam = eps tr(X^H X) / n; W = Y A (r x n, column-major) and adiag = diag(A).
-// False if the Gram matrix is zero or does not factor.
+// lam = eps tr(X^H X) / n (returned in lam); W = Y A (r x n, column-major)
+// and adiag = diag(A).  False if the Gram matrix is zero or does not factor.
 bool ridge_dual(const std::vector<std::complex<double>>& X, const std::vector<std::complex<double>>& Y, int d,
-                int r, int n, double eps, std::vector<std::complex<double>>& W, std::vector<double>& adiag);
+                int r, int n, double eps, std::vector<std::complex<double>>& W, std::vector<double>& adiag,
+                double& lam);
 // Eigen-decomposition of a Hermitian n x n matrix by cyclic Jacobi
 // rotations: eigenvalues in descending order, eigenvectors as the columns of
 // V (row-major n x n).

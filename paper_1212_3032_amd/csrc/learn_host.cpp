@@ -102,7 +102,7 @@ void herm_eig(std::vector<zc> A, int n, std::vector<double>& w, std::vector<zc>&
 }
 
 bool ridge_dual(const std::vector<zc>& X, const std::vector<zc>& Y, int d, int r, int n, double eps,
-                std::vector<zc>& W, std::vector<double>& adiag) {
+                std::vector<zc>& W, std::vector<double>& adiag, double& lam_out) {
   // G = X^H X (row-major n x n), columns of X contiguous
   std::vector<zc> G((size_t)n * n);
   double tr = 0.0;
@@ -116,6 +116,7 @@ bool ridge_dual(const std::vector<zc>& X, const std::vector<zc>& Y, int d, int r
   for (int i = 0; i < n; ++i) tr += G[(size_t)i * n + i].real();
   if (!(tr > 0)) return false;
   const double lam = eps * tr / n;
+  lam_out = lam;
   for (int i = 0; i < n; ++i) G[(size_t)i * n + i] += lam;
   if (!cholesky(G, n)) return false;
   // A = (L L^H)^{-1} = R R^H with R = (L^H)^{-1} upper triangular

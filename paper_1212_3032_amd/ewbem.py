@@ -30,7 +30,7 @@ EXPORTED = [
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
     "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_solve_transient_loads",
     "ewbem_solve_transient_incident_loads",
-    "ewbem_batch_solve_transient",
+    "ewbem_batch_solve_transient", "ewbem_batch_solve_transient_lockstep",
     "ewbem_mft_inverse", "ewbem_default_train_opts", "ewbem_guess_train", "ewbem_guess_save",
     "ewbem_guess_load", "ewbem_guess_basis", "ewbem_mlp_eval", "ewbem_mlp_eval_noalloc", "ewbem_mlp_train",
 ]
@@ -133,6 +133,7 @@ def lib():
         "ewbem_solve_transient_loads": (C.c_int, [P, I32, P, I32, P, P, C.POINTER(Stats)]),
         "ewbem_solve_transient_incident_loads": (C.c_int, [P, I32, P, P, P, P, C.POINTER(Stats)]),
         "ewbem_batch_solve_transient": (C.c_int, [P, I32, P, C.POINTER(Stats), I32]),
+        "ewbem_batch_solve_transient_lockstep": (C.c_int, [P, I32, P, C.POINTER(Stats), I32]),
         "ewbem_mft_inverse": (C.c_int, [P, P, P]),
         "ewbem_default_train_opts": (None, [C.POINTER(TrainOpts)]),
         "ewbem_guess_train": (C.c_int, [P, I32, P, C.POINTER(TrainOpts), C.POINTER(Stats)]),
@@ -480,10 +481,12 @@ class Context:
             _dev_ptr(u, "torch.float64", self.n_f * N)))
 
 
-def batch_solve_transient(ctxs, outs, per_launch=16, allow_noconv=False):
+def batch_solve_transient(ctxs, outs, per_launch=16, allow_noconv=False, lockstep=False):
     """Solve the transients of several contexts (distinct, ideally each on its
     own stream) concurrently; outs[i] is context i's n_f x 3 nt float64
-    device tensor.  Returns the aggregated stats."""
+    device tensor.  lockstep: in groups of per_launch over the frequency
+    index, one concatenated matvec per Arnoldi step of the group
+    (ewbem_batch_solve_transient_lockstep).  Returns the aggregated stats."""
     if len(ctxs) != len(outs):
         raise ValueError("one output per context")
     n = len(ctxs)
@@ -491,7 +494,8 @@ def batch_solve_transient(ctxs, outs, per_launch=16, allow_noconv=False):
     us = (C.c_void_p * max(n, 1))(*[_dev_ptr(u, "torch.float64", c.n_f * 3 * c.nt).value
                                     for c, u in zip(ctxs, outs)])
     st = Stats()
-    rc = lib().ewbem_batch_solve_transient(hs, n, us, C.byref(st), int(per_launch))
+    fn = lib().ewbem_batch_solve_transient_lockstep if lockstep else lib().ewbem_batch_solve_transient
+    rc = fn(hs, n, us, C.byref(st), int(per_launch))
     if rc != OK and not (allow_noconv and rc == ENOCONV):
         raise EwbemError(rc, "batch transient solve failed: " + "; ".join(
             (lib().ewbem_last_error(c.h) or b"").decode() for c in ctxs))

@@ -126,6 +126,7 @@ def test_mlp_train_matches_oracle_adam(env):
 SUB, NF, PERIOD = 3, 64, 8.0
 N_TRAIN, N_HELD = 48, 4
 R = 128
+GAIN = 0.08  # fraction of the extrapolation's GMRES iterations the trained guess removes (measured 10.9%)
 
 
 def _setup(E, xyz, tri, guess, p0):
@@ -219,6 +220,67 @@ def _model_map(blob, N):
     return rn, rk, list(X), list(W)
 
 
+def test_learned_guess_matches_oracle_recomputation(env, trained):
+    """The library's learned guess against the oracle's definition on the
+    same history: a model fitted without network epochs (its last layer is
+    zero, so the prediction is the least-squares map alone) solves a
+    held-out load; from its own solutions and saved model the oracle forms,
+    at every k, the least-squares extrapolation (Sec. 4.2, K = min(k, 3))
+    and for k >= 3 the learned step (oracle.learn.learned_guess with the
+    map's prediction); the summed guess residuals must agree with the
+    library's to 1e-8 relative (rounding of the same products)."""
+    torch, dev, E = env
+    loads = trained["loads"]
+    N = 3 * len(trained["tri"])
+    nk = NF // 2 + 1
+    c = _setup(E, trained["xyz"], trained["tri"], E.GUESS_LEARNED, loads[0])
+    c.guess_train(loads[:N_TRAIN], pressures=True, n_modes=R, epochs=0)
+    rn, rk, Xs, Ws = _model_map(c.guess_save(), N)
+    r = c.guess_basis()
+    phi = torch.zeros(r * N, dtype=torch.complex128, device=dev)
+    c.guess_basis(phi)
+    Phi = phi.cpu().numpy().reshape(r, N).T
+    i = N_TRAIN
+    c.set_load_pressure(loads[i], ramp_history(NF, PERIOD, 0.05))
+    u = torch.zeros(NF * N, dtype=torch.float64, device=dev)
+    spec = torch.zeros(nk * N, dtype=torch.complex128, device=dev)
+    st = c.solve_transient(u, spec)
+    sol = spec.cpu().numpy().reshape(nk, N)
+    d = _setup(E, trained["xyz"], trained["tri"], E.GUESS_SEM, loads[i])
+
+    def A(x):
+        y = torch.zeros(N, dtype=torch.complex128, device=dev)
+        d.apply(torch.tensor(np.ascontiguousarray(x), device=dev), y)
+        return y.cpu().numpy()
+
+    tot = 0.0
+    for k in range(nk):
+        d.assemble(k)
+        b = torch.zeros(N, dtype=torch.complex128, device=dev)
+        d.get_rhs(b)
+        b = b.cpu().numpy()
+        K = min(k, 3)
+        if K == 0:
+            tot += 1.0
+            continue
+        X = np.stack([sol[k - 1 - j] for j in range(K)], 1)
+        Y = np.stack([A(X[:, j]) for j in range(K)], 1)
+        co, *_ = np.linalg.lstsq(Y, b, rcond=None)
+        xs, rs = X @ co, b - Y @ co
+        if k >= 3:
+            cs = [Phi.conj().T @ sol[k - j] for j in (1, 2, 3)]
+            p = OL.ridge_predict(Xs[k - 3], Ws[k - 3], np.concatenate(cs))
+            xs, rs, _ = OL.learned_guess(xs, rs, Phi, p, A)
+        tot += np.linalg.norm(rs) / np.linalg.norm(b)
+    d.close()
+    e = abs(tot - st["guess_resid_sum"]) / tot
+    _say(f"learned guess, load {i}: guess residual sum library {st['guess_resid_sum']:.10f}, oracle {tot:.10f} "
+         f"(rel. {e:.1e}); {st['iters_total']} iterations, {st['guess_learned']} learned steps")
+    assert st["guess_learned"] == nk - 3
+    assert e < 1e-8
+    c.close()
+
+
 def test_learned_guess_on_held_out_loads(env, trained):
     torch, dev, E = env
     c, loads = trained["ctx"], trained["loads"]
@@ -244,13 +306,12 @@ def test_learned_guess_on_held_out_loads(env, trained):
         g_l += b["guess_resid_sum"]
     _say(f"held-out total: iterations SEM {it_s}, learned {it_l} ({100 * (1 - it_l / it_s):.1f}% fewer); "
          f"guess residual sum {g_s:.3e} -> {g_l:.3e}")
-    # the extra column can only lower the least-squares residual over the
-    # same history; the histories differ by the solver tolerance, so the
-    # sums are compared, not each frequency.  Iterations are reported: on
-    # this workload the basis-projection residual of the exact solution is
-    # itself about 1e-2, the extrapolation's level, so the gain is small
-    assert g_l <= g_s
-    assert it_l <= 1.02 * it_s
+    # the learned step can only lower the residual of the extrapolation over
+    # the same history; the histories differ by the solver tolerance, so the
+    # sums are compared, not each frequency.  What the trained model gains:
+    # GAIN of the extrapolation's iterations at least (measured below)
+    assert g_l < g_s
+    assert it_l <= (1.0 - GAIN) * it_s
     sem.close()
 
 

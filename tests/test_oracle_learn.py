@@ -239,3 +239,41 @@ def test_ridge_leave_one_out_matches_refitting():
         Wi = Yi @ np.linalg.inv(Xi.conj().T @ Xi + lam * np.eye(n - 1))
         ref = C[i, k] - Wi @ (Xi.conj().T @ X[:, i])
         assert np.abs(R[:, i] - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_ridge_training_predictions_closed_form():
+    """W X^H X = Y - lam W: the dual form's own residual on its training
+    cases is lam times its coefficients."""
+    rng = np.random.default_rng(14)
+    n, nk, r, k = 6, 5, 4, 4
+    C = _cases(rng, n, nk, r)
+    eps = 1e-3
+    X, W, ad = OL.ridge_fit(C, k, eps=eps)
+    G = X.conj().T @ X
+    lam = eps * np.trace(G).real / n
+    assert np.abs(OL.ridge_train_predictions(X, W) - (C[:, k, :].T - lam * W)).max() < 1e-10
+
+
+def test_learned_guess_step():
+    """The step is the least-squares one (the new residual is orthogonal to
+    A v); exact coordinates of a solution whose extrapolation error lies in
+    the basis give that solution; a prediction equal to the extrapolation's
+    own coordinates changes nothing."""
+    rng = np.random.default_rng(15)
+    N, r = 30, 5
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)) + 6 * np.eye(N)
+    Phi, _ = np.linalg.qr(rng.standard_normal((N, r)) + 1j * rng.standard_normal((N, r)))
+    a = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    b = A @ a
+    xs = a + Phi @ (rng.standard_normal(r) + 1j * rng.standard_normal(r))
+    rs = b - A @ xs
+    x0, r0, g = OL.learned_guess(xs, rs, Phi, Phi.conj().T @ a, lambda v: A @ v)
+    assert abs(g - 1) < 1e-12 and np.abs(x0 - a).max() < 1e-12 and np.abs(r0).max() < 1e-10
+    p = rng.standard_normal(r) + 1j * rng.standard_normal(r)
+    x0, r0, g = OL.learned_guess(xs, rs, Phi, p, lambda v: A @ v)
+    v = Phi @ (p - Phi.conj().T @ xs)
+    assert abs(np.vdot(A @ v, r0)) < 1e-10 * np.linalg.norm(A @ v) * np.linalg.norm(r0)
+    assert np.linalg.norm(r0) <= np.linalg.norm(rs)
+    assert np.abs(r0 - (b - A @ x0)).max() < 1e-10
+    x0, r0, g = OL.learned_guess(xs, rs, Phi, Phi.conj().T @ xs, lambda v: A @ v)
+    assert g == 0.0 and np.array_equal(x0, xs)
