@@ -98,6 +98,10 @@ typedef struct {
                            the complex128 copy never exists for all blocks at once (the
                            meshes whose complex128 far field would not fit).  The factors are
                            the same; only the memory differs.  Not with the pipeline. */
+  int32_t mv_mfma;      /* 1: the panel products of a matvec on eight right-hand sides (several
+                           loads' lock-step GMRES, the learned guess's training) on the FP64
+                           matrix cores, 0: on the vector units (default 0).  The summation
+                           order differs, the results agree to rounding. */
 } ewbem_op_opts;
 
 typedef struct {

@@ -296,3 +296,37 @@ def plane_s_wave_stress(x, s, mat, direction, polarisation):
     ph = np.exp(-complex(s) * (x @ d) / mat["cs"])
     S = -(mat["mu"] * complex(s) / mat["cs"]) * (np.outer(q, d) + np.outer(d, q))
     return ph[:, None, None] * S[None]
+
+
+# ---- Stokes' solution: a point force with a time history in the infinite solid
+
+def stokes_point_force(x, x0, direction, t, F, mat, n_quad=96):
+    """Displacement u(x, t) of the infinite solid under the point force
+    F(t) d at x0 (Stokes, 1849; in the form of Aki and Richards, eq. 4.23):
+      4 pi rho u_i = (3 g_i g_j - delta_ij) r^-3 int_{r/c_p}^{r/c_s} tau F(t - tau) dtau
+                   + g_i g_j r^-1 c_p^-2 F(t - r/c_p)
+                   - (g_i g_j - delta_ij) r^-1 c_s^-2 F(t - r/c_s)
+    with r = |x - x0|, g = (x - x0)/r, summed over j with d_j.  F: callable
+    of an array of times (zero before its onset); the near-field integral by
+    Gauss-Legendre with n_quad nodes.  Returns (len(t), n_points, 3)."""
+    x = np.atleast_2d(np.asarray(x, float))
+    d = np.asarray(direction, float)
+    t = np.asarray(t, float)
+    dx = x - np.asarray(x0, float)[None, :]
+    r = np.linalg.norm(dx, axis=1)
+    g = dx / r[:, None]
+    gd = g @ d
+    cp, cs, rho = mat["cp"], mat["cs"], mat["rho"]
+    xg, wg = np.polynomial.legendre.leggauss(n_quad)
+    out = np.zeros((len(t), len(r), 3))
+    for p in range(len(r)):
+        a, b = r[p] / cp, r[p] / cs
+        tau = 0.5 * (b - a) * xg + 0.5 * (b + a)
+        wq = 0.5 * (b - a) * wg
+        near = np.array([np.sum(wq * tau * F(ti - tau)) for ti in t])
+        fp, fs = F(t - a), F(t - b)
+        A = (3 * gd[p] * g[p] - d) / r[p] ** 3           # (3 g_i g_j - delta_ij) d_j
+        B = gd[p] * g[p] / (r[p] * cp ** 2)                # g_i g_j d_j
+        C = (gd[p] * g[p] - d) / (r[p] * cs ** 2)          # (g_i g_j - delta_ij) d_j
+        out[:, p, :] = (near[:, None] * A[None, :] + fp[:, None] * B[None, :] - fs[:, None] * C[None, :]) / (4 * pi * rho)
+    return out

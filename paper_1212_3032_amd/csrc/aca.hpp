@@ -134,17 +134,7 @@ constexpr int WS_LDS_MID = 4480;
 constexpr int WS_LDS_LARGE = 8960;
 constexpr int WS_CH = 8;             // substitution terms solved together in registers (coefficient padding)
 constexpr int WS_LU_NR_LDS = 2;     // LDS classes hold cores of at most 128 rows
-// Side streams and events on which launch_ws runs independent kernels
-// concurrently (the row and column evaluations; the five core-elimination
-// size classes; the U and V substitutions); null streams: everything on s.
-constexpr int WS_SIDE = 4;
-struct WsStreams {
-  hipStream_t side[WS_SIDE] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t fork[3] = {nullptr, nullptr, nullptr};        // recorded on s
-  hipEvent_t done[3][WS_SIDE] = {};                        // recorded on the side streams
-};
-void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s,
-               const WsStreams* ss = nullptr);
+void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s);
 
 // ---- H-matrix matvec
 // Phase 1 task: z[zidx + j] = sum_c V[c, j] x[x0 + c] for j < ncol, with V
@@ -185,9 +175,10 @@ constexpr int HMV_MAXROWS = 192;
 // nrhs = 1..4 right-hand sides: columns of x (stride ldx), z (ldz), the
 // partial sums (ldp) and y (ldy).
 void launch_far_vt(const VtTask* tasks, int ntask, int cols_per_wave, int store_c64, const cd* x, long long ldx,
-                   int nrhs, cd* z, long long ldz, hipStream_t st);
+                   int nrhs, cd* z, long long ldz, hipStream_t st, int mfma = 0);
+// mfma: eight right-hand sides on the matrix cores (k_hmv_mfma8)
 void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, long long ldx, int nrhs,
-                const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st);
+                const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st, int mfma = 0);
 void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, long long ldp, int nrhs, cd* y,
                        long long ldy, hipStream_t st);
 constexpr int HMV_MAXRHS = 8;  // right-hand sides of one multi-right-hand-side matvec

@@ -193,7 +193,8 @@ __device__ __forceinline__ void wave_argmax(double& v, int& e) {
 // that each pivot costs one barrier.  W is in LDS when it has at most MAXE
 // entries; MAXE = 0 works on the copy of W in global memory (large cores).
 // NR: row chunks of 64 a lane covers (R3 <= 64 NR).
-constexpr int WS_LU_NW = 8;  // wavefronts per elimination workgroup (tiny cores: 2)
+constexpr int WS_LU_NW = 8;      // wavefronts per elimination workgroup, cores in global memory
+constexpr int WS_LU_NW_LDS = 8;  // the same for the LDS classes (tiny cores: 2)
 template <int MAXE, int NR, int NW>
 __global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb, const int* __restrict__ list,
                                                const FarBlk* __restrict__ blks, const int* __restrict__ plist,
@@ -563,69 +564,42 @@ __global__ __launch_bounds__(256) void k_ws_finish(WsArgs A, const FarBlk* __res
   st[w.blk] = s;
 }
 
-void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s,
-               const WsStreams* ss) {
+void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s) {
   if (A.nwarm <= 0) return;
-  const bool par = ss && ss->side[0];
-  // stream for the q-th concurrent launch of a phase (q = 0: s itself)
-  auto on = [&](int q) { return (par && q > 0) ? ss->side[q - 1] : s; };
-  // fork: the side streams wait for everything enqueued on s so far
-  auto fork = [&](int ph, int nside) {
-    if (!par) return;
-    EWBEM_HIP_CHECK(hipEventRecord(ss->fork[ph], s));
-    for (int q = 0; q < nside; ++q) EWBEM_HIP_CHECK(hipStreamWaitEvent(ss->side[q], ss->fork[ph], 0));
-  };
-  // join: s waits for the side streams' work of this phase
-  auto join = [&](int ph, int nside) {
-    if (!par) return;
-    for (int q = 0; q < nside; ++q) {
-      EWBEM_HIP_CHECK(hipEventRecord(ss->done[ph][q], ss->side[q]));
-      EWBEM_HIP_CHECK(hipStreamWaitEvent(s, ss->done[ph][q], 0));
-    }
-  };
   hipLaunchKernelGGL(k_ws_init, dim3((A.nwarm + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, W.blks, W.st, W.used,
                      W.plist);
-  // the cross: rows on a side stream, columns on s (disjoint outputs)
-  fork(0, 1);
   if (A.tot_er > 0)
-    hipLaunchKernelGGL(k_ws_eval_rows, dim3((A.tot_er + 255) / 256), dim3(256), 0, on(1), A.wb, A.nwarm, A.er_off,
-                       W.blks, W.plist, A.cross, g, P);
+    hipLaunchKernelGGL(k_ws_eval_rows, dim3((A.tot_er + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, A.er_off, W.blks,
+                       W.plist, A.cross, g, P);
   if (A.tot_ec > 0)
     hipLaunchKernelGGL(k_ws_eval_cols, dim3((A.tot_ec + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, A.ec_off, W.blks,
                        W.plist, A.cross, g, P);
-  join(0, 1);
-  // the elimination in five size classes, each block's own outputs: W of up
-  // to 1024 entries and 64 rows with two wavefronts, of up to 2304, 4480 and
-  // 8960 entries with eight, all in LDS, larger in global memory (the
-  // longest, on s)
-  fork(1, 4);
-  const int nt = 64 * WS_LU_NW;
+  // the elimination in five size classes: W of up to 1024 entries and 64
+  // rows with two wavefronts, of up to 2304, 4480 and 8960 entries with
+  // eight, all in LDS, larger in global memory
+  const int nt = 64 * WS_LU_NW, ntl = 64 * WS_LU_NW_LDS;
   const int* lst = A.lu_list;
   if (A.n_lu[0] > 0)
-    hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS, WS_LU_NW>), dim3(A.n_lu[0]), dim3(nt), 0, on(1), A.wb, lst,
-                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[0]), dim3(ntl), 0, s, A.wb,
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
   lst += A.n_lu[0];
   if (A.n_lu[1] > 0)
-    hipLaunchKernelGGL((k_ws_lu<WS_LDS_MID, WS_LU_NR_LDS, WS_LU_NW>), dim3(A.n_lu[1]), dim3(nt), 0, on(2), A.wb, lst,
-                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_MID, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[1]), dim3(ntl), 0, s, A.wb,
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
   lst += A.n_lu[1];
   if (A.n_lu[2] > 0)
-    hipLaunchKernelGGL((k_ws_lu<WS_LDS_LARGE, WS_LU_NR_LDS, WS_LU_NW>), dim3(A.n_lu[2]), dim3(nt), 0, on(3), A.wb, lst,
-                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_LARGE, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[2]), dim3(ntl), 0, s, A.wb,
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
   lst += A.n_lu[2];
   if (A.n_lu[3] > 0)
     hipLaunchKernelGGL((k_ws_lu<0, (3 * WS_MAXLIST + 63) / 64, WS_LU_NW>), dim3(A.n_lu[3]), dim3(nt), 0, s, A.wb, lst,
                        W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
   lst += A.n_lu[3];
   if (A.n_lu[4] > 0)
-    hipLaunchKernelGGL((k_ws_lu<WS_LDS_TINY, 1, 2>), dim3(A.n_lu[4]), dim3(128), 0, on(4), A.wb, lst, W.blks, W.plist,
+    hipLaunchKernelGGL((k_ws_lu<WS_LDS_TINY, 1, 2>), dim3(A.n_lu[4]), dim3(128), 0, s, A.wb, lst, W.blks, W.plist,
                        A.cross, A.pq, A.rho, A.coef);
-  join(1, 4);
-  // the substitutions: U on s, V on a side stream (disjoint outputs)
-  fork(2, 1);
   hipLaunchKernelGGL(k_ws_form_u, dim3((A.tot_tu + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, A.coef);
-  hipLaunchKernelGGL(k_ws_form_v, dim3((A.tot_tv + 3) / 4), dim3(256), 0, on(1), A, W.blks, A.coef);
-  join(2, 1);
+  hipLaunchKernelGGL(k_ws_form_v, dim3((A.tot_tv + 3) / 4), dim3(256), 0, s, A, W.blks, A.coef);
   hipLaunchKernelGGL(k_ws_finish, dim3((A.nwarm + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, W.plist,
                      W.nlist, tol);
 }

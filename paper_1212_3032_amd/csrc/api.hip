@@ -160,7 +160,6 @@ struct ewbem_ctx {
   DevBuf<cd> d_wsf[2];
   int fslot = 0;
   hipStream_t astream = nullptr;  // the overlapped ACA's stream (library-owned)
-  WsStreams ws_streams;           // the warm start's side streams and events (library-owned)
   // one buffer per capacity-retry round of the current frequency; all stay
   // alive until the next frequency is assembled (blocks retried in an
   // earlier round keep pointing into their round's buffer)
@@ -437,13 +436,6 @@ void ensure_device(ewbem_ctx* c) {
   }
   EWBEM_HIP_CHECK(hipSetDevice(c->device));
   if (!c->astream) EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking));
-  if (!c->ws_streams.side[0]) {
-    WsStreams& w = c->ws_streams;
-    for (hipEvent_t& e : w.fork) EWBEM_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    for (auto& row : w.done)
-      for (hipEvent_t& e : row) EWBEM_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    for (hipStream_t& q : w.side) EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
-  }
   hipStream_t st = c->stream;
   const HostGeom& g = c->hg;
   c->d_cen.upload(g.cen, st);
@@ -620,7 +612,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     WsArgs A{c->d_wsb.p, nw, c->d_wsoff.p, c->d_wsoff.p + (nw + 1), c->d_wsoff.p + 2 * (nw + 1),
              c->d_wsoff.p + 3 * (nw + 1), (int)er, (int)ec, (int)tu, (int)tv, c->d_cross.p, c->d_wspq.p,
              c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p, {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4]}};
-    launch_ws(A, W0, g, c->P, c->op.aca_tol, st, &c->ws_streams);
+    launch_ws(A, W0, g, c->P, c->op.aca_tol, st);
   }
   if (count_starts) {
     c->acc.aca_warm_blocks += nw;
@@ -1099,8 +1091,10 @@ void apply_tree_multi(ewbem_ctx* c, const cd* X, cd* Y, int nrhs) {
   hipStream_t st = c->stream;
   const long long N = 3LL * c->nt;
   if (nrhs < 1 || nrhs > HMV_MAXRHS) fail(EWBEM_EINVAL, "internal: matvec right-hand sides out of range");
-  launch_far_vt(c->d_vt.p, c->n_vt, c->vt_cols, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st);
-  launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, X, N, nrhs, c->d_z.p, c->z_len, c->d_mvpart.p, c->mvpart_len, st);
+  launch_far_vt(c->d_vt.p, c->n_vt, c->vt_cols, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st,
+                c->op.mv_mfma);
+  launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, X, N, nrhs, c->d_z.p, c->z_len, c->d_mvpart.p, c->mvpart_len, st,
+             c->op.mv_mfma);
   launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, c->mvpart_len, nrhs, Y, N, st);
   c->acc.matvecs += nrhs;
 }
@@ -2462,18 +2456,6 @@ void ewbem_destroy(ewbem_ctx* ctx) {
       (void)hipStreamDestroy(ctx->astream);
       ctx->astream = nullptr;
     }
-    WsStreams& w = ctx->ws_streams;
-    for (hipStream_t& q : w.side)
-      if (q) {
-        (void)hipStreamSynchronize(q);
-        (void)hipStreamDestroy(q);
-        q = nullptr;
-      }
-    for (hipEvent_t& e : w.fork)
-      if (e) (void)hipEventDestroy(e);
-    for (auto& row : w.done)
-      for (hipEvent_t& e : row)
-        if (e) (void)hipEventDestroy(e);
   }
   delete ctx;
 }
@@ -2654,7 +2636,7 @@ int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
         !(o->eta_adm > 0) || !(o->aca_tol > 0 && o->aca_tol < 1) ||
         (o->far_store != EWBEM_STORE_C128 && o->far_store != EWBEM_STORE_C64) || o->self_order < 4 ||
         o->self_order > MAX_SELF_ORDER || (o->aca_reuse != 0 && o->aca_reuse != 1) ||
-        (o->autotune != 0 && o->autotune != 1) || o->aca_batch_mb < 0 ||
+        (o->autotune != 0 && o->autotune != 1) || (o->mv_mfma != 0 && o->mv_mfma != 1) || o->aca_batch_mb < 0 ||
         (o->aca_batch_mb > 0 && (o->far_store != EWBEM_STORE_C64 || o->kind != EWBEM_OP_HMAT)))
       fail(EWBEM_EINVAL, "operator options out of range");
     ctx->op = *o;

@@ -89,6 +89,48 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
   }
 }
 
+// Phase 1 for eight right-hand sides on the matrix cores: one wavefront per
+// task (up to 16 factor columns j; here at most NC <= 8).  Per step of four
+// rows c of the factor, v_mfma_f64_16x16x4f64 twice with A the 16 x 4 block
+// V(c, j)^T (lane l: column j = l % 16, row c = l / 16) and B the x entries
+// (lane l: row c = l / 16, output column n = l % 16):
+//   Z += Re(V^T) [Re X | Im X] + Im(V^T) [-Im X | Re X] = [Re V^T X | Im V^T X].
+// Lane l ends with Z rows (factor columns) l / 16 + 4 v of output column
+// l % 16 (real parts of the eight products, then imaginary parts).
+typedef double fvt_v4d __attribute__((ext_vector_type(4)));
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__ tasks, int ntask,
+                                                      const cd* __restrict__ x, long long ldx, cd* __restrict__ z,
+                                                      long long ldz) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= ntask) return;
+  const VtTask T = tasks[t];
+  const TS* __restrict__ V = (const TS*)T.V;
+  const cd* __restrict__ xs = x + T.x0;
+  const int C = T.C, nc = T.ncol;
+  const int j = lane & 15, kr = lane >> 4, q = j & 7;
+  const bool jv = j < nc;
+  fvt_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < C; c0 += 4) {
+    const int c = c0 + kr;
+    const bool cv = c < C;
+    const cd a = (jv && cv) ? to_cd(V[(size_t)j * C + c]) : mk(0.0);
+    const cd xv = cv ? xs[c + q * ldx] : mk(0.0);
+    const double b1 = j < 8 ? xv.x : xv.y;
+    const double b2 = j < 8 ? -xv.y : xv.x;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b2, acc, 0, 0, 0);
+  }
+  const int comp = j >> 3;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = kr + 4 * v;
+    if (i < nc) ((double*)(z + T.zidx + i + q * ldz))[comp] = acc[v];
+  }
+}
+
 template <int NR, int NC>
 void far_vt_nr(const VtTask* tasks, int ntask, int store_c64, const cd* x, long long ldx, cd* z, long long ldz,
                hipStream_t st) {
@@ -116,8 +158,16 @@ void far_vt_nc(const VtTask* tasks, int ntask, int store_c64, const cd* x, long 
 }
 
 void launch_far_vt(const VtTask* tasks, int ntask, int cols_per_wave, int store_c64, const cd* x, long long ldx,
-                   int nrhs, cd* z, long long ldz, hipStream_t st) {
+                   int nrhs, cd* z, long long ldz, hipStream_t st, int mfma) {
   if (ntask <= 0) return;
+  if (nrhs == 8 && mfma) {
+    dim3 grid((ntask + 3) / 4);
+    if (store_c64)
+      hipLaunchKernelGGL((k_far_vt_mfma8<cf>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
+    else
+      hipLaunchKernelGGL((k_far_vt_mfma8<cd>), grid, dim3(256), 0, st, tasks, ntask, x, ldx, z, ldz);
+    return;
+  }
   switch (cols_per_wave) {
     case 2: far_vt_nc<2>(tasks, ntask, store_c64, x, ldx, nrhs, z, ldz, st); break;
     case 4: far_vt_nc<4>(tasks, ntask, store_c64, x, ldx, nrhs, z, ldz, st); break;
@@ -266,8 +316,99 @@ __global__ __launch_bounds__(256) void k_hmv(const RowTask* __restrict__ tasks, 
   }
 }
 
+// Phase 2 for eight right-hand sides on the matrix cores.  A task's rows
+// form up to twelve tiles of 16; wave w of the four takes tiles w, w + 4,
+// w + 8.  Per step of four panel columns and tile, v_mfma_f64_16x16x4f64
+// twice: with A the tile's 16 x 4 entries (lane l: row l % 16, column
+// l / 16) and B the staged x entries (lane l: column l / 16, output column
+// n = l % 16),
+//   C += Re(A) [Re X | Im X] + Im(A) [-Im X | Re X] = [Re AX | Im AX],
+// the 16 output columns holding the real parts of the eight products, then
+// their imaginary parts.  Lane l holds C rows l / 16 + 4 v, v < 4, of
+// output column l % 16 (the layout of this instruction's result, checked on
+// the device).
+typedef double hmv_v4d __attribute__((ext_vector_type(4)));
+
+template <typename TS>
+__device__ __forceinline__ cd panel_entry(const void* A, size_t i) {
+  if constexpr (sizeof(TS) == 16) {
+    return ((const cd*)A)[i];
+  } else {
+    const cf v = ((const cf*)A)[i];
+    return cd{(double)v.x, (double)v.y};
+  }
+}
+
+template <typename TS>
+__device__ __forceinline__ void tiles_mfma(const void* A, int ld, int rows, int c0, int nch, const cd* xs, int lane,
+                                           int w, hmv_v4d (&acc)[3]) {
+  const int kr = lane >> 4, n = lane & 15;
+  for (int cc = 0; cc < nch; cc += 4) {
+    const int col = cc + kr;
+    const bool cv = col < nch;
+    const cd xv = cv ? xs[col * 8 + (n & 7)] : mk(0.0);
+    const double b1 = n < 8 ? xv.x : xv.y;
+    const double b2 = n < 8 ? -xv.y : xv.x;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int row = 16 * (w + 4 * q) + n;
+      const cd a = (cv && row < rows) ? panel_entry<TS>(A, (size_t)(c0 + col) * ld + row) : mk(0.0);
+      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1, acc[q], 0, 0, 0);
+      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b2, acc[q], 0, 0, 0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hmv_mfma8(const RowTask* __restrict__ tasks, const Seg* __restrict__ segs,
+                                                   const cd* __restrict__ x, long long ldx,
+                                                   const cd* __restrict__ z, long long ldz,
+                                                   cd* __restrict__ partial, long long ldp) {
+  constexpr int NR = 8;
+  const RowTask T = tasks[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ cd xs[HMV_XCH * NR];
+  hmv_v4d acc[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) acc[q] = hmv_v4d{0.0, 0.0, 0.0, 0.0};
+  for (int s = T.s0; s < T.s1; ++s) {
+    const Seg S = segs[s];
+    const bool fz = (S.flags & SEG_FROM_Z) != 0;
+    const cd* src = (fz ? z : x) + S.src;
+    const long long lds = fz ? ldz : ldx;
+    for (int c0 = 0; c0 < S.ncols; c0 += HMV_XCH) {
+      const int nch = min(HMV_XCH, S.ncols - c0);
+      __syncthreads();
+      for (int i = threadIdx.x; i < nch * NR; i += blockDim.x) {
+        const int q = i / nch, cc = i - q * nch;
+        xs[cc * NR + q] = src[c0 + cc + q * lds];
+      }
+      __syncthreads();
+      if (S.flags & SEG_C64)
+        tiles_mfma<cf>(S.A, S.ld, T.rows, c0, nch, xs, lane, w, acc);
+      else
+        tiles_mfma<cd>(S.A, S.ld, T.rows, c0, nch, xs, lane, w, acc);
+    }
+  }
+  const int j = lane & 15, q = j & 7, comp = j >> 3;
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * (w + 4 * t) + (lane >> 4) + 4 * v;
+      if (row < T.rows) {
+        double* p = (double*)(partial + q * ldp + (size_t)blockIdx.x * HMV_MAXROWS + row);
+        p[comp] = acc[t][v];
+      }
+    }
+}
+
 void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, long long ldx, int nrhs,
-                const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st) {
+                const cd* z, long long ldz, cd* partial, long long ldp, hipStream_t st, int mfma) {
+  if (ntask > 0 && nrhs == 8 && mfma) {
+    hipLaunchKernelGGL(k_hmv_mfma8, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp);
+    return;
+  }
   if (ntask <= 0) return;
   switch (nrhs) {
     case 1: hipLaunchKernelGGL(k_hmv<1>, dim3(ntask), dim3(256), 0, st, tasks, segs, x, ldx, z, ldz, partial, ldp); break;

@@ -43,7 +43,8 @@ class Z(C.Structure):
 class OpOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("leaf_size", C.c_int32), ("eta_adm", C.c_double),
                 ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32),
-                ("aca_reuse", C.c_int32), ("autotune", C.c_int32), ("aca_batch_mb", C.c_int32)]
+                ("aca_reuse", C.c_int32), ("autotune", C.c_int32), ("aca_batch_mb", C.c_int32),
+                ("mv_mfma", C.c_int32)]
 
 
 class SolverOpts(C.Structure):

@@ -290,3 +290,38 @@ def test_incident_loads_match_oracle():
         e = _rel(U[l].ravel(), ref["u"].ravel())
         _say(f"incident wave {l}: relative L2 error against the oracle {e:.2e}")
         assert e < 1e-6
+
+
+@pytest.mark.parametrize("store", ["c128", "c64"])
+def test_loads_on_the_matrix_cores(store):
+    """Eight loads through one frequency loop with the eight-right-hand-side
+    panel products on the FP64 matrix cores (op.mv_mfma) against the same on
+    the vector units: the products differ in summation order only, so the
+    transients agree to 1e-10 relative (rounding carried through GMRES at
+    tol 1e-8) and the iteration counts to 1%."""
+    import torch
+    from paper_1212_3032_amd import ewbem as E
+    dev = torch.device("cuda:0")
+    xyz, tri = icosphere(3)
+    rng = np.random.default_rng(88)
+    loads = np.array([sh_pressure(xyz, tri, rng)[0] for _ in range(8)])
+    N = 3 * len(tri)
+    out = {}
+    for mfma in (0, 1):
+        c = E.Context(0)
+        c.set_mesh(xyz, tri, exterior=True)
+        c.set_material(1.0, 1.0, 0.25)
+        c.set_time(PERIOD, NF, 6.0 / PERIOD, 1)
+        c.set_load_pressure(loads[0], ramp_history(NF, PERIOD, 0.05))
+        c.set_operator(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-6, autotune=0, mv_mfma=mfma,
+                       far_store=E.STORE_C64 if store == "c64" else E.STORE_C128)
+        c.set_solver(tol=1e-8, guess=E.GUESS_SEM)
+        u = torch.zeros(8 * NF * N, dtype=torch.float64, device=dev)
+        st = c.solve_transient_loads(loads, u, pressures=True)
+        out[mfma] = (u.cpu().numpy().reshape(8, -1), st["iters_total"])
+        _say(f"8 loads, {store}, matrix cores {mfma}: {st['iters_total']} iterations")
+        c.close()
+    e = max(_rel(out[1][0][i], out[0][0][i]) for i in range(8))
+    _say(f"  transients differ by at most {e:.1e}")
+    assert e < 1e-10
+    assert abs(out[1][1] - out[0][1]) <= 0.01 * out[0][1]
