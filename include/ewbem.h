@@ -99,9 +99,18 @@ typedef struct {
                            meshes whose complex128 far field would not fit).  The factors are
                            the same; only the memory differs.  Not with the pipeline. */
   int32_t mv_mfma;      /* 1: the panel products of a matvec on eight right-hand sides (several
-                           loads' lock-step GMRES, the learned guess's training) on the FP64
-                           matrix cores, 0: on the vector units (default 0).  The summation
-                           order differs, the results agree to rounding. */
+                           loads' lock-step GMRES, the learned guess's training,
+                           ewbem_apply_multi) on the FP64 matrix cores, 0: on the vector units
+                           (default 1).  The summation order differs, the results agree to
+                           rounding. */
+  int32_t pad;
+  double ws_pivot_rel;  /* warm start: the elimination of the cross's core A(I, J) stops at
+                           the first pivot whose modulus is at most ws_pivot_rel times the
+                           first pivot's; in [0, 1), 0 (default) takes aca_tol.  A term's norm
+                           |u_t| |v_t| is at least its pivot's modulus, so the terms past this
+                           point rarely pass the stopping test that follows; a smaller value
+                           eliminates more of them, and the ordinary steps after the warm
+                           start add any that the new frequency needs. */
 } ewbem_op_opts;
 
 typedef struct {
@@ -151,10 +160,14 @@ typedef struct {
                               squared norm inside the reduced basis */
   double train_loss_first; /* ewbem_guess_train: mean squared error of the network on */
   double train_loss_last;  /*   its samples before the first and after the last step */
-  int64_t aca_core_blocks[5]; /* warm starts by the size class of the core eliminated (complex
-                                 entries of A(I, J), held in LDS unless stated): [0] at most
-                                 2,304, [1] 4,480, [2] 8,960, [3] larger or over 128 rows
-                                 (global memory), [4] at most 64 rows and 1,024 entries */
+  int64_t aca_core_blocks[7]; /* warm starts by the size class of the core eliminated (complex
+                                 entries of A(I, J)): [5] at most 64 x 64 and [6] at most
+                                 128 x 128, in registers; the rest in LDS: [0] at most 2,304,
+                                 [1] 4,480, [2] 8,960 entries, [4] at most 64 rows and 1,024
+                                 entries; [3] larger or over 128 rows, in global memory */
+  int64_t aca_warm_pivots;  /* pivots eliminated in the warm starts' cores, summed */
+  int64_t aca_warm_kept;    /* of their terms, those kept up to the stopping test, summed */
+  int64_t aca_retries;      /* far blocks approximated again with more capacity */
 } ewbem_stats;
 
 /* Training of the learned initial guess (ewbem_guess_train). */
@@ -325,6 +338,15 @@ int ewbem_assemble(ewbem_ctx* ctx, int32_t k, ewbem_stats* stats);
 
 /* y = A_k x with the assembled operator.  x, y: device, N (caller order). */
 int ewbem_apply(ewbem_ctx* ctx, const ewbem_z* x, ewbem_z* y);
+
+/* Y(:, j) = A_k X(:, j), j < nrhs, with the assembled operator read once for
+ * all columns (the product that the extrapolation over previous solutions,
+ * Sec. 4.2, and several loads' GMRES use).  X, Y: device, N x nrhs
+ * column-major (column j starts at j N), caller order, owned by the caller;
+ * nrhs in 1..8, else EWBEM_EINVAL; X and Y must not overlap.  With
+ * ewbem_op_opts.mv_mfma and nrhs = 8 the panel products run on the FP64
+ * matrix cores. */
+int ewbem_apply_multi(ewbem_ctx* ctx, const ewbem_z* X, int32_t nrhs, ewbem_z* Y);
 
 /* b_k of the assembled frequency.  b: device, N (caller order). */
 int ewbem_get_rhs(ewbem_ctx* ctx, ewbem_z* b);

@@ -125,8 +125,10 @@ struct WsArgs {
   int* rho;
   double* part;
   cd* coef;
-  const int* lu_list;  // warm blocks by size class of W (n_lu[0..4] entries)
-  int n_lu[5];
+  const int* lu_list;  // warm blocks by size class of W (n_lu[0..WS_NCLASS) entries)
+  int n_lu[7];
+  double stop2;        // the elimination stops at |pivot|^2 <= stop2 |first pivot|^2
+  unsigned long long* cnt;  // [0] += pivots eliminated, [1] += terms kept (zeroed by the caller)
 };
 constexpr int WS_LDS_TINY = 1024;   // entries of W held in LDS by the LDS classes (tiny: <= 64 rows)
 constexpr int WS_LDS_SMALL = 2304;
@@ -134,6 +136,12 @@ constexpr int WS_LDS_MID = 4480;
 constexpr int WS_LDS_LARGE = 8960;
 constexpr int WS_CH = 8;             // substitution terms solved together in registers (coefficient padding)
 constexpr int WS_LU_NR_LDS = 2;     // LDS classes hold cores of at most 128 rows
+// Size classes of the core elimination: 0..2 W in LDS (at most 2,304, 4,480,
+// 8,960 entries), 3 in global memory, 4 tiny (at most 64 rows, 1,024 entries,
+// two wavefronts), 5 in registers (at most 64 x 64), 6 in registers (at most
+// 128 x 128).
+constexpr int WS_NCLASS = 7;
+constexpr int WS_REG_SMALL = 64, WS_REG_LARGE = 128;
 void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s);
 
 // ---- H-matrix matvec
@@ -174,6 +182,7 @@ constexpr int HMV_MAXROWS = 192;
 
 // nrhs = 1..4 right-hand sides: columns of x (stride ldx), z (ldz), the
 // partial sums (ldp) and y (ldy).
+// mfma (with nrhs = 8): tasks of up to HMV_MFMA_COLS columns on the matrix cores (k_far_vt_mfma8)
 void launch_far_vt(const VtTask* tasks, int ntask, int cols_per_wave, int store_c64, const cd* x, long long ldx,
                    int nrhs, cd* z, long long ldz, hipStream_t st, int mfma = 0);
 // mfma: eight right-hand sides on the matrix cores (k_hmv_mfma8)
@@ -182,5 +191,6 @@ void launch_hmv(const RowTask* tasks, int ntask, const Seg* segs, const cd* x, l
 void launch_hmv_reduce(const LeafRange* leaves, int nleaf, const cd* partial, long long ldp, int nrhs, cd* y,
                        long long ldy, hipStream_t st);
 constexpr int HMV_MAXRHS = 8;  // right-hand sides of one multi-right-hand-side matvec
+constexpr int HMV_MFMA_COLS = 16;  // factor columns per phase-1 task on the matrix cores
 
 }  // namespace ewbem

@@ -11,10 +11,12 @@
 //   k_ws_eval_cols  A(:, J) into Cc, one thread per (listed column element,
 //                   row element);
 //   k_ws_lu*        one workgroup per block: W = A(I, J), Gaussian
-//                   elimination with complete pivoting, stopping at pivots
-//                   below 1e-10 of the first (the same rule as a step of the
-//                   cold approximation); the pivot order (p_t, q_t) and the
-//                   eliminated W;
+//                   elimination with complete pivoting, stopping at the
+//                   first pivot below a set fraction of the first one's
+//                   modulus (ewbem_op_opts.ws_pivot_rel, by default the ACA
+//                   tolerance: a term's norm is at least its pivot's
+//                   modulus, so later terms rarely pass the stopping test);
+//                   the pivot order (p_t, q_t) and the eliminated W;
 //                   It also writes the coefficients of the substitutions;
 //   k_ws_form_u     u_t = residual of column q_t: the forward substitution
 //                   Cc(:, q) = U M with M unit upper triangular,
@@ -199,7 +201,7 @@ template <int MAXE, int NR, int NW>
 __global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb, const int* __restrict__ list,
                                                const FarBlk* __restrict__ blks, const int* __restrict__ plist,
                                                cd* __restrict__ cross, int* __restrict__ pq,
-                                               int* __restrict__ rho_out, cd* __restrict__ coef) {
+                                               int* __restrict__ rho_out, cd* __restrict__ coef, double stop2) {
   __shared__ cd Wl[MAXE > 0 ? MAXE : 1];
   __shared__ short cl[2][3 * WS_MAXLIST];
   __shared__ short sP[3 * WS_MAXLIST], sQ[3 * WS_MAXLIST];
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb,
   pick(0);
   const double max0 = best;
   int t = 0, nac = C3;
-  while (t < w.rcap && best > 1e-20 * max0 && best > 0.0) {
+  while (t < w.rcap && best > stop2 * max0 && best > 0.0) {
     const int p = be % R3, q = be / R3;
     const short* L = cl[t & 1];
     short* Ln = cl[(t + 1) & 1];
@@ -336,6 +338,209 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb,
     }
   }
   for (int tt = tid; tt < rho; tt += NT) Dn[tt] = cinv(W[sQ[tt] * R3 + sP[tt]]);
+}
+
+// The same elimination with the core in registers, for cores of at most
+// 64 NRC rows and NW CPW columns.  Column j belongs to wavefront j % NW (its
+// slot j / NW); lane l holds rows l + 64 r of its wavefront's columns, so the
+// rank-one update of a pivot touches registers only.  After the update each
+// wavefront puts the column of its own largest entry into LDS beside the
+// entry's key; one barrier later every wavefront knows the pivot (p, q),
+// reads column q from the winner's slot and broadcasts row p of its own
+// columns from the lane that holds it.  The candidate columns are
+// double-buffered by pivot parity: a slot is rewritten two pivots later,
+// after a barrier every wavefront has passed with its reads done.
+// An entry's key packs its squared modulus rounded to float (monotone bits)
+// above the complement of its column-major index, so one unsigned maximum
+// picks the largest entry and, among entries equal in float, the first:
+// complete pivoting up to float rounding of the comparison.  The update
+// arithmetic and the stopping rule are those of k_ws_lu; at the end the
+// eliminated core goes to the global copy of W and the substitution
+// coefficients are formed from it as there.
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ unsigned long long lu_key(double v, int e) {
+  return ((unsigned long long)__float_as_uint((float)v) << 32) | (unsigned)(0x7fffffff - e);
+}
+__device__ __forceinline__ double key_val(unsigned long long k) { return (double)__uint_as_float((unsigned)(k >> 32)); }
+__device__ __forceinline__ int key_idx(unsigned long long k) { return 0x7fffffff - (int)(unsigned)(k & 0xffffffffu); }
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_max(unsigned long long k) {
+  const unsigned lo = (unsigned)k, hi = (unsigned)(k >> 32);
+  const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, 0xf, 0xf, false);
+  const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, 0xf, 0xf, false);
+  const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
+  return o > k ? o : k;
+}
+
+// Largest key of the wavefront (every lane active), wavefront-uniform:
+// within rows of 16 lanes by DPP (quad swaps, half-row and row mirrors),
+// then across the four rows by lane reads.
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long k) {
+  k = dpp_max<0xB1>(k);   // quad_perm [1, 0, 3, 2]
+  k = dpp_max<0x4E>(k);   // quad_perm [2, 3, 0, 1]
+  k = dpp_max<0x141>(k);  // row_half_mirror
+  k = dpp_max<0x140>(k);  // row_mirror
+  const unsigned lo = (unsigned)k, hi = (unsigned)(k >> 32);
+  unsigned long long m = 0ull;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned long long o =
+        ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)hi, 16 * r) << 32) |
+        (unsigned)__builtin_amdgcn_readlane((int)lo, 16 * r);
+    m = o > m ? o : m;
+  }
+  return m;
+}
+
+template <int NW, int CPW, int NRC>
+__global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__ wb, const int* __restrict__ list,
+                                                   const FarBlk* __restrict__ blks, const int* __restrict__ plist,
+                                                   cd* __restrict__ cross, int* __restrict__ pq,
+                                                   int* __restrict__ rho_out, cd* __restrict__ coef, double stop2) {
+  __shared__ cd pcand[2][NW][64 * NRC];
+  __shared__ unsigned long long skey[2][NW];
+  __shared__ short sP[64 * NRC], sQ[64 * NRC];
+  constexpr int NT = 64 * NW;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = list[blockIdx.x];
+  const WsBlk w = wb[wi];
+  const FarBlk B = blks[w.blk];
+  const int R3 = 3 * w.nr, C3 = 3 * w.nc;
+  const size_t M3 = 3 * (size_t)B.m;
+  const cd* Cc = cross + w.cc;
+  cd* Wg = cross + w.w;
+  const int* rows = plist + B.poff;
+  cd a[CPW][NRC];
+  unsigned ralive = 0u, calive = 0u;
+  unsigned long long key = 0ull;  // this lane's largest live entry (0: none)
+#pragma unroll
+  for (int r = 0; r < NRC; ++r) {
+    const int i = r * 64 + lane;
+    if (i < R3) ralive |= 1u << r;
+    const size_t ro = i < R3 ? 3 * (size_t)rows[i / 3] + i % 3 : 0;
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) {
+      const int j = wv + NW * s;
+      const bool ok = i < R3 && j < C3;
+      const cd v = Cc[ok ? (size_t)j * M3 + ro : 0];
+      a[s][r] = ok ? v : mk(0.0);
+      const unsigned long long kk = ok ? lu_key(norm2(v), j * R3 + i) : 0ull;
+      key = kk > key ? kk : key;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < CPW; ++s)
+    if (wv + NW * s < C3) calive |= 1u << s;
+  // a wavefront's candidate: its largest entry's key and that entry's column
+  auto offer = [&](int slot) {
+    key = wave_max_key(key);
+    if (key != 0ull) {
+      const int sc = (key_idx(key) / R3 - wv) / NW;  // wavefront-uniform
+#pragma unroll
+      for (int s = 0; s < CPW; ++s)
+        if (s == sc) {
+#pragma unroll
+          for (int r = 0; r < NRC; ++r) pcand[slot][wv][r * 64 + lane] = a[s][r];
+        }
+    }
+    if (lane == 0) skey[slot][wv] = key;
+  };
+  auto pick = [&](int slot) {
+    unsigned long long kk[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) kk[q] = skey[slot][q];
+    unsigned long long m = kk[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) m = kk[q] > m ? kk[q] : m;
+    return m;
+  };
+  offer(0);
+  __syncthreads();
+  unsigned long long best = pick(0);
+  const double max0 = key_val(best);
+  int t = 0;
+  while (t < w.rcap && best != 0ull && key_val(best) > stop2 * max0 && key_val(best) > 0.0) {
+    const int slot = t & 1;
+    const int be = key_idx(best);
+    const int p = be % R3, q = be / R3;
+    const int qw = q % NW, pl = p & 63, pr = p >> 6;
+    if (tid == 0) {
+      sP[t] = (short)p;
+      sQ[t] = (short)q;
+    }
+    if (pl == lane) ralive &= ~(1u << pr);
+    if (wv == qw) calive &= ~(1u << (q / NW));
+    const cd* col = pcand[slot][qw];
+    const cd ipiv = cinv(col[p]);
+    cd pc[NRC];
+#pragma unroll
+    for (int r = 0; r < NRC; ++r) pc[r] = col[r * 64 + lane];
+    key = 0ull;
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) {
+      if (!(calive & (1u << s))) continue;  // wavefront-uniform
+      cd rv = a[s][0];
+#pragma unroll
+      for (int r = 1; r < NRC; ++r)
+        if (pr == r) rv = a[s][r];
+      const cd prow = cd{bcast_lane(rv.x, pl), bcast_lane(rv.y, pl)} * ipiv;
+      const int j = wv + NW * s;
+#pragma unroll
+      for (int r = 0; r < NRC; ++r) {
+        const bool ok = (ralive >> r) & 1u;
+        cd nv = a[s][r];
+        cms(nv, pc[r], prow);
+        a[s][r].x = ok ? nv.x : a[s][r].x;
+        a[s][r].y = ok ? nv.y : a[s][r].y;
+        const unsigned long long kk = ok ? lu_key(norm2(nv), j * R3 + r * 64 + lane) : 0ull;
+        key = kk > key ? kk : key;
+      }
+    }
+    ++t;
+    offer(t & 1);
+    __syncthreads();
+    best = pick(t & 1);
+  }
+  const int rho = t;
+  // the eliminated core to its global copy, for the coefficients
+#pragma unroll
+  for (int s = 0; s < CPW; ++s) {
+    const int j = wv + NW * s;
+    if (j < C3) {
+#pragma unroll
+      for (int r = 0; r < NRC; ++r) {
+        const int i = r * 64 + lane;
+        if (i < R3) Wg[(size_t)j * R3 + i] = a[s][r];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) rho_out[wi] = rho;
+  int* Pp = pq + w.pq;
+  int* Qp = Pp + w.rcap;
+  for (int tt = tid; tt < rho; tt += NT) {
+    Pp[tt] = sP[tt];
+    Qp[tt] = sQ[tt];
+  }
+  const int rc = w.rcap, ldc = w.rcap + WS_CH;
+  cd* Mc = coef + w.co;
+  cd* Nc = Mc + (size_t)ldc * rc;
+  cd* Dn = Nc + (size_t)ldc * rc;
+  for (int e = tid; e < rho * rho; e += NT) {
+    const int l = e / rho, tt = e - l * rho;
+    if (l < tt) {
+      Mc[(size_t)l * ldc + tt] = Wg[sQ[tt] * R3 + sP[l]] * cinv(Wg[sQ[l] * R3 + sP[l]]);
+      Nc[(size_t)l * ldc + tt] = Wg[sQ[l] * R3 + sP[tt]];
+    }
+  }
+  for (int tt = tid; tt < rho; tt += NT) Dn[tt] = cinv(Wg[sQ[tt] * R3 + sP[tt]]);
 }
 
 // U terms: one wavefront per 21 row elements of a block (four independent
@@ -538,6 +743,8 @@ __global__ __launch_bounds__(256) void k_ws_finish(WsArgs A, const FarBlk* __res
     if (kc[q]) cl[nc++] = cl[q];
   nlist[2 * w.blk] = nr;
   nlist[2 * w.blk + 1] = nc;
+  atomicAdd(&A.cnt[0], (unsigned long long)rho);
+  atomicAdd(&A.cnt[1], (unsigned long long)kept);
   AcaState s = st[w.blk];
   s.k = kept;
   s.normS2 = normS2;
@@ -574,30 +781,40 @@ void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParam
   if (A.tot_ec > 0)
     hipLaunchKernelGGL(k_ws_eval_cols, dim3((A.tot_ec + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, A.ec_off, W.blks,
                        W.plist, A.cross, g, P);
-  // the elimination in five size classes: W of up to 1024 entries and 64
+  // the elimination in seven size classes: cores of at most 64 x 64 and
+  // 128 x 128 in registers; the rest with W of up to 1024 entries and 64
   // rows with two wavefronts, of up to 2304, 4480 and 8960 entries with
   // eight, all in LDS, larger in global memory
   const int nt = 64 * WS_LU_NW, ntl = 64 * WS_LU_NW_LDS;
   const int* lst = A.lu_list;
   if (A.n_lu[0] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[0]), dim3(ntl), 0, s, A.wb,
-                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
   lst += A.n_lu[0];
   if (A.n_lu[1] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_MID, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[1]), dim3(ntl), 0, s, A.wb,
-                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
   lst += A.n_lu[1];
   if (A.n_lu[2] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_LARGE, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[2]), dim3(ntl), 0, s, A.wb,
-                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
   lst += A.n_lu[2];
   if (A.n_lu[3] > 0)
     hipLaunchKernelGGL((k_ws_lu<0, (3 * WS_MAXLIST + 63) / 64, WS_LU_NW>), dim3(A.n_lu[3]), dim3(nt), 0, s, A.wb, lst,
-                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef);
+                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
   lst += A.n_lu[3];
   if (A.n_lu[4] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_TINY, 1, 2>), dim3(A.n_lu[4]), dim3(128), 0, s, A.wb, lst, W.blks, W.plist,
-                       A.cross, A.pq, A.rho, A.coef);
+                       A.cross, A.pq, A.rho, A.coef, A.stop2);
+  lst += A.n_lu[4];
+  // cores in registers: 4 x 16 columns of 64 rows, 8 x 16 columns of 128 rows
+  if (A.n_lu[5] > 0)
+    hipLaunchKernelGGL((k_ws_lu_reg<WS_REG_SMALL / 16, 16, 1>), dim3(A.n_lu[5]), dim3(WS_REG_SMALL / 16 * 64), 0,
+                       s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
+  lst += A.n_lu[5];
+  if (A.n_lu[6] > 0)
+    hipLaunchKernelGGL((k_ws_lu_reg<WS_REG_LARGE / 16, 16, 2>), dim3(A.n_lu[6]), dim3(WS_REG_LARGE / 16 * 64), 0,
+                       s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
   hipLaunchKernelGGL(k_ws_form_u, dim3((A.tot_tu + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, A.coef);
   hipLaunchKernelGGL(k_ws_form_v, dim3((A.tot_tv + 3) / 4), dim3(256), 0, s, A, W.blks, A.coef);
   hipLaunchKernelGGL(k_ws_finish, dim3((A.nwarm + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, W.plist,

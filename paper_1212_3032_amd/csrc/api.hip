@@ -185,6 +185,7 @@ struct ewbem_ctx {
   std::vector<int> nlist_h;
   DevBuf<WsBlk> d_wsb;
   DevBuf<int> d_wsoff, d_wspq, d_wsrho, d_wslu;
+  DevBuf<unsigned long long> d_wscnt;  // warm-start pivot and kept-term counts of one call
   DevBuf<cd> d_cross, d_wscoef;
   DevBuf<double> d_wspart;
   DevBuf<unsigned> d_used;
@@ -195,6 +196,8 @@ struct ewbem_ctx {
   DevBuf<LeafRange> d_lr;
   // host copies of the matvec tables, for the batch's concatenated launch
   std::vector<VtTask> vt_h;
+  DevBuf<VtTask> d_vt16;  // phase-1 tasks of 16 factor columns (eight vectors on the matrix cores)
+  int n_vt16 = 0;
   std::vector<Seg> seg_h;
   std::vector<RowTask> rt_h;
   std::vector<LeafRange> lr_h;
@@ -216,6 +219,7 @@ struct ewbem_ctx {
   int n_minv = 0;
   // vectors (tree order)
   DevBuf<cd> d_b, d_x, d_r, d_w, d_u, d_zt, d_V, d_small, d_tmp_in, d_tmp_out;
+  DevBuf<cd> d_amx;  // ewbem_apply_multi: the columns in tree order, in and out
   DevBuf<cd> d_Y, d_hist_sol, d_spec;
   int hist_n = 0, hist_head = 0;  // ring buffer of the last sem_k solutions
   std::vector<int> hist_slot;  // newest first
@@ -512,6 +516,9 @@ cd s_of_k(ewbem_ctx* c, int k) { return cd{c->sigma, 2.0 * M_PI * k / c->period}
 
 // ---- ACA with capacity retries, then matvec task lists
 
+// Cores of at most 128 x 128 are eliminated in registers (k_ws_lu_reg).
+constexpr bool kWsLuReg = true;
+
 // Lock-step cross approximation of the far blocks ids (their FarBlk
 // entries already on the device).  Blocks with pivot lists from the previous
 // frequency (and warm set) start from the cross on those pivots, the others
@@ -561,7 +568,8 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     tv += ntv;
   }
   const int nw = (int)wb.size();
-  int n_lu_count[5] = {0, 0, 0, 0, 0};
+  int n_lu_count[WS_NCLASS] = {0, 0, 0, 0, 0, 0, 0};
+  unsigned long long ws_cnt[2] = {0ull, 0ull};
   if (er > INT32_MAX / 2 || ec > INT32_MAX / 2 || tu > INT32_MAX / 2 || tv > INT32_MAX / 2 || pqn > INT32_MAX / 2)
     fail(EWBEM_EINVAL, "warm start larger than its index range");
   AcaWork W0{c->d_far.p, c->d_acast.p, c->d_acaplan.p, c->d_used.p, nullptr, nullptr, c->d_plist.p, c->d_nlist.p};
@@ -592,33 +600,47 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     c->d_wscoef.reserve_grow(std::max<long long>(coefn, 1));
     // size classes of the core elimination
     std::vector<int> lu_list;
-    int n_lu[5] = {0, 0, 0, 0, 0};
-    for (int cls = 0; cls < 5; ++cls)
-      for (int i = 0; i < nw; ++i) {
-        const long long e = 9LL * wb[i].nr * wb[i].nc;
-        const int ci = 3 * wb[i].nr > 64 * WS_LU_NR_LDS ? 3
-                       : (3 * wb[i].nr <= 64 && e <= WS_LDS_TINY) ? 4
-                       : e <= WS_LDS_SMALL             ? 0
-                       : e <= WS_LDS_MID               ? 1
-                       : e <= WS_LDS_LARGE             ? 2
-                                                       : 3;
-        if (ci == cls) {
+    int n_lu[WS_NCLASS] = {0, 0, 0, 0, 0, 0, 0};
+    std::vector<int> cls_of(nw);
+    for (int i = 0; i < nw; ++i) {
+      const int R3 = 3 * wb[i].nr, C3 = 3 * wb[i].nc;
+      const long long e = (long long)R3 * C3;
+      cls_of[i] = (kWsLuReg && R3 <= WS_REG_SMALL && C3 <= WS_REG_SMALL)   ? 5
+                  : (kWsLuReg && R3 <= WS_REG_LARGE && C3 <= WS_REG_LARGE) ? 6
+                  : R3 > 64 * WS_LU_NR_LDS                                  ? 3
+                  : (R3 <= 64 && e <= WS_LDS_TINY)                          ? 4
+                  : e <= WS_LDS_SMALL                                       ? 0
+                  : e <= WS_LDS_MID                                         ? 1
+                  : e <= WS_LDS_LARGE                                       ? 2
+                                                                            : 3;
+    }
+    for (int cls = 0; cls < WS_NCLASS; ++cls)
+      for (int i = 0; i < nw; ++i)
+        if (cls_of[i] == cls) {
           lu_list.push_back(i);
           ++n_lu[cls];
         }
-      }
     c->d_wslu.upload(lu_list, st);
-    for (int cls = 0; cls < 5; ++cls) n_lu_count[cls] = n_lu[cls];
+    for (int cls = 0; cls < WS_NCLASS; ++cls) n_lu_count[cls] = n_lu[cls];
     WsArgs A{c->d_wsb.p, nw, c->d_wsoff.p, c->d_wsoff.p + (nw + 1), c->d_wsoff.p + 2 * (nw + 1),
              c->d_wsoff.p + 3 * (nw + 1), (int)er, (int)ec, (int)tu, (int)tv, c->d_cross.p, c->d_wspq.p,
-             c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p, {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4]}};
+             c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p,
+             {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4], n_lu[5], n_lu[6]}, 0.0, nullptr};
+    const double prel = c->op.ws_pivot_rel > 0 ? c->op.ws_pivot_rel : c->op.aca_tol;
+    A.stop2 = prel * prel;
+    c->d_wscnt.reserve(2);
+    A.cnt = c->d_wscnt.p;
+    EWBEM_HIP_CHECK(hipMemsetAsync(A.cnt, 0, 2 * sizeof(unsigned long long), st));
     launch_ws(A, W0, g, c->P, c->op.aca_tol, st);
+    // read with the first step's synchronisation below
+    EWBEM_HIP_CHECK(hipMemcpyAsync(ws_cnt, A.cnt, sizeof(ws_cnt), hipMemcpyDeviceToHost, st));
   }
   if (count_starts) {
     c->acc.aca_warm_blocks += nw;
     c->acc.aca_cold_blocks += (long long)cold.size();
-    for (int cls = 0; cls < 5; ++cls) c->acc.aca_core_blocks[cls] += n_lu_count[cls];
+    for (int cls = 0; cls < WS_NCLASS; ++cls) c->acc.aca_core_blocks[cls] += n_lu_count[cls];
   }
+  bool counted = !count_starts || nw == 0;
   // the active list: every block still ACA_ACTIVE after its start
   EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, 0, 1, st));
   launch_aca_compact(c->d_aca_ids.p, n, c->d_acast.p, c->d_act.p, count, st);
@@ -635,6 +657,11 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     launch_aca_scan(act, count, c->d_far.p, c->d_offs.p, stride, c->d_tot.p, st);
     EWBEM_HIP_CHECK(hipMemcpyAsync(tot, c->d_tot.p, 5 * sizeof(int), hipMemcpyDeviceToHost, st));
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    if (!counted) {
+      c->acc.aca_warm_pivots += (long long)ws_cnt[0];
+      c->acc.aca_warm_kept += (long long)ws_cnt[1];
+      counted = true;
+    }
     const int nact = tot[4];
     if (nact == 0) break;
     if (nact < 0 || nact > n || it > max_steps) fail(EWBEM_EINVAL, "internal: ACA active list out of range");
@@ -794,6 +821,7 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipS
       for (int b : ids)
         if (c->status_h[b] != 0) over.push_back(b);
       if (over.empty()) break;
+      c->acc.aca_retries += (long long)over.size();
       long long tot2 = 0;
       for (int b : over) {
         FarBlk& f = c->far_h[b];
@@ -815,8 +843,15 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipS
         o2 += 3LL * f.n * f.kcap;
       }
       c->d_far.upload(c->far_h, st);
+      // the retry starts warm from the elements of every pivot accepted so
+      // far (the lists the overflowing run left), not from scratch
+      if (warm) {
+        EWBEM_HIP_CHECK(hipMemcpyAsync(c->nlist_h.data(), c->d_nlist.p, 2 * (size_t)nf * sizeof(int),
+                                       hipMemcpyDeviceToHost, st));
+        EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+      }
       EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
-      aca_lockstep(c, g, over, false, false, st);
+      aca_lockstep(c, g, over, warm, false, st);
       EWBEM_HIP_CHECK(hipEventRecord(ev.b, st));
       EWBEM_HIP_CHECK(hipMemcpyAsync(c->rank_h.data(), c->d_rank.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
       EWBEM_HIP_CHECK(hipMemcpyAsync(c->status_h.data(), c->d_status.p, nf * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -924,18 +959,24 @@ void build_matvec(ewbem_ctx* c) {
   }
   // phase 1 tasks
   const int vc = c->mv_cols;
-  std::vector<VtTask> vt;
+  // phase-1 tasks of vc factor columns, and of 16 for the eight-vector
+  // product on the matrix cores
+  std::vector<VtTask> vt, vt16;
+  const bool want16 = c->op.mv_mfma != 0;
   for (int b = 0; b < nf; ++b) {
     const FarBlk& f = c->far_h[b];
     const int k = c->rank_h[b], C = 3 * f.n;
-    for (int l0 = 0; l0 < k; l0 += vc) {
-      VtTask t{};
-      t.V = c64 ? (const void*)(v32(b) + (size_t)l0 * C) : (const void*)(f.V + (size_t)l0 * C);
-      t.zidx = zoff[b] + l0;
-      t.C = C;
-      t.x0 = 3 * f.c0;
-      t.ncol = std::min(vc, k - l0);
-      vt.push_back(t);
+    for (int w = 0; w < (want16 ? 2 : 1); ++w) {
+      const int cols = w == 0 ? vc : HMV_MFMA_COLS;
+      for (int l0 = 0; l0 < k; l0 += cols) {
+        VtTask t{};
+        t.V = c64 ? (const void*)(v32(b) + (size_t)l0 * C) : (const void*)(f.V + (size_t)l0 * C);
+        t.zidx = zoff[b] + l0;
+        t.C = C;
+        t.x0 = 3 * f.c0;
+        t.ncol = std::min(cols, k - l0);
+        (w == 0 ? vt : vt16).push_back(t);
+      }
     }
   }
   // phase 2 segments per leaf
@@ -1024,11 +1065,13 @@ void build_matvec(ewbem_ctx* c) {
       return ok;
     };
     const long long es = c64 ? (long long)sizeof(cf) : (long long)sizeof(cd);
-    for (const VtTask& t : vt) {
-      if (t.ncol < 1 || t.ncol > vc || t.x0 < 0 || t.x0 + (long long)t.C > N || t.zidx < 0 ||
-          t.zidx + t.ncol > ztot || !store_ok(t.V, (long long)t.ncol * t.C * es))
-        fail(EWBEM_EINVAL, "internal: phase-1 task out of range");
-    }
+    for (int w = 0; w < 2; ++w)
+      for (const VtTask& t : w == 0 ? vt : vt16) {
+        if (t.ncol < 1 || t.ncol > (w == 0 ? vc : HMV_MFMA_COLS) || t.C < 1 || t.x0 < 0 ||
+            t.x0 + (long long)t.C > N || t.zidx < 0 || t.zidx + t.ncol > ztot ||
+            !store_ok(t.V, (long long)t.ncol * t.C * es))
+          fail(EWBEM_EINVAL, "internal: phase-1 task out of range");
+      }
     for (size_t i = 0; i < rt.size(); ++i) {
       const RowTask& T = rt[i];
       if (T.rows < 1 || T.rows > HMV_MAXROWS || T.row0 < 0 || T.row0 + T.rows > N || T.s0 < 0 ||
@@ -1057,6 +1100,8 @@ void build_matvec(ewbem_ctx* c) {
   }
   c->d_vt.upload(vt, st);
   c->vt_cols = vc;
+  if (want16) c->d_vt16.upload(vt16, st);
+  c->n_vt16 = (int)vt16.size();
   c->d_seg.upload(flat, st);
   c->d_rt.upload(rt, st);
   c->d_lr.upload(lr, st);
@@ -1091,8 +1136,10 @@ void apply_tree_multi(ewbem_ctx* c, const cd* X, cd* Y, int nrhs) {
   hipStream_t st = c->stream;
   const long long N = 3LL * c->nt;
   if (nrhs < 1 || nrhs > HMV_MAXRHS) fail(EWBEM_EINVAL, "internal: matvec right-hand sides out of range");
-  launch_far_vt(c->d_vt.p, c->n_vt, c->vt_cols, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st,
-                c->op.mv_mfma);
+  if (c->op.mv_mfma && nrhs == HMV_MAXRHS)
+    launch_far_vt(c->d_vt16.p, c->n_vt16, HMV_MFMA_COLS, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st, 1);
+  else
+    launch_far_vt(c->d_vt.p, c->n_vt, c->vt_cols, c->store_c64_active, X, N, nrhs, c->d_z.p, c->z_len, st, 0);
   launch_hmv(c->d_rt.p, c->n_rt, c->d_seg.p, X, N, nrhs, c->d_z.p, c->z_len, c->d_mvpart.p, c->mvpart_len, st,
              c->op.mv_mfma);
   launch_hmv_reduce(c->d_lr.p, c->n_lr, c->d_mvpart.p, c->mvpart_len, nrhs, Y, N, st);
@@ -2401,6 +2448,10 @@ void ewbem_default_op_opts(ewbem_op_opts* o) {
   o->self_order = 24;
   o->aca_reuse = 1;
   o->autotune = 1;
+  o->aca_batch_mb = 0;
+  o->mv_mfma = 1;
+  o->pad = 0;
+  o->ws_pivot_rel = 0.0;
 }
 
 void ewbem_default_solver_opts(ewbem_solver_opts* o) {
@@ -2637,6 +2688,7 @@ int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
         (o->far_store != EWBEM_STORE_C128 && o->far_store != EWBEM_STORE_C64) || o->self_order < 4 ||
         o->self_order > MAX_SELF_ORDER || (o->aca_reuse != 0 && o->aca_reuse != 1) ||
         (o->autotune != 0 && o->autotune != 1) || (o->mv_mfma != 0 && o->mv_mfma != 1) || o->aca_batch_mb < 0 ||
+        !(o->ws_pivot_rel >= 0 && o->ws_pivot_rel < 1) ||
         (o->aca_batch_mb > 0 && (o->far_store != EWBEM_STORE_C64 || o->kind != EWBEM_OP_HMAT)))
       fail(EWBEM_EINVAL, "operator options out of range");
     ctx->op = *o;
@@ -2793,6 +2845,26 @@ int ewbem_apply(ewbem_ctx* ctx, const ewbem_z* x, ewbem_z* y) {
   });
 }
 
+int ewbem_apply_multi(ewbem_ctx* ctx, const ewbem_z* X, int32_t nrhs, ewbem_z* Y) {
+  return guard(ctx, [&] {
+    require_gpu(ctx);
+    if (ctx->assembled_k < 0 || !ctx->device_ok) fail(EWBEM_ESTATE, "apply_multi: no assembled operator");
+    if (!X || !Y) fail(EWBEM_EINVAL, "apply_multi: null matrix");
+    if (nrhs < 1 || nrhs > HMV_MAXRHS) fail(EWBEM_EINVAL, "apply_multi: nrhs must be 1..8");
+    hipStream_t st = ctx->stream;
+    const long long N = 3LL * ctx->nt;
+    ctx->d_amx.reserve(2 * (size_t)HMV_MAXRHS * N);
+    cd* Xt = ctx->d_amx.p;
+    cd* Yt = Xt + (size_t)HMV_MAXRHS * N;
+    for (int j = 0; j < nrhs; ++j) launch_permute((const cd*)X + j * N, ctx->d_perm.p, ctx->nt, 1, Xt + j * N, st);
+    apply_tree_multi(ctx, Xt, Yt, nrhs);
+    for (int j = 0; j < nrhs; ++j) launch_permute(Yt + j * N, ctx->d_perm.p, ctx->nt, 0, (cd*)Y + j * N, st);
+    EWBEM_HIP_CHECK(hipGetLastError());
+    EWBEM_HIP_CHECK(hipStreamSynchronize(st));
+    return EWBEM_OK;
+  });
+}
+
 int ewbem_get_rhs(ewbem_ctx* ctx, ewbem_z* b) {
   return guard(ctx, [&] {
     require_gpu(ctx);
@@ -2896,7 +2968,10 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
       a.matvecs_timed += b.matvecs_timed;
       a.aca_warm_blocks += b.aca_warm_blocks;
       a.aca_cold_blocks += b.aca_cold_blocks;
-      for (int cls = 0; cls < 5; ++cls) a.aca_core_blocks[cls] += b.aca_core_blocks[cls];
+      for (int cls = 0; cls < WS_NCLASS; ++cls) a.aca_core_blocks[cls] += b.aca_core_blocks[cls];
+      a.aca_warm_pivots += b.aca_warm_pivots;
+      a.aca_warm_kept += b.aca_warm_kept;
+      a.aca_retries += b.aca_retries;
       a.guess_learned += b.guess_learned;
     }
     *stats = a;
@@ -3408,7 +3483,10 @@ int ewbem_batch_solve_transient_lockstep(ewbem_ctx** ctxs, int32_t n, double** u
       a.matvecs_timed += b.matvecs_timed;
       a.aca_warm_blocks += b.aca_warm_blocks;
       a.aca_cold_blocks += b.aca_cold_blocks;
-      for (int cls = 0; cls < 5; ++cls) a.aca_core_blocks[cls] += b.aca_core_blocks[cls];
+      for (int cls = 0; cls < WS_NCLASS; ++cls) a.aca_core_blocks[cls] += b.aca_core_blocks[cls];
+      a.aca_warm_pivots += b.aca_warm_pivots;
+      a.aca_warm_kept += b.aca_warm_kept;
+      a.aca_retries += b.aca_retries;
       a.guess_learned += b.guess_learned;
     }
     *stats = a;

@@ -90,10 +90,10 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
 }
 
 // Phase 1 for eight right-hand sides on the matrix cores: one wavefront per
-// task (up to 16 factor columns j; here at most NC <= 8).  Per step of four
-// rows c of the factor, v_mfma_f64_16x16x4f64 twice with A the 16 x 4 block
-// V(c, j)^T (lane l: column j = l % 16, row c = l / 16) and B the x entries
-// (lane l: row c = l / 16, output column n = l % 16):
+// task of up to 16 factor columns j (a task list of its own).  Per four rows
+// c of the factor, v_mfma_f64_16x16x4f64 twice with A the 16 x 4 block
+// V(c, j)^T (lane l: column j = l % 16, row index l / 16) and B the x
+// entries (lane l: the same row, output column n = l % 16):
 //   Z += Re(V^T) [Re X | Im X] + Im(V^T) [-Im X | Re X] = [Re V^T X | Im V^T X].
 // Lane l ends with Z rows (factor columns) l / 16 + 4 v of output column
 // l % 16 (real parts of the eight products, then imaginary parts).
@@ -112,16 +112,50 @@ __global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__
   const int C = T.C, nc = T.ncol;
   const int j = lane & 15, kr = lane >> 4, q = j & 7;
   const bool jv = j < nc;
+  // columns past ncol read column 0 (in bounds) and multiply zero
+  const TS* __restrict__ Vj = V + (size_t)(jv ? j : 0) * C;
+  const cd* __restrict__ xq = xs + q * ldx;
   fvt_v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int c0 = 0; c0 < C; c0 += 4) {
-    const int c = c0 + kr;
-    const bool cv = c < C;
-    const cd a = (jv && cv) ? to_cd(V[(size_t)j * C + c]) : mk(0.0);
-    const cd xv = cv ? xs[c + q * ldx] : mk(0.0);
-    const double b1 = j < 8 ? xv.x : xv.y;
-    const double b2 = j < 8 ? -xv.y : xv.x;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b2, acc, 0, 0, 0);
+  // a step is eight rows, two products: product h pairs lane row kr with
+  // factor row c0 + 2 kr + h, so a lane's two rows are adjacent in memory
+  // (rows past C read row C - 1 and are zeroed)
+  auto load = [&](int c0, cd (&a)[2], cd (&xv)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = c0 + 2 * kr + h;
+      const bool cv = c < C;
+      const int cc = cv ? c : C - 1;
+      const cd av = to_cd(Vj[cc]);
+      const cd xx = xq[cc];
+      a[h] = (jv && cv) ? av : mk(0.0);
+      xv[h] = cv ? xx : mk(0.0);
+    }
+  };
+  auto mma = [&](const cd (&a)[2], const cd (&xv)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double b1 = j < 8 ? xv[h].x : xv[h].y;
+      const double b2 = j < 8 ? -xv[h].y : xv[h].x;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].x, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].y, b2, acc, 0, 0, 0);
+    }
+  };
+  // three steps in flight: the loads of steps s + 1 and s + 2 are issued
+  // before the products of step s
+  cd a0[2], x0[2], a1[2], x1[2], a2[2], x2[2];
+  load(0, a0, x0);
+  if (8 < C) load(8, a1, x1);
+  for (int c0 = 0; c0 < C; c0 += 24) {
+    if (c0 + 16 < C) load(c0 + 16, a2, x2);
+    mma(a0, x0);
+    if (c0 + 8 < C) {
+      if (c0 + 24 < C) load(c0 + 24, a0, x0);
+      mma(a1, x1);
+    }
+    if (c0 + 16 < C) {
+      if (c0 + 32 < C) load(c0 + 32, a1, x1);
+      mma(a2, x2);
+    }
   }
   const int comp = j >> 3;
 #pragma unroll
@@ -320,8 +354,8 @@ __global__ __launch_bounds__(256) void k_hmv(const RowTask* __restrict__ tasks, 
 // form up to twelve tiles of 16; wave w of the four takes tiles w, w + 4,
 // w + 8.  Per step of four panel columns and tile, v_mfma_f64_16x16x4f64
 // twice: with A the tile's 16 x 4 entries (lane l: row l % 16, column
-// l / 16) and B the staged x entries (lane l: column l / 16, output column
-// n = l % 16),
+// l / 16) and B the x entries (lane l: column l / 16, output column
+// n = l % 16, read directly: no staging, no barrier),
 //   C += Re(A) [Re X | Im X] + Im(A) [-Im X | Re X] = [Re AX | Im AX],
 // the 16 output columns holding the real parts of the eight products, then
 // their imaginary parts.  Lane l holds C rows l / 16 + 4 v, v < 4, of
@@ -339,22 +373,47 @@ __device__ __forceinline__ cd panel_entry(const void* A, size_t i) {
   }
 }
 
+// acc[tile] += panel(tile rows, columns of one segment) X(columns, 8) with
+// the x entries read directly (lane l: column l / 16, vector (l % 16) % 8);
+// the next step's four columns are loaded before this step's products.
 template <typename TS>
-__device__ __forceinline__ void tiles_mfma(const void* A, int ld, int rows, int c0, int nch, const cd* xs, int lane,
-                                           int w, hmv_v4d (&acc)[3]) {
+__device__ __forceinline__ void seg_mfma(const void* A, int ld, int rows, int ncols, const cd* src, long long lds,
+                                         int lane, int w, hmv_v4d (&acc)[3]) {
   const int kr = lane >> 4, n = lane & 15;
-  for (int cc = 0; cc < nch; cc += 4) {
-    const int col = cc + kr;
-    const bool cv = col < nch;
-    const cd xv = cv ? xs[col * 8 + (n & 7)] : mk(0.0);
+  const cd* __restrict__ xq = src + (n & 7) * lds;
+  // columns past the segment and rows past the task read an in-bounds entry
+  // and are zeroed
+  auto load = [&](int c0, cd (&a)[3], cd& xv) {
+    const int col = c0 + kr;
+    const bool cv = col < ncols;
+    const int cc = cv ? col : ncols - 1;
+    const size_t cb = (size_t)cc * ld;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int row = 16 * (w + 4 * q) + n;
+      const cd v = panel_entry<TS>(A, cb + (row < rows ? row : rows - 1));
+      a[q] = (cv && row < rows) ? v : mk(0.0);
+    }
+    const cd xx = xq[cc];
+    xv = cv ? xx : mk(0.0);
+  };
+  auto mma = [&](const cd (&a)[3], const cd& xv) {
     const double b1 = n < 8 ? xv.x : xv.y;
     const double b2 = n < 8 ? -xv.y : xv.x;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      const int row = 16 * (w + 4 * q) + n;
-      const cd a = (cv && row < rows) ? panel_entry<TS>(A, (size_t)(c0 + col) * ld + row) : mk(0.0);
-      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1, acc[q], 0, 0, 0);
-      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b2, acc[q], 0, 0, 0);
+      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b1, acc[q], 0, 0, 0);
+      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].y, b2, acc[q], 0, 0, 0);
+    }
+  };
+  cd a0[3], a1[3], x0, x1;
+  load(0, a0, x0);
+  for (int c0 = 0; c0 < ncols; c0 += 8) {
+    if (c0 + 4 < ncols) load(c0 + 4, a1, x1);
+    mma(a0, x0);
+    if (c0 + 4 < ncols) {
+      if (c0 + 8 < ncols) load(c0 + 8, a0, x0);
+      mma(a1, x1);
     }
   }
 }
@@ -363,31 +422,23 @@ __global__ __launch_bounds__(256) void k_hmv_mfma8(const RowTask* __restrict__ t
                                                    const cd* __restrict__ x, long long ldx,
                                                    const cd* __restrict__ z, long long ldz,
                                                    cd* __restrict__ partial, long long ldp) {
-  constexpr int NR = 8;
   const RowTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  __shared__ cd xs[HMV_XCH * NR];
   hmv_v4d acc[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) acc[q] = hmv_v4d{0.0, 0.0, 0.0, 0.0};
-  for (int s = T.s0; s < T.s1; ++s) {
-    const Seg S = segs[s];
-    const bool fz = (S.flags & SEG_FROM_Z) != 0;
-    const cd* src = (fz ? z : x) + S.src;
-    const long long lds = fz ? ldz : ldx;
-    for (int c0 = 0; c0 < S.ncols; c0 += HMV_XCH) {
-      const int nch = min(HMV_XCH, S.ncols - c0);
-      __syncthreads();
-      for (int i = threadIdx.x; i < nch * NR; i += blockDim.x) {
-        const int q = i / nch, cc = i - q * nch;
-        xs[cc * NR + q] = src[c0 + cc + q * lds];
-      }
-      __syncthreads();
+  // a wavefront whose tiles all lie past the task's rows has nothing to do
+  if (16 * w < T.rows) {
+    for (int s = T.s0; s < T.s1; ++s) {
+      const Seg S = segs[s];
+      const bool fz = (S.flags & SEG_FROM_Z) != 0;
+      const cd* src = (fz ? z : x) + S.src;
+      const long long lds = fz ? ldz : ldx;
       if (S.flags & SEG_C64)
-        tiles_mfma<cf>(S.A, S.ld, T.rows, c0, nch, xs, lane, w, acc);
+        seg_mfma<cf>(S.A, S.ld, T.rows, S.ncols, src, lds, lane, w, acc);
       else
-        tiles_mfma<cd>(S.A, S.ld, T.rows, c0, nch, xs, lane, w, acc);
+        seg_mfma<cd>(S.A, S.ld, T.rows, S.ncols, src, lds, lane, w, acc);
     }
   }
   const int j = lane & 15, q = j & 7, comp = j >> 3;

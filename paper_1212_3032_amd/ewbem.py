@@ -28,7 +28,7 @@ EXPORTED = [
     "ewbem_set_operator",
     "ewbem_set_solver", "ewbem_info", "ewbem_get_partition", "ewbem_load_spectrum",
     "ewbem_kernel_eval", "ewbem_assemble_dense", "ewbem_assemble", "ewbem_apply",
-    "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_solve_transient_loads",
+    "ewbem_apply_multi", "ewbem_get_rhs", "ewbem_solve_frequency", "ewbem_solve_transient", "ewbem_solve_transient_loads",
     "ewbem_solve_transient_incident_loads",
     "ewbem_batch_solve_transient", "ewbem_batch_solve_transient_lockstep",
     "ewbem_mft_inverse", "ewbem_default_train_opts", "ewbem_guess_train", "ewbem_guess_save",
@@ -44,7 +44,7 @@ class OpOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("leaf_size", C.c_int32), ("eta_adm", C.c_double),
                 ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32),
                 ("aca_reuse", C.c_int32), ("autotune", C.c_int32), ("aca_batch_mb", C.c_int32),
-                ("mv_mfma", C.c_int32)]
+                ("mv_mfma", C.c_int32), ("pad", C.c_int32), ("ws_pivot_rel", C.c_double)]
 
 
 class SolverOpts(C.Structure):
@@ -66,7 +66,8 @@ class Stats(C.Structure):
                 ("aca_warm_blocks", C.c_int64), ("aca_cold_blocks", C.c_int64),
                 ("guess_learned", C.c_int64), ("pod_energy", C.c_double),
                 ("train_loss_first", C.c_double), ("train_loss_last", C.c_double),
-                ("aca_core_blocks", C.c_int64 * 5)]
+                ("aca_core_blocks", C.c_int64 * 7), ("aca_warm_pivots", C.c_int64),
+                ("aca_warm_kept", C.c_int64), ("aca_retries", C.c_int64)]
 
     def as_dict(self):
         return {f: (list(getattr(self, f)) if f == "aca_core_blocks" else getattr(self, f))
@@ -128,6 +129,7 @@ def lib():
         "ewbem_assemble_dense": (C.c_int, [P, Z, P, P]),
         "ewbem_assemble": (C.c_int, [P, I32, C.POINTER(Stats)]),
         "ewbem_apply": (C.c_int, [P, P, P]),
+        "ewbem_apply_multi": (C.c_int, [P, P, I32, P]),
         "ewbem_get_rhs": (C.c_int, [P, P]),
         "ewbem_solve_frequency": (C.c_int, [P, I32, P, P, C.POINTER(Stats)]),
         "ewbem_solve_transient": (C.c_int, [P, P, P, C.POINTER(Stats)]),
@@ -344,6 +346,15 @@ class Context:
         N = 3 * self.nt
         self._check(self._L.ewbem_apply(self.h, _dev_ptr(x, "torch.complex128", N),
                                         _dev_ptr(y, "torch.complex128", N)))
+
+    def apply_multi(self, X, Y):
+        """Y[j] = A X[j] for the rows of X (nrhs x N complex128, nrhs <= 8)."""
+        N = 3 * self.nt
+        nrhs = int(X.shape[0])
+        if tuple(X.shape) != (nrhs, N) or tuple(Y.shape) != (nrhs, N):
+            raise ValueError("apply_multi: X and Y must be nrhs x N")
+        self._check(self._L.ewbem_apply_multi(self.h, _dev_ptr(X, "torch.complex128", nrhs * N), nrhs,
+                                              _dev_ptr(Y, "torch.complex128", nrhs * N)))
 
     def get_rhs(self, b):
         self._check(self._L.ewbem_get_rhs(self.h, _dev_ptr(b, "torch.complex128", 3 * self.nt)))

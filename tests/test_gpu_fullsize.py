@@ -94,9 +94,10 @@ def test_warm_sequence_sampled_rows(setup):
     consecutive frequencies with the ACA warm-started from the previous
     frequency's pivots (k = 56..64, where ranks and cores are largest).
     After each frequency the operator's action on sampled rows is checked
-    against the oracle's rows, and every size class of the warm start's core
-    elimination (LDS classes and the global-memory class for cores over 128
-    rows or 8,960 entries) must have run over the sequence."""
+    against the oracle's rows, and the size classes of the warm start's core
+    elimination that this mesh reaches (cores of at most 64 x 64 and
+    128 x 128 in registers, larger ones in global memory) must have run over
+    the sequence."""
     torch, E, d, g, mat, elems = setup
     dev = torch.device("cuda:0")
     N = 3 * g["ne"]
@@ -107,7 +108,7 @@ def test_warm_sequence_sampled_rows(setup):
     xd = torch.tensor(x, device=dev)
     y = torch.zeros(N, dtype=torch.complex128, device=dev)
     c = _ctx(E, d)
-    classes = np.zeros(5, np.int64)
+    classes = np.zeros(7, np.int64)
     worst = 0.0
     for k in range(56, 65):
         st = c.assemble(k)
@@ -125,7 +126,7 @@ def test_warm_sequence_sampled_rows(setup):
     c.close()
     _say(f"  core eliminations by size class: {classes.tolist()}")
     assert worst < 10 * ACA_TOL
-    assert classes[2] > 0 and classes[3] > 0 and classes[0] > 0
+    assert classes[5] > 0 and classes[6] > 0 and classes[3] > 0
 
 
 def test_complex64_factors_match_complex128(setup):

@@ -6,8 +6,10 @@ follows, and the loads' GMRES run in lock-step groups of up to eight whose
 matvecs are one multi-right-hand-side product.
 
 The operators are those a lone transient builds (the same warm-started ACA
-sequence over k = 0..N_f/2), and the multi-right-hand-side matvec sums every
-column in the order the single one does.  The multi-load right-hand-side
+sequence over k = 0..N_f/2); the multi-right-hand-side matvec sums every
+column in the order the single one does, except that a group of eight takes
+the FP64 matrix cores by default (op.mv_mfma), another order of the same
+sums.  The multi-load right-hand-side
 kernel evaluates each frequency's phases directly where the single-load one
 advances them by a rotation, so b agrees to rounding (about 1e-16
 relative), not bit for bit.  Hence: every load's transient and spectrum

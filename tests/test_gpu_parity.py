@@ -272,6 +272,84 @@ def test_hmatrix_apply_and_solve(torch_dev, E, sub3_system, aca_tol, store):
     c.close()
 
 
+@pytest.mark.parametrize("mfma", [0, 1])
+@pytest.mark.parametrize("store", ["c128", "c64"])
+def test_apply_multi(torch_dev, E, sub3_system, store, mfma):
+    """ewbem_apply_multi: every column of an 8-, 3- and 1-column product
+    equals the one-column product of that column to rounding (the operator
+    is read once for all; with mv_mfma the 8-column panels run on the FP64
+    matrix cores, in another summation order), and the dense oracle's T X
+    to the ACA bound."""
+    torch, dev = torch_dev
+    d, sysk = sub3_system
+    N = 3 * len(d["tri"])
+    T, _ = sysk[40]
+    aca_tol = 1e-6
+    c = _ctx(E, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=aca_tol, mv_mfma=mfma,
+                           far_store=E.STORE_C64 if store == "c64" else E.STORE_C128),
+             solver=dict(tol=1e-10, guess=E.GUESS_ZERO))
+    c.assemble(40)
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((8, N)) + 1j * rng.standard_normal((8, N))
+    Xd = torch.tensor(X, device=dev)
+    one = np.zeros((8, N), complex)
+    for j in range(8):
+        y = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.apply(Xd[j].contiguous(), y)
+        one[j] = y.cpu().numpy()
+    bound = max(30 * aca_tol, 1e-6 if store == "c64" else 1e-12)
+    for nrhs in (8, 3, 1):
+        _say(f"apply_multi sub=3 k=40 {store} mfma={mfma} nrhs={nrhs}")
+        Y = torch.zeros(nrhs, N, dtype=torch.complex128, device=dev)
+        c.apply_multi(Xd[:nrhs].contiguous(), Y)
+        Yh = Y.cpu().numpy()
+        e_one = max(_l2(Yh[j], one[j]) for j in range(nrhs))
+        e_ref = max(_l2(Yh[j], T @ X[j]) for j in range(nrhs))
+        _say(f"  against one column at a time {e_one:.1e}, against the oracle {e_ref:.1e}")
+        assert e_one < 1e-13
+        assert e_ref < bound
+    with pytest.raises(E.EwbemError):
+        c.apply_multi(torch.zeros(9, N, dtype=torch.complex128, device=dev),
+                      torch.zeros(9, N, dtype=torch.complex128, device=dev))
+    c.close()
+
+
+def test_warm_start_pivot_threshold(torch_dev, E, sub3_system):
+    """The warm start's core elimination may stop early
+    (op.ws_pivot_rel): fewer pivots are eliminated as the threshold rises,
+    and the ordinary steps that follow keep every operator within the ACA
+    bound of the dense oracle -- the threshold changes the cost, not the
+    tolerance.  (The pivot counts of nearby thresholds need not be ordered:
+    each run's pivot lists carry its own history.)"""
+    torch, dev = torch_dev
+    d, sysk = sub3_system
+    T, _ = sysk[40]
+    N = 3 * len(d["tri"])
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    tol = 1e-6
+    piv = []
+    for rel in (1e-10, 1e-7, 0.0, 1e-4):  # 0: the ACA tolerance, 1e-6
+        c = _ctx(E, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=tol, ws_pivot_rel=rel),
+                 solver=dict(tol=1e-10, guess=E.GUESS_ZERO))
+        pivots = kept = retries = 0
+        for k in range(30, 41):
+            st = c.assemble(k)
+            pivots += st["aca_warm_pivots"]
+            kept += st["aca_warm_kept"]
+            retries += st["aca_retries"]
+        y = torch.zeros(N, dtype=torch.complex128, device=dev)
+        c.apply(torch.tensor(x, device=dev), y)
+        e_apply = _l2(y.cpu().numpy(), T @ x)
+        _say(f"ws_pivot_rel={rel:.0e}: pivots {pivots} kept {kept} retries {retries} "
+             f"ranks sum={st['rank_sum']} e_apply={e_apply:.2e}")
+        assert 0 < kept <= pivots
+        assert e_apply < 30 * tol
+        piv.append(pivots)
+        c.close()
+    assert piv[-1] < piv[0]
+
+
 def test_hmatrix_warm_start(torch_dev, E, sub3_system):
     """ACA started from the previous frequency's pivots, over eleven
     consecutive frequencies (k = 30..40), against ACA from scratch at k = 40:
