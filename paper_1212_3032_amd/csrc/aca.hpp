@@ -107,10 +107,10 @@ struct WsBlk {
   long long cc;     // Cc: 3m x 3nc column-major (column = cross column)
   long long w;      // W = A(I, J): 3nr x 3nc column-major, factored in place
   int pq;           // pivot order: p[rcap] (cross rows), q[rcap] (cross columns)
-  int tu, tv;       // first U-forming task (21-row-element tiles), V-forming task (64 columns)
+  int tu, tv;       // first U-forming and V-forming task (48-row tiles)
   int pad;
   long long pu, pv; // norm partials: (tasks of the block) x rcap doubles each
-  long long co;     // substitution coefficients: Mc, Nc ((rcap + 8) x rcap each), Dn (rcap + 8)
+  long long co;     // substitution panels: U side, then V side, ws_panel_elems(rcap) each
 };
 struct WsArgs {
   const WsBlk* wb;
@@ -134,7 +134,13 @@ constexpr int WS_LDS_TINY = 1024;   // entries of W held in LDS by the LDS class
 constexpr int WS_LDS_SMALL = 2304;
 constexpr int WS_LDS_MID = 4480;
 constexpr int WS_LDS_LARGE = 8960;
-constexpr int WS_CH = 8;             // substitution terms solved together in registers (coefficient padding)
+// Substitutions on the matrix cores: 48-row tiles (16 row elements) per
+// wavefront, chunks of 16 terms; panel k holds (16 + 16 k) x 16 complex.
+constexpr int WS_TILE_ROWS = 48;
+__host__ __device__ inline long long ws_panel_elems(int rcap) {
+  const long long nk = (rcap + 15) / 16;
+  return 256 * (nk * (nk + 1) / 2);
+}
 constexpr int WS_LU_NR_LDS = 2;     // LDS classes hold cores of at most 128 rows
 // Size classes of the core elimination: 0..2 W in LDS (at most 2,304, 4,480,
 // 8,960 entries), 3 in global memory, 4 tiny (at most 64 rows, 1,024 entries,

@@ -98,6 +98,8 @@ __device__ __forceinline__ void cms(cd& acc, cd x, cd m) {
 // LDS written by some lanes of a wavefront, then read by others: the
 // wavefront's LDS operations complete in order; this keeps the compiler
 // from moving them across the point.
+typedef double wfv4d __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -201,7 +203,7 @@ template <int MAXE, int NR, int NW>
 __global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb, const int* __restrict__ list,
                                                const FarBlk* __restrict__ blks, const int* __restrict__ plist,
                                                cd* __restrict__ cross, int* __restrict__ pq,
-                                               int* __restrict__ rho_out, cd* __restrict__ coef, double stop2) {
+                                               int* __restrict__ rho_out, double stop2) {
   __shared__ cd Wl[MAXE > 0 ? MAXE : 1];
   __shared__ short cl[2][3 * WS_MAXLIST];
   __shared__ short sP[3 * WS_MAXLIST], sQ[3 * WS_MAXLIST];
@@ -321,23 +323,12 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb,
     Pp[tt] = sP[tt];
     Qp[tt] = sQ[tt];
   }
-  // coefficients of the forward substitutions, by earlier term l (rows of
-  // length rc + WS_CH, so a chunk of later terms t is contiguous):
-  //   Mc[l][t] = M[l][t] = W[p_l][q_t] / W[p_l][q_l]   (l < t)
-  //   Nc[l][t] = N[t][l] = W[p_t][q_l]                (l < t)
-  //   Dn[t]    = 1 / W[p_t][q_t]
-  const int rc = w.rcap, ldc = w.rcap + WS_CH;
-  cd* Mc = coef + w.co;
-  cd* Nc = Mc + (size_t)ldc * rc;
-  cd* Dn = Nc + (size_t)ldc * rc;
-  for (int e = tid; e < rho * rho; e += NT) {
-    const int l = e / rho, tt = e - l * rho;
-    if (l < tt) {
-      Mc[(size_t)l * ldc + tt] = W[sQ[tt] * R3 + sP[l]] * cinv(W[sQ[l] * R3 + sP[l]]);
-      Nc[(size_t)l * ldc + tt] = W[sQ[l] * R3 + sP[tt]];
-    }
+  // the eliminated core to its global copy (the LDS classes), for the
+  // substitution panels
+  if (MAXE > 0) {
+    cd* Wg = cross + w.w;
+    for (int e = tid; e < tot; e += NT) Wg[e] = W[e];
   }
-  for (int tt = tid; tt < rho; tt += NT) Dn[tt] = cinv(W[sQ[tt] * R3 + sP[tt]]);
 }
 
 // The same elimination with the core in registers, for cores of at most
@@ -350,13 +341,15 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu(const WsBlk* __restrict__ wb,
 // columns from the lane that holds it.  The candidate columns are
 // double-buffered by pivot parity: a slot is rewritten two pivots later,
 // after a barrier every wavefront has passed with its reads done.
-// An entry's key packs its squared modulus rounded to float (monotone bits)
-// above the complement of its column-major index, so one unsigned maximum
-// picks the largest entry and, among entries equal in float, the first:
-// complete pivoting up to float rounding of the comparison.  The update
-// arithmetic and the stopping rule are those of k_ws_lu; at the end the
-// eliminated core goes to the global copy of W and the substitution
-// coefficients are formed from it as there.
+// Each lane keeps its largest live entry exactly; across lanes and
+// wavefronts the entries compare by a key that packs the squared modulus
+// rounded to float (monotone bits) above the complement of the column-major
+// index, so one unsigned maximum picks the largest entry and, among entries
+// equal in float, the first: complete pivoting up to float rounding of the
+// comparison.  The update scales the pivot column (zero on eliminated rows,
+// which then keep their values) instead of the pivot row; the stopping rule
+// is that of k_ws_lu.  At the end the eliminated core goes to the global copy
+// of W for the substitution panels.
 __device__ __forceinline__ double bcast_lane(double v, int l) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
@@ -403,12 +396,13 @@ template <int NW, int CPW, int NRC>
 __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__ wb, const int* __restrict__ list,
                                                    const FarBlk* __restrict__ blks, const int* __restrict__ plist,
                                                    cd* __restrict__ cross, int* __restrict__ pq,
-                                                   int* __restrict__ rho_out, cd* __restrict__ coef, double stop2) {
+                                                   int* __restrict__ rho_out, double stop2) {
   __shared__ cd pcand[2][NW][64 * NRC];
   __shared__ unsigned long long skey[2][NW];
   __shared__ short sP[64 * NRC], sQ[64 * NRC];
   constexpr int NT = 64 * NW;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wi = list[blockIdx.x];
   const WsBlk w = wb[wi];
   const FarBlk B = blks[w.blk];
@@ -419,28 +413,35 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__
   const int* rows = plist + B.poff;
   cd a[CPW][NRC];
   unsigned ralive = 0u, calive = 0u;
-  unsigned long long key = 0ull;  // this lane's largest live entry (0: none)
+  // this lane's largest live entry: squared modulus and column-major index
+  // (entries are scanned in increasing index, so a strict comparison keeps
+  // the first of equals)
+  double best = -1.0;
+  int be = 0x7fffffff;
 #pragma unroll
-  for (int r = 0; r < NRC; ++r) {
-    const int i = r * 64 + lane;
-    if (i < R3) ralive |= 1u << r;
-    const size_t ro = i < R3 ? 3 * (size_t)rows[i / 3] + i % 3 : 0;
+  for (int s = 0; s < CPW; ++s)
 #pragma unroll
-    for (int s = 0; s < CPW; ++s) {
+    for (int r = 0; r < NRC; ++r) {
+      const int i = r * 64 + lane;
       const int j = wv + NW * s;
       const bool ok = i < R3 && j < C3;
+      const size_t ro = i < R3 ? 3 * (size_t)rows[i / 3] + i % 3 : 0;
       const cd v = Cc[ok ? (size_t)j * M3 + ro : 0];
       a[s][r] = ok ? v : mk(0.0);
-      const unsigned long long kk = ok ? lu_key(norm2(v), j * R3 + i) : 0ull;
-      key = kk > key ? kk : key;
+      const double m = norm2(v);
+      const bool take = ok && m > best;
+      best = take ? m : best;
+      be = take ? j * R3 + i : be;
     }
-  }
+#pragma unroll
+  for (int r = 0; r < NRC; ++r)
+    if (r * 64 + lane < R3) ralive |= 1u << r;
 #pragma unroll
   for (int s = 0; s < CPW; ++s)
     if (wv + NW * s < C3) calive |= 1u << s;
   // a wavefront's candidate: its largest entry's key and that entry's column
   auto offer = [&](int slot) {
-    key = wave_max_key(key);
+    const unsigned long long key = wave_max_key(best >= 0.0 ? lu_key(best, be) : 0ull);
     if (key != 0ull) {
       const int sc = (key_idx(key) / R3 - wv) / NW;  // wavefront-uniform
 #pragma unroll
@@ -463,13 +464,13 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__
   };
   offer(0);
   __syncthreads();
-  unsigned long long best = pick(0);
-  const double max0 = key_val(best);
+  unsigned long long key = pick(0);
+  const double max0 = key_val(key);
   int t = 0;
-  while (t < w.rcap && best != 0ull && key_val(best) > stop2 * max0 && key_val(best) > 0.0) {
+  while (t < w.rcap && key != 0ull && key_val(key) > stop2 * max0 && key_val(key) > 0.0) {
     const int slot = t & 1;
-    const int be = key_idx(best);
-    const int p = be % R3, q = be / R3;
+    const int kb = key_idx(key);
+    const int p = kb % R3, q = kb / R3;
     const int qw = q % NW, pl = p & 63, pr = p >> 6;
     if (tid == 0) {
       sP[t] = (short)p;
@@ -479,10 +480,16 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__
     if (wv == qw) calive &= ~(1u << (q / NW));
     const cd* col = pcand[slot][qw];
     const cd ipiv = cinv(col[p]);
-    cd pc[NRC];
+    // the pivot column over the pivot, zero on eliminated rows: their
+    // entries then stay as they are (a - 0 x = a)
+    cd pcs[NRC];
 #pragma unroll
-    for (int r = 0; r < NRC; ++r) pc[r] = col[r * 64 + lane];
-    key = 0ull;
+    for (int r = 0; r < NRC; ++r) {
+      const cd v = col[r * 64 + lane] * ipiv;
+      pcs[r] = ((ralive >> r) & 1u) ? v : mk(0.0);
+    }
+    best = -1.0;
+    be = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < CPW; ++s) {
       if (!(calive & (1u << s))) continue;  // wavefront-uniform
@@ -490,26 +497,24 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__
 #pragma unroll
       for (int r = 1; r < NRC; ++r)
         if (pr == r) rv = a[s][r];
-      const cd prow = cd{bcast_lane(rv.x, pl), bcast_lane(rv.y, pl)} * ipiv;
+      const cd prow = cd{bcast_lane(rv.x, pl), bcast_lane(rv.y, pl)};
       const int j = wv + NW * s;
 #pragma unroll
       for (int r = 0; r < NRC; ++r) {
-        const bool ok = (ralive >> r) & 1u;
-        cd nv = a[s][r];
-        cms(nv, pc[r], prow);
-        a[s][r].x = ok ? nv.x : a[s][r].x;
-        a[s][r].y = ok ? nv.y : a[s][r].y;
-        const unsigned long long kk = ok ? lu_key(norm2(nv), j * R3 + r * 64 + lane) : 0ull;
-        key = kk > key ? kk : key;
+        cms(a[s][r], pcs[r], prow);
+        const double m = norm2(a[s][r]);
+        const bool take = ((ralive >> r) & 1u) && m > best;
+        best = take ? m : best;
+        be = take ? j * R3 + r * 64 + lane : be;
       }
     }
     ++t;
     offer(t & 1);
     __syncthreads();
-    best = pick(t & 1);
+    key = pick(t & 1);
   }
   const int rho = t;
-  // the eliminated core to its global copy, for the coefficients
+  // the eliminated core to its global copy, for the substitution panels
 #pragma unroll
   for (int s = 0; s < CPW; ++s) {
     const int j = wv + NW * s;
@@ -521,7 +526,6 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__
       }
     }
   }
-  __syncthreads();
   if (tid == 0) rho_out[wi] = rho;
   int* Pp = pq + w.pq;
   int* Qp = Pp + w.rcap;
@@ -529,148 +533,256 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__
     Pp[tt] = sP[tt];
     Qp[tt] = sQ[tt];
   }
-  const int rc = w.rcap, ldc = w.rcap + WS_CH;
-  cd* Mc = coef + w.co;
-  cd* Nc = Mc + (size_t)ldc * rc;
-  cd* Dn = Nc + (size_t)ldc * rc;
-  for (int e = tid; e < rho * rho; e += NT) {
-    const int l = e / rho, tt = e - l * rho;
-    if (l < tt) {
-      Mc[(size_t)l * ldc + tt] = Wg[sQ[tt] * R3 + sP[l]] * cinv(Wg[sQ[l] * R3 + sP[l]]);
-      Nc[(size_t)l * ldc + tt] = Wg[sQ[l] * R3 + sP[tt]];
-    }
-  }
-  for (int tt = tid; tt < rho; tt += NT) Dn[tt] = cinv(Wg[sQ[tt] * R3 + sP[tt]]);
 }
 
-// U terms: one wavefront per 21 row elements of a block (four independent
-// wavefronts per workgroup, so that more of them are resident per compute
-// unit).  Row r of Cc(:, q) = U M is solved for U(r, :) by forward
-// substitution; the coefficients are wavefront-uniform reads of Mc.
-__global__ __launch_bounds__(256) void k_ws_form_u(WsArgs A, const FarBlk* __restrict__ blks,
-                                                   AcaState* __restrict__ st, const unsigned* __restrict__ used,
-                                                   const cd* __restrict__ coef) {
-  const int task = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  if (task >= A.tot_tu) return;
-  const int i = find_seg(A.tu_off, A.nwarm, task);
+// The substitutions as products on the FP64 matrix cores.
+//
+// With the pivot order (p_t, q_t) of the eliminated core W, the terms are
+//   U = C_Q M^{-1},  M[l][t] = W[p_l][q_t] / W[p_l][q_l] (unit upper),
+//   V = R_P^T N^{-T}, N^T[l][t] = W[p_t][q_l] (upper, diagonal W[p_t][q_t]),
+// C_Q the cross columns q_t and R_P the cross rows p_t.  Taken in chunks
+// T_k of 16 terms, with D_k the inverse of S[T_k, T_k] (S = M or N^T),
+//   X[:, T_k] = (Src[:, T_k] - X[:, T_<k] S[T_<k, T_k]) D_k
+//             = [Src[:, T_k] | X[:, T_<k]] P_k,  P_k = [D_k ; -S[T_<k, T_k] D_k],
+// so each chunk is one product whose first 16 inner rows read the source
+// columns and the rest the terms already formed.  k_ws_panels forms the
+// panels P_k ((16 + 16 k) x 16, row-major; columns of terms past rho are
+// zero), one workgroup per warm block.  The algebra is that of the forward
+// substitutions; only the summation order differs.
+__global__ __launch_bounds__(256) void k_ws_panels(WsArgs A) {
+  __shared__ cd Sd[2][16][16];  // S[T_k, T_k] of each side
+  __shared__ cd Dk[2][16][16];  // its inverse
+  __shared__ int sP[3 * WS_MAXLIST], sQ[3 * WS_MAXLIST];
+  const int i = blockIdx.x;
+  const WsBlk w = A.wb[i];
+  const int rho = A.rho[i];
+  if (rho == 0) return;  // the whole workgroup
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int R3 = 3 * w.nr;
+  const cd* __restrict__ W = A.cross + w.w;
+  cd* PU = A.coef + w.co;
+  cd* PV = PU + ws_panel_elems(w.rcap);
+  for (int t = tid; t < rho; t += nt) {
+    sP[t] = A.pq[w.pq + t];
+    sQ[t] = A.pq[w.pq + w.rcap + t];
+  }
+  __syncthreads();
+  // W[p_l][q_t]
+  auto Wlt = [&](int l, int t) { return W[(size_t)sQ[t] * R3 + sP[l]]; };
+  const int nk = (rho + 15) / 16;
+  for (int k = 0; k < nk; ++k) {
+    const int t0 = 16 * k;
+    // the diagonal blocks: S_0[j][l] = M = W[p_j][q_l] / W[p_j][q_j],
+    // S_1[j][l] = N^T = W[p_l][q_j] (j <= l; zero elsewhere and past rho)
+    for (int e = tid; e < 512; e += nt) {
+      const int side = e >> 8, j = (e >> 4) & 15, l = e & 15;
+      cd v = mk(0.0);
+      if (j <= l && t0 + l < rho) {
+        if (side == 0)
+          v = j == l ? mk(1.0) : Wlt(t0 + j, t0 + l) * cinv(Wlt(t0 + j, t0 + j));
+        else
+          v = Wlt(t0 + l, t0 + j);
+      }
+      Sd[side][j][l] = v;
+      Dk[side][j][l] = mk(0.0);
+    }
+    __syncthreads();
+    // column c of D_k: back substitution S[T_k, T_k] x = e_c, one thread each
+    if (tid < 32) {
+      const int side = tid >> 4, c = tid & 15;
+      if (t0 + c < rho) {
+        Dk[side][c][c] = cinv(Sd[side][c][c]);
+        for (int j = c - 1; j >= 0; --j) {
+          cd acc = mk(0.0);
+          for (int l = j + 1; l <= c; ++l) acc += Sd[side][j][l] * Dk[side][l][c];
+          Dk[side][j][c] = -(acc * cinv(Sd[side][j][j]));
+        }
+      }
+    }
+    __syncthreads();
+    const size_t pof = 256 * (size_t)(k * (k + 1) / 2);
+    // rows 0..15: D_k
+    for (int e = tid; e < 512; e += nt) {
+      const int side = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      (side == 0 ? PU : PV)[pof + (size_t)r * 16 + c] = Dk[side][r][c];
+    }
+    // rows 16 + l, l < t0: -S[l, T_k] D_k, one thread per (side, l)
+    for (int e = tid; e < 2 * t0; e += nt) {
+      const int side = e / t0, l = e - side * t0;
+      cd srow[16];
+      const cd il = side == 0 ? cinv(Wlt(l, l)) : mk(0.0);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int t = t0 + j < rho ? t0 + j : rho - 1;
+        srow[j] = side == 0 ? Wlt(l, t) * il : Wlt(t, l);
+      }
+      cd* dst = (side == 0 ? PU : PV) + pof + (size_t)(16 + l) * 16;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        cd acc = mk(0.0);
+#pragma unroll
+        for (int j = 0; j <= c; ++j) acc += srow[j] * Dk[side][j][c];
+        dst[c] = -acc;
+      }
+    }
+    __syncthreads();  // Sd and Dk are rewritten by the next chunk
+  }
+}
+
+// X = [Src | X] P_k chunk by chunk: one wavefront per 48 rows of a block
+// (16 row elements of the U side; three 16-row tiles of the product), four
+// independent wavefronts per workgroup.  Per step of four inner rows,
+// v_mfma_f64_16x16x4f64 twice per tile and half-chunk of eight terms, with
+// A the 16 x 4 source entries (lane l: row l % 16, inner row l / 16) and B
+// the panel entries in the layout [Re P | Im P] and [-Im P | Re P]
+// (lane l: inner row l / 16, term (l % 16) % 8); lane l ends with rows
+// l / 16 + 4 v of column l % 16: the real (l % 16 < 8) or imaginary part of
+// a term.  The chunk's terms are stored, and their squared norms summed per
+// wavefront; the U side also offers the next row element (largest entry of
+// the last term among unused rows).  A chunk reads the terms that earlier
+// chunks of the same wavefront stored (other lanes' stores): the wavefront
+// waits for its stores before the next chunk's loads.
+template <bool USIDE>
+__global__ __launch_bounds__(256) void k_ws_form_mfma(WsArgs A, const FarBlk* __restrict__ blks,
+                                                      AcaState* __restrict__ st, const unsigned* __restrict__ used) {
+  __shared__ double rowsq[4][WS_TILE_ROWS];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int task = blockIdx.x * 4 + wv;
+  const int ntask = USIDE ? A.tot_tu : A.tot_tv;
+  if (task >= ntask) return;  // wavefront-uniform; no barrier below
+  const int* off = USIDE ? A.tu_off : A.tv_off;
+  const int i = find_seg(off, A.nwarm, task);
   const WsBlk w = A.wb[i];
   const FarBlk B = blks[w.blk];
   const int rho = A.rho[i];
   if (rho == 0) return;
-  const int tile = task - A.tu_off[i];
-  const int lane = threadIdx.x & 63;
-  const size_t M3 = 3 * (size_t)B.m;
-  const int r = tile * (3 * ACA_ROWS_PER_WAVE) + lane;
-  const bool valid = lane < 3 * ACA_ROWS_PER_WAVE && r < (int)M3;
-  const int rc = w.rcap, ldc = w.rcap + WS_CH;
-  const int* Qp = A.pq + w.pq + rc;
-  const cd* Cc = A.cross + w.cc;
-  const cd* __restrict__ Mc = coef + w.co;
-  cd* U = B.U;
-  double* part = A.part + w.pu + (size_t)tile * rc;
-  double elast = 0.0;
-  for (int t0 = 0; t0 < rho; t0 += WS_CH) {
-    const int nj = min(WS_CH, rho - t0);
-    cd acc[WS_CH];
+  const int tile = task - off[i];
+  const int nrow = USIDE ? 3 * B.m : 3 * B.n;
+  const int r0 = tile * WS_TILE_ROWS;
+  const int* __restrict__ perm = A.pq + w.pq + (USIDE ? w.rcap : 0);  // q_t (U) or p_t (V)
+  const cd* src = A.cross + (USIDE ? w.cc : w.rr);                   // column t: src + perm[t] nrow
+  cd* out = USIDE ? B.U : B.V;
+  const cd* pan = A.coef + w.co + (USIDE ? 0 : ws_panel_elems(w.rcap));
+  double* part = A.part + (USIDE ? w.pu : w.pv) + (size_t)tile * w.rcap;
+  const int kr = lane >> 4, n = lane & 15;
+  const int nk = (rho + 15) / 16;
+  for (int k = 0; k < nk; ++k) {
+    const int t0 = 16 * k;
+    const cd* __restrict__ P = pan + 256 * (size_t)(k * (k + 1) / 2);
+    wfv4d acc[3][2];
 #pragma unroll
-    for (int j = 0; j < WS_CH; ++j) acc[j] = (valid && j < nj) ? Cc[(size_t)Qp[t0 + j] * M3 + r] : mk(0.0);
-    // terms t0 + j >= rho are padding: their accumulators are never stored
-    int l = 0;
-    for (; l + 2 <= t0; l += 2) {
-      const cd x0 = valid ? U[(size_t)l * M3 + r] : mk(0.0);
-      const cd x1 = valid ? U[(size_t)(l + 1) * M3 + r] : mk(0.0);
+    for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
-      for (int j = 0; j < WS_CH; ++j) {
-        cms(acc[j], x0, Mc[(size_t)l * ldc + t0 + j]);
-        cms(acc[j], x1, Mc[(size_t)(l + 1) * ldc + t0 + j]);
+      for (int h = 0; h < 2; ++h) acc[tt][h] = wfv4d{0.0, 0.0, 0.0, 0.0};
+    const int K = 16 + t0;
+    // one step's operands; the next step's are loaded before this step's
+    // products
+    auto load = [&](int kk, cd (&a)[3], cd& p0, cd& p1) {
+      const int kap = kk + kr;
+      // inner rows below 16 read the source columns of this chunk's terms
+      // (terms past rho read the last one; their panel rows are zero), the
+      // rest the terms already formed
+      const cd* col;
+      if (kk < 16) {
+        const int t = t0 + kap < rho ? t0 + kap : rho - 1;
+        col = src + (size_t)perm[t] * nrow;
+      } else {
+        col = out + (size_t)(kap - 16) * nrow;
+      }
+#pragma unroll
+      for (int tt = 0; tt < 3; ++tt) {
+        const int r = r0 + 16 * tt + n;
+        const cd v = col[r < nrow ? r : nrow - 1];
+        a[tt] = r < nrow ? v : mk(0.0);
+      }
+      p0 = P[(size_t)kap * 16 + (n & 7)];
+      p1 = P[(size_t)kap * 16 + 8 + (n & 7)];
+    };
+    // the six accumulators in turn, so that no product waits on the one
+    // just issued
+    auto mma = [&](const cd (&a)[3], const cd& p0, const cd& p1) {
+      double b1[2], b2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const cd pb = h ? p1 : p0;
+        b1[h] = n < 8 ? pb.x : pb.y;
+        b2[h] = n < 8 ? -pb.y : pb.x;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt)
+          acc[tt][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tt].x, b1[h], acc[tt][h], 0, 0, 0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt)
+          acc[tt][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tt].y, b2[h], acc[tt][h], 0, 0, 0);
+    };
+    cd a0[3], a1[3], p00, p01, p10, p11;
+    load(0, a0, p00, p01);
+    for (int kk = 0; kk < K; kk += 8) {
+      if (kk + 4 < K) load(kk + 4, a1, p10, p11);
+      mma(a0, p00, p01);
+      if (kk + 4 < K) {
+        if (kk + 8 < K) load(kk + 8, a0, p00, p01);
+        mma(a1, p10, p11);
       }
     }
-    if (l < t0) {
-      const cd x = valid ? U[(size_t)l * M3 + r] : mk(0.0);
+    // store the chunk's terms; squared norms per term over this tile's rows
+    double sq[2] = {0.0, 0.0};
+    const int comp = n >> 3;
 #pragma unroll
-      for (int j = 0; j < WS_CH; ++j) cms(acc[j], x, Mc[(size_t)l * ldc + t0 + j]);
+    for (int h = 0; h < 2; ++h) {
+      const int t = t0 + 8 * h + (n & 7);
+#pragma unroll
+      for (int tt = 0; tt < 3; ++tt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = r0 + 16 * tt + kr + 4 * v;
+          if (r < nrow && t < rho) {
+            const double x = acc[tt][h][v];
+            ((double*)(out + (size_t)t * nrow + r))[comp] = x;
+            sq[h] += x * x;
+          }
+        }
     }
 #pragma unroll
-    for (int j = 0; j < WS_CH; ++j) {
-      if (j < nj) {
-        const cd x = acc[j];
-        if (valid) U[(size_t)(t0 + j) * M3 + r] = x;
+    for (int h = 0; h < 2; ++h) {
+      double q = sq[h];
+      q += __shfl_xor(q, 8, 64);
+      q += __shfl_xor(q, 16, 64);
+      q += __shfl_xor(q, 32, 64);
+      if (lane < 8 && t0 + 8 * h + lane < rho) part[t0 + 8 * h + lane] = q;
+    }
+    if (USIDE && k == nk - 1) {
+      // the last term's squared entries per row, then per row element
+      const int tl = rho - 1 - t0, hl = tl >> 3, nl = tl & 7;
 #pragma unroll
-        for (int jp = j + 1; jp < WS_CH; ++jp)
-          if (jp < nj) acc[jp] -= x * Mc[(size_t)(t0 + j) * ldc + t0 + jp];
-        const double q2 = valid ? norm2(x) : 0.0;
-        if (t0 + j == rho - 1) elast = q2;
-        const double sq = wsum(q2);
-        if (lane == 0) part[t0 + j] = sq;
+      for (int tt = 0; tt < 3; ++tt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double x = hl ? acc[tt][1][v] : acc[tt][0][v];
+          double q = x * x;
+          q += __shfl_xor(q, 8, 64);
+          if (n == nl) rowsq[wv][16 * tt + kr + 4 * v] = q;
+        }
+      wave_sync();
+      unsigned long long cand = 0ull;
+      if (lane < WS_TILE_ROWS / 3) {
+        const int a = r0 / 3 + lane;
+        if (3 * a < nrow && !(used[B.bitoff + (a >> 5)] & (1u << (a & 31)))) {
+          const double e = rowsq[wv][3 * lane] + rowsq[wv][3 * lane + 1] + rowsq[wv][3 * lane + 2];
+          cand = pack_best(sqrt(e), a);
+        }
       }
+      cand = wave_max_u64(cand);
+      if (lane == 0 && cand) atomicMax(&st[w.blk].best_row, cand);
     }
-  }
-  // next row element: largest last-term entry among unused rows
-  const double e1 = __shfl_down(elast, 1, 64), e2 = __shfl_down(elast, 2, 64);
-  unsigned long long cand = 0ull;
-  if (valid && lane % 3 == 0) {
-    const int a = r / 3;
-    if (!(used[B.bitoff + (a >> 5)] & (1u << (a & 31)))) cand = pack_best(sqrt(elast + e1 + e2), a);
-  }
-  cand = wave_max_u64(cand);
-  if (lane == 0 && cand) atomicMax(&st[w.blk].best_row, cand);
-}
-
-// V terms: one wavefront per 64 columns of a block (four per workgroup).
-// Column c of Rr(p, :) = N V^T is solved for V(c, :) by forward substitution.
-__global__ __launch_bounds__(256) void k_ws_form_v(WsArgs A, const FarBlk* __restrict__ blks,
-                                                   const cd* __restrict__ coef) {
-  const int task = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  if (task >= A.tot_tv) return;
-  const int i = find_seg(A.tv_off, A.nwarm, task);
-  const WsBlk w = A.wb[i];
-  const FarBlk B = blks[w.blk];
-  const int rho = A.rho[i];
-  if (rho == 0) return;
-  const int tile = task - A.tv_off[i];
-  const int lane = threadIdx.x & 63;
-  const size_t N3 = 3 * (size_t)B.n;
-  const int c = tile * 64 + lane;
-  const bool valid = c < (int)N3;
-  const int rc = w.rcap, ldc = w.rcap + WS_CH;
-  const int* Pp = A.pq + w.pq;
-  const cd* Rr = A.cross + w.rr;
-  const cd* __restrict__ Nc = coef + w.co + (size_t)ldc * rc;
-  const cd* __restrict__ Dn = Nc + (size_t)ldc * rc;
-  cd* V = B.V;
-  double* part = A.part + w.pv + (size_t)tile * rc;
-  for (int t0 = 0; t0 < rho; t0 += WS_CH) {
-    const int nj = min(WS_CH, rho - t0);
-    cd acc[WS_CH];
-#pragma unroll
-    for (int j = 0; j < WS_CH; ++j) acc[j] = (valid && j < nj) ? Rr[(size_t)Pp[t0 + j] * N3 + c] : mk(0.0);
-    int l = 0;
-    for (; l + 2 <= t0; l += 2) {
-      const cd y0 = valid ? V[(size_t)l * N3 + c] : mk(0.0);
-      const cd y1 = valid ? V[(size_t)(l + 1) * N3 + c] : mk(0.0);
-#pragma unroll
-      for (int j = 0; j < WS_CH; ++j) {
-        cms(acc[j], y0, Nc[(size_t)l * ldc + t0 + j]);
-        cms(acc[j], y1, Nc[(size_t)(l + 1) * ldc + t0 + j]);
-      }
-    }
-    if (l < t0) {
-      const cd y = valid ? V[(size_t)l * N3 + c] : mk(0.0);
-#pragma unroll
-      for (int j = 0; j < WS_CH; ++j) cms(acc[j], y, Nc[(size_t)l * ldc + t0 + j]);
-    }
-#pragma unroll
-    for (int j = 0; j < WS_CH; ++j) {
-      if (j < nj) {
-        const cd y = acc[j] * Dn[t0 + j];
-        if (valid) V[(size_t)(t0 + j) * N3 + c] = y;
-#pragma unroll
-        for (int jp = j + 1; jp < WS_CH; ++jp)
-          if (jp < nj) acc[jp] -= y * Nc[(size_t)(t0 + j) * ldc + t0 + jp];
-        const double sq = wsum(valid ? norm2(y) : 0.0);
-        if (lane == 0) part[t0 + j] = sq;
-      }
-    }
+    // the next chunk reads these stores (other lanes'): wait for them
+    __builtin_amdgcn_s_waitcnt(0);
+    wave_sync();
   }
 }
 
@@ -789,34 +901,35 @@ void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParam
   const int* lst = A.lu_list;
   if (A.n_lu[0] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[0]), dim3(ntl), 0, s, A.wb,
-                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
   lst += A.n_lu[0];
   if (A.n_lu[1] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_MID, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[1]), dim3(ntl), 0, s, A.wb,
-                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
   lst += A.n_lu[1];
   if (A.n_lu[2] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_LARGE, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[2]), dim3(ntl), 0, s, A.wb,
-                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
+                       lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
   lst += A.n_lu[2];
   if (A.n_lu[3] > 0)
     hipLaunchKernelGGL((k_ws_lu<0, (3 * WS_MAXLIST + 63) / 64, WS_LU_NW>), dim3(A.n_lu[3]), dim3(nt), 0, s, A.wb, lst,
-                       W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
+                       W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
   lst += A.n_lu[3];
   if (A.n_lu[4] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_TINY, 1, 2>), dim3(A.n_lu[4]), dim3(128), 0, s, A.wb, lst, W.blks, W.plist,
-                       A.cross, A.pq, A.rho, A.coef, A.stop2);
+                       A.cross, A.pq, A.rho, A.stop2);
   lst += A.n_lu[4];
   // cores in registers: 4 x 16 columns of 64 rows, 8 x 16 columns of 128 rows
   if (A.n_lu[5] > 0)
     hipLaunchKernelGGL((k_ws_lu_reg<WS_REG_SMALL / 16, 16, 1>), dim3(A.n_lu[5]), dim3(WS_REG_SMALL / 16 * 64), 0,
-                       s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
+                       s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
   lst += A.n_lu[5];
   if (A.n_lu[6] > 0)
     hipLaunchKernelGGL((k_ws_lu_reg<WS_REG_LARGE / 16, 16, 2>), dim3(A.n_lu[6]), dim3(WS_REG_LARGE / 16 * 64), 0,
-                       s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.coef, A.stop2);
-  hipLaunchKernelGGL(k_ws_form_u, dim3((A.tot_tu + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, A.coef);
-  hipLaunchKernelGGL(k_ws_form_v, dim3((A.tot_tv + 3) / 4), dim3(256), 0, s, A, W.blks, A.coef);
+                       s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
+  hipLaunchKernelGGL(k_ws_panels, dim3(A.nwarm), dim3(256), 0, s, A);
+  hipLaunchKernelGGL((k_ws_form_mfma<true>), dim3((A.tot_tu + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used);
+  hipLaunchKernelGGL((k_ws_form_mfma<false>), dim3((A.tot_tv + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used);
   hipLaunchKernelGGL(k_ws_finish, dim3((A.nwarm + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used, W.plist,
                      W.nlist, tol);
 }

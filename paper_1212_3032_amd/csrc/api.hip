@@ -552,7 +552,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     cross += 9LL * nr * nc;
     w.pq = (int)pqn;
     pqn += 2LL * w.rcap;
-    const int ntu = (f.m + ACA_ROWS_PER_WAVE - 1) / ACA_ROWS_PER_WAVE, ntv = (3 * f.n + 63) / 64;
+    const int ntu = (3 * f.m + WS_TILE_ROWS - 1) / WS_TILE_ROWS, ntv = (3 * f.n + WS_TILE_ROWS - 1) / WS_TILE_ROWS;
     w.tu = (int)tu;
     w.tv = (int)tv;
     w.pu = part;
@@ -560,7 +560,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     w.pv = part;
     part += (long long)ntv * w.rcap;
     w.co = coefn;
-    coefn += 2LL * (w.rcap + WS_CH) * w.rcap + w.rcap + WS_CH;  // Mc, Nc, Dn with one chunk of padding
+    coefn += 2 * ws_panel_elems(w.rcap);  // substitution panels, U and V sides
     wb.push_back(w);
     er += (long long)nr * f.n;
     ec += (long long)nc * f.m;
@@ -588,8 +588,8 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
       const FarBlk& f = c->far_h[wb[i].blk];
       woff[i + 1] = woff[i] + wb[i].nr * f.n;
       woff[(nw + 1) + i + 1] = woff[(nw + 1) + i] + wb[i].nc * f.m;
-      woff[2 * (nw + 1) + i + 1] = woff[2 * (nw + 1) + i] + (f.m + ACA_ROWS_PER_WAVE - 1) / ACA_ROWS_PER_WAVE;
-      woff[3 * (nw + 1) + i + 1] = woff[3 * (nw + 1) + i] + (3 * f.n + 63) / 64;
+      woff[2 * (nw + 1) + i + 1] = woff[2 * (nw + 1) + i] + (3 * f.m + WS_TILE_ROWS - 1) / WS_TILE_ROWS;
+      woff[3 * (nw + 1) + i + 1] = woff[3 * (nw + 1) + i] + (3 * f.n + WS_TILE_ROWS - 1) / WS_TILE_ROWS;
     }
     c->d_wsb.upload(wb, st);
     c->d_wsoff.upload(woff, st);

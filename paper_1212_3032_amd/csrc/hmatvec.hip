@@ -115,7 +115,11 @@ __global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__
   // columns past ncol read column 0 (in bounds) and multiply zero
   const TS* __restrict__ Vj = V + (size_t)(jv ? j : 0) * C;
   const cd* __restrict__ xq = xs + q * ldx;
-  fvt_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  // four accumulators (row half h, real or imaginary factor part), summed
+  // at the end, so that no product waits on the one just issued
+  fvt_v4d acc4[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc4[u] = fvt_v4d{0.0, 0.0, 0.0, 0.0};
   // a step is eight rows, two products: product h pairs lane row kr with
   // factor row c0 + 2 kr + h, so a lane's two rows are adjacent in memory
   // (rows past C read row C - 1 and are zeroed)
@@ -136,8 +140,8 @@ __global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__
     for (int h = 0; h < 2; ++h) {
       const double b1 = j < 8 ? xv[h].x : xv[h].y;
       const double b2 = j < 8 ? -xv[h].y : xv[h].x;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].x, b1, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].y, b2, acc, 0, 0, 0);
+      acc4[2 * h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].x, b1, acc4[2 * h], 0, 0, 0);
+      acc4[2 * h + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].y, b2, acc4[2 * h + 1], 0, 0, 0);
     }
   };
   // three steps in flight: the loads of steps s + 1 and s + 2 are issued
@@ -157,6 +161,7 @@ __global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__
       mma(a2, x2);
     }
   }
+  const fvt_v4d acc = (acc4[0] + acc4[2]) + (acc4[1] + acc4[3]);
   const int comp = j >> 3;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -397,14 +402,15 @@ __device__ __forceinline__ void seg_mfma(const void* A, int ld, int rows, int nc
     const cd xx = xq[cc];
     xv = cv ? xx : mk(0.0);
   };
+  // the three accumulators in turn, so that no product waits on the one
+  // just issued
   auto mma = [&](const cd (&a)[3], const cd& xv) {
     const double b1 = n < 8 ? xv.x : xv.y;
     const double b2 = n < 8 ? -xv.y : xv.x;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b1, acc[q], 0, 0, 0);
-      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].y, b2, acc[q], 0, 0, 0);
-    }
+    for (int q = 0; q < 3; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b1, acc[q], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].y, b2, acc[q], 0, 0, 0);
   };
   cd a0[3], a1[3], x0, x1;
   load(0, a0, x0);
