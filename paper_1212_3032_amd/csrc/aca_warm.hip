@@ -61,11 +61,11 @@ __device__ __forceinline__ void A_elem(const double* x, int e, const DevGeom& g,
 #pragma unroll
   for (int i = 0; i < 9; ++i) T[i] = mk(0.0);
   if (g.bc && g.bc[e]) {
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < 7; ++q) acc_U<false>(x, g.qp + 21 * (size_t)e + 3 * q, -g.qw[7 * (size_t)e + q], P, T);
   } else {
     const double* n = g.nrm + 3 * (size_t)e;
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < 7; ++q) acc_T<false>(x, g.qp + 21 * (size_t)e + 3 * q, n, g.qw[7 * (size_t)e + q], P, T);
   }
 }

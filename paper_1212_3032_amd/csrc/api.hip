@@ -186,6 +186,8 @@ struct ewbem_ctx {
   DevBuf<WsBlk> d_wsb;
   DevBuf<int> d_wsoff, d_wspq, d_wsrho, d_wslu;
   DevBuf<unsigned long long> d_wscnt;  // warm-start pivot and kept-term counts of one call
+  DevBuf<double> d_ser;  // series coefficients of the kernels (KParams::ser)
+  double ser_g = -1.0;   // the c_s / c_p they were formed for
   DevBuf<cd> d_cross, d_wscoef;
   DevBuf<double> d_wspart;
   DevBuf<unsigned> d_used;
@@ -250,7 +252,10 @@ struct ewbem_ctx {
 
 namespace {
 
-KParams make_params(double rho, double mu, double nu, cd s) {
+// Kernel parameters at s; the series coefficients (material constants) live
+// in a small device buffer of the context, uploaded when the material changes.
+KParams make_params(ewbem_ctx* c, cd s) {
+  const double rho = c->rho, mu = c->mu, nu = c->nu;
   KParams P{};
   const double lam = 2.0 * mu * nu / (1.0 - 2.0 * nu);
   const double cs = std::sqrt(mu / rho), cp = std::sqrt((lam + 2.0 * mu) / rho);
@@ -267,21 +272,28 @@ KParams make_params(double rho, double mu, double nu, cd s) {
   // Taylor coefficients of r phi, r psi in z = s r / c_s (index m = n - 2):
   //   r phi: (-1)^n (n-1)(n-1+g^n)/n!,  r psi: (-1)^n (n-1)(n-3)(1-g^n)/n!,
   //   r^2 phi', r^2 psi': the same times (n-3).
-  double fact = 1.0;  // n!
-  for (int n = 1; n <= 1; ++n) fact *= n;
+  double ser[4 * NSER];  // c_phi, c_psi, c_dphi, c_dpsi
+  double fact = 1.0;     // n!
   for (int n = 2; n < NSER + 2; ++n) {
     fact *= n;
     const double sgn = (n % 2 == 0) ? 1.0 : -1.0;
     const double gn = std::pow(g, n);
     const double cphi = sgn * (n - 1) * (n - 1 + gn) / fact;
     const double cpsi = sgn * (n - 1) * (n - 3) * (1.0 - gn) / fact;
-    P.c_phi[n - 2] = cphi;
-    P.c_psi[n - 2] = cpsi;
-    P.c_dphi[n - 2] = (n - 3) * cphi;
-    P.c_dpsi[n - 2] = (n - 3) * cpsi;
+    ser[n - 2] = cphi;
+    ser[NSER + n - 2] = cpsi;
+    ser[2 * NSER + n - 2] = (n - 3) * cphi;
+    ser[3 * NSER + n - 2] = (n - 3) * cpsi;
   }
-  P.stat_rphi = P.c_phi[0];
-  P.stat_rpsi = P.c_psi[0];
+  P.stat_rphi = ser[0];
+  P.stat_rpsi = ser[NSER];
+  if (c->device >= 0 && (!c->d_ser.p || c->ser_g != g)) {
+    c->d_ser.reserve(4 * NSER);
+    EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_ser.p, ser, sizeof(ser), hipMemcpyHostToDevice, c->stream));
+    EWBEM_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->ser_g = g;
+  }
+  P.ser = c->d_ser.p;
   return P;
 }
 
@@ -488,7 +500,7 @@ void ensure_device(ewbem_ctx* c) {
   c->S.nt = c->S.nr = c->op.self_order;
   gauss_legendre01(c->op.self_order, c->S.t, c->S.wt);
   gauss_legendre01(c->op.self_order, c->S.u, c->S.wu);
-  c->P = make_params(c->rho, c->mu, c->nu, mk(0.0));
+  c->P = make_params(c, mk(0.0));
   c->hist_n = 0;
   c->hist_head = 0;
   c->hist_slot.clear();
@@ -1293,7 +1305,7 @@ void assemble_k(ewbem_ctx* c, int k, bool aca_done = false) {
   if (k < 0 || k > c->n_f / 2) fail(EWBEM_EINVAL, "frequency index out of range 0..N_f/2");
   hipStream_t st = c->stream;
   const auto t0 = Clock::now();
-  c->P = make_params(c->rho, c->mu, c->nu, s_of_k(c, k));
+  c->P = make_params(c, s_of_k(c, k));
   const DevGeom g = dev_geom(c);
   EventPair ev;
   EWBEM_HIP_CHECK(hipEventRecord(ev.a, st));
@@ -1915,7 +1927,7 @@ int frequency_loop(ewbem_ctx* c) {
     }
     if (c->assembled_k != k) assemble_k(c, k);
     const int slot = 1 - c->fslot;
-    c->P = make_params(c->rho, c->mu, c->nu, s_of_k(c, k + 1));
+    c->P = make_params(c, s_of_k(c, k + 1));
     const DevGeom g = dev_geom(c);
     double aca_ms = 0.0, aca_wall = 0.0;
     std::exception_ptr err;
@@ -2780,7 +2792,7 @@ int ewbem_kernel_eval(ewbem_ctx* ctx, ewbem_z s, int64_t n, const double* x, con
     if (!ctx->have_mat) fail(EWBEM_ESTATE, "material not set");
     if (n < 0 || (n > 0 && (!x || !y || (T && !nrm)))) fail(EWBEM_EINVAL, "kernel_eval: bad arguments");
     EWBEM_HIP_CHECK(hipSetDevice(ctx->device));
-    KParams P = make_params(ctx->rho, ctx->mu, ctx->nu, cd{s.re, s.im});
+    KParams P = make_params(ctx, cd{s.re, s.im});
     launch_kernel_eval(P, n, x, y, nrm, (cd*)U, (cd*)T, ctx->stream);
     EWBEM_HIP_CHECK(hipGetLastError());
     EWBEM_HIP_CHECK(hipStreamSynchronize(ctx->stream));
@@ -2808,7 +2820,7 @@ int ewbem_assemble_dense(ewbem_ctx* ctx, ewbem_z s, ewbem_z* T, ewbem_z* U) {
     S.nt = S.nr = ctx->op.self_order;
     gauss_legendre01(S.nt, S.t, S.wt);
     gauss_legendre01(S.nr, S.u, S.wu);
-    KParams P = make_params(ctx->rho, ctx->mu, ctx->nu, cd{s.re, s.im});
+    KParams P = make_params(ctx, cd{s.re, s.im});
     DevGeom dg = dev_geom(ctx);
     dg.bc = nullptr;  // the raw T and U
     launch_self(dg, P, S, ctx->d_selfT.p, ctx->d_selfU.p, nullptr, st);

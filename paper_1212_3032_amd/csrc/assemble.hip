@@ -341,10 +341,10 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
             const cd z = cd{zx, (kst + j) * th};
             cd rphi, rpsi;
             if (norm2(z) < P.series_z2) {
-              cd a1 = mk(P.c_phi[NSER - 1]), b1 = mk(P.c_psi[NSER - 1]);
+              cd a1 = mk(P.ser[NSER - 1]), b1 = mk(P.ser[2 * NSER - 1]);
               for (int m = NSER - 2; m >= 0; --m) {
-                a1 = a1 * z + P.c_phi[m];
-                b1 = b1 * z + P.c_psi[m];
+                a1 = a1 * z + P.ser[m];
+                b1 = b1 * z + P.ser[NSER + m];
               }
               rphi = a1;
               rpsi = b1;
@@ -463,10 +463,10 @@ __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double 
         const cd z = cd{zx, zy};
         cd rphi, rpsi;
         if (norm2(z) < P.series_z2) {
-          cd a1 = mk(P.c_phi[NSER - 1]), b1 = mk(P.c_psi[NSER - 1]);
+          cd a1 = mk(P.ser[NSER - 1]), b1 = mk(P.ser[2 * NSER - 1]);
           for (int m = NSER - 2; m >= 0; --m) {
-            a1 = a1 * z + P.c_phi[m];
-            b1 = b1 * z + P.c_psi[m];
+            a1 = a1 * z + P.ser[m];
+            b1 = b1 * z + P.ser[NSER + m];
           }
           rphi = a1;
           rpsi = b1;

@@ -61,7 +61,10 @@ struct KParams {
   double cpv;        // gamma^2 / (4 pi)
   double series_z2;  // |z_s|^2 below which the series is used
   double stat_rphi, stat_rpsi;  // static (n = 2) terms of r phi, r psi
-  double c_phi[NSER], c_psi[NSER], c_dphi[NSER], c_dpsi[NSER];
+  // device, 4 x NSER: Taylor coefficients of r phi, r psi, r^2 phi', r^2 psi'
+  // in z (material constants; read only on the rare small-|z| branch, so they
+  // are not kernel arguments held in scalar registers)
+  const double* ser;
 };
 
 // Geometry of the mesh on the device, elements in cluster-tree order.

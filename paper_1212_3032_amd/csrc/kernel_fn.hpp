@@ -33,15 +33,18 @@ __device__ __forceinline__ Radial radial(double r, const KParams& P) {
   const cd z = P.s * (r * P.inv_cs);
   Radial o;
   if (norm2(z) < P.series_z2) {
-    cd a = mk(P.c_phi[NSER - 1]), b = mk(P.c_psi[NSER - 1]);
-    cd c = mk(P.c_dphi[NSER - 1]), d = mk(P.c_dpsi[NSER - 1]);
-#pragma unroll
+    const double* __restrict__ c_phi = P.ser;
+    const double* __restrict__ c_psi = P.ser + NSER;
+    const double* __restrict__ c_dphi = P.ser + 2 * NSER;
+    const double* __restrict__ c_dpsi = P.ser + 3 * NSER;
+    cd a = mk(c_phi[NSER - 1]), b = mk(c_psi[NSER - 1]);
+    cd c = mk(c_dphi[NSER - 1]), d = mk(c_dpsi[NSER - 1]);
     for (int m = NSER - 2; m >= 1; --m) {
-      a = a * z + P.c_phi[m];
-      b = b * z + P.c_psi[m];
+      a = a * z + c_phi[m];
+      b = b * z + c_psi[m];
       if (DERIV) {
-        c = c * z + P.c_dphi[m];
-        d = d * z + P.c_dpsi[m];
+        c = c * z + c_dphi[m];
+        d = d * z + c_dpsi[m];
       }
     }
     a = a * z;
@@ -51,11 +54,11 @@ __device__ __forceinline__ Radial radial(double r, const KParams& P) {
       d = d * z;
     }
     if (!TAIL) {
-      a = a + P.c_phi[0];
-      b = b + P.c_psi[0];
+      a = a + c_phi[0];
+      b = b + c_psi[0];
       if (DERIV) {
-        c = c + P.c_dphi[0];
-        d = d + P.c_dpsi[0];
+        c = c + c_dphi[0];
+        d = d + c_dpsi[0];
       }
     }
     o.rphi = a;
