@@ -99,6 +99,7 @@ __device__ __forceinline__ void cms(cd& acc, cd x, cd m) {
 // wavefront's LDS operations complete in order; this keeps the compiler
 // from moving them across the point.
 typedef double wfv4d __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -667,9 +668,22 @@ __global__ __launch_bounds__(256) void k_ws_form_mfma(WsArgs A, const FarBlk* __
   double* part = A.part + (USIDE ? w.pu : w.pv) + (size_t)tile * w.rcap;
   const int kr = lane >> 4, n = lane & 15;
   const int nk = (rho + 15) / 16;
+  // sources, formed terms and panels through buffer resources (vector
+  // memory counter only; every span is far below 4 GiB)
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)src, 0, (unsigned)((size_t)nrow * (USIDE ? 3 * w.nc : 3 * w.nr) * sizeof(cd)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rout =
+      __builtin_amdgcn_make_buffer_rsrc((void*)out, 0, (unsigned)((size_t)nrow * rho * sizeof(cd)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rpan = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)pan, 0, (unsigned)(ws_panel_elems(w.rcap) * sizeof(cd)), 0x00020000);
+  auto bload = [](__amdgpu_buffer_rsrc_t rs, unsigned i) -> cd {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, i * (unsigned)sizeof(cd), 0, 0);
+    const double2 d = __builtin_bit_cast(double2, v);
+    return cd{d.x, d.y};
+  };
   for (int k = 0; k < nk; ++k) {
     const int t0 = 16 * k;
-    const cd* __restrict__ P = pan + 256 * (size_t)(k * (k + 1) / 2);
+    const unsigned pofs = 256u * (unsigned)(k * (k + 1) / 2);
     wfv4d acc[3][2];
 #pragma unroll
     for (int tt = 0; tt < 3; ++tt)
@@ -683,21 +697,18 @@ __global__ __launch_bounds__(256) void k_ws_form_mfma(WsArgs A, const FarBlk* __
       // inner rows below 16 read the source columns of this chunk's terms
       // (terms past rho read the last one; their panel rows are zero), the
       // rest the terms already formed
-      const cd* col;
-      if (kk < 16) {
-        const int t = t0 + kap < rho ? t0 + kap : rho - 1;
-        col = src + (size_t)perm[t] * nrow;
-      } else {
-        col = out + (size_t)(kap - 16) * nrow;
-      }
+      const bool fromsrc = kk < 16;
+      const int t = t0 + kap < rho ? t0 + kap : rho - 1;
+      const unsigned col = fromsrc ? (unsigned)perm[t] * (unsigned)nrow : (unsigned)(kap - 16) * (unsigned)nrow;
 #pragma unroll
       for (int tt = 0; tt < 3; ++tt) {
         const int r = r0 + 16 * tt + n;
-        const cd v = col[r < nrow ? r : nrow - 1];
+        const unsigned i = col + (unsigned)(r < nrow ? r : nrow - 1);
+        const cd v = fromsrc ? bload(rsrc, i) : bload(rout, i);
         a[tt] = r < nrow ? v : mk(0.0);
       }
-      p0 = P[(size_t)kap * 16 + (n & 7)];
-      p1 = P[(size_t)kap * 16 + 8 + (n & 7)];
+      p0 = bload(rpan, pofs + (unsigned)kap * 16u + (unsigned)(n & 7));
+      p1 = bload(rpan, pofs + (unsigned)kap * 16u + 8u + (unsigned)(n & 7));
     };
     // the six accumulators in turn, so that no product waits on the one
     // just issued
@@ -743,7 +754,8 @@ __global__ __launch_bounds__(256) void k_ws_form_mfma(WsArgs A, const FarBlk* __
           const int r = r0 + 16 * tt + kr + 4 * v;
           if (r < nrow && t < rho) {
             const double x = acc[tt][h][v];
-            ((double*)(out + (size_t)t * nrow + r))[comp] = x;
+            const unsigned off = ((unsigned)t * (unsigned)nrow + (unsigned)r) * (unsigned)sizeof(cd) + 8u * comp;
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), rout, off, 0, 0);
             sq[h] += x * x;
           }
         }

@@ -703,8 +703,9 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
 void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipStream_t st, int slot) {
   const int nf = (int)c->far_h.size();
   if (nf == 0) return;
-  // Capacity: 30% above the previous frequency's rank (ranks grow with
-  // frequency), else a size-based first guess; retries are the exception.
+  // Capacity: 50% (at least 24 terms) above the previous frequency's rank
+  // (ranks grow with frequency), else a size-based first guess; retries
+  // are the exception.
   // 3 min(m, n) + 2 columns always suffice: a block stops at full rank, and
   // a step adds at most three terms.
   // pivot lists for warm starts: allocated with the partition, empty until a
@@ -727,7 +728,7 @@ void run_aca(ewbem_ctx* c, const DevGeom& g, EventPair& ev, double& aca_ms, hipS
   for (int b = 0; b < nf; ++b) {
     const FarBlk& f = c->far_h[b];
     const int full = 3 * std::min(f.m, f.n) + 2;
-    int want = c->kcap_prev[b] > 0 ? c->rank_h[b] + std::max(12, (3 * c->rank_h[b]) / 10)
+    int want = c->kcap_prev[b] > 0 ? c->rank_h[b] + std::max(24, c->rank_h[b] / 2)
                                    : 24 + (f.m + f.n) / 8;
     const int nr = c->nlist_h[2 * b], nc = c->nlist_h[2 * b + 1];
     if (warm && nr > 0 && nc > 0) want = std::max(want, 3 * std::min(nr, nc) + 6);

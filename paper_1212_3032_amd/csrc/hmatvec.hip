@@ -89,6 +89,22 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
   }
 }
 
+// One entry of a panel through a buffer resource: counted by the vector
+// memory counter only (a flat load would also hold every wait on the scalar
+// x loads), and bounded by the resource's size.
+template <typename TS>
+__device__ __forceinline__ cd panel_load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  if constexpr (sizeof(TS) == 16) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    const double2 d = __builtin_bit_cast(double2, v);
+    return cd{d.x, d.y};
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    const float2 f = __builtin_bit_cast(float2, v);
+    return cd{(double)f.x, (double)f.y};
+  }
+}
+
 // Phase 1 for eight right-hand sides on the matrix cores: one wavefront per
 // task of up to 16 factor columns j (a task list of its own).  Per four rows
 // c of the factor, v_mfma_f64_16x16x4f64 twice with A the 16 x 4 block
@@ -103,7 +119,7 @@ template <typename TS>
 __global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__ tasks, int ntask,
                                                       const cd* __restrict__ x, long long ldx, cd* __restrict__ z,
                                                       long long ldz) {
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int t = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform task
   const int lane = threadIdx.x & 63;
   if (t >= ntask) return;
   const VtTask T = tasks[t];
@@ -112,8 +128,11 @@ __global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__
   const int C = T.C, nc = T.ncol;
   const int j = lane & 15, kr = lane >> 4, q = j & 7;
   const bool jv = j < nc;
-  // columns past ncol read column 0 (in bounds) and multiply zero
-  const TS* __restrict__ Vj = V + (size_t)(jv ? j : 0) * C;
+  // the task's factor columns through a buffer resource (vector memory
+  // counter only); columns past ncol read column 0 and multiply zero
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V, 0, (unsigned)((size_t)nc * C * sizeof(TS)), 0x00020000);
+  const unsigned vcol = (unsigned)(jv ? j : 0) * (unsigned)C;
   const cd* __restrict__ xq = xs + q * ldx;
   // four accumulators (row half h, real or imaginary factor part), summed
   // at the end, so that no product waits on the one just issued
@@ -129,7 +148,7 @@ __global__ __launch_bounds__(256) void k_far_vt_mfma8(const VtTask* __restrict__
       const int c = c0 + 2 * kr + h;
       const bool cv = c < C;
       const int cc = cv ? c : C - 1;
-      const cd av = to_cd(Vj[cc]);
+      const cd av = panel_load<TS>(rs, (vcol + (unsigned)cc) * (unsigned)sizeof(TS));
       const cd xx = xq[cc];
       a[h] = (jv && cv) ? av : mk(0.0);
       xv[h] = cv ? xx : mk(0.0);
@@ -212,22 +231,6 @@ void launch_far_vt(const VtTask* tasks, int ntask, int cols_per_wave, int store_
     case 4: far_vt_nc<4>(tasks, ntask, store_c64, x, ldx, nrhs, z, ldz, st); break;
     case 8: far_vt_nc<8>(tasks, ntask, store_c64, x, ldx, nrhs, z, ldz, st); break;
     default: throw ApiError(-1, "matvec: 2, 4 or 8 factor columns per wavefront");
-  }
-}
-
-// One entry of a panel through a buffer resource: counted by the vector
-// memory counter only (a flat load would also hold every wait on the scalar
-// x loads), and bounded by the resource's size.
-template <typename TS>
-__device__ __forceinline__ cd panel_load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
-  if constexpr (sizeof(TS) == 16) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-    const double2 d = __builtin_bit_cast(double2, v);
-    return cd{d.x, d.y};
-  } else {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-    const float2 f = __builtin_bit_cast(float2, v);
-    return cd{(double)f.x, (double)f.y};
   }
 }
 
@@ -368,16 +371,6 @@ __global__ __launch_bounds__(256) void k_hmv(const RowTask* __restrict__ tasks, 
 // the device).
 typedef double hmv_v4d __attribute__((ext_vector_type(4)));
 
-template <typename TS>
-__device__ __forceinline__ cd panel_entry(const void* A, size_t i) {
-  if constexpr (sizeof(TS) == 16) {
-    return ((const cd*)A)[i];
-  } else {
-    const cf v = ((const cf*)A)[i];
-    return cd{(double)v.x, (double)v.y};
-  }
-}
-
 // acc[tile] += panel(tile rows, columns of one segment) X(columns, 8) with
 // the x entries read directly (lane l: column l / 16, vector (l % 16) % 8);
 // the next step's four columns are loaded before this step's products.
@@ -386,17 +379,20 @@ __device__ __forceinline__ void seg_mfma(const void* A, int ld, int rows, int nc
                                          int lane, int w, hmv_v4d (&acc)[3]) {
   const int kr = lane >> 4, n = lane & 15;
   const cd* __restrict__ xq = src + (n & 7) * lds;
-  // columns past the segment and rows past the task read an in-bounds entry
-  // and are zeroed
+  // the panel through a buffer resource (vector memory counter only; its
+  // span is below 4 GiB, checked on the host); columns past the segment and
+  // rows past the task read an in-bounds entry and are zeroed
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)A, 0, (unsigned)(((size_t)(ncols - 1) * ld + rows) * sizeof(TS)), 0x00020000);
   auto load = [&](int c0, cd (&a)[3], cd& xv) {
     const int col = c0 + kr;
     const bool cv = col < ncols;
     const int cc = cv ? col : ncols - 1;
-    const size_t cb = (size_t)cc * ld;
+    const unsigned cb = (unsigned)cc * (unsigned)ld;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int row = 16 * (w + 4 * q) + n;
-      const cd v = panel_entry<TS>(A, cb + (row < rows ? row : rows - 1));
+      const cd v = panel_load<TS>(rs, (cb + (unsigned)(row < rows ? row : rows - 1)) * (unsigned)sizeof(TS));
       a[q] = (cv && row < rows) ? v : mk(0.0);
     }
     const cd xx = xq[cc];
