@@ -112,7 +112,71 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known "
                          "traffic that calibrates the HBM counters)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no run: summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "'bench.py --copy-probe ...' into profiles/hmatvec_traffic.json")
     return ap.parse_args()
+
+
+def _counter_means(d, counter):
+    """Mean per dispatch of one counter, per kernel name, from a rocprofv3
+    --pmc csv directory (the counter_collection file)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    acc = {}
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") != counter:
+                    continue
+                k = r["Kernel_Name"]
+                key = (k, r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+                acc.setdefault(k, {}).setdefault(key, 0.0)
+                acc[k][key] += float(r["Counter_Value"])  # summed over the counter's instances
+    return {k: (sum(v.values()) / len(v), len(v)) for k, v in acc.items()}
+
+
+def traffic_summary(fetch_dir, write_dir, out_path=None):
+    """HBM bytes of one single-vector matvec from the FETCH_SIZE and
+    WRITE_SIZE runs, each counter scaled by what it reads for the 1 GiB
+    device copy of --copy-probe; written with the hash of the matvec source
+    it was taken on."""
+    fe = _counter_means(fetch_dir, "FETCH_SIZE")
+    wr = _counter_means(write_dir, "WRITE_SIZE")
+
+    def pick(tab, pred):
+        ks = [k for k in tab if pred(k)]
+        if not ks:
+            raise SystemExit("kernel not found in the counters")
+        k = max(ks, key=lambda k: tab[k][1])  # the shape that ran most often
+        return k, tab[k][0], tab[k][1]
+
+    copy = lambda k: "copyBuffer" in k or "elementwise" in k.lower() or "copy" in k.lower()
+    ck, cf, _ = pick(fe, copy)
+    _, cw, _ = pick(wr, copy)
+    gib = float(1 << 30)
+    fscale, wscale = gib / (cf * 1024.0), gib / (cw * 1024.0)
+    out = {"source_sha256_16": _hash(os.path.join(ROOT, "paper_1212_3032_amd", "csrc", "hmatvec.hip")),
+           "copy_calibration": {"copy_kernel": ck, "copy_bytes": int(gib), "fetch_KiB_reported": cf,
+                                "write_KiB_reported": cw, "fetch_scale": fscale, "write_scale": wscale},
+           "kernels": {}}
+    total = 0.0
+    for name, pred in (("far_vt", lambda k: "k_far_vt<" in k and ", 1, " in k),
+                       ("hmv", lambda k: "k_hmv<1>" in k), ("reduce", lambda k: "k_hmv_reduce" in k)):
+        k, f, n = pick(fe, pred)
+        _, w, _ = pick(wr, pred)
+        b = (f * fscale + w * wscale) * 1024.0
+        total += b
+        out["kernels"][name] = {"kernel": k, "fetch_KiB": f, "write_KiB": w, "dispatches": n, "hbm_bytes": b}
+    out["hbm_bytes_per_matvec"] = total
+    p = out_path or os.path.join(ROOT, "profiles", "hmatvec_traffic.json")
+    with open(p, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+    return out
 
 
 def copy_probe():
@@ -218,6 +282,10 @@ def run_gpu(args, store, pipeline=0, guess=None, after=None):
     tot["u_last"] = u.cpu().numpy()  # the last timed transient (untimed copy)
     free, total = torch.cuda.mem_get_info()
     tot["device_memory_GB"] = (total - free) / 1e9  # the context, torch's buffers and the runtime
+    tot["library_memory_GB"] = {"total": info["lib_device_bytes"] / 1e9,  # the context's own buffers
+                                "far_work_areas": info["far_work_bytes"] / 1e9,
+                                "aca_scratch": info["aca_scratch_bytes"] / 1e9,
+                                "near_field": 16.0 * info["near_entries"] / 1e9}
     extra = after(ctx, d, u) if after is not None else None
     ctx.close()
     return d, N, elapsed, tot, extra
@@ -813,9 +881,11 @@ def cpu_baseline(args):
     N = 3 * g["ne"]
     t_lu = t_lu3 * (N / (3 * g3["ne"])) ** 3
     threads = 1
+    blas = []
     for info in threadpool_info():
         if info.get("user_api") == "blas":
             threads = max(threads, info.get("num_threads", 1))
+            blas.append(f"{info.get('internal_api')} {info.get('version')} ({info.get('architecture')})")
     return {
         "value": 1.0 / (t_asm + t_lu), "unit": "freq-solves/s", "cores": threads,
         "kind": "oracle",
@@ -823,6 +893,7 @@ def cpu_baseline(args):
                    f"(scaled to all rows: {t_asm:.0f} s) + LAPACK LU at N={3 * g3['ne']} in "
                    f"{t_lu3:.2f} s (scaled by N^3: {t_lu:.0f} s); extrapolated, one frequency"),
         "host_cpus": len(os.sched_getaffinity(0)),
+        "blas": "; ".join(blas) or "unknown",
     }
 
 
@@ -941,8 +1012,12 @@ def learned_leg(args, d4, held, plain):
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build uses one GPU; --gpus must be 1",
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (the split of the frequencies "
+                                   "over several GPUs is a design, not built)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "rod-table1":
@@ -1033,6 +1108,7 @@ def main():
         "resid_max": st["resid_max"],
         "stored_operator_GB": st["stored_bytes"] / 1e9,
         "device_memory_GB": st["device_memory_GB"],
+        "library_memory_GB": st["library_memory_GB"],
         "far_blocks": st["n_far"], "near_blocks": st["n_near"], "rank_max": st["rank_max"],
     }
     if not args.no_read_probe:

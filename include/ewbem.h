@@ -209,6 +209,14 @@ typedef struct {
   int32_t pad;
   double mv_tune_best_ms;    /* tuning: one matvec with the chosen shapes, and with the */
   double mv_tune_default_ms; /*   default ones (4, 4096), on the operator it ran on; 0 before */
+  int64_t lib_device_bytes;  /* device memory held by the library's buffers, summed over every
+                                context of the process (the allocation-free entry point's
+                                static array excluded) */
+  int64_t far_work_bytes;    /* of this context: the far factors' work areas (complex128 at
+                                their capacity, both slots and the retry buffers) and the
+                                complex64 store */
+  int64_t aca_scratch_bytes; /* of this context: the warm start's cross, substitution panels
+                                and norm partials, the ordinary steps' partials */
 } ewbem_info_t;
 
 /* Fill option structs with their defaults. */

@@ -28,6 +28,9 @@ using namespace ewbem;
 
 namespace {
 
+// device bytes held by the library's buffers, all contexts of the process
+std::atomic<long long> g_dev_bytes{0};
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
@@ -37,7 +40,10 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      g_dev_bytes -= (long long)(n * sizeof(T));
+    }
     p = nullptr;
     n = 0;
   }
@@ -49,6 +55,7 @@ struct DevBuf {
     if (cnt) {
       EWBEM_HIP_CHECK(hipMalloc((void**)&p, cnt * sizeof(T)));
       n = cnt;
+      g_dev_bytes += (long long)(n * sizeof(T));
     }
   }
   // for buffers that grow with the frequency (ranks, task lists): a quarter
@@ -2750,6 +2757,17 @@ int ewbem_info(ewbem_ctx* ctx, ewbem_info_t* info) {
     info->pad = 0;
     info->mv_tune_best_ms = ctx->mv_tuned ? ctx->mv_best_ms : 0.0;
     info->mv_tune_default_ms = ctx->mv_tuned ? ctx->mv_default_ms : 0.0;
+    info->lib_device_bytes = g_dev_bytes.load();
+    long long fw = 0;
+    for (int sl = 0; sl < 2; ++sl) {
+      fw += (long long)(ctx->d_wsf[sl].n * sizeof(cd));
+      for (const auto& r : ctx->d_retry[sl]) fw += (long long)(r->n * sizeof(cd));
+    }
+    fw += (long long)(ctx->d_f32.n * sizeof(cf));
+    for (const auto& ch : ctx->d_f32s) fw += (long long)(ch->n * sizeof(cf));
+    info->far_work_bytes = fw;
+    info->aca_scratch_bytes = (long long)(ctx->d_cross.n * sizeof(cd) + ctx->d_wscoef.n * sizeof(cd) +
+                                          ctx->d_wspart.n * sizeof(double) + ctx->d_aca_part.n * sizeof(double));
     return EWBEM_OK;
   });
 }

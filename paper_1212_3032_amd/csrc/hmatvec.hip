@@ -22,6 +22,27 @@ __device__ __forceinline__ double wsum64(double v) {
   return v;
 }
 
+// One entry of a panel through a buffer resource: counted by the vector
+// memory counter only (a flat load would also hold every wait on the scalar
+// x loads), and bounded by the resource's size.  POL is the load's cache
+// policy: 0, or CPOL_NT (the non-temporal hint for data read once: the
+// matvec's panels and phase-1 factor columns on the vector units, measured
+// 9% faster with it; the matrix-core products, which touch each line twice,
+// are slower with it).
+constexpr int CPOL_NT = 2;
+template <typename TS, int POL = 0>
+__device__ __forceinline__ cd panel_load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  if constexpr (sizeof(TS) == 16) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, POL);
+    const double2 d = __builtin_bit_cast(double2, v);
+    return cd{d.x, d.y};
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, POL);
+    const float2 f = __builtin_bit_cast(float2, v);
+    return cd{(double)f.x, (double)f.y};
+  }
+}
+
 // NR right-hand sides at once (columns of x, z, partial and y, strides ldx,
 // ldz, ldp, ldy): every factor and near-block entry is loaded once and
 // multiplied against the NR vectors.  Phase 1 takes NC factor columns per
@@ -54,13 +75,15 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
 #pragma unroll
       for (int q = 0; q < NR; ++q) a[k][q] = mk(0.0);
     // columns past ncol read column 0 again (in bounds) and are discarded
-    const TS* __restrict__ Vc[NCS];
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)V, 0, (unsigned)((size_t)nc * C * sizeof(TS)), 0x00020000);
+    unsigned Vc[NCS];
 #pragma unroll
-    for (int k = 0; k < NCS; ++k) Vc[k] = V + (size_t)(nc > k0 + k ? k0 + k : 0) * C;
+    for (int k = 0; k < NCS; ++k) Vc[k] = (unsigned)(nc > k0 + k ? k0 + k : 0) * (unsigned)C;
     for (int c = lane; c < C; c += 64) {
       cd v[NCS];
 #pragma unroll
-      for (int k = 0; k < NCS; ++k) v[k] = to_cd(Vc[k][c]);
+      for (int k = 0; k < NCS; ++k) v[k] = panel_load<TS, CPOL_NT>(rs, (Vc[k] + (unsigned)c) * (unsigned)sizeof(TS));
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
         const cd xv = xs[c + q * ldx];
@@ -86,22 +109,6 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
           if (nc > k0 + k) zz[k] = a[k][q];
       }
     }
-  }
-}
-
-// One entry of a panel through a buffer resource: counted by the vector
-// memory counter only (a flat load would also hold every wait on the scalar
-// x loads), and bounded by the resource's size.
-template <typename TS>
-__device__ __forceinline__ cd panel_load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
-  if constexpr (sizeof(TS) == 16) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-    const double2 d = __builtin_bit_cast(double2, v);
-    return cd{d.x, d.y};
-  } else {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-    const float2 f = __builtin_bit_cast(float2, v);
-    return cd{(double)f.x, (double)f.y};
   }
 }
 
@@ -260,7 +267,7 @@ __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __
     const unsigned offn = off + 4 * stride;
     const bool more = cn + 3 * G < ncols;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) nxt[i] = panel_load<TS>(rs, offn + i * stride);
+    for (int i = 0; i < 4; ++i) nxt[i] = panel_load<TS, CPOL_NT>(rs, offn + i * stride);
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       acc[q] += cur[0] * xv(c, q);
@@ -275,12 +282,12 @@ __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __
   if (c + 3 * G < ncols) {
     cd a[4], b[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = panel_load<TS>(rs, off + i * stride);
+    for (int i = 0; i < 4; ++i) a[i] = panel_load<TS, CPOL_NT>(rs, off + i * stride);
     while (step(a, b) && step(b, a)) {
     }
   }
   for (; c < ncols; c += G, off += stride) {
-    const cd a0 = panel_load<TS>(rs, off);
+    const cd a0 = panel_load<TS, CPOL_NT>(rs, off);
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] += a0 * xv(c, q);
   }

@@ -28,3 +28,31 @@ def test_workloads_parse():
             assert bench.parse().workload == w
     finally:
         sys.argv = saved
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path):
+    """The counter summary: per-dispatch means per kernel, each counter scaled
+    by what it reads for the 1 GiB copy (here FETCH_SIZE reports half)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    gib_kib = float(1 << 20)
+    rows = {"FETCH_SIZE": [("__amd_rocclr_copyBuffer", gib_kib / 2), ("void ewbem::k_far_vt<ewbem::cd, 1, 4>(x)", 100.0),
+                           ("void ewbem::k_far_vt<ewbem::cd, 1, 4>(x)", 300.0), ("void ewbem::k_hmv<1>(y)", 1000.0),
+                           ("ewbem::k_hmv_reduce(z)", 10.0)],
+            "WRITE_SIZE": [("__amd_rocclr_copyBuffer", gib_kib), ("void ewbem::k_far_vt<ewbem::cd, 1, 4>(x)", 4.0),
+                           ("void ewbem::k_hmv<1>(y)", 8.0), ("ewbem::k_hmv_reduce(z)", 2.0)]}
+    dirs = []
+    for c, rr in rows.items():
+        d = tmp_path / c
+        d.mkdir()
+        with open(d / "run_counter_collection.csv", "w") as f:
+            f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+            for i, (k, v) in enumerate(rr):
+                f.write(f'{i},"{k}",{c},{v}\n')
+        dirs.append(str(d))
+    out = bench.traffic_summary(dirs[0], dirs[1], str(tmp_path / "t.json"))
+    assert abs(out["copy_calibration"]["fetch_scale"] - 2.0) < 1e-12
+    assert abs(out["copy_calibration"]["write_scale"] - 1.0) < 1e-12
+    k = out["kernels"]
+    assert abs(k["far_vt"]["hbm_bytes"] - (200.0 * 2 + 4.0) * 1024) < 1e-6
+    assert abs(out["hbm_bytes_per_matvec"] - ((200 * 2 + 4) + (1000 * 2 + 8) + (10 * 2 + 2)) * 1024) < 1e-6

@@ -350,6 +350,33 @@ def test_warm_start_pivot_threshold(torch_dev, E, sub3_system):
     assert piv[-1] < piv[0]
 
 
+def test_memory_accounting(torch_dev, E, sub3_system):
+    """ewbem_info's device-memory figures: the library's buffers include the
+    far factors' work areas, which hold at least the stored far factors, and
+    the warm start's scratch; closing the context returns its buffers."""
+    torch, dev = torch_dev
+    d, _ = sub3_system
+    c = _ctx(E, d, op=dict(kind=E.OP_HMAT, leaf_size=64, eta_adm=1.0, aca_tol=1e-6),
+             solver=dict(tol=1e-10, guess=E.GUESS_ZERO))
+    for k in (30, 31):
+        st = c.assemble(k)
+    inf = c.info()
+    far_stored = st["stored_bytes"] - 16.0 * inf["near_entries"]
+    _say(f"library {inf['lib_device_bytes'] / 1e6:.1f} MB, far work {inf['far_work_bytes'] / 1e6:.1f} MB "
+         f"(stored far {far_stored / 1e6:.1f} MB), ACA scratch {inf['aca_scratch_bytes'] / 1e6:.1f} MB")
+    assert inf["far_work_bytes"] >= far_stored > 0
+    assert inf["aca_scratch_bytes"] > 0
+    assert inf["lib_device_bytes"] >= inf["far_work_bytes"] + inf["aca_scratch_bytes"] + 16 * inf["near_entries"]
+    held = inf["lib_device_bytes"]
+    probe = E.Context(0)
+    probe.set_mesh(d["xyz"], d["tri"], exterior=True)
+    c.close()
+    after = probe.info()["lib_device_bytes"]
+    probe.close()
+    _say(f"  after closing: {after / 1e6:.1f} MB")
+    assert after < held
+
+
 def test_hmatrix_warm_start(torch_dev, E, sub3_system):
     """ACA started from the previous frequency's pivots, over eleven
     consecutive frequencies (k = 30..40), against ACA from scratch at k = 40:
