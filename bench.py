@@ -136,7 +136,7 @@ def _counter_means(d, counter):
                 key = (k, r.get("Dispatch_Id", r.get("Correlation_Id", "")))
                 acc.setdefault(k, {}).setdefault(key, 0.0)
                 acc[k][key] += float(r["Counter_Value"])  # summed over the counter's instances
-    return {k: (sum(v.values()) / len(v), len(v)) for k, v in acc.items()}
+    return {k: list(v.values()) for k, v in acc.items()}
 
 
 def traffic_summary(fetch_dir, write_dir, out_path=None):
@@ -151,12 +151,21 @@ def traffic_summary(fetch_dir, write_dir, out_path=None):
         ks = [k for k in tab if pred(k)]
         if not ks:
             raise SystemExit("kernel not found in the counters")
-        k = max(ks, key=lambda k: tab[k][1])  # the shape that ran most often
-        return k, tab[k][0], tab[k][1]
+        k = max(ks, key=lambda k: len(tab[k]))  # the shape that ran most often
+        return k, sum(tab[k]) / len(tab[k]), len(tab[k])
 
-    copy = lambda k: "copyBuffer" in k or "elementwise" in k.lower() or "copy" in k.lower()
-    ck, cf, _ = pick(fe, copy)
-    _, cw, _ = pick(wr, copy)
+    def pick_copy(tab):
+        # the 1 GiB copies: the largest dispatches of the runtime's copy kernel
+        # (it also serves the run's small copies)
+        ks = [k for k in tab if "copy" in k.lower()]
+        if not ks:
+            raise SystemExit("copy kernel not found in the counters")
+        k = max(ks, key=lambda k: max(tab[k]))
+        big = [v for v in tab[k] if v >= 0.5 * max(tab[k])]
+        return k, sum(big) / len(big)
+
+    ck, cf = pick_copy(fe)
+    _, cw = pick_copy(wr)
     gib = float(1 << 30)
     fscale, wscale = gib / (cf * 1024.0), gib / (cw * 1024.0)
     out = {"source_sha256_16": _hash(os.path.join(ROOT, "paper_1212_3032_amd", "csrc", "hmatvec.hip")),
