@@ -26,9 +26,9 @@ __device__ __forceinline__ double wsum64(double v) {
 // memory counter only (a flat load would also hold every wait on the scalar
 // x loads), and bounded by the resource's size.  POL is the load's cache
 // policy: 0, or CPOL_NT (the non-temporal hint for data read once: the
-// matvec's panels and phase-1 factor columns on the vector units, measured
-// 9% faster with it; the matrix-core products, which touch each line twice,
-// are slower with it).
+// matvec's complex128 panels and phase-1 factor columns on the vector units,
+// measured 9% faster with it; complex64 panels measured 1% slower, and the
+// matrix-core products, which touch each line twice, 6% slower).
 constexpr int CPOL_NT = 2;
 template <typename TS, int POL = 0>
 __device__ __forceinline__ cd panel_load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_far_vt(const VtTask* __restrict__ tasks
     for (int c = lane; c < C; c += 64) {
       cd v[NCS];
 #pragma unroll
-      for (int k = 0; k < NCS; ++k) v[k] = panel_load<TS, CPOL_NT>(rs, (Vc[k] + (unsigned)c) * (unsigned)sizeof(TS));
+      for (int k = 0; k < NCS; ++k) v[k] = panel_load<TS, sizeof(TS) == 16 ? CPOL_NT : 0>(rs, (Vc[k] + (unsigned)c) * (unsigned)sizeof(TS));
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
         const cd xv = xs[c + q * ldx];
@@ -267,7 +267,7 @@ __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __
     const unsigned offn = off + 4 * stride;
     const bool more = cn + 3 * G < ncols;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) nxt[i] = panel_load<TS, CPOL_NT>(rs, offn + i * stride);
+    for (int i = 0; i < 4; ++i) nxt[i] = panel_load<TS, sizeof(TS) == 16 ? CPOL_NT : 0>(rs, offn + i * stride);
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       acc[q] += cur[0] * xv(c, q);
@@ -282,12 +282,12 @@ __device__ __forceinline__ void panel_dot(const TS* __restrict__ A, const cd* __
   if (c + 3 * G < ncols) {
     cd a[4], b[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = panel_load<TS, CPOL_NT>(rs, off + i * stride);
+    for (int i = 0; i < 4; ++i) a[i] = panel_load<TS, sizeof(TS) == 16 ? CPOL_NT : 0>(rs, off + i * stride);
     while (step(a, b) && step(b, a)) {
     }
   }
   for (; c < ncols; c += G, off += stride) {
-    const cd a0 = panel_load<TS, CPOL_NT>(rs, off);
+    const cd a0 = panel_load<TS, sizeof(TS) == 16 ? CPOL_NT : 0>(rs, off);
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] += a0 * xv(c, q);
   }
