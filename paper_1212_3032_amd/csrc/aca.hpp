@@ -123,8 +123,8 @@ struct WsArgs {
   cd* cross;
   int* pq;
   int* rho;
-  double* part;
-  cd* coef;
+  double* part;        // per-task squared norms of the terms (pu, pv of each block)
+  cd* coef;            // substitution panels (co of each block)
   const int* lu_list;  // warm blocks by size class of W (n_lu[0..WS_NCLASS) entries)
   int n_lu[7];
   double stop2;        // the elimination stops at |pivot|^2 <= stop2 |first pivot|^2

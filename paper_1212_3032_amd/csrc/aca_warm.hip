@@ -10,22 +10,23 @@
 //                   column element);
 //   k_ws_eval_cols  A(:, J) into Cc, one thread per (listed column element,
 //                   row element);
-//   k_ws_lu*        one workgroup per block: W = A(I, J), Gaussian
-//                   elimination with complete pivoting, stopping at the
-//                   first pivot below a set fraction of the first one's
-//                   modulus (ewbem_op_opts.ws_pivot_rel, by default the ACA
+//   k_ws_lu_reg,    one workgroup per block: W = A(I, J), Gaussian
+//   k_ws_lu         elimination with complete pivoting (cores of at most
+//                   128 x 128 in registers, larger ones in LDS or global
+//                   memory), stopping at the first pivot below a set
+//                   fraction of the first one's modulus
+//                   (ewbem_op_opts.ws_pivot_rel, by default the ACA
 //                   tolerance: a term's norm is at least its pivot's
 //                   modulus, so later terms rarely pass the stopping test);
 //                   the pivot order (p_t, q_t) and the eliminated W;
-//                   It also writes the coefficients of the substitutions;
-//   k_ws_form_u     u_t = residual of column q_t: the forward substitution
-//                   Cc(:, q) = U M with M unit upper triangular,
-//                   M[l][t] = W[p_l][q_t] / W[p_l][q_l]; column norms, and
-//                   the next row element (largest entry of the last term
-//                   among unused rows);
-//   k_ws_form_v     v_t = residual of row p_t over its pivot: the forward
-//                   substitution Rr(p, :) = N V^T with N[t][l] = W[p_t][q_l]
-//                   (l <= t);
+//   k_ws_panels     per chunk of 16 terms, the panels of the substitutions
+//                   U = C_Q M^{-1} (M unit upper triangular,
+//                   M[l][t] = W[p_l][q_t] / W[p_l][q_l]) and
+//                   V = R_P^T N^{-T} (N^T[l][t] = W[p_t][q_l], l <= t);
+//   k_ws_form_mfma  the terms u_t (residual of column q_t) and v_t (residual
+//                   of row p_t over its pivot) as chunked products on the
+//                   matrix cores; column norms, and the next row element
+//                   (largest entry of the last term among unused rows);
 //   k_ws_finish     the terms up to the first that meets the stopping test,
 //                   the norm estimate sum_t |u_t|^2 |v_t|^2, the lists cut to
 //                   the kept pivots' elements, and the next row, so the
