@@ -112,9 +112,10 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a kernel of known "
                          "traffic that calibrates the HBM counters)")
-    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "RUN_LOG"),
                     help="no run: summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
-                         "'bench.py --copy-probe ...' into profiles/hmatvec_traffic.json")
+                         "'bench.py --copy-probe ...' into profiles/hmatvec_traffic.json, with the "
+                         "algorithmic bytes from the bench line in the FETCH_SIZE run's output (RUN_LOG)")
     return ap.parse_args()
 
 
@@ -139,11 +140,22 @@ def _counter_means(d, counter):
     return {k: list(v.values()) for k, v in acc.items()}
 
 
-def traffic_summary(fetch_dir, write_dir, out_path=None):
+def _run_algorithmic_bytes(log_path):
+    """algorithmic_bytes_per_launch of the bench line in a run's log."""
+    with open(log_path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{") and "algorithmic_bytes_per_launch" in line:
+                return json.loads(line)["roofline"]["algorithmic_bytes_per_launch"]
+    raise SystemExit(f"no bench line with algorithmic_bytes_per_launch in {log_path}")
+
+
+def traffic_summary(fetch_dir, write_dir, out_path=None, run_log=None):
     """HBM bytes of one single-vector matvec from the FETCH_SIZE and
     WRITE_SIZE runs, each counter scaled by what it reads for the 1 GiB
     device copy of --copy-probe; written with the hash of the matvec source
-    it was taken on."""
+    it was taken on and, from the counter run's own bench line (run_log),
+    the algorithmic bytes of the operator it applied."""
     fe = _counter_means(fetch_dir, "FETCH_SIZE")
     wr = _counter_means(write_dir, "WRITE_SIZE")
 
@@ -181,6 +193,8 @@ def traffic_summary(fetch_dir, write_dir, out_path=None):
         total += b
         out["kernels"][name] = {"kernel": k, "fetch_KiB": f, "write_KiB": w, "dispatches": n, "hbm_bytes": b}
     out["hbm_bytes_per_matvec"] = total
+    if run_log:
+        out["algorithmic_bytes_per_launch"] = _run_algorithmic_bytes(run_log)
     p = out_path or os.path.join(ROOT, "profiles", "hmatvec_traffic.json")
     with open(p, "w") as f:
         json.dump(out, f, indent=1)
@@ -223,15 +237,20 @@ def _hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(bytes_per_launch):
+def traffic_from_profiles(bytes_per_launch, path=None):
     """HBM bytes per matvec from the committed rocprofv3 counter summary, if
-    it was taken on the current matvec source (else None)."""
-    p = os.path.join(ROOT, "profiles", "hmatvec_traffic.json")
+    it was taken on the current matvec source and on an operator of the same
+    algorithmic bytes (within 0.5%; the ranks, hence the bytes, change with
+    the approximation), else None."""
+    p = path or os.path.join(ROOT, "profiles", "hmatvec_traffic.json")
     src = os.path.join(ROOT, "paper_1212_3032_amd", "csrc", "hmatvec.hip")
     try:
         with open(p) as f:
             t = json.load(f)
         if t.get("source_sha256_16") != _hash(src):
+            return None
+        alg = t.get("algorithmic_bytes_per_launch")
+        if alg is None or not abs(alg - bytes_per_launch) <= 0.005 * bytes_per_launch:
             return None
         return t["hbm_bytes_per_matvec"]
     except (OSError, KeyError, ValueError):
@@ -1022,7 +1041,8 @@ def learned_leg(args, d4, held, plain):
 def main():
     args = parse()
     if args.traffic_summary:
-        traffic_summary(*args.traffic_summary)
+        fetch_dir, write_dir, run_log = args.traffic_summary
+        traffic_summary(fetch_dir, write_dir, run_log=run_log)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: --gpus must be 1 (the split of the frequencies "

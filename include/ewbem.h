@@ -103,14 +103,18 @@ typedef struct {
                            ewbem_apply_multi) on the FP64 matrix cores, 0: on the vector units
                            (default 1).  The summation order differs, the results agree to
                            rounding. */
-  int32_t pad;
+  int32_t ws_keep;      /* warm start: 1 (default) keeps every term the core elimination
+                           formed, 0 only those up to the first that meets the ACA stopping
+                           test.  At least one ordinary step follows either way, with the
+                           usual stopping test, and adds what the new frequency needs; 0
+                           leaves it more to add (each step reads the block's factors), 1
+                           stores a few more terms. */
   double ws_pivot_rel;  /* warm start: the elimination of the cross's core A(I, J) stops at
                            the first pivot whose modulus is at most ws_pivot_rel times the
-                           first pivot's; in [0, 1), 0 (default) takes aca_tol.  A term's norm
-                           |u_t| |v_t| is at least its pivot's modulus, so the terms past this
-                           point rarely pass the stopping test that follows; a smaller value
-                           eliminates more of them, and the ordinary steps after the warm
-                           start add any that the new frequency needs. */
+                           first pivot's; in [0, 1), 0 (default) takes aca_tol.  With ws_keep
+                           1 this sets the warm start's rank: a smaller value keeps more
+                           terms, a larger one leaves more to the ordinary steps.  (A term's
+                           norm |u_t| |v_t| is at least its pivot's modulus.) */
 } ewbem_op_opts;
 
 typedef struct {
@@ -168,6 +172,10 @@ typedef struct {
   int64_t aca_warm_pivots;  /* pivots eliminated in the warm starts' cores, summed */
   int64_t aca_warm_kept;    /* of their terms, those kept up to the stopping test, summed */
   int64_t aca_retries;      /* far blocks approximated again with more capacity */
+  int64_t aca_steps;        /* lock steps of the ACA after the starts (each adds terms to
+                               every still-active block), summed */
+  int64_t aca_step_blocks;  /* active blocks summed over those steps */
+  int64_t aca_step_first;   /* blocks still active after their start (warm or cold), summed */
 } ewbem_stats;
 
 /* Training of the learned initial guess (ewbem_guess_train). */

@@ -128,6 +128,7 @@ struct WsArgs {
   const int* lu_list;  // warm blocks by size class of W (n_lu[0..WS_NCLASS) entries)
   int n_lu[7];
   double stop2;        // the elimination stops at |pivot|^2 <= stop2 |first pivot|^2
+  int keep_all;        // 1: keep every eliminated term, 0: up to the first meeting the stopping test
   unsigned long long* cnt;  // [0] += pivots eliminated, [1] += terms kept (zeroed by the caller)
 };
 constexpr int WS_LDS_TINY = 1024;   // entries of W held in LDS by the LDS classes (tiny: <= 64 rows)

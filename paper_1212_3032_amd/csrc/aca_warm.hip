@@ -802,8 +802,8 @@ __global__ __launch_bounds__(256) void k_ws_form_mfma(WsArgs A, const FarBlk* __
 // One wavefront per warm block.  The terms are taken in pivot order until
 // the stopping test of a cold step holds for one of them,
 // |u_t|^2 |v_t|^2 <= tol^2 sum_{l<=t} |u_l|^2 |v_l|^2 (that term is kept, as
-// a cold step keeps its last terms); the pivot lists shrink to the elements
-// of the kept pivots.  At least one ordinary step follows, on a row outside
+// a cold step keeps its last terms), or all of them with keep_all; the
+// pivot lists shrink to the elements of the kept pivots.  At least one ordinary step follows, on a row outside
 // the cross, so growth of the rank at the new frequency is still detected.
 __global__ __launch_bounds__(256) void k_ws_finish(WsArgs A, const FarBlk* __restrict__ blks,
                                                    AcaState* __restrict__ st, const unsigned* __restrict__ used,
@@ -838,7 +838,7 @@ __global__ __launch_bounds__(256) void k_ws_finish(WsArgs A, const FarBlk* __res
       const double y = __shfl_up(inc, off, 64);
       if (lane >= off) inc += y;
     }
-    const bool stop = t < rho && term <= tol * tol * (normS2 + inc);
+    const bool stop = !A.keep_all && t < rho && term <= tol * tol * (normS2 + inc);
     const unsigned long long bal = __ballot(stop);
     if (bal) {
       const int first = __ffsll((long long)bal) - 1;

@@ -644,9 +644,10 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     WsArgs A{c->d_wsb.p, nw, c->d_wsoff.p, c->d_wsoff.p + (nw + 1), c->d_wsoff.p + 2 * (nw + 1),
              c->d_wsoff.p + 3 * (nw + 1), (int)er, (int)ec, (int)tu, (int)tv, c->d_cross.p, c->d_wspq.p,
              c->d_wsrho.p, c->d_wspart.p, c->d_wscoef.p, c->d_wslu.p,
-             {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4], n_lu[5], n_lu[6]}, 0.0, nullptr};
+             {n_lu[0], n_lu[1], n_lu[2], n_lu[3], n_lu[4], n_lu[5], n_lu[6]}, 0.0, 0, nullptr};
     const double prel = c->op.ws_pivot_rel > 0 ? c->op.ws_pivot_rel : c->op.aca_tol;
     A.stop2 = prel * prel;
+    A.keep_all = c->op.ws_keep;
     c->d_wscnt.reserve(2);
     A.cnt = c->d_wscnt.p;
     EWBEM_HIP_CHECK(hipMemsetAsync(A.cnt, 0, 2 * sizeof(unsigned long long), st));
@@ -682,7 +683,10 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
       counted = true;
     }
     const int nact = tot[4];
+    if (it == 0) c->acc.aca_step_first += nact;
     if (nact == 0) break;
+    c->acc.aca_steps += 1;
+    c->acc.aca_step_blocks += nact;
     if (nact < 0 || nact > n || it > max_steps) fail(EWBEM_EINVAL, "internal: ACA active list out of range");
     EWBEM_HIP_CHECK(hipMemsetD32Async((hipDeviceptr_t)count, 0, 1, st));
     // the first step has the most active blocks, so the largest task counts
@@ -2470,7 +2474,7 @@ void ewbem_default_op_opts(ewbem_op_opts* o) {
   o->autotune = 1;
   o->aca_batch_mb = 0;
   o->mv_mfma = 1;
-  o->pad = 0;
+  o->ws_keep = 1;
   o->ws_pivot_rel = 0.0;
 }
 
@@ -2708,7 +2712,7 @@ int ewbem_set_operator(ewbem_ctx* ctx, const ewbem_op_opts* o) {
         (o->far_store != EWBEM_STORE_C128 && o->far_store != EWBEM_STORE_C64) || o->self_order < 4 ||
         o->self_order > MAX_SELF_ORDER || (o->aca_reuse != 0 && o->aca_reuse != 1) ||
         (o->autotune != 0 && o->autotune != 1) || (o->mv_mfma != 0 && o->mv_mfma != 1) || o->aca_batch_mb < 0 ||
-        !(o->ws_pivot_rel >= 0 && o->ws_pivot_rel < 1) ||
+        !(o->ws_pivot_rel >= 0 && o->ws_pivot_rel < 1) || (o->ws_keep != 0 && o->ws_keep != 1) ||
         (o->aca_batch_mb > 0 && (o->far_store != EWBEM_STORE_C64 || o->kind != EWBEM_OP_HMAT)))
       fail(EWBEM_EINVAL, "operator options out of range");
     ctx->op = *o;
@@ -3003,6 +3007,9 @@ int ewbem_batch_solve_transient(ewbem_ctx** ctxs, int32_t n, double** u_out, ewb
       a.aca_warm_pivots += b.aca_warm_pivots;
       a.aca_warm_kept += b.aca_warm_kept;
       a.aca_retries += b.aca_retries;
+      a.aca_steps += b.aca_steps;
+      a.aca_step_blocks += b.aca_step_blocks;
+      a.aca_step_first += b.aca_step_first;
       a.guess_learned += b.guess_learned;
     }
     *stats = a;
@@ -3518,6 +3525,9 @@ int ewbem_batch_solve_transient_lockstep(ewbem_ctx** ctxs, int32_t n, double** u
       a.aca_warm_pivots += b.aca_warm_pivots;
       a.aca_warm_kept += b.aca_warm_kept;
       a.aca_retries += b.aca_retries;
+      a.aca_steps += b.aca_steps;
+      a.aca_step_blocks += b.aca_step_blocks;
+      a.aca_step_first += b.aca_step_first;
       a.guess_learned += b.guess_learned;
     }
     *stats = a;

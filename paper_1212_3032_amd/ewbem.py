@@ -44,7 +44,7 @@ class OpOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("leaf_size", C.c_int32), ("eta_adm", C.c_double),
                 ("aca_tol", C.c_double), ("far_store", C.c_int32), ("self_order", C.c_int32),
                 ("aca_reuse", C.c_int32), ("autotune", C.c_int32), ("aca_batch_mb", C.c_int32),
-                ("mv_mfma", C.c_int32), ("pad", C.c_int32), ("ws_pivot_rel", C.c_double)]
+                ("mv_mfma", C.c_int32), ("ws_keep", C.c_int32), ("ws_pivot_rel", C.c_double)]
 
 
 class SolverOpts(C.Structure):
@@ -67,7 +67,8 @@ class Stats(C.Structure):
                 ("guess_learned", C.c_int64), ("pod_energy", C.c_double),
                 ("train_loss_first", C.c_double), ("train_loss_last", C.c_double),
                 ("aca_core_blocks", C.c_int64 * 7), ("aca_warm_pivots", C.c_int64),
-                ("aca_warm_kept", C.c_int64), ("aca_retries", C.c_int64)]
+                ("aca_warm_kept", C.c_int64), ("aca_retries", C.c_int64),
+                ("aca_steps", C.c_int64), ("aca_step_blocks", C.c_int64), ("aca_step_first", C.c_int64)]
 
     def as_dict(self):
         return {f: (list(getattr(self, f)) if f == "aca_core_blocks" else getattr(self, f))

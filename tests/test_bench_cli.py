@@ -52,9 +52,17 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
             for i, (k, v) in enumerate(rr):
                 f.write(f'{i},"{k}",{c},{v}\n')
         dirs.append(str(d))
-    out = bench.traffic_summary(dirs[0], dirs[1], str(tmp_path / "t.json"))
+    log = tmp_path / "run.log"
+    log.write_text("# a progress line\n" + json.dumps({"metric": "m", "roofline": {
+        "algorithmic_bytes_per_launch": 2000.0 * 1024}}) + "\n")
+    out = bench.traffic_summary(dirs[0], dirs[1], str(tmp_path / "t.json"), str(log))
     assert abs(out["copy_calibration"]["fetch_scale"] - 2.0) < 1e-12
     assert abs(out["copy_calibration"]["write_scale"] - 1.0) < 1e-12
     k = out["kernels"]
     assert abs(k["far_vt"]["hbm_bytes"] - (200.0 * 2 + 4.0) * 1024) < 1e-6
     assert abs(out["hbm_bytes_per_matvec"] - ((200 * 2 + 4) + (1000 * 2 + 8) + (10 * 2 + 2)) * 1024) < 1e-6
+    # reported only for the operator (algorithmic bytes) the counters were taken on
+    assert out["algorithmic_bytes_per_launch"] == 2000.0 * 1024
+    p = str(tmp_path / "t.json")
+    assert bench.traffic_from_profiles(2000.0 * 1024 * 1.004, p) == out["hbm_bytes_per_matvec"]
+    assert bench.traffic_from_profiles(2000.0 * 1024 * 1.02, p) is None
