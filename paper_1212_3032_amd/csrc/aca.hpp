@@ -149,7 +149,15 @@ constexpr int WS_LU_NR_LDS = 2;     // LDS classes hold cores of at most 128 row
 // 128 x 128).
 constexpr int WS_NCLASS = 7;
 constexpr int WS_REG_SMALL = 64, WS_REG_LARGE = 128;
-void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s);
+// A second stream for the core eliminations outside registers (cores over
+// 128 x 128 and the LDS classes: few, long workgroups), so that they overlap
+// the register classes; null runs everything on the caller's stream.
+struct WsSide {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;  // timing disabled
+};
+void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s,
+               const WsSide& side);
 
 // ---- H-matrix matvec
 // Phase 1 task: z[zidx + j] = sum_c V[c, j] x[x0 + c] for j < ncol, with V

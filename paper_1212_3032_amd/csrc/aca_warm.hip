@@ -896,7 +896,8 @@ __global__ __launch_bounds__(256) void k_ws_finish(WsArgs A, const FarBlk* __res
   st[w.blk] = s;
 }
 
-void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s) {
+void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParams& P, double tol, hipStream_t s,
+               const WsSide& side) {
   if (A.nwarm <= 0) return;
   hipLaunchKernelGGL(k_ws_init, dim3((A.nwarm + 255) / 256), dim3(256), 0, s, A.wb, A.nwarm, W.blks, W.st, W.used,
                      W.plist);
@@ -912,6 +913,15 @@ void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParam
   // eight, all in LDS, larger in global memory
   const int nt = 64 * WS_LU_NW, ntl = 64 * WS_LU_NW_LDS;
   const int* lst = A.lu_list;
+  // classes 0..4 on the side stream when there is one: it starts after the
+  // cross evaluation and the caller's stream waits for it before the panels
+  const bool fork = side.stream && A.n_lu[0] + A.n_lu[1] + A.n_lu[2] + A.n_lu[3] + A.n_lu[4] > 0;
+  const hipStream_t s0 = s;
+  if (fork) {
+    EWBEM_HIP_CHECK(hipEventRecord(side.fork, s0));
+    EWBEM_HIP_CHECK(hipStreamWaitEvent(side.stream, side.fork, 0));
+    s = side.stream;
+  }
   if (A.n_lu[0] > 0)
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_SMALL, WS_LU_NR_LDS, WS_LU_NW_LDS>), dim3(A.n_lu[0]), dim3(ntl), 0, s, A.wb,
                        lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
@@ -932,6 +942,10 @@ void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParam
     hipLaunchKernelGGL((k_ws_lu<WS_LDS_TINY, 1, 2>), dim3(A.n_lu[4]), dim3(128), 0, s, A.wb, lst, W.blks, W.plist,
                        A.cross, A.pq, A.rho, A.stop2);
   lst += A.n_lu[4];
+  if (fork) {
+    EWBEM_HIP_CHECK(hipEventRecord(side.join, s));
+    s = s0;
+  }
   // cores in registers: 4 x 16 columns of 64 rows, 8 x 16 columns of 128 rows
   if (A.n_lu[5] > 0)
     hipLaunchKernelGGL((k_ws_lu_reg<WS_REG_SMALL / 16, 16, 1>), dim3(A.n_lu[5]), dim3(WS_REG_SMALL / 16 * 64), 0,
@@ -940,6 +954,7 @@ void launch_ws(const WsArgs& A, const AcaWork& W, const DevGeom& g, const KParam
   if (A.n_lu[6] > 0)
     hipLaunchKernelGGL((k_ws_lu_reg<WS_REG_LARGE / 16, 16, 2>), dim3(A.n_lu[6]), dim3(WS_REG_LARGE / 16 * 64), 0,
                        s, A.wb, lst, W.blks, W.plist, A.cross, A.pq, A.rho, A.stop2);
+  if (fork) EWBEM_HIP_CHECK(hipStreamWaitEvent(s, side.join, 0));
   hipLaunchKernelGGL(k_ws_panels, dim3(A.nwarm), dim3(256), 0, s, A);
   hipLaunchKernelGGL((k_ws_form_mfma<true>), dim3((A.tot_tu + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used);
   hipLaunchKernelGGL((k_ws_form_mfma<false>), dim3((A.tot_tv + 3) / 4), dim3(256), 0, s, A, W.blks, W.st, W.used);

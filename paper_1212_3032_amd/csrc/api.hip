@@ -167,6 +167,7 @@ struct ewbem_ctx {
   DevBuf<cd> d_wsf[2];
   int fslot = 0;
   hipStream_t astream = nullptr;  // the overlapped ACA's stream (library-owned)
+  WsSide ws_side;                 // the warm start's second stream (library-owned)
   // one buffer per capacity-retry round of the current frequency; all stay
   // alive until the next frequency is assembled (blocks retried in an
   // earlier round keep pointing into their round's buffer)
@@ -268,6 +269,8 @@ KParams make_params(ewbem_ctx* c, cd s) {
   const double cs = std::sqrt(mu / rho), cp = std::sqrt((lam + 2.0 * mu) / rho);
   const double g = cs / cp;
   P.s = s;
+  const double s2 = s.x * s.x + s.y * s.y;
+  P.cs_over_s = s2 > 0.0 ? cd{cs * s.x / s2, -cs * s.y / s2} : mk(0.0);
   P.inv_cs = 1.0 / cs;
   P.gamma = g;
   P.g2 = g * g;
@@ -459,6 +462,11 @@ void ensure_device(ewbem_ctx* c) {
   }
   EWBEM_HIP_CHECK(hipSetDevice(c->device));
   if (!c->astream) EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&c->astream, hipStreamNonBlocking));
+  if (!c->ws_side.stream) {
+    EWBEM_HIP_CHECK(hipStreamCreateWithFlags(&c->ws_side.stream, hipStreamNonBlocking));
+    EWBEM_HIP_CHECK(hipEventCreateWithFlags(&c->ws_side.fork, hipEventDisableTiming));
+    EWBEM_HIP_CHECK(hipEventCreateWithFlags(&c->ws_side.join, hipEventDisableTiming));
+  }
   hipStream_t st = c->stream;
   const HostGeom& g = c->hg;
   c->d_cen.upload(g.cen, st);
@@ -651,7 +659,7 @@ void aca_lockstep(ewbem_ctx* c, const DevGeom& g, const std::vector<int>& ids, b
     c->d_wscnt.reserve(2);
     A.cnt = c->d_wscnt.p;
     EWBEM_HIP_CHECK(hipMemsetAsync(A.cnt, 0, 2 * sizeof(unsigned long long), st));
-    launch_ws(A, W0, g, c->P, c->op.aca_tol, st);
+    launch_ws(A, W0, g, c->P, c->op.aca_tol, st, c->ws_side);
     // read with the first step's synchronisation below
     EWBEM_HIP_CHECK(hipMemcpyAsync(ws_cnt, A.cnt, sizeof(ws_cnt), hipMemcpyDeviceToHost, st));
   }
@@ -2530,6 +2538,13 @@ void ewbem_destroy(ewbem_ctx* ctx) {
       (void)hipStreamSynchronize(ctx->astream);
       (void)hipStreamDestroy(ctx->astream);
       ctx->astream = nullptr;
+    }
+    if (ctx->ws_side.stream) {
+      (void)hipStreamSynchronize(ctx->ws_side.stream);
+      (void)hipStreamDestroy(ctx->ws_side.stream);
+      (void)hipEventDestroy(ctx->ws_side.fork);
+      (void)hipEventDestroy(ctx->ws_side.join);
+      ctx->ws_side = WsSide{};
     }
   }
   delete ctx;

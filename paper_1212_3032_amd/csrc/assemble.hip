@@ -273,9 +273,14 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
                                                    int nk, const double* __restrict__ t0,
                                                    const double* __restrict__ tau, cd* __restrict__ partial) {
   __shared__ double sq[RHS_TILE * 21], sw[RHS_TILE * 7], stt[RHS_TILE * 3], stau[INC ? RHS_TILE : 1];
+  __shared__ cd scs[RHS_NK];  // c_s / s_k of the pass: 1 / z_s = (c_s / s_k) / r
   const int ne = g.ne;
   const int kst = k0 + blockIdx.y * RHS_NK;          // first frequency of this pass
   const int nkc = min(RHS_NK, k0 + nk - kst);        // frequencies in this pass
+  if (!INC && threadIdx.x < RHS_NK) {  // read after the first barrier below
+    const double w = (kst + (int)threadIdx.x) * dw, d = sigma * sigma + w * w, csv = 1.0 / P.inv_cs;
+    scs[threadIdx.x] = d > 0.0 ? cd{csv * sigma / d, -csv * w / d} : mk(0.0);
+  }
   const int split = blockIdx.z, nsplit = gridDim.z;
   const int s0 = (int)((long long)ne * split / nsplit), s1 = (int)((long long)ne * (split + 1) / nsplit);
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -349,7 +354,10 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
               rphi = a1;
               rpsi = b1;
             } else {
-              const cd iz = cinv(z);
+              // without the plane wave, 1 / z_s = (c_s / s_k) / r by a product; with
+              // it the division (the products' extra registers would halve
+              // the occupancy of that variant)
+              const cd iz = INC ? cinv(z) : scs[j] * ir;
               const cd iz2 = iz * iz;
               const cd gi = iz * gam;
               rphi = ph * (1.0 + iz + iz2) - php * (gi + iz2);

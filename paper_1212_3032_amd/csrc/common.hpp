@@ -52,6 +52,8 @@ constexpr int MAX_SELF_ORDER = 32;
 // Everything a kernel evaluation needs at one Laplace parameter s.
 struct KParams {
   cd s;              // Laplace parameter sigma + i omega_k
+  cd cs_over_s;      // c_s / s, so that 1 / z_s = (c_s / s) / r (zero at s = 0,
+                     // where every |z| takes the series branch)
   double inv_cs;     // 1 / c_s
   double gamma;      // c_s / c_p
   double g2;         // gamma^2

@@ -26,10 +26,11 @@ struct Radial {
   cd rphi, rpsi, r2dphi, r2dpsi;
 };
 
-// r phi, r psi (and r^2 phi', r^2 psi' when DERIV) at distance r.  TAIL drops
-// the static n = 2 terms, leaving the part that stays bounded as r -> 0.
+// r phi, r psi (and r^2 phi', r^2 psi' when DERIV) at distance r, with
+// ir = 1 / r.  TAIL drops the static n = 2 terms, leaving the part that stays
+// bounded as r -> 0.  1 / z = (c_s / s) / r takes a product, not a division.
 template <bool TAIL, bool DERIV>
-__device__ __forceinline__ Radial radial(double r, const KParams& P) {
+__device__ __forceinline__ Radial radial(double r, double ir, const KParams& P) {
   const cd z = P.s * (r * P.inv_cs);
   Radial o;
   if (norm2(z) < P.series_z2) {
@@ -75,7 +76,7 @@ __device__ __forceinline__ Radial radial(double r, const KParams& P) {
   const double e2 = exp(-g * z.x);
   sincos(g * z.y, &sn, &cs);
   const cd ep = cd{e2 * cs, -e2 * sn};
-  const cd iz = cinv(z);
+  const cd iz = P.cs_over_s * ir;
   const cd iz2 = iz * iz;
   const cd gi = iz * g;  // gamma^2 / z_p
   const cd rphi = es * (1.0 + iz + iz2) - ep * (gi + iz2);
@@ -107,7 +108,7 @@ __device__ __forceinline__ void acc_T(const double* x, const double* y, const do
   const double ir = 1.0 / r;
   const double h[3] = {d0 * ir, d1 * ir, d2 * ir};
   const double drdn = h[0] * n[0] + h[1] * n[1] + h[2] * n[2];
-  const Radial R = radial<TAIL, true>(r, P);
+  const Radial R = radial<TAIL, true>(r, ir, P);
   const double ir2 = ir * ir;
   const cd psir = R.rpsi * ir2;
   const cd dphi = R.r2dphi * ir2;
@@ -136,7 +137,7 @@ __device__ __forceinline__ void acc_U(const double* x, const double* y, double w
   const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   const double ir = 1.0 / r;
   const double h[3] = {d0 * ir, d1 * ir, d2 * ir};
-  const Radial R = radial<TAIL, false>(r, P);
+  const Radial R = radial<TAIL, false>(r, ir, P);
   const double sc = w * P.inv4pimu * ir;
   const cd phi = R.rphi * sc;
   const cd psi = R.rpsi * sc;
@@ -159,7 +160,7 @@ __device__ __forceinline__ void acc_Ut(const double* x, const double* y, double 
   const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   const double ir = 1.0 / r;
   const double h0 = d0 * ir, h1 = d1 * ir, h2 = d2 * ir;
-  const Radial R = radial<false, false>(r, P);
+  const Radial R = radial<false, false>(r, ir, P);
   const double sc = w * P.inv4pimu * ir;
   const double ht = h0 * t[0] + h1 * t[1] + h2 * t[2];
   const cd phi = R.rphi * sc;
