@@ -62,9 +62,7 @@ __device__ __forceinline__ void A_elem(const double* x, int e, const DevGeom& g,
 #pragma unroll 1
     for (int q = 0; q < 7; ++q) acc_U<false>(x, g.qp + 21 * (size_t)e + 3 * q, -g.qw[7 * (size_t)e + q], P, T);
   } else {
-    const double* n = g.nrm + 3 * (size_t)e;
-#pragma unroll 1
-    for (int q = 0; q < 7; ++q) acc_T<false>(x, g.qp + 21 * (size_t)e + 3 * q, n, g.qw[7 * (size_t)e + q], P, T);
+    elem_T<false>(x, g.qp + 21 * (size_t)e, g.qw + 7 * (size_t)e, g.nrm + 3 * (size_t)e, P, T);
   }
 }
 
@@ -185,7 +183,7 @@ __global__ __launch_bounds__(1024) void k_aca_scan(const int* __restrict__ act, 
 
 // Row step, evaluation: one thread per (block, column element) writes the
 // 3 x 3 entries A(3a* + j, 3b + jj) into V[3b + jj, k + j].
-__global__ __launch_bounds__(256) void k_aca_row_eval(const int* __restrict__ act, int nact,
+__global__ __launch_bounds__(256, 4) void k_aca_row_eval(const int* __restrict__ act, int nact,
                                                       const int* __restrict__ offs_n,
                                                       const FarBlk* __restrict__ blks,
                                                       const AcaState* __restrict__ st, DevGeom g, KParams P) {
@@ -417,7 +415,7 @@ __global__ __launch_bounds__(64) void k_aca_pivot(const int* __restrict__ act, i
 
 // Column step, evaluation: one thread per (block, row element) writes
 // A(3a + ii, 3b* + jj) into U[3a + ii, k + jj].
-__global__ __launch_bounds__(256) void k_aca_col_eval(const int* __restrict__ act, int nact,
+__global__ __launch_bounds__(256, 4) void k_aca_col_eval(const int* __restrict__ act, int nact,
                                                       const int* __restrict__ offs_m,
                                                       const FarBlk* __restrict__ blks,
                                                       const AcaState* __restrict__ st, DevGeom g, KParams P) {

@@ -65,9 +65,7 @@ __device__ __forceinline__ void A_elem(const double* x, int e, const DevGeom& g,
 #pragma unroll 1
     for (int q = 0; q < 7; ++q) acc_U<false>(x, g.qp + 21 * (size_t)e + 3 * q, -g.qw[7 * (size_t)e + q], P, T);
   } else {
-    const double* n = g.nrm + 3 * (size_t)e;
-#pragma unroll 1
-    for (int q = 0; q < 7; ++q) acc_T<false>(x, g.qp + 21 * (size_t)e + 3 * q, n, g.qw[7 * (size_t)e + q], P, T);
+    elem_T<false>(x, g.qp + 21 * (size_t)e, g.qw + 7 * (size_t)e, g.nrm + 3 * (size_t)e, P, T);
   }
 }
 
@@ -129,7 +127,9 @@ __global__ void k_ws_init(const WsBlk* __restrict__ wb, int nwarm, const FarBlk*
 }
 
 // Rr[(3s + j), 3b + jj] = A(3 a_s + j, 3b + jj): thread per (block, s, b).
-__global__ __launch_bounds__(256) void k_ws_eval_rows(const WsBlk* __restrict__ wb, int nwarm,
+// At most 128 registers, four wavefronts per SIMD (a few bytes of the
+// quadrature loop's state spill; measured faster than three wavefronts).
+__global__ __launch_bounds__(256, 4) void k_ws_eval_rows(const WsBlk* __restrict__ wb, int nwarm,
                                                       const int* __restrict__ off, const FarBlk* __restrict__ blks,
                                                       const int* __restrict__ plist, cd* __restrict__ cross, DevGeom g,
                                                       KParams P) {
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_ws_eval_rows(const WsBlk* __restrict__ 
 }
 
 // Cc[3a + ii, (3s + jj)] = A(3a + ii, 3 b_s + jj): thread per (block, s, a).
-__global__ __launch_bounds__(256) void k_ws_eval_cols(const WsBlk* __restrict__ wb, int nwarm,
+__global__ __launch_bounds__(256, 4) void k_ws_eval_cols(const WsBlk* __restrict__ wb, int nwarm,
                                                       const int* __restrict__ off, const FarBlk* __restrict__ blks,
                                                       const int* __restrict__ plist, cd* __restrict__ cross, DevGeom g,
                                                       KParams P) {

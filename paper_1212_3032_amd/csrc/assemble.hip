@@ -170,8 +170,7 @@ __global__ __launch_bounds__(256) void k_near(const NearBlk* __restrict__ blks, 
 #pragma unroll
       for (int q = 0; q < 7; ++q) acc_U<false>(sx + 3 * a, sq + 21 * b + 3 * q, -sw[7 * b + q], P, T);
     } else {
-#pragma unroll
-      for (int q = 0; q < 7; ++q) acc_T<false>(sx + 3 * a, sq + 21 * b + 3 * q, sn + 3 * b, sw[7 * b + q], P, T);
+      elem_T<false>(sx + 3 * a, sq + 21 * b, sw + 7 * b, sn + 3 * b, P, T);
     }
     cd* out = D + B.off + (size_t)(3 * b) * ld + 3 * a;
 #pragma unroll
@@ -322,8 +321,8 @@ __global__ __launch_bounds__(256) void k_rhs_multi(DevGeom g, KParams P, double 
       for (int qq = 0; qq < 7; ++qq) {
         const double* y = sq + 21 * b + 3 * qq;
         const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
-        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double ir = 1.0 / r;
+        double r, ir;
+        dist_inv(d0 * d0 + d1 * d1 + d2 * d2, r, ir);
         const double h0 = d0 * ir, h1 = d1 * ir, h2 = d2 * ir;
         const double ht = h0 * tb[0] + h1 * tb[1] + h2 * tb[2];
         const double sc = sw[7 * b + qq] * P.inv4pimu * ir;
@@ -456,8 +455,8 @@ __global__ __launch_bounds__(256) void k_rhs_loads(DevGeom g, KParams P, double 
       for (int qq = 0; qq < 7; ++qq) {
         const double* y = sq + 21 * b + 3 * qq;
         const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
-        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double ir = 1.0 / r;
+        double r, ir;
+        dist_inv(d0 * d0 + d1 * d1 + d2 * d2, r, ir);
         const double h0 = d0 * ir, h1 = d1 * ir, h2 = d2 * ir;
         const double sc = sw[7 * b + qq] * P.inv4pimu * ir;
         const double zx = sigma * r * ics;

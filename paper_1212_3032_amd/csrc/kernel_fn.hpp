@@ -22,6 +22,22 @@
 
 namespace ewbem {
 
+// r = |d| and ir = 1 / r from d2 = |d|^2 > 0: the hardware reciprocal square
+// root (about single precision) refined by two Newton steps
+// y <- y + y (1 - d2 y^2) / 2, each squaring the relative error, then r = d2 y;
+// both to a few units in the last place, in fewer operations than a square
+// root and a division.
+__device__ __forceinline__ void dist_inv(double d2, double& r, double& ir) {
+  double y = __builtin_amdgcn_rsq(d2);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d2, y * y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  ir = y;
+  r = d2 * y;
+}
+
 struct Radial {
   cd rphi, rpsi, r2dphi, r2dpsi;
 };
@@ -99,34 +115,92 @@ __device__ __forceinline__ Radial radial(double r, double ir, const KParams& P) 
   return o;
 }
 
-// T[3i+j] += w * T_ij(x, y; n)
+// The coefficients of w T_ij(x, y; n) = A n_i h_j + B h_i h_j + C h_i n_j
+// + Ad delta_ij, with h the unit vector from x to y.
+struct TCoef {
+  double h[3];
+  cd A, B, C, Ad;
+};
+
 template <bool TAIL>
-__device__ __forceinline__ void acc_T(const double* x, const double* y, const double* n, double w,
-                                      const KParams& P, cd* T) {
+__device__ __forceinline__ TCoef t_coef(const double* x, const double* y, const double* n, double w,
+                                        const KParams& P) {
+  TCoef o;
   const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
-  const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-  const double ir = 1.0 / r;
-  const double h[3] = {d0 * ir, d1 * ir, d2 * ir};
-  const double drdn = h[0] * n[0] + h[1] * n[1] + h[2] * n[2];
+  double r, ir;
+  dist_inv(d0 * d0 + d1 * d1 + d2 * d2, r, ir);
+  o.h[0] = d0 * ir;
+  o.h[1] = d1 * ir;
+  o.h[2] = d2 * ir;
+  const double drdn = o.h[0] * n[0] + o.h[1] * n[1] + o.h[2] * n[2];
   const Radial R = radial<TAIL, true>(r, ir, P);
   const double ir2 = ir * ir;
   const cd psir = R.rpsi * ir2;
   const cd dphi = R.r2dphi * ir2;
   const cd dpsi = R.r2dpsi * ir2;
   const double sc = w * P.inv4pi;
-  const cd A = (dphi - psir) * sc;
-  const cd B = (2.0 * (2.0 * psir - dpsi)) * (sc * drdn);
-  const cd C = (P.ratio * (dphi - dpsi - 2.0 * psir) - 2.0 * (dphi - dpsi - psir)) * sc;
-  const cd Ad = A * drdn;
+  o.A = (dphi - psir) * sc;
+  o.B = (2.0 * (2.0 * psir - dpsi)) * (sc * drdn);
+  o.C = (P.ratio * (dphi - dpsi - 2.0 * psir) - 2.0 * (dphi - dpsi - psir)) * sc;
+  o.Ad = o.A * drdn;
+  return o;
+}
+
+// T[3i+j] += w * T_ij(x, y; n)
+template <bool TAIL>
+__device__ __forceinline__ void acc_T(const double* x, const double* y, const double* n, double w,
+                                      const KParams& P, cd* T) {
+  const TCoef c = t_coef<TAIL>(x, y, n, w, P);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      cd v = A * (n[i] * h[j]) + B * (h[i] * h[j]) + C * (h[i] * n[j]);
-      if (i == j) v += Ad;
+      cd v = c.A * (n[i] * c.h[j]) + c.B * (c.h[i] * c.h[j]) + c.C * (c.h[i] * n[j]);
+      if (i == j) v += c.Ad;
       T[3 * i + j] += v;
     }
   }
+}
+
+// T[3i+j] = sum_q w_q T_ij(x, y_q; n) over the seven points y_q (weights w_q)
+// of one element, whose normal n is shared: T = n a^T + S + c n^T with
+// a = sum A_q h_q, c = sum C_q h_q and the symmetric S = sum (B_q h_q h_q^T
+// + Ad_q I), so that a point costs 12 complex updates instead of 9 full
+// entries.  UNROLL: the points unrolled (more registers) or in a loop.
+template <bool UNROLL>
+__device__ __forceinline__ void elem_T(const double* x, const double* y, const double* w, const double* n,
+                                       const KParams& P, cd* T) {
+  cd a[3], c[3], S[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a[i] = c[i] = mk(0.0);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) S[i] = mk(0.0);
+  auto point = [&](int q) {
+    const TCoef k = t_coef<false>(x, y + 3 * q, n, w[q], P);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      a[i] += k.A * k.h[i];
+      c[i] += k.C * k.h[i];
+    }
+    S[0] += k.B * (k.h[0] * k.h[0]) + k.Ad;
+    S[1] += k.B * (k.h[0] * k.h[1]);
+    S[2] += k.B * (k.h[0] * k.h[2]);
+    S[3] += k.B * (k.h[1] * k.h[1]) + k.Ad;
+    S[4] += k.B * (k.h[1] * k.h[2]);
+    S[5] += k.B * (k.h[2] * k.h[2]) + k.Ad;
+  };
+  if (UNROLL) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) point(q);
+  } else {
+#pragma unroll 1
+    for (int q = 0; q < 7; ++q) point(q);
+  }
+  constexpr int si[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = a[j] * n[i] + S[si[i][j]] + c[i] * n[j];
 }
 
 // U[3i+j] += w * U_ij(x, y)   (only the 6 distinct entries are formed)
@@ -134,8 +208,8 @@ template <bool TAIL>
 __device__ __forceinline__ void acc_U(const double* x, const double* y, double w,
                                       const KParams& P, cd* U) {
   const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
-  const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-  const double ir = 1.0 / r;
+  double r, ir;
+  dist_inv(d0 * d0 + d1 * d1 + d2 * d2, r, ir);
   const double h[3] = {d0 * ir, d1 * ir, d2 * ir};
   const Radial R = radial<TAIL, false>(r, ir, P);
   const double sc = w * P.inv4pimu * ir;
@@ -157,8 +231,8 @@ __device__ __forceinline__ void acc_U(const double* x, const double* y, double w
 __device__ __forceinline__ void acc_Ut(const double* x, const double* y, double w, const double* t,
                                        const KParams& P, cd* u) {
   const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
-  const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-  const double ir = 1.0 / r;
+  double r, ir;
+  dist_inv(d0 * d0 + d1 * d1 + d2 * d2, r, ir);
   const double h0 = d0 * ir, h1 = d1 * ir, h2 = d2 * ir;
   const Radial R = radial<false, false>(r, ir, P);
   const double sc = w * P.inv4pimu * ir;
