@@ -5,7 +5,9 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <exception>
 #include <functional>
 #include <thread>
@@ -30,6 +32,16 @@ namespace {
 
 // device bytes held by the library's buffers, all contexts of the process
 std::atomic<long long> g_dev_bytes{0};
+
+// Debugging aid: with EWBEM_POISON_ALLOC set in the environment, every new
+// floating-point buffer starts as all-ones bytes (NaN), so a kernel that
+// reads device memory no kernel wrote shows NaN in its results instead of
+// whatever the allocation held.  Integer buffers are left alone (an index
+// read unwritten could point anywhere).
+bool poison_alloc() {
+  static const bool on = std::getenv("EWBEM_POISON_ALLOC") != nullptr;
+  return on;
+}
 
 template <typename T>
 struct DevBuf {
@@ -56,6 +68,11 @@ struct DevBuf {
       EWBEM_HIP_CHECK(hipMalloc((void**)&p, cnt * sizeof(T)));
       n = cnt;
       g_dev_bytes += (long long)(n * sizeof(T));
+      if (std::is_floating_point<T>::value || std::is_same<T, cd>::value || std::is_same<T, cf>::value)
+        if (poison_alloc()) {
+          EWBEM_HIP_CHECK(hipMemset(p, 0xff, cnt * sizeof(T)));
+          EWBEM_HIP_CHECK(hipDeviceSynchronize());
+        }
     }
   }
   // for buffers that grow with the frequency (ranks, task lists): a quarter
@@ -1740,7 +1757,9 @@ void sem_guess(ewbem_ctx* c, cd* x, cd* r, const cd* extra = nullptr) {
     cy[kept[i]] = v;
   }
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p, cx.data(), ncap * sizeof(cd), hipMemcpyHostToDevice, st));
-  launch_gemv_acc(c->d_hist_sol.p, N, ncap, c->d_small.p, cd{0.0, 0.0}, x, N, st);
+  // only the slots written so far (0..hist_n): the others hold whatever the
+  // allocation held, and a zero coefficient times a NaN there is NaN
+  launch_gemv_acc(c->d_hist_sol.p, N, c->hist_n, c->d_small.p, cd{0.0, 0.0}, x, N, st);
   if (extra) launch_axpby(cext, extra, cd{1.0, 0.0}, x, N, st);
   EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p + ncap, cy.data(), Kt * sizeof(cd), hipMemcpyHostToDevice, st));
   launch_gemv_sub(Y, N, Kt, c->d_small.p + ncap, r, N, st);
@@ -1870,7 +1889,7 @@ void guess_k(ewbem_ctx* c, int k, const ewbem_z* x0) {
     std::vector<cd> cx(ncap, cd{0, 0});
     for (int j = 0; j < K; ++j) cx[c->hist_slot[j]] = cd{coef[K][j], 0};
     EWBEM_HIP_CHECK(hipMemcpyAsync(c->d_small.p, cx.data(), ncap * sizeof(cd), hipMemcpyHostToDevice, st));
-    launch_gemv_acc(c->d_hist_sol.p, N, ncap, c->d_small.p, cd{0, 0}, c->d_x.p, N, st);
+    launch_gemv_acc(c->d_hist_sol.p, N, c->hist_n, c->d_small.p, cd{0, 0}, c->d_x.p, N, st);  // written slots only
     apply_tree(c, c->d_x.p, c->d_r.p, &ev);
     launch_axpby(cd{1, 0}, c->d_b.p, cd{-1, 0}, c->d_r.p, N, st);
     EWBEM_HIP_CHECK(hipStreamSynchronize(st));
