@@ -554,6 +554,7 @@ __global__ __launch_bounds__(64 * NW) void k_ws_lu_reg(const WsBlk* __restrict__
 __global__ __launch_bounds__(256) void k_ws_panels(WsArgs A) {
   __shared__ cd Sd[2][16][16];  // S[T_k, T_k] of each side
   __shared__ cd Dk[2][16][16];  // its inverse
+  __shared__ cd sInv[16];       // 1 / W[p_t][q_t] of the chunk's terms
   __shared__ int sP[3 * WS_MAXLIST], sQ[3 * WS_MAXLIST];
   const int i = blockIdx.x;
   const WsBlk w = A.wb[i];
@@ -574,6 +575,10 @@ __global__ __launch_bounds__(256) void k_ws_panels(WsArgs A) {
   const int nk = (rho + 15) / 16;
   for (int k = 0; k < nk; ++k) {
     const int t0 = 16 * k;
+    // the chunk's pivot inverses, once each (the diagonal of S_1, and the row
+    // scales of S_0), so that no division sits in the serial substitution below
+    if (tid < 16) sInv[tid] = t0 + tid < rho ? cinv(Wlt(t0 + tid, t0 + tid)) : mk(1.0);
+    __syncthreads();
     // the diagonal blocks: S_0[j][l] = M = W[p_j][q_l] / W[p_j][q_j],
     // S_1[j][l] = N^T = W[p_l][q_j] (j <= l; zero elsewhere and past rho)
     for (int e = tid; e < 512; e += nt) {
@@ -581,7 +586,7 @@ __global__ __launch_bounds__(256) void k_ws_panels(WsArgs A) {
       cd v = mk(0.0);
       if (j <= l && t0 + l < rho) {
         if (side == 0)
-          v = j == l ? mk(1.0) : Wlt(t0 + j, t0 + l) * cinv(Wlt(t0 + j, t0 + j));
+          v = j == l ? mk(1.0) : Wlt(t0 + j, t0 + l) * sInv[j];
         else
           v = Wlt(t0 + l, t0 + j);
       }
@@ -590,14 +595,15 @@ __global__ __launch_bounds__(256) void k_ws_panels(WsArgs A) {
     }
     __syncthreads();
     // column c of D_k: back substitution S[T_k, T_k] x = e_c, one thread each
+    // (the diagonal of S_0 is one, that of S_1 the pivots)
     if (tid < 32) {
       const int side = tid >> 4, c = tid & 15;
       if (t0 + c < rho) {
-        Dk[side][c][c] = cinv(Sd[side][c][c]);
+        Dk[side][c][c] = side == 0 ? mk(1.0) : sInv[c];
         for (int j = c - 1; j >= 0; --j) {
           cd acc = mk(0.0);
           for (int l = j + 1; l <= c; ++l) acc += Sd[side][j][l] * Dk[side][l][c];
-          Dk[side][j][c] = -(acc * cinv(Sd[side][j][j]));
+          Dk[side][j][c] = -(side == 0 ? acc : acc * sInv[j]);
         }
       }
     }
@@ -858,14 +864,33 @@ __global__ __launch_bounds__(256) void k_ws_finish(WsArgs A, const FarBlk* __res
     kc[Qp[t] / 3] = 1;
   }
   wave_sync();
-  if (lane != 0) return;
+  // the lists compacted by the whole wavefront: every entry read first (and
+  // waited for), then each kept one stored at its rank among the kept
   int* rl = plist + B.poff;
   int* cl = plist + B.poff + B.m;
+  constexpr int NQ = (WS_MAXLIST + 63) / 64;
+  int rv[NQ], cv[NQ];
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    const int q = lane + 64 * u;
+    rv[u] = q < w.nr ? rl[q] : 0;
+    cv[u] = q < w.nc ? cl[q] : 0;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  wave_sync();
   int nr = 0, nc = 0;
-  for (int q = 0; q < w.nr; ++q)
-    if (kr[q]) rl[nr++] = rl[q];
-  for (int q = 0; q < w.nc; ++q)
-    if (kc[q]) cl[nc++] = cl[q];
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    const int q = lane + 64 * u;
+    const bool kr_ = q < w.nr && kr[q], kc_ = q < w.nc && kc[q];
+    const unsigned long long br = __ballot(kr_), bc = __ballot(kc_);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (kr_) rl[nr + __popcll(br & below)] = rv[u];
+    if (kc_) cl[nc + __popcll(bc & below)] = cv[u];
+    nr += __popcll(br);
+    nc += __popcll(bc);
+  }
+  if (lane != 0) return;
   nlist[2 * w.blk] = nr;
   nlist[2 * w.blk + 1] = nc;
   atomicAdd(&A.cnt[0], (unsigned long long)rho);
