@@ -214,7 +214,9 @@ typedef struct {
   int32_t mv_cols;         /* matvec shapes in use: factor columns per phase-1 wavefront */
   int32_t mv_task_div;     /*   phase-2 task size = all panel columns / mv_task_div (>= 96) */
   int32_t mv_tuned;        /*   1 once chosen by timing (ewbem_op_opts.autotune) */
-  int32_t pad;
+  int32_t mv_tune_cached;  /*   1 when taken from an earlier context of the process on the
+                                same device and partition (unknowns, block counts and sizes,
+                                factor storage), which timed them: tuned once per problem */
   double mv_tune_best_ms;    /* tuning: one matvec with the chosen shapes, and with the */
   double mv_tune_default_ms; /*   default ones (4, 4096), on the operator it ran on; 0 before */
   int64_t lib_device_bytes;  /* device memory held by the library's buffers, summed over every

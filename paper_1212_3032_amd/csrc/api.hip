@@ -11,7 +11,9 @@
 #include <exception>
 #include <functional>
 #include <thread>
+#include <tuple>
 #include <atomic>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -234,6 +236,7 @@ struct ewbem_ctx {
   // the first assembled operator when op.autotune is set
   int mv_cols = 4, mv_div = 4096, vt_cols = 4;
   bool mv_tuned = false;
+  bool mv_tune_cached = false;  // shapes from an earlier context's tuning
   double mv_best_ms = 0, mv_default_ms = 0;  // tuning: fastest and default shapes' matvec time
   DevBuf<cd> d_z, d_hpart, d_mvpart;
   long long z_len = 0, mvpart_len = 0;  // one right-hand side's share of d_z, d_mvpart
@@ -373,6 +376,7 @@ void ensure_structure(ewbem_ctx* c) {
   c->kcap_prev.assign(c->far_h.size(), 0);
   c->plist_ok = false;
   c->mv_tuned = false;
+  c->mv_tune_cached = false;
   c->mv_cols = 4;
   c->mv_div = 4096;
   c->rank_h.assign(c->far_h.size(), 0);
@@ -1285,9 +1289,42 @@ void rhs_finish_k(ewbem_ctx* c, int k) {
 // counts and phase-2 task sizes is built and timed (one warm apply, then
 // three timed) on the operator just assembled; the fastest is kept for the
 // rest of the context's life (until the partition changes).
+// Shapes tuned in this process, by device and partition: the candidates cut
+// the same bytes in different ways, so contexts of one problem (a batch, the
+// loads of a training set, a repeated bench) share the first one's timing.
+struct TunedShapes {
+  int cols, div;
+  double best_ms, default_ms;
+};
+using TuneKey = std::tuple<int, long long, long long, long long, long long, long long, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, TunedShapes> g_tuned;
+
+TuneKey tune_key(const ewbem_ctx* c) {
+  long long far_rows = 0;
+  for (const FarBlk& f : c->far_h) far_rows += (long long)f.m + f.n;
+  return TuneKey{c->device, (long long)c->nt, (long long)c->near_h.size(), (long long)c->far_h.size(),
+                 c->near_entries, far_rows, c->op.far_store};
+}
+
 void tune_matvec(ewbem_ctx* c) {
   static const int kCols[] = {2, 4, 8};
   static const int kDivs[] = {2048, 4096, 8192};
+  const TuneKey key = tune_key(c);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      c->mv_cols = it->second.cols;
+      c->mv_div = it->second.div;
+      c->mv_best_ms = it->second.best_ms;
+      c->mv_default_ms = it->second.default_ms;
+      c->mv_tuned = true;
+      c->mv_tune_cached = true;
+      build_matvec(c);
+      return;
+    }
+  }
   hipStream_t st = c->stream;
   const long long N = 3LL * c->nt;
   {
@@ -1331,8 +1368,11 @@ void tune_matvec(ewbem_ctx* c) {
   c->mv_cols = bc;
   c->mv_div = bd;
   c->mv_tuned = true;
+  c->mv_tune_cached = false;
   c->mv_best_ms = best;
   build_matvec(c);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = TunedShapes{bc, bd, best, c->mv_default_ms};
 }
 
 // Operator, right-hand side and preconditioner of frequency k.  aca_done:
@@ -2792,7 +2832,7 @@ int ewbem_info(ewbem_ctx* ctx, ewbem_info_t* info) {
     info->mv_cols = ctx->mv_cols;
     info->mv_task_div = ctx->mv_div;
     info->mv_tuned = ctx->mv_tuned ? 1 : 0;
-    info->pad = 0;
+    info->mv_tune_cached = ctx->mv_tuned && ctx->mv_tune_cached ? 1 : 0;
     info->mv_tune_best_ms = ctx->mv_tuned ? ctx->mv_best_ms : 0.0;
     info->mv_tune_default_ms = ctx->mv_tuned ? ctx->mv_default_ms : 0.0;
     info->lib_device_bytes = g_dev_bytes.load();

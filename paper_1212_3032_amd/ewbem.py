@@ -88,7 +88,7 @@ class Info(C.Structure):
                 ("n_leaves", C.c_int64), ("n_near", C.c_int64), ("n_far", C.c_int64),
                 ("near_entries", C.c_int64), ("max_leaf", C.c_int32), ("min_leaf", C.c_int32),
                 ("mv_cols", C.c_int32), ("mv_task_div", C.c_int32), ("mv_tuned", C.c_int32),
-                ("pad", C.c_int32), ("mv_tune_best_ms", C.c_double), ("mv_tune_default_ms", C.c_double),
+                ("mv_tune_cached", C.c_int32), ("mv_tune_best_ms", C.c_double), ("mv_tune_default_ms", C.c_double),
                 ("lib_device_bytes", C.c_int64), ("far_work_bytes", C.c_int64),
                 ("aca_scratch_bytes", C.c_int64)]
 

@@ -1,7 +1,9 @@
 """The matvec's task shapes chosen by timing (ewbem_op_opts.autotune) change
 only the summation order: the tuned and the default operator give the same
 products (1e-13 relative; the library itself also checks every candidate
-against the first, 1e-12) and the same solutions."""
+against the first, 1e-12) and the same solutions.  They are timed once per
+device and partition in a process; later contexts of the same problem reuse
+them."""
 
 import sys
 
@@ -51,5 +53,28 @@ def test_tuned_shapes_give_the_same_operator(sub):
     a.solve_frequency(6, sa)
     b.solve_frequency(6, sb)
     assert float(torch.linalg.norm(sa - sb) / torch.linalg.norm(sb)) < 1e-9
+    a.close()
+    b.close()
+
+
+def test_shapes_tuned_once_per_partition():
+    """A second context of the same problem takes the shapes the first one
+    timed (ewbem_info.mv_tune_cached), without timing them again."""
+    import time
+    from paper_1212_3032_amd import ewbem as E
+    xyz, tri = icosphere(3)
+    a = _ctx(E, xyz, tri, 1)
+    a.assemble(5)
+    b = _ctx(E, xyz, tri, 1)
+    t0 = time.perf_counter()
+    b.assemble(5)
+    tb = time.perf_counter() - t0
+    ia, ib = a.info(), b.info()
+    print(f"first context: cols {ia['mv_cols']} div {ia['mv_task_div']} cached {ia['mv_tune_cached']}; "
+          f"second: cols {ib['mv_cols']} div {ib['mv_task_div']} cached {ib['mv_tune_cached']} "
+          f"(assembly {tb * 1e3:.0f} ms)", flush=True)
+    assert ia["mv_tuned"] == 1 and ib["mv_tuned"] == 1 and ib["mv_tune_cached"] == 1
+    assert (ib["mv_cols"], ib["mv_task_div"]) == (ia["mv_cols"], ia["mv_task_div"])
+    assert ib["mv_tune_best_ms"] == ia["mv_tune_best_ms"]
     a.close()
     b.close()
