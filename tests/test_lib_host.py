@@ -28,6 +28,8 @@ def test_defaults():
     assert (o.kind, o.leaf_size, o.eta_adm, o.aca_tol) == (ewbem.OP_HMAT, 64, 1.0, 1e-5)
     # the fields after the doubles sit where the C struct has them
     assert (o.far_store, o.self_order, o.aca_reuse, o.autotune) == (ewbem.STORE_C128, 24, 1, 1)
+    # the warm start keeps every term it eliminates, down to the ACA tolerance
+    assert (o.mv_mfma, o.ws_keep, o.ws_pivot_rel) == (1, 1, 0.0)
     s = ewbem.default_solver_opts()
     assert (s.tol, s.restart, s.guess, s.sem_k, s.pipeline) == (1e-6, 100, ewbem.GUESS_SEM, 3, 0)
 
@@ -98,6 +100,11 @@ def test_input_validation():
         c.set_operator(leaf_size=65)
     with pytest.raises(ewbem.EwbemError):
         c.set_operator(aca_reuse=2)
+    with pytest.raises(ewbem.EwbemError):
+        c.set_operator(ws_keep=2)
+    with pytest.raises(ewbem.EwbemError):
+        c.set_operator(ws_pivot_rel=1.0)
+    c.set_operator(ws_keep=0, ws_pivot_rel=1e-6)
     c.set_mesh(xyz, tri)
     c.set_time(8.0, 16, 0.75)
     with pytest.raises(ewbem.EwbemError):
