@@ -170,7 +170,7 @@ typedef struct {
                                  [1] 4,480, [2] 8,960 entries, [4] at most 64 rows and 1,024
                                  entries; [3] larger or over 128 rows, in global memory */
   int64_t aca_warm_pivots;  /* pivots eliminated in the warm starts' cores, summed */
-  int64_t aca_warm_kept;    /* of their terms, those kept up to the stopping test, summed */
+  int64_t aca_warm_kept;    /* of their terms, those kept (all of them with ws_keep 1), summed */
   int64_t aca_retries;      /* far blocks approximated again with more capacity */
   int64_t aca_steps;        /* lock steps of the ACA after the starts (each adds terms to
                                every still-active block), summed */
